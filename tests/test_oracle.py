@@ -1,0 +1,374 @@
+"""Pins for the CPU oracle: every check compares it with something other than
+itself -- exact integer/dyadic constructions, brute-force unblocked versions,
+closed forms, LAPACK (scipy) as a third-party cross-check, and the ABFT
+invariants.  None of these tests needs a GPU."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.linalg import lapack
+
+import oracle
+from paper_2301_03166_amd import gen
+
+U64 = 2.0 ** -53
+
+
+def lower(a):
+    return np.tril(a)
+
+
+def unit_lower(a):
+    return np.tril(a, -1) + np.eye(a.shape[0])
+
+
+def perm_from_ipiv(ipiv, n):
+    p = np.arange(n)
+    for j, q in enumerate(ipiv):
+        q -= 1
+        p[j], p[q] = p[q], p[j]
+    return p
+
+
+# ------------------------------------------------------------------ Cholesky
+@pytest.mark.parametrize("n,nb", [(1, 1), (7, 3), (16, 4), (33, 8), (50, 16), (64, 64), (40, 128)])
+def test_potrf_exact_integer(n, nb):
+    """A = L0 L0^T with small integers: every intermediate is an exact integer,
+    so the blocked factor must equal L0 bit for bit, and every carried checksum
+    must equal the recomputed one exactly (d = 0 at every verify)."""
+    A, L0 = gen.chol_exact(n, seed=n * 31 + nb)
+    info, rep = oracle.potrf(A, nb)
+    assert info == 0
+    assert np.array_equal(lower(A), L0)
+    assert rep.flagged_tiles == 0 and rep.panel_flags == 0 and rep.status == 0
+    assert rep.max_ratio == 0.0
+
+
+def test_potrf_diag_perfect_squares():
+    d = np.array([1.0, 4.0, 9.0, 16.0, 25.0, 36.0])
+    A = np.asfortranarray(np.diag(d))
+    info, _ = oracle.potrf(A, 4)
+    assert info == 0 and np.array_equal(np.diag(A), np.sqrt(d))
+
+
+@pytest.mark.parametrize("n,nb", [(17, 5), (48, 16), (64, 7)])
+def test_potrf_blocked_vs_unblocked(n, nb):
+    A0 = gen.spd(n, seed=n + nb)
+    A1, A2 = A0.copy(order="F"), A0.copy(order="F")
+    assert oracle.potrf(A1, nb)[0] == 0
+    assert oracle.potrf_unb(A2) == 0
+    assert np.max(np.abs(lower(A1) - lower(A2))) <= 64 * n * U64 * np.max(np.abs(lower(A2)))
+
+
+def test_potrf_vs_lapack_and_backward_error():
+    n, nb = 96, 32
+    A0 = gen.spd(n, seed=5)
+    A = A0.copy(order="F")
+    assert oracle.potrf(A, nb)[0] == 0
+    L = lower(A)
+    ref, info = lapack.dpotrf(A0, lower=1)
+    assert info == 0
+    assert np.linalg.norm(L - np.tril(ref)) <= 16 * n * U64 * np.linalg.norm(np.tril(ref))
+    assert np.linalg.norm(A0 - L @ L.T) / np.linalg.norm(A0) < 1e-15
+
+
+def test_potrf_not_spd_info():
+    A, _ = gen.chol_exact(12, seed=3)
+    A[7, 7] = -1.0  # leading minor of order 8 is no longer positive definite
+    A = np.asfortranarray(A)
+    info, _ = oracle.potrf(A, 4)
+    assert info == 8
+
+
+# ------------------------------------------------------------------------ LU
+@pytest.mark.parametrize("n,nb", [(1, 1), (9, 4), (24, 8), (37, 10), (64, 16), (30, 64)])
+def test_getrf_exact_dyadic(n, nb):
+    """A = P0 L0 U0 with |l| < 1 and dyadic values: partial pivoting must
+    recover P0, L0 and U0 exactly, for any summation order."""
+    A, P, L0, U0 = gen.lu_exact(n, seed=7 * n + nb)
+    ipiv, info, rep = oracle.getrf(A, nb)
+    assert info == 0
+    assert np.array_equal(unit_lower(A), L0)
+    assert np.array_equal(np.triu(A), U0)
+    perm = perm_from_ipiv(ipiv, n)
+    assert np.array_equal(np.eye(n)[perm] @ P, np.eye(n))  # P A = L U  with  P = P0^T
+    assert rep.flagged_tiles == 0 and rep.panel_flags == 0 and rep.max_ratio == 0.0
+
+
+def test_getrf_first_index_tie_break():
+    """L0 entries in {-1,0,1}: each pivot column has ties; only a first-index
+    rule keeps the identity permutation."""
+    n = 20
+    A = gen.lu_tie(n, seed=11)
+    ipiv, info, _ = oracle.getrf(A, 8)
+    assert info == 0
+    assert np.array_equal(ipiv, np.arange(1, n + 1))
+
+
+def test_getrf_singular_column():
+    n = 10
+    A = gen.general(n, seed=2)
+    A[:, 4] = 0.0
+    A = np.asfortranarray(A)
+    _, info, _ = oracle.getrf(A, 3, protect=False)
+    assert info == 5
+
+
+@pytest.mark.parametrize("n,nb", [(33, 8), (64, 16)])
+def test_getrf_vs_lapack(n, nb):
+    A0 = gen.general(n, seed=n)
+    A = A0.copy(order="F")
+    ipiv, info, _ = oracle.getrf(A, nb)
+    lu, piv, linfo = lapack.dgetrf(A0)
+    assert info == 0 and linfo == 0
+    assert np.array_equal(ipiv, piv + 1)
+    assert np.max(np.abs(A - lu)) <= 1e3 * U64 * np.max(np.abs(lu))
+    B = A0.copy(order="F")
+    ipiv2, _ = oracle.getrf_unb(B)
+    assert np.array_equal(ipiv2, ipiv)
+    perm = perm_from_ipiv(ipiv, n)
+    L, U = unit_lower(A), np.triu(A)
+    assert np.linalg.norm(A0[perm] - L @ U) / np.linalg.norm(A0) < 1e-15
+
+
+# ------------------------------------------------------------------------ QR
+def qr_q(A, tau):
+    n = A.shape[0]
+    Q = np.eye(n)
+    for j in range(n - 1, -1, -1):
+        v = np.zeros(n)
+        v[j] = 1.0
+        v[j + 1:] = A[j + 1:, j]
+        Q -= tau[j] * np.outer(v, v @ Q)
+    return Q
+
+
+def test_geqrf_upper_triangular_is_fixed_point():
+    n = 21
+    A0 = np.asfortranarray(np.triu(gen.general(n, seed=4)))
+    A = A0.copy(order="F")
+    tau, rep = oracle.geqrf(A, 8)
+    assert np.all(tau == 0.0)
+    assert np.array_equal(A, A0)
+    assert rep.flagged_tiles == 0 and rep.panel_flags == 0
+
+
+def test_geqrf_orthogonal_input_closed_form():
+    """A = Q from the reflector generator: R must be diagonal with |R_ii| = 1."""
+    n = 40
+    _, _, V = gen.mp_matrix(n, 1.0, seed=9)
+    Q = np.eye(n)
+    for v in V:
+        Q = Q - (2.0 / (v @ v)) * np.outer(Q @ v, v)
+    A = np.asfortranarray(Q)
+    oracle.geqrf(A, 16)
+    R = np.triu(A)
+    assert np.allclose(np.abs(np.diag(R)), 1.0, atol=1e-13)
+    assert np.max(np.abs(R - np.diag(np.diag(R)))) < 1e-13
+
+
+@pytest.mark.parametrize("n,nb", [(30, 8), (64, 16), (45, 45)])
+def test_geqrf_vs_lapack_and_invariants(n, nb):
+    A0 = gen.general(n, seed=3 * n + nb)
+    A = A0.copy(order="F")
+    tau, rep = oracle.geqrf(A, nb)
+    qr, ltau, _, info = lapack.dgeqrf(A0)
+    assert info == 0
+    assert np.max(np.abs(tau - ltau)) < 1e-13
+    assert np.max(np.abs(np.triu(A) - np.triu(qr))) < 1e-12 * np.max(np.abs(qr))
+    Q = qr_q(A, tau)
+    R = np.triu(A)
+    assert np.linalg.norm(A0 - Q @ R) / np.linalg.norm(A0) < 1e-14
+    assert np.linalg.norm(np.eye(n) - Q.T @ Q) / np.sqrt(n) < 1e-14
+    assert rep.flagged_tiles == 0 and rep.panel_flags == 0
+
+
+def test_geqrf_blocked_vs_unblocked():
+    n = 50
+    A0 = gen.general(n, seed=8)
+    A1, A2 = A0.copy(order="F"), A0.copy(order="F")
+    t1, _ = oracle.geqrf(A1, 12)
+    t2 = oracle.geqrf_unb(A2)
+    assert np.max(np.abs(t1 - t2)) < 1e-13
+    assert np.max(np.abs(A1 - A2)) < 1e-12
+
+
+# ---------------------------------------------------------------- ABFT layer
+def test_encode_closed_form():
+    """Column side [e, w] per tile-row and row side [e, w] per tile-column."""
+    m, n, nb = 5, 4, 2
+    A = np.asfortranarray(np.arange(1.0, m * n + 1).reshape(n, m).T)
+    colchk, rowchk = oracle.encode(A, nb)
+    for I in range(3):
+        rows = A[I * nb:(I + 1) * nb]
+        w = np.arange(1, rows.shape[0] + 1)
+        assert np.array_equal(colchk[2 * I], rows.sum(0))
+        assert np.array_equal(colchk[2 * I + 1], w @ rows)
+    for J in range(2):
+        cols = A[:, J * nb:(J + 1) * nb]
+        w = np.arange(1, cols.shape[1] + 1)
+        assert np.array_equal(rowchk[:, 2 * J], cols.sum(1))
+        assert np.array_equal(rowchk[:, 2 * J + 1], cols @ w)
+    nfl, flags, mr = oracle.verify(A, nb, colchk, rowchk)
+    assert nfl == 0 and mr == 0.0
+    B = A.copy(order="F")
+    B[3, 2] += 1.0
+    nfl, flags, _ = oracle.verify(B, nb, colchk, rowchk)
+    assert nfl == 1 and flags[1, 1] == 1
+
+
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
+def test_no_false_alarms_random(kind):
+    n, nb = 96, 16
+    for seed in range(4):
+        A = gen.spd(n, seed) if kind == "chol" else gen.general(n, seed)
+        if kind == "chol":
+            info, rep = oracle.potrf(A, nb)
+        elif kind == "lu":
+            _, info, rep = oracle.getrf(A, nb)
+        else:
+            _, rep = oracle.geqrf(A, nb)
+        assert rep.flagged_tiles == 0 and rep.panel_flags == 0 and rep.status == 0
+        assert 0.0 < rep.max_ratio < 0.35
+
+
+def _run(kind, A, nb, faults=None, tau_scale=2.0):
+    if kind == "chol":
+        info, rep = oracle.potrf(A, nb, faults=faults, tau_scale=tau_scale)
+        return rep, {}
+    if kind == "lu":
+        ipiv, info, rep = oracle.getrf(A, nb, faults=faults, tau_scale=tau_scale)
+        return rep, {"ipiv": ipiv}
+    tau, rep = oracle.geqrf(A, nb, faults=faults, tau_scale=tau_scale)
+    return rep, {"tau": tau}
+
+
+def _make(kind, n, seed):
+    return gen.spd(n, seed) if kind == "chol" else gen.general(n, seed)
+
+
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
+@pytest.mark.parametrize("bit", [62, 60, 55, 52, 45])
+def test_single_flip_detected_and_corrected(kind, bit):
+    """A significant single-bit flip in the trailing matrix is located at the
+    injected element and corrected; the factors then match the clean run."""
+    n, nb = 80, 16
+    A0 = _make(kind, n, seed=bit)
+    clean = A0.copy(order="F")
+    rep0, aux0 = _run(kind, clean, nb)
+    f = gen.fault_plan(kind, n, nb, seed=1000 + bit)
+    f["bit"] = bit
+    A = A0.copy(order="F")
+    rep, aux = _run(kind, A, nb, faults=[f])
+    assert rep.status & oracle.ST_CORRECTED and not rep.status & oracle.ST_UNCORRECTABLE
+    assert rep.corrected == 1 and rep.first_flag_iter == f["iter"]
+    ev = rep.events()
+    assert ev[0] == (f["iter"], 1, f["row"], f["col"])
+    scale = np.max(np.abs(clean))
+    assert np.max(np.abs(A - clean)) <= 1e-12 * scale
+    for k in aux0:
+        assert np.allclose(aux[k], aux0[k], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
+def test_low_bit_flip_harmless(kind):
+    """Bit 0 changes an element by one ulp: undetectable by any floating-point
+    checksum and harmless for the backward error."""
+    n, nb = 64, 16
+    A0 = _make(kind, n, seed=2)
+    f = gen.fault_plan(kind, n, nb, seed=77)
+    f["bit"] = 0
+    A = A0.copy(order="F")
+    rep, _ = _run(kind, A, nb, faults=[f])
+    assert not rep.status & oracle.ST_UNCORRECTABLE
+    clean = A0.copy(order="F")
+    _run(kind, clean, nb)
+    assert np.max(np.abs(A - clean)) <= 1e-12 * np.max(np.abs(clean))
+
+
+@pytest.mark.parametrize("kind", ["lu", "qr"])
+def test_two_flips_same_tile_uncorrectable(kind):
+    n, nb = 64, 16
+    A = _make(kind, n, seed=5)
+    k = 1
+    base = (k + 1) * nb
+    f1 = {"iter": k, "row": base + 2, "col": base + 3, "bit": 61}
+    f2 = {"iter": k, "row": base + 5, "col": base + 9, "bit": 61}
+    rep, _ = _run(kind, A, nb, faults=[f1, f2])
+    assert rep.status & oracle.ST_UNCORRECTABLE
+
+
+def test_nan_and_inf_flips_corrected():
+    n, nb = 64, 16
+    A0 = gen.general(n, seed=6)
+    clean = A0.copy(order="F")
+    _run("lu", clean, nb)
+    # bit 62 on an entry of magnitude in [1,2) turns it into +-Inf/NaN territory
+    A = A0.copy(order="F")
+    f = {"iter": 0, "row": 40, "col": 50, "bit": 62}
+    rep, _ = _run("lu", A, nb, faults=[f])
+    assert rep.corrected == 1 and not rep.status & oracle.ST_UNCORRECTABLE
+    assert np.max(np.abs(A - clean)) <= 1e-12 * np.max(np.abs(clean))
+
+
+@pytest.mark.parametrize("target", [1, 2])
+def test_checksum_flip_repaired(target):
+    n, nb = 64, 16
+    A0 = gen.general(n, seed=9)
+    clean = A0.copy(order="F")
+    _run("lu", clean, nb)
+    A = A0.copy(order="F")
+    # column checksums: row 2I (+1) of tile-row I; row checksums: column 2J (+1)
+    f = {"iter": 1, "target": target, "row": 2 * 3 if target == 1 else 50, "col": 45 if target == 1 else 2 * 3,
+         "bit": 58}
+    rep, _ = _run("lu", A, nb, faults=[f])
+    assert rep.status & oracle.ST_REPAIRED and rep.checksum_repaired == 1
+    assert not rep.status & (oracle.ST_CORRECTED | oracle.ST_UNCORRECTABLE)
+    assert np.array_equal(A, clean)
+
+
+# ------------------------------------------------------------ MP + refinement
+def test_bf16_fp16_rounding_vs_libraries():
+    import torch
+    x = gen.rng(1).standard_normal(4000) * np.exp(gen.rng(2).uniform(-30, 30, 4000))
+    x = x.astype(np.float32).astype(np.float64)
+    bf = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(oracle.round_bf16(x), bf)
+    h = x.astype(np.float16).astype(np.float64)
+    assert np.array_equal(oracle.round_fp16(x), h)
+
+
+def test_mp_generator_closed_form_and_reference_solve():
+    n, kappa = 200, 1e6
+    A, s, V = gen.mp_matrix(n, kappa, seed=21)
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert abs(sv[0] / sv[-1] / kappa - 1) < 1e-6
+    b = gen.rhs(n, seed=24)
+    xs = gen.mp_exact_solution(b, s, V)
+    xr = oracle.solve_ref(A, b)
+    assert np.linalg.norm(xr - xs, np.inf) / np.linalg.norm(xs, np.inf) < 50 * kappa * U64
+
+
+@pytest.mark.parametrize("prec,kappa,expect", [(oracle.PR32, 1e2, True), (oracle.PR32, 1e6, True),
+                                                (oracle.PRBF16, 1e2, True), (oracle.PRBF16, 1e10, False),
+                                                (oracle.PRF16, 1e2, True)])
+def test_mp_refinement_outcomes(prec, kappa, expect):
+    n = 128
+    A, s, V = gen.mp_matrix(n, kappa, seed=21)
+    b = gen.rhs(n, seed=24)
+    x, info, ir = oracle.gesv_mp(A, b, prec, nb=32)
+    assert info == 0
+    assert bool(ir.converged) == expect
+    if expect:
+        xr = oracle.solve_ref(A, b)
+        err = np.linalg.norm(x - xr, np.inf) / np.linalg.norm(xr, np.inf)
+        assert err < max(1e-12, 20 * kappa * U64)
+
+
+def test_mp_cholesky_refinement():
+    n = 96
+    A, s, V = gen.mp_matrix(n, 1e2, seed=22)
+    b = gen.rhs(n, seed=24)
+    x, info, ir = oracle.gesv_mp(A, b, oracle.PRBF16, nb=32, chol=True)
+    assert info == 0 and ir.converged
+    xs = gen.mp_exact_solution(b, s, V)
+    assert np.linalg.norm(x - xs, np.inf) / np.linalg.norm(xs, np.inf) < 1e-12
