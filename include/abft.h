@@ -1,0 +1,201 @@
+/*
+ * abft.h -- C ABI of the ABFT-protected one-sided decomposition library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the blocked one-sided decompositions of Chen et al.,
+ * "Improving Energy Saving of One-sided Matrix Decompositions on CPU-GPU
+ * Heterogeneous Systems" (PPoPP'23), section "State-of-the-art matrix
+ * decompositions": each iteration performs a panel decomposition (PD), a
+ * panel update (PU) and a trailing-matrix update (TMU).  The fault tolerance
+ * follows the paper's ABFT description (section "Design of ABFT-OC"):
+ * checksums are encoded before an operation, the same operation is applied to
+ * them, and the relation is verified after every iteration (the detection
+ * interval); full checksums cover rows and columns of every b x b block.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are column-major, element (i,j) at A[i + j*lda], lda >= n.
+ *   - Every pointer argument whose name starts with `d` is DEVICE memory owned
+ *     by the caller (for instance a PyTorch tensor).  The library never
+ *     allocates device memory; scratch space is the caller's `dwork` buffer,
+ *     sized with abft_workspace_size().  `opts` and fault plans are host
+ *     memory and are read before the call returns.
+ *   - Calls are asynchronous on the handle's HIP stream.  Results, `dinfo`
+ *     and the report become valid once the stream has been synchronized.
+ *   - Return value: 0 on success; -i when argument i (1-based) is invalid;
+ *     ABFT_ERR_HIP when a HIP call failed (launch or cooperative-launch
+ *     error); ABFT_ERR_WORKSPACE when `work_bytes` is too small;
+ *     ABFT_ERR_UNSUPPORTED for an option combination that is not built.
+ *   - Numerical status is written to device memory: potrf `*dinfo = j > 0`
+ *     when the leading minor of order j is not positive definite; getrf
+ *     `*dinfo = j > 0` when U(j,j) is exactly zero (factorization completes,
+ *     LAPACK semantics).  The ABFT outcome is in the report.
+ */
+#ifndef ABFT_H
+#define ABFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct abft_handle_s* abft_handle;
+
+enum {
+  ABFT_OK = 0,
+  ABFT_ERR_HIP = -100,
+  ABFT_ERR_WORKSPACE = -101,
+  ABFT_ERR_UNSUPPORTED = -102
+};
+
+/* protection level: no checksums, or full (row + column) checksums */
+enum { ABFT_PROTECT_NONE = 0, ABFT_PROTECT_FULL = 2 };
+
+/* arithmetic of a factorization: FP64, FP32, or FP32 data whose trailing
+   update multiplies bf16 / fp16 operands with FP32 accumulation */
+enum { ABFT_F64 = 0, ABFT_F32 = 1, ABFT_BF16 = 2, ABFT_F16 = 3 };
+
+/* operation codes for abft_workspace_size */
+enum {
+  ABFT_OP_POTRF = 1,
+  ABFT_OP_GETRF = 2,
+  ABFT_OP_GEQRF = 3,
+  ABFT_OP_GESV_MP = 4,
+  ABFT_OP_POSV_MP = 5,
+  ABFT_OP_POTRF_BATCHED = 6,
+  ABFT_OP_GETRF_BATCHED = 7
+};
+
+/* report status bits */
+enum {
+  ABFT_ST_CORRECTED = 1,     /* at least one element was located and recomputed */
+  ABFT_ST_REPAIRED = 2,      /* a checksum entry itself was wrong and re-encoded */
+  ABFT_ST_UNCORRECTABLE = 4, /* a flagged tile could not be corrected: result untrustworthy */
+  ABFT_ST_PANEL = 8,         /* a panel / panel-update check failed (detection only) */
+  ABFT_ST_INTERNAL = 16      /* a cooperative kernel hit its wait limit: result invalid */
+};
+
+/* A test-only fault plan: after the trailing update of iteration `iter`, flip
+   bit `bit` (0..63 of the binary64 pattern; 0..31 of binary32 data) of one
+   element.  target 0 = the matrix (row, col are matrix indices), 1 = the
+   column-checksum array (row in [0, 2*ceil(n/nb))), 2 = the row-checksum array
+   (col in [0, 2*ceil(n/nb))).  `matrix` selects the matrix of a batch. */
+typedef struct {
+  int32_t iter, target;
+  int64_t row, col;
+  int32_t bit, matrix;
+} abft_fault;
+
+typedef struct {
+  int32_t iter, kind; /* 1 corrected, 2 checksum repaired, 3 uncorrectable, 4 panel flag */
+  int64_t row, col;   /* corrected element, or the flagged tile's first row / column */
+} abft_event;
+
+#define ABFT_MAX_EVENTS 16
+
+/* Device-resident outcome of one protected call (zeroed by the call itself). */
+typedef struct {
+  int64_t flagged_tiles, corrected, checksum_repaired, uncorrectable, panel_flags;
+  int32_t first_flag_iter, status; /* first iteration with a flag (-1 none); ABFT_ST_* bits */
+  double max_ratio;                /* largest |d| / tau over the unflagged comparisons */
+  int32_t nev, pad;
+  abft_event ev[ABFT_MAX_EVENTS];
+} abft_report;
+
+typedef struct {
+  int32_t nb;          /* block size = checksum tile size (1..1024) */
+  int32_t protect;     /* ABFT_PROTECT_NONE or ABFT_PROTECT_FULL */
+  double tau_scale;    /* threshold scale (default 4.0 when <= 0) */
+  const abft_fault* faults; /* host array of fault plans (test use), may be NULL */
+  int32_t nfaults;
+  int32_t flags;       /* reserved, 0 */
+} abft_opts;
+
+typedef struct {
+  int32_t iters, converged, failed_reason, info; /* reason: 0 ok, 1 no contraction, 2 non-finite, 3 max iter, 4 factorization info */
+  double resid_norm, x_norm, a_norm, last_dx;    /* infinity norms at exit */
+} abft_ir_report;
+
+/* Handle: holds the stream and device properties.  `stream` is a hipStream_t
+   (NULL = the default stream).  Returns 0 or ABFT_ERR_HIP. */
+int abft_create(abft_handle* h, void* stream);
+int abft_destroy(abft_handle h);
+int abft_set_stream(abft_handle h, void* stream);
+
+/* Bytes of device workspace needed by operation `op` on an n x n problem
+   (for the batched ops: n = the largest matrix order, `batch` matrices). */
+int abft_workspace_size(abft_handle h, int op, int64_t n, int32_t batch, const abft_opts* opts, size_t* bytes);
+
+/* Cholesky A = L L^T of the lower triangle (the strict upper triangle is
+   neither read nor written).  Blocked right-looking with block size opts->nb;
+   the trailing update carries per-tile row and column checksums of the
+   symmetric trailing matrix, verified and corrected every iteration.
+   dinfo: device int32.  drep: device abft_report (may be NULL). */
+int abft_potrf(abft_handle h, int64_t n, double* dA, int64_t lda, void* dwork, size_t work_bytes,
+               const abft_opts* opts, int32_t* dinfo, abft_report* drep);
+
+/* LU with partial pivoting P A = L U (L unit lower, U upper, both in A).
+   dipiv: device int32[n], 1-based LAPACK row interchanges; ties in the pivot
+   search take the first (smallest) row index. */
+int abft_getrf(abft_handle h, int64_t n, double* dA, int64_t lda, int32_t* dipiv, void* dwork, size_t work_bytes,
+               const abft_opts* opts, int32_t* dinfo, abft_report* drep);
+
+/* Householder QR A = Q R, LAPACK geqrf storage: R in the upper triangle, the
+   reflector vectors v (v(j) = 1 implicit) below the diagonal, dtau[n] the
+   scalar factors (H_j = I - tau_j v_j v_j^T). */
+int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, void* dwork, size_t work_bytes,
+               const abft_opts* opts, int32_t* dinfo, abft_report* drep);
+
+/* Standalone per-tile checksums of an m x n matrix with tile size nb:
+   dcolchk is (2*ceil(m/nb)) x n with leading dimension ldc >= 2*ceil(m/nb):
+   row 2I holds the column sums of tile-row I, row 2I+1 the sums weighted by
+   the row's position in the tile (1..nb).  drowchk is m x (2*ceil(n/nb)) with
+   ldr >= m: column 2J holds the row sums over tile-column J, column 2J+1 the
+   sums weighted by the column's position in the tile. */
+int abft_encode(abft_handle h, int64_t m, int64_t n, const double* dA, int64_t lda, int32_t nb, double* dcolchk,
+                int64_t ldc, double* drowchk, int64_t ldr);
+
+/* Compare the matrix with checksums from abft_encode.  dflags (device int32,
+   ceil(m/nb) x ceil(n/nb), column-major, may be NULL) receives 1 for a
+   flagged tile.  With correct != 0, flagged tiles go through the same
+   locate / correct step as the factorizations (A and the checksums are then
+   modified in place).  drep receives counters and max_ratio. */
+int abft_verify(abft_handle h, int64_t m, int64_t n, double* dA, int64_t lda, int32_t nb, double* dcolchk,
+                int64_t ldc, double* drowchk, int64_t ldr, double tau_scale, int32_t correct, int32_t* dflags,
+                abft_report* drep);
+
+/* Mixed-precision solve of A x = b (A n x n FP64, not modified): factor a
+   binary32 copy of A (LU with partial pivoting, or Cholesky for posv) whose
+   trailing updates run in `prec` (ABFT_F32, ABFT_BF16 or ABFT_F16 operands
+   with FP32 accumulation), then refine in FP64: r = b - A x, d = solve(r),
+   x += d, until ||d|| <= u ||x|| or ||r|| <= u ||A|| ||x|| (u = 2^-53), with
+   failure on non-finite values, on ||d_i|| > ||d_(i-1)||/2 while far from
+   convergence, or after max_iter corrections.  prec == ABFT_F64 factors in
+   FP64 and solves directly (the reference method).  dir: device
+   abft_ir_report. */
+int abft_gesv_mp(abft_handle h, int64_t n, const double* dA, int64_t lda, const double* db, double* dx, int32_t prec,
+                 int32_t max_iter, void* dwork, size_t work_bytes, const abft_opts* opts, abft_ir_report* dir,
+                 abft_report* drep);
+int abft_posv_mp(abft_handle h, int64_t n, const double* dA, int64_t lda, const double* db, double* dx, int32_t prec,
+                 int32_t max_iter, void* dwork, size_t work_bytes, const abft_opts* opts, abft_ir_report* dir,
+                 abft_report* drep);
+
+/* Batched protected factorizations of `batch` independent matrices of
+   uneven orders.  dn[i], dlda[i] (device int32) and dA[i] (device array of
+   device pointers) describe matrix i; prec is ABFT_F64 (double data) or
+   ABFT_F32 (float data; dA then holds float pointers).  nmax bounds every
+   dn[i] (<= 512).  dinfo[i] and dreps[i] receive each matrix's status.
+   Fault plans select their matrix with abft_fault.matrix.  Calls are
+   captured in a HIP graph by the library on first use and replayed. */
+int abft_potrf_batched(abft_handle h, int32_t batch, int32_t nmax, const int32_t* dn, void* const* dA,
+                       const int32_t* dlda, int32_t prec, void* dwork, size_t work_bytes, const abft_opts* opts,
+                       int32_t* dinfo, abft_report* dreps);
+int abft_getrf_batched(abft_handle h, int32_t batch, int32_t nmax, const int32_t* dn, void* const* dA,
+                       const int32_t* dlda, int32_t* const* dipiv, int32_t prec, void* dwork, size_t work_bytes,
+                       const abft_opts* opts, int32_t* dinfo, abft_report* dreps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABFT_H */

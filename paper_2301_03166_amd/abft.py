@@ -1,0 +1,226 @@
+"""Python binding of the C ABI in include/abft.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libabft.so`` built in-tree by
+``paper_2301_03166_amd._build``; there is no fallback path.  PyTorch provides
+device memory and the stream: matrices are CUDA (HIP) tensors in column-major
+layout, i.e. ``A.stride(0) == 1`` and ``lda = A.stride(1)`` -- a
+Fortran-ordered numpy array passed through ``torch.from_numpy(...).cuda()``
+keeps that layout, and ``colmajor(t)`` makes one from any tensor.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libabft.so")
+
+F64, F32, BF16, F16 = 0, 1, 2, 3
+PROTECT_NONE, PROTECT_FULL = 0, 2
+OP_POTRF, OP_GETRF, OP_GEQRF, OP_GESV_MP, OP_POSV_MP, OP_POTRF_BATCHED, OP_GETRF_BATCHED = 1, 2, 3, 4, 5, 6, 7
+ST_CORRECTED, ST_REPAIRED, ST_UNCORRECTABLE, ST_PANEL, ST_INTERNAL = 1, 2, 4, 8, 16
+
+
+class Fault(C.Structure):
+    _fields_ = [("iter", C.c_int32), ("target", C.c_int32), ("row", C.c_int64), ("col", C.c_int64),
+                ("bit", C.c_int32), ("matrix", C.c_int32)]
+
+
+class Event(C.Structure):
+    _fields_ = [("iter", C.c_int32), ("kind", C.c_int32), ("row", C.c_int64), ("col", C.c_int64)]
+
+
+class Report(C.Structure):
+    _fields_ = [("flagged_tiles", C.c_int64), ("corrected", C.c_int64), ("checksum_repaired", C.c_int64),
+                ("uncorrectable", C.c_int64), ("panel_flags", C.c_int64), ("first_flag_iter", C.c_int32),
+                ("status", C.c_int32), ("max_ratio", C.c_double), ("nev", C.c_int32), ("pad", C.c_int32),
+                ("ev", Event * 16)]
+
+    def events(self):
+        return sorted((self.ev[i].iter, self.ev[i].kind, self.ev[i].row, self.ev[i].col)
+                      for i in range(min(self.nev, 16)))
+
+
+class IRReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("failed_reason", C.c_int32), ("info", C.c_int32),
+                ("resid_norm", C.c_double), ("x_norm", C.c_double), ("a_norm", C.c_double), ("last_dx", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("protect", C.c_int32), ("tau_scale", C.c_double),
+                ("faults", C.POINTER(Fault)), ("nfaults", C.c_int32), ("flags", C.c_int32)]
+
+
+class AbftError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libabft.so; raise if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise AbftError(f"{LIB_PATH} is missing: build it with paper_2301_03166_amd._build.build()")
+        L = C.CDLL(LIB_PATH)
+        P, i64, i32, d, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_size_t
+        L.abft_create.argtypes = [C.POINTER(P), P]
+        L.abft_destroy.argtypes = [P]
+        L.abft_set_stream.argtypes = [P, P]
+        L.abft_workspace_size.argtypes = [P, C.c_int, i64, i32, C.POINTER(Opts), C.POINTER(sz)]
+        L.abft_potrf.argtypes = [P, i64, P, i64, P, sz, C.POINTER(Opts), P, P]
+        L.abft_getrf.argtypes = [P, i64, P, i64, P, P, sz, C.POINTER(Opts), P, P]
+        L.abft_geqrf.argtypes = [P, i64, P, i64, P, P, sz, C.POINTER(Opts), P, P]
+        L.abft_encode.argtypes = [P, i64, i64, P, i64, i32, P, i64, P, i64]
+        L.abft_verify.argtypes = [P, i64, i64, P, i64, i32, P, i64, P, i64, d, i32, P, P]
+        L.abft_gesv_mp.argtypes = [P, i64, P, i64, P, P, i32, i32, P, sz, C.POINTER(Opts), P, P]
+        L.abft_posv_mp.argtypes = [P, i64, P, i64, P, P, i32, i32, P, sz, C.POINTER(Opts), P, P]
+        L.abft_potrf_batched.argtypes = [P, i32, i32, P, P, P, i32, P, sz, C.POINTER(Opts), P, P]
+        L.abft_getrf_batched.argtypes = [P, i32, i32, P, P, P, P, i32, P, sz, C.POINTER(Opts), P, P]
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise AbftError(f"{what} returned {rc}")
+
+
+def colmajor(t):
+    """A column-major copy (stride(0) == 1) of a 2-D tensor with the same values."""
+    return t.t().contiguous().t()
+
+
+def _ld(A):
+    if A.dim() != 2 or A.stride(0) != 1:
+        raise AbftError("matrices must be column-major 2-D tensors (stride(0) == 1)")
+    return max(A.stride(1), A.shape[0], 1)
+
+
+def make_opts(nb, protect=True, tau_scale=4.0, faults=None):
+    o = Opts()
+    o.nb, o.protect, o.tau_scale = int(nb), PROTECT_FULL if protect else PROTECT_NONE, float(tau_scale)
+    keep = None
+    if faults:
+        keep = (Fault * len(faults))()
+        for q, f in enumerate(faults):
+            keep[q].iter, keep[q].target = int(f["iter"]), int(f.get("target", 0))
+            keep[q].row, keep[q].col, keep[q].bit = int(f["row"]), int(f["col"]), int(f["bit"])
+            keep[q].matrix = int(f.get("matrix", 0))
+        o.faults, o.nfaults = C.cast(keep, C.POINTER(Fault)), len(faults)
+    return o, keep
+
+
+class Handle:
+    """Owns an abft_handle bound to torch's current stream and cached workspaces."""
+
+    def __init__(self, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().abft_create(C.byref(self._h), C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+                   "abft_create")
+        self._ws = {}
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().abft_destroy(self._h)
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        lib().abft_set_stream(self._h, C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream))
+
+    def workspace(self, op, n, opts, batch=0):
+        size = C.c_size_t()
+        _check(lib().abft_workspace_size(self._h, op, int(n), int(batch), C.byref(opts), C.byref(size)),
+               "abft_workspace_size")
+        buf = self._ws.get(op)
+        if buf is None or buf.numel() < size.value:
+            self._ws[op] = buf = self.torch.empty(max(size.value, 1), dtype=self.torch.uint8, device=self.device)
+        return buf, size.value
+
+    def new_report(self):
+        return self.torch.zeros(C.sizeof(Report), dtype=self.torch.uint8, device=self.device)
+
+    @staticmethod
+    def read_report(buf):
+        raw = bytes(buf.cpu().numpy().tobytes())
+        return Report.from_buffer_copy(raw)
+
+    # ------------------------------------------------------------ factorizations
+    def potrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True):
+        """In-place Cholesky (lower) of column-major A; returns (info, Report) when sync."""
+        return self._factor(OP_POTRF, A, nb, protect, tau_scale, faults, report, info, sync)
+
+    def getrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, ipiv=None, report=None, info=None, sync=True):
+        torch = self.torch
+        if ipiv is None:
+            ipiv = torch.zeros(A.shape[0], dtype=torch.int32, device=self.device)
+        out = self._factor(OP_GETRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=ipiv)
+        return (ipiv,) + out if sync else ipiv
+
+    def geqrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, tau=None, report=None, info=None, sync=True):
+        torch = self.torch
+        if tau is None:
+            tau = torch.zeros(A.shape[0], dtype=torch.float64, device=self.device)
+        out = self._factor(OP_GEQRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=tau)
+        return (tau,) + out if sync else tau
+
+    def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None):
+        torch = self.torch
+        n = A.shape[0]
+        if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
+            raise AbftError("expected a square float64 device matrix")
+        lda = _ld(A)
+        opts, keep = make_opts(nb, protect, tau_scale, faults)
+        ws, wbytes = self.workspace(op, n, opts)
+        rep = report if report is not None else self.new_report()
+        inf = info if info is not None else torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._sync_stream()
+        L = lib()
+        if op == OP_POTRF:
+            rc = L.abft_potrf(self._h, n, A.data_ptr(), lda, ws.data_ptr(), wbytes, C.byref(opts), inf.data_ptr(),
+                              rep.data_ptr())
+        elif op == OP_GETRF:
+            rc = L.abft_getrf(self._h, n, A.data_ptr(), lda, aux.data_ptr(), ws.data_ptr(), wbytes, C.byref(opts),
+                              inf.data_ptr(), rep.data_ptr())
+        else:
+            rc = L.abft_geqrf(self._h, n, A.data_ptr(), lda, aux.data_ptr(), ws.data_ptr(), wbytes, C.byref(opts),
+                              inf.data_ptr(), rep.data_ptr())
+        del keep
+        _check(rc, f"op {op}")
+        if not sync:
+            return ()
+        torch.cuda.synchronize(self.device)
+        return int(inf.item()), self.read_report(rep)
+
+    # ------------------------------------------------------------ checksums
+    def encode(self, A, nb):
+        torch = self.torch
+        m, n = A.shape
+        Tr, Tc = -(-m // nb), -(-n // nb)
+        colchk = colmajor(torch.zeros((2 * Tr, n), dtype=torch.float64, device=self.device))
+        rowchk = colmajor(torch.zeros((m, 2 * Tc), dtype=torch.float64, device=self.device))
+        self._sync_stream()
+        _check(lib().abft_encode(self._h, m, n, A.data_ptr(), _ld(A), nb, colchk.data_ptr(), _ld(colchk),
+                                 rowchk.data_ptr(), _ld(rowchk)), "abft_encode")
+        return colchk, rowchk
+
+    def verify(self, A, nb, colchk, rowchk, tau_scale=4.0, correct=False):
+        torch = self.torch
+        m, n = A.shape
+        Tr, Tc = -(-m // nb), -(-n // nb)
+        flags = colmajor(torch.zeros((Tr, Tc), dtype=torch.int32, device=self.device))
+        rep = self.new_report()
+        self._sync_stream()
+        _check(lib().abft_verify(self._h, m, n, A.data_ptr(), _ld(A), nb, colchk.data_ptr(), _ld(colchk),
+                                 rowchk.data_ptr(), _ld(rowchk), tau_scale, int(bool(correct)), flags.data_ptr(),
+                                 rep.data_ptr()), "abft_verify")
+        torch.cuda.synchronize(self.device)
+        return flags, self.read_report(rep)

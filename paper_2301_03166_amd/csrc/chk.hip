@@ -1,0 +1,675 @@
+// Checksum kernels: per-tile encode / verify / locate-and-correct, fault
+// injection, checksum vectors of update operands and the panel checks.
+//
+// Layout (all double, column-major):
+//   colchk (2N x n, ld 2N): row 2I = column sums of tile-row I,
+//                           row 2I+1 = sums weighted by the row's position (1..nb)
+//   rowchk (n x 2N, ld n):  column 2J = row sums over tile-column J,
+//                           column 2J+1 = sums weighted by the column's position
+//   gc / gr: same shapes, the magnitude sum |x||y| of this iteration's update
+// The comparison threshold is tau = ts*u*(4 a + g) with a the |.|-sum of the
+// recomputed entries; verification streams every trailing tile once.
+#include "common.hpp"
+#include "kernels.hpp"
+
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+
+namespace abft {
+
+constexpr int MAXNB = 512;
+constexpr int QROWS = MAXNB / 64;
+
+template <typename T>
+__device__ __forceinline__ double ld(const T* p) {
+  return (double)*p;
+}
+
+// LDS scratch of one tile's sums (40 KB)
+struct TileSums {
+  double ce[MAXNB], cw[MAXNB], ca[MAXNB], cwa[MAXNB];
+  double res[MAXNB], rec[MAXNB], rws[MAXNB], rwc[MAXNB], ra[MAXNB], rwa[MAXNB];
+};
+
+// All column and row sums of tile (r0, c0, h x w); in the symmetric view an
+// element above the diagonal is read from its mirror below it.  Waves take
+// columns round-robin and lanes walk the rows (coalesced); each lane keeps
+// its rows' partial row sums, merged across waves in a fixed order.
+template <typename T>
+__device__ void tile_sums(const T* A, int64_t lda, int64_t r0, int64_t c0, int h, int w, bool sym, TileSums& ts) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  acc2 pe[QROWS], pw[QROWS];
+  double pa[QROWS], pwa[QROWS];
+#pragma unroll
+  for (int q = 0; q < QROWS; ++q) { pe[q] = {0, 0}; pw[q] = {0, 0}; pa[q] = 0; pwa[q] = 0; }
+  for (int j = wv; j < w; j += 4) {
+    acc2 se{0, 0}, sw{0, 0};
+    double sa = 0, swa = 0;
+    const double wj = (double)(j + 1);
+#pragma unroll
+    for (int q = 0; q < QROWS; ++q) {
+      int i = lane + 64 * q;
+      if (i < h) {
+        double v = (sym && i < j) ? ld(A + (r0 + j) + (c0 + i) * lda) : ld(A + (r0 + i) + (c0 + j) * lda);
+        double wi = (double)(i + 1), av = fabs(v);
+        cadd(se, v);
+        cfma(sw, wi, v);
+        sa += av;
+        swa += wi * av;
+        cadd(pe[q], v);
+        cfma(pw[q], wj, v);
+        pa[q] += av;
+        pwa[q] += wj * av;
+      }
+    }
+    se = wave_csum(se);
+    sw = wave_csum(sw);
+    sa = wave_sum(sa);
+    swa = wave_sum(swa);
+    if (lane == 0) {
+      ts.ce[j] = cval(se);
+      ts.cw[j] = cval(sw);
+      ts.ca[j] = sa;
+      ts.cwa[j] = swa;
+    }
+  }
+  for (int s = 0; s < 4; ++s) {
+    if (wv == s) {
+#pragma unroll
+      for (int q = 0; q < QROWS; ++q) {
+        int i = lane + 64 * q;
+        if (i < h) {
+          if (s == 0) {
+            ts.res[i] = pe[q].s; ts.rec[i] = pe[q].c;
+            ts.rws[i] = pw[q].s; ts.rwc[i] = pw[q].c;
+            ts.ra[i] = pa[q]; ts.rwa[i] = pwa[q];
+          } else {
+            acc2 e{ts.res[i], ts.rec[i]}, ww{ts.rws[i], ts.rwc[i]};
+            cmerge(e, pe[q]);
+            cmerge(ww, pw[q]);
+            ts.res[i] = e.s; ts.rec[i] = e.c;
+            ts.rws[i] = ww.s; ts.rwc[i] = ww.c;
+            ts.ra[i] += pa[q]; ts.rwa[i] += pwa[q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < h; i += blockDim.x) {
+    ts.res[i] = ts.res[i] + ts.rec[i];
+    ts.rws[i] = ts.rws[i] + ts.rwc[i];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void tile_geom(int bid, int I0, int J0, int nI, int nb, int64_t nr, int64_t nc, int& I,
+                                          int& J, int& h, int& w) {
+  I = I0 + bid % nI;
+  J = J0 + bid / nI;
+  h = (int)min((int64_t)nb, nr - (int64_t)I * nb);
+  w = (int)min((int64_t)nb, nc - (int64_t)J * nb);
+}
+
+// write the sums of a tile into the checksum arrays
+__device__ void store_sums(const TileSums& ts, int I, int J, int nb, int h, int w, double* colchk, int64_t ldc,
+                           double* rowchk, int64_t ldr) {
+  int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
+  for (int j = threadIdx.x; j < w; j += blockDim.x) {
+    colchk[2 * I + (c0 + j) * ldc] = ts.ce[j];
+    colchk[2 * I + 1 + (c0 + j) * ldc] = ts.cw[j];
+  }
+  for (int i = threadIdx.x; i < h; i += blockDim.x) {
+    rowchk[(r0 + i) + (2 * J) * ldr] = ts.res[i];
+    rowchk[(r0 + i) + (2 * J + 1) * ldr] = ts.rws[i];
+  }
+}
+
+// flags of every column / row of a tile against the carried checksums
+struct TileFlags {
+  double de[MAXNB], dw[MAXNB], he[MAXNB], hw[MAXNB];
+  unsigned char fe[MAXNB], fw[MAXNB], ge[MAXNB], gw[MAXNB];
+  int nflag;
+  double maxr;
+};
+
+__device__ void tile_compare(const TileSums& ts, TileFlags& tf, int I, int J, int nb, int h, int w,
+                             const double* colchk, int64_t ldc, const double* rowchk, int64_t ldr, const double* gc,
+                             const double* gr, double tsu) {
+  int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
+  if (threadIdx.x == 0) { tf.nflag = 0; tf.maxr = 0.0; }
+  __syncthreads();
+  int nfl = 0;
+  double mr = 0.0;
+  for (int j = threadIdx.x; j < w; j += blockDim.x) {
+    int64_t o = 2 * I + (c0 + j) * ldc;
+    double de = ts.ce[j] - colchk[o], dw = ts.cw[j] - colchk[o + 1];
+    double te = tau_verify(tsu, ts.ca[j], gc ? gc[o] : 0.0), tw = tau_verify(tsu, ts.cwa[j], gc ? gc[o + 1] : 0.0);
+    bool be = bad(de, te), bw = bad(dw, tw);
+    tf.de[j] = de; tf.dw[j] = dw; tf.fe[j] = be; tf.fw[j] = bw;
+    nfl += be + bw;
+    if (!be && te > 0) mr = fmax(mr, fabs(de) / te);
+    if (!bw && tw > 0) mr = fmax(mr, fabs(dw) / tw);
+  }
+  for (int i = threadIdx.x; i < h; i += blockDim.x) {
+    int64_t o = (r0 + i) + (2 * J) * ldr;
+    double de = ts.res[i] - rowchk[o], dw = ts.rws[i] - rowchk[o + ldr];
+    double te = tau_verify(tsu, ts.ra[i], gr ? gr[o] : 0.0), tw = tau_verify(tsu, ts.rwa[i], gr ? gr[o + ldr] : 0.0);
+    bool be = bad(de, te), bw = bad(dw, tw);
+    tf.he[i] = de; tf.hw[i] = dw; tf.ge[i] = be; tf.gw[i] = bw;
+    nfl += be + bw;
+    if (!be && te > 0) mr = fmax(mr, fabs(de) / te);
+    if (!bw && tw > 0) mr = fmax(mr, fabs(dw) / tw);
+  }
+  if (nfl) atomicAdd(&tf.nflag, nfl);
+  // max over the workgroup: wave max then one LDS atomic per wave (order-free)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mr = fmax(mr, __shfl_xor(mr, o));
+  if ((threadIdx.x & 63) == 0 && mr > 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(&tf.maxr), (unsigned long long)__double_as_longlong(mr));
+  __syncthreads();
+}
+
+// mode 0: encode (write sums); mode 1: verify (flag, refresh clean tiles);
+// mode 2: verify only
+template <typename T>
+__global__ __launch_bounds__(256) void k_verify(const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0,
+                                                int nI, int sym, int mode, double* colchk, int64_t ldc, double* rowchk,
+                                                int64_t ldr, const double* gc, const double* gr, double tsu,
+                                                int* tflags, abft_report* rep, int iter) {
+  __shared__ TileSums ts;
+  __shared__ TileFlags tf;
+  int I, J, h, w;
+  tile_geom(blockIdx.x, I0, J0, nI, nb, nr, nc, I, J, h, w);
+  const int tile = I + J * (int)((nr + nb - 1) / nb);
+  if (sym && I < J) return;
+  tile_sums(A, lda, (int64_t)I * nb, (int64_t)J * nb, h, w, sym && I == J, ts);
+  if (mode == 0) {
+    store_sums(ts, I, J, nb, h, w, colchk, ldc, rowchk, ldr);
+    return;
+  }
+  tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu);
+  const bool flagged = tf.nflag > 0;
+  if (!flagged && mode == 1) store_sums(ts, I, J, nb, h, w, colchk, ldc, rowchk, ldr);
+  if (threadIdx.x == 0) {
+    if (tflags) tflags[tile] = flagged ? 1 : 0;
+    if (rep) {
+      if (flagged) {
+        atomicAdd((unsigned long long*)&rep->flagged_tiles, 1ull);
+        rep_flag_iter(rep, iter);
+      }
+      if (tf.maxr > 0) rep_max_ratio(rep, tf.maxr);
+    }
+  }
+}
+
+__device__ __forceinline__ int ratio_index(double dw, double de, int len) {
+  if (!(de != 0.0)) return -1;
+  double r = dw / de;
+  if (!(fabs(r) <= 1.79e308)) return -1;
+  double k = floor(r + 0.5);
+  if (fabs(r - k) > 0.25) return -1;
+  if (k < 1.0 || k > (double)len) return -1;
+  return (int)k - 1;
+}
+
+// Locate and correct a flagged tile (one fault per tile per iteration).
+// Decision rules are those of the reference description: intersection of a
+// single flagged column and row; a single flagged line located by the ratio
+// of its weighted and plain differences; a lone weighted-checksum mismatch is
+// a checksum error; anything else is uncorrectable.  The element is
+// recomputed from its column checksum with itself left out.
+template <typename T>
+__global__ __launch_bounds__(256) void k_correct(T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0,
+                                                 int nI, int sym, double* colchk, int64_t ldc, double* rowchk,
+                                                 int64_t ldr, const double* gc, const double* gr, double tsu,
+                                                 const int* tflags, abft_report* rep, int iter) {
+  __shared__ TileSums ts;
+  __shared__ TileFlags tf;
+  __shared__ int s_ci, s_cj, s_kind;
+  __shared__ double s_old;
+  int I, J, h, w;
+  tile_geom(blockIdx.x, I0, J0, nI, nb, nr, nc, I, J, h, w);
+  const int tile = I + J * (int)((nr + nb - 1) / nb);
+  if (sym && I < J) return;
+  if (!tflags[tile]) return;
+  const int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
+  const bool diag = sym && I == J;
+  tile_sums(A, lda, r0, c0, h, w, diag, ts);
+  tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu);
+  if (threadIdx.x == 0) {
+    int nFe = 0, nGe = 0, nFw = 0, nGw = 0, jf0 = -1, jf1 = -1, ig = -1;
+    for (int j = 0; j < w; ++j) {
+      if (tf.fe[j]) {
+        if (nFe == 0) jf0 = j; else if (nFe == 1) jf1 = j;
+        nFe++;
+      }
+      nFw += tf.fw[j];
+    }
+    for (int i = 0; i < h; ++i) {
+      if (tf.ge[i]) { ig = i; nGe++; }
+      nGw += tf.gw[i];
+    }
+    int ci = -1, cj = -1, repair = 0;
+    if (tf.nflag == 0) {
+      repair = -1;  // nothing left to do (flag raised by a concurrent writer)
+    } else if (diag) {
+      if (nFe == 1) {
+        int i = ratio_index(tf.dw[jf0], tf.de[jf0], h);
+        if (i == jf0) { ci = i; cj = i; }
+      } else if (nFe == 2) {
+        if (ratio_index(tf.dw[jf0], tf.de[jf0], h) == jf1 && ratio_index(tf.dw[jf1], tf.de[jf1], h) == jf0) {
+          ci = jf1; cj = jf0;
+        }
+      } else if (nFe == 0) {
+        repair = 1;
+      }
+    } else {
+      if (nFe == 1 && nGe == 1) {
+        ci = ig; cj = jf0;
+      } else if (nFe == 1 && nGe == 0) {
+        int i = ratio_index(tf.dw[jf0], tf.de[jf0], h);
+        if (i >= 0) { ci = i; cj = jf0; } else if (nGw == 0) repair = 1;
+      } else if (nFe == 0 && nGe == 1) {
+        int j = ratio_index(tf.hw[ig], tf.he[ig], w);
+        if (j >= 0) { ci = ig; cj = j; } else if (nFw == 0) repair = 1;
+      } else if (nFe == 0 && nGe == 0) {
+        repair = 1;
+      }
+    }
+    s_ci = ci; s_cj = cj;
+    s_kind = (repair == -1) ? 0 : (ci >= 0 ? 1 : (repair ? 2 : 3));
+  }
+  __syncthreads();
+  if (s_kind == 1) {
+    // recompute the element from the carried column-e checksum of column cj
+    const int ci = s_ci, cj = s_cj;
+    if (threadIdx.x < 64) {
+      acc2 s{0, 0};
+      for (int i = threadIdx.x; i < h; i += 64) {
+        if (i == ci) continue;
+        double v = (diag && i < cj) ? ld(A + (r0 + cj) + (c0 + i) * lda) : ld(A + (r0 + i) + (c0 + cj) * lda);
+        cadd(s, v);
+      }
+      s = wave_csum(s);
+      if (threadIdx.x == 0) {
+        double val = colchk[2 * I + (c0 + cj) * ldc] - cval(s);
+        T* p = A + (r0 + ci) + (c0 + cj) * lda;
+        s_old = ld(p);
+        *p = (T)val;
+      }
+    }
+    __syncthreads();
+    __threadfence_block();
+    tile_sums(A, lda, r0, c0, h, w, diag, ts);
+    tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu);
+    if (tf.nflag != 0) {
+      if (threadIdx.x == 0) {
+        A[(r0 + ci) + (c0 + cj) * lda] = (T)s_old;
+        s_kind = 3;
+      }
+      __syncthreads();
+      __threadfence_block();
+    }
+  }
+  if (s_kind == 0) return;
+  // refresh the tile's checksums from the (corrected) data
+  tile_sums(A, lda, r0, c0, h, w, diag, ts);
+  store_sums(ts, I, J, nb, h, w, colchk, ldc, rowchk, ldr);
+  if (threadIdx.x == 0 && rep) {
+    if (s_kind == 1) {
+      atomicAdd((unsigned long long*)&rep->corrected, 1ull);
+      atomicOr(&rep->status, (int)ABFT_ST_CORRECTED);
+      rep_event(rep, iter, 1, r0 + s_ci, c0 + s_cj);
+    } else if (s_kind == 2) {
+      atomicAdd((unsigned long long*)&rep->checksum_repaired, 1ull);
+      atomicOr(&rep->status, (int)ABFT_ST_REPAIRED);
+      rep_event(rep, iter, 2, r0, c0);
+    } else {
+      atomicAdd((unsigned long long*)&rep->uncorrectable, 1ull);
+      atomicOr(&rep->status, (int)ABFT_ST_UNCORRECTABLE);
+      rep_event(rep, iter, 3, r0, c0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Checksum vectors of an update's left operand X (rows of tile-rows I0..N-1,
+// kw columns).  Rows inside tile-row dI are read through `mode`: 0 full,
+// 1 lower with diagonal, 2 unit lower (implicit unit diagonal, zeros above).
+// Output S (2N x nb, ld 2N): S[2I,p] = sum, S[2I+1,p] = weighted sum;
+// Sa: the same with |x|.  `rnd` applies the operand rounding of the update.
+// ---------------------------------------------------------------------------
+template <typename T, int RND>
+__device__ __forceinline__ double opval(const T* p) {
+  return (double)*p;
+}
+template <>
+__device__ __forceinline__ double opval<float, 1>(const float* p) {
+  uint32_t u = __float_as_uint(*p);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (double)*p;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (double)__uint_as_float(u & 0xffff0000u);
+}
+template <>
+__device__ __forceinline__ double opval<float, 2>(const float* p) {
+  return (double)__half2float(__float2half_rn(*p));
+}
+
+template <typename T, int RND>
+__global__ __launch_bounds__(256) void k_xsums(const T* A, int64_t lda, int64_t n, int nb, int I0, int64_t xc0, int kw,
+                                               int dI, int mode, double* S, double* Sa, int ldS) {
+  const int I = I0 + blockIdx.x;
+  const int64_t r0 = (int64_t)I * nb;
+  const int h = (int)min((int64_t)nb, n - r0);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int p = wv; p < kw; p += 4) {
+    acc2 se{0, 0}, sw{0, 0};
+    double sa = 0, swa = 0;
+    for (int i = lane; i < h; i += 64) {
+      double v;
+      if (I == dI && mode != 0 && i < p) v = 0.0;
+      else if (I == dI && mode == 2 && i == p) v = 1.0;
+      else v = opval<T, RND>(A + (r0 + i) + (xc0 + p) * lda);
+      double wi = (double)(i + 1);
+      cadd(se, v);
+      cfma(sw, wi, v);
+      sa += fabs(v);
+      swa += wi * fabs(v);
+    }
+    se = wave_csum(se);
+    sw = wave_csum(sw);
+    sa = wave_sum(sa);
+    swa = wave_sum(swa);
+    if (lane == 0) {
+      S[2 * I + p * (int64_t)ldS] = cval(se);
+      S[2 * I + 1 + p * (int64_t)ldS] = cval(sw);
+      Sa[2 * I + p * (int64_t)ldS] = sa;
+      Sa[2 * I + 1 + p * (int64_t)ldS] = swa;
+    }
+  }
+}
+
+// Row sums of an update's right operand Y (kw x cols, Y(p,j) = Y[p + j*ldy])
+// over tile-columns J0..N-1.  Output Tm (nb x 2N, ld nb): Tm[p,2J] = sum,
+// Tm[p,2J+1] = weighted sum; Ta with |y|.
+template <typename T, int RND>
+__global__ __launch_bounds__(256) void k_ysums(const T* Y, int64_t ldy, int64_t n, int nb, int J0, int kw,
+                                               double* Tm, double* Ta, int ldT) {
+  const int J = J0 + blockIdx.x;
+  const int64_t c0 = (int64_t)J * nb;
+  const int w = (int)min((int64_t)nb, n - c0);
+  for (int p = threadIdx.x; p < kw; p += blockDim.x) {
+    acc2 se{0, 0}, sw{0, 0};
+    double sa = 0, swa = 0;
+    for (int j = 0; j < w; ++j) {
+      double v = opval<T, RND>(Y + p + (c0 + j) * ldy);
+      double wj = (double)(j + 1);
+      cadd(se, v);
+      cfma(sw, wj, v);
+      sa += fabs(v);
+      swa += wj * fabs(v);
+    }
+    Tm[p + (2 * J) * (int64_t)ldT] = cval(se);
+    Tm[p + (2 * J + 1) * (int64_t)ldT] = cval(sw);
+    Ta[p + (2 * J) * (int64_t)ldT] = sa;
+    Ta[p + (2 * J + 1) * (int64_t)ldT] = swa;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Panel / panel-update check (detection only): for tile-rows I in [I0, I1)
+// and columns j in [0, ncols) (global column cj0 + j), the carried column
+// checksums must equal S_I * M(:, j) (+ QR's exact part E).  M(p, j) =
+// mscale * Mp[p*msp + j*msj], restricted to p <= j + pjoff when `tri`.
+// Mabs (optional) gives the magnitude matrix; else |M| is used.
+// QR adds, for tile-row Ik, the e/w sums of R(:, j) (E[4*j + 0..3]) and for
+// every tile-row the backward-error allowance bt[j].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_panel_check(const double* S, const double* Sa, int ldS, int I0, int I1, int kw,
+                                                     const double* Mp, int64_t msp, int64_t msj, int tri, int pjoff,
+                                                     double mscale, const double* Mabs, const double* E,
+                                                     const double* bt, int Ik, const double* colchk, int64_t ldc,
+                                                     int64_t cj0, int ncols, double tsu_p, abft_report* rep,
+                                                     int iter, int nb) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int I = I0 + blockIdx.y;
+  __shared__ int flag;
+  __shared__ unsigned long long smax;
+  if (threadIdx.x == 0) { flag = 0; smax = 0; }
+  __syncthreads();
+  if (j < ncols && I < I1) {
+    double ce = colchk[2 * I + (cj0 + j) * ldc], cw = colchk[2 * I + 1 + (cj0 + j) * ldc];
+    acc2 xe{ce, 0}, xw{cw, 0};
+    double ge = 0, gw = 0;
+    int pmax = tri ? min(kw, j + pjoff + 1) : kw;
+    for (int p = 0; p < pmax; ++p) {
+      double m = mscale * Mp[p * msp + j * msj];
+      double ma = Mabs ? Mabs[p * msp + j * msj] : fabs(m);
+      cfma(xe, -S[2 * I + p * (int64_t)ldS], m);
+      cfma(xw, -S[2 * I + 1 + p * (int64_t)ldS], m);
+      ge += Sa[2 * I + p * (int64_t)ldS] * ma;
+      gw += Sa[2 * I + 1 + p * (int64_t)ldS] * ma;
+    }
+    if (E) {
+      if (I == Ik) {
+        cadd(xe, -E[4 * j + 0]);
+        cadd(xw, -E[4 * j + 1]);
+        ge += E[4 * j + 2];
+        gw += E[4 * j + 3];
+      }
+      ge += bt[j];
+      gw += bt[j] * (double)nb;
+    }
+    double de = cval(xe), dw = cval(xw);
+    double te = tsu_p * (fabs(ce) + ge), tw = tsu_p * (fabs(cw) + gw);
+    if (bad(de, te) || bad(dw, tw)) {
+      atomicOr(&flag, 1);
+    } else {
+      double r = 0;
+      if (te > 0) r = fabs(de) / te;
+      if (tw > 0) r = fmax(r, fabs(dw) / tw);
+      if (r > 0) atomicMax(&smax, (unsigned long long)__double_as_longlong(r));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && rep) {
+    if (smax) rep_max_ratio(rep, __longlong_as_double((long long)smax));
+    if (flag) {
+      atomicAdd((unsigned long long*)&rep->panel_flags, 1ull);
+      atomicOr(&rep->status, (int)ABFT_ST_PANEL);
+      rep_flag_iter(rep, iter);
+      rep_event(rep, iter, 4, (int64_t)I * nb, cj0 + blockIdx.x * blockDim.x);
+    }
+  }
+}
+
+// QR panel check helpers: Z = T (V1^T R), Zabs = |T| (|V1|^T |R|) for the
+// w x w diagonal block at (c0, c0); E[4j..] = e/w sums of R(:,j) and their
+// magnitudes; bt[j] = sqrt(m) ||R(:, j)||.
+__global__ void k_qr_check_prep(const double* A, int64_t lda, int64_t c0, int w, int64_t m, const double* T, int ldt,
+                                double* Y, double* Ya, double* Z, double* Zabs, double* E, double* bt) {
+  const int j = blockIdx.x;
+  const double* R = A + c0 + c0 * lda;
+  for (int p = threadIdx.x; p < w; p += blockDim.x) {
+    double s = 0, sa = 0;
+    for (int i = p; i <= j; ++i) {
+      double v = (i == p) ? 1.0 : R[i + p * lda];
+      double r = R[i + j * lda];
+      s += v * r;
+      sa += fabs(v) * fabs(r);
+    }
+    Y[p + j * w] = s;
+    Ya[p + j * w] = sa;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < w; p += blockDim.x) {
+    double s = 0, sa = 0;
+    for (int q = p; q < w; ++q) {
+      s += T[p + q * ldt] * Y[q + j * w];
+      sa += fabs(T[p + q * ldt]) * Ya[q + j * w];
+    }
+    Z[p + j * w] = s;
+    Zabs[p + j * w] = sa;
+  }
+  if (threadIdx.x == 0) {
+    acc2 e{0, 0}, ww{0, 0};
+    double a = 0, wa = 0, n2 = 0;
+    for (int i = 0; i <= j; ++i) {
+      double r = R[i + j * lda];
+      cadd(e, r);
+      cfma(ww, (double)(i + 1), r);
+      a += fabs(r);
+      wa += (double)(i + 1) * fabs(r);
+      n2 += r * r;
+    }
+    E[4 * j + 0] = cval(e);
+    E[4 * j + 1] = cval(ww);
+    E[4 * j + 2] = a;
+    E[4 * j + 3] = wa;
+    bt[j] = sqrt((double)m) * sqrt(n2);
+  }
+}
+
+// fault injection (test use): XOR one bit of one element
+__global__ void k_inject64(double* p, int bit) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(*p);
+  u ^= 1ull << bit;
+  *p = __longlong_as_double((long long)u);
+}
+__global__ void k_inject32(float* p, int bit) {
+  unsigned u = __float_as_uint(*p);
+  u ^= 1u << (bit & 31);
+  *p = __uint_as_float(u);
+}
+
+__global__ void k_fill_zero(uint32_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// report initialisation / finalisation
+__global__ void k_report_init(abft_report* r, int32_t* info) {
+  if (r) {
+    r->flagged_tiles = r->corrected = r->checksum_repaired = r->uncorrectable = r->panel_flags = 0;
+    r->first_flag_iter = 0x7fffffff;
+    r->status = 0;
+    r->max_ratio = 0.0;
+    r->nev = 0;
+    r->pad = 0;
+  }
+  if (info) *info = 0;
+}
+__global__ void k_report_fini(abft_report* r) {
+  if (r->first_flag_iter == 0x7fffffff) r->first_flag_iter = -1;
+  if (r->nev > ABFT_MAX_EVENTS) r->nev = ABFT_MAX_EVENTS;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+int verify_tiles(hipStream_t s, const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
+                 int mode, double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc,
+                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter) {
+  int Nr = (int)((nr + nb - 1) / nb), Nc = (int)((nc + nb - 1) / nb);
+  int nI = Nr - I0, nJ = Nc - J0;
+  if (nI <= 0 || nJ <= 0) return 0;
+  hipLaunchKernelGGL(k_verify<T>, dim3(nI * nJ), dim3(256), 0, s, A, lda, nr, nc, nb, I0, J0, nI, sym, mode, colchk,
+                     ldc, rowchk, ldr, gc, gr, tsu, tflags, rep, iter);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+template <typename T>
+int correct_tiles(hipStream_t s, T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
+                  double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc, const double* gr,
+                  double tsu, const int* tflags, abft_report* rep, int iter) {
+  int Nr = (int)((nr + nb - 1) / nb), Nc = (int)((nc + nb - 1) / nb);
+  int nI = Nr - I0, nJ = Nc - J0;
+  if (nI <= 0 || nJ <= 0) return 0;
+  hipLaunchKernelGGL(k_correct<T>, dim3(nI * nJ), dim3(256), 0, s, A, lda, nr, nc, nb, I0, J0, nI, sym, colchk, ldc,
+                     rowchk, ldr, gc, gr, tsu, tflags, rep, iter);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+template int verify_tiles<double>(hipStream_t, const double*, int64_t, int64_t, int64_t, int, int, int, int, int,
+                                  double*, int64_t, double*, int64_t, const double*, const double*, double, int*,
+                                  abft_report*, int);
+template int verify_tiles<float>(hipStream_t, const float*, int64_t, int64_t, int64_t, int, int, int, int, int, double*,
+                                 int64_t, double*, int64_t, const double*, const double*, double, int*, abft_report*,
+                                 int);
+template int correct_tiles<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int, int, int, int, double*,
+                                   int64_t, double*, int64_t, const double*, const double*, double, const int*,
+                                   abft_report*, int);
+template int correct_tiles<float>(hipStream_t, float*, int64_t, int64_t, int64_t, int, int, int, int, double*, int64_t,
+                                  double*, int64_t, const double*, const double*, double, const int*, abft_report*,
+                                  int);
+
+template <typename T>
+int xsums(hipStream_t s, const T* A, int64_t lda, int64_t n, int nb, int I0, int64_t xc0, int kw, int dI, int mode,
+          double* S, double* Sa, int ldS, int rnd) {
+  int N = (int)((n + nb - 1) / nb);
+  if (N - I0 <= 0 || kw <= 0) return 0;
+  if (rnd == 1) hipLaunchKernelGGL((k_xsums<T, 1>), dim3(N - I0), dim3(256), 0, s, A, lda, n, nb, I0, xc0, kw, dI, mode, S, Sa, ldS);
+  else if (rnd == 2) hipLaunchKernelGGL((k_xsums<T, 2>), dim3(N - I0), dim3(256), 0, s, A, lda, n, nb, I0, xc0, kw, dI, mode, S, Sa, ldS);
+  else hipLaunchKernelGGL((k_xsums<T, 0>), dim3(N - I0), dim3(256), 0, s, A, lda, n, nb, I0, xc0, kw, dI, mode, S, Sa, ldS);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+template <typename T>
+int ysums(hipStream_t s, const T* Y, int64_t ldy, int64_t n, int nb, int J0, int kw, double* Tm, double* Ta, int ldT,
+          int rnd) {
+  int N = (int)((n + nb - 1) / nb);
+  if (N - J0 <= 0 || kw <= 0) return 0;
+  if (rnd == 1) hipLaunchKernelGGL((k_ysums<T, 1>), dim3(N - J0), dim3(256), 0, s, Y, ldy, n, nb, J0, kw, Tm, Ta, ldT);
+  else if (rnd == 2) hipLaunchKernelGGL((k_ysums<T, 2>), dim3(N - J0), dim3(256), 0, s, Y, ldy, n, nb, J0, kw, Tm, Ta, ldT);
+  else hipLaunchKernelGGL((k_ysums<T, 0>), dim3(N - J0), dim3(256), 0, s, Y, ldy, n, nb, J0, kw, Tm, Ta, ldT);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+template int xsums<double>(hipStream_t, const double*, int64_t, int64_t, int, int, int64_t, int, int, int, double*,
+                           double*, int, int);
+template int xsums<float>(hipStream_t, const float*, int64_t, int64_t, int, int, int64_t, int, int, int, double*,
+                          double*, int, int);
+template int ysums<double>(hipStream_t, const double*, int64_t, int64_t, int, int, int, double*, double*, int, int);
+template int ysums<float>(hipStream_t, const float*, int64_t, int64_t, int, int, int, double*, double*, int, int);
+
+int panel_check(hipStream_t s, const double* S, const double* Sa, int ldS, int I0, int I1, int kw, const double* Mp,
+                int64_t msp, int64_t msj, int tri, int pjoff, double mscale, const double* Mabs, const double* E,
+                const double* bt, int Ik, const double* colchk, int64_t ldc, int64_t cj0, int ncols, double tsu_p,
+                abft_report* rep, int iter, int nb) {
+  if (I1 <= I0 || ncols <= 0) return 0;
+  dim3 grid((ncols + 255) / 256, I1 - I0);
+  hipLaunchKernelGGL(k_panel_check, grid, dim3(256), 0, s, S, Sa, ldS, I0, I1, kw, Mp, msp, msj, tri, pjoff, mscale,
+                     Mabs, E, bt, Ik, colchk, ldc, cj0, ncols, tsu_p, rep, iter, nb);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
+int qr_check_prep(hipStream_t s, const double* A, int64_t lda, int64_t c0, int w, int64_t m, const double* T, int ldt,
+                  double* scratch, double* Z, double* Zabs, double* E, double* bt) {
+  hipLaunchKernelGGL(k_qr_check_prep, dim3(w), dim3(256), 0, s, A, lda, c0, w, m, T, ldt, scratch,
+                     scratch + (size_t)w * w, Z, Zabs, E, bt);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
+int inject(hipStream_t s, void* p, int is_float, int bit) {
+  if (is_float) hipLaunchKernelGGL(k_inject32, dim3(1), dim3(1), 0, s, (float*)p, bit);
+  else hipLaunchKernelGGL(k_inject64, dim3(1), dim3(1), 0, s, (double*)p, bit);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
+int fill_zero(hipStream_t s, void* p, size_t bytes) {
+  size_t n = bytes / 4;
+  if (!n) return 0;
+  unsigned grid = (unsigned)std::min<size_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, s, (uint32_t*)p, n);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
+int report_init(hipStream_t s, abft_report* r, int32_t* info) {
+  hipLaunchKernelGGL(k_report_init, dim3(1), dim3(1), 0, s, r, info);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+int report_fini(hipStream_t s, abft_report* r) {
+  if (!r) return 0;
+  hipLaunchKernelGGL(k_report_fini, dim3(1), dim3(1), 0, s, r);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
+}  // namespace abft

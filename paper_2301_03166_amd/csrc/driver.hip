@@ -1,0 +1,539 @@
+// Host drivers and the C ABI (include/abft.h).
+//
+// Every factorization is a sequence of kernel launches on the handle's
+// stream with no host synchronisation inside the loop: per iteration the
+// panel (recursive, leaves of 32 columns), the interchanges (LU), the panel
+// update, the trailing update on FP64 MFMA, the checksum carry (four thin
+// GEMMs: values and magnitudes for the column and the row side), an optional
+// planned bit flip, and the verify / correct pass over the trailing tiles.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace abft;
+
+struct abft_handle_s {
+  hipStream_t stream;
+  int device;
+  int cus;
+};
+
+namespace {
+
+constexpr int LEAFW = 32;
+constexpr int MAXNB = 512;
+constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
+constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
+
+#define TRY(x)                 \
+  do {                         \
+    int _e = (x);              \
+    if (_e) return _e;         \
+  } while (0)
+
+inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace carve-up shared by the three factorizations.
+struct Ws {
+  double *colchk, *rowchk, *gc, *gr, *S, *Sa, *Tm, *Ta;
+  double *Tfac, *W, *W2, *Wp, *Wp2, *Xq, *Yq, *Z, *Zabs, *E, *bt, *scr;
+  double *porig, *stage, *slots;
+  int *tflags, *moves;
+  unsigned* ctr;
+  size_t bytes;
+};
+
+Ws carve(char* base, int64_t n, int nb, int op, int elem) {
+  Ws w;
+  memset(&w, 0, sizeof(w));
+  const int64_t N = (n + nb - 1) / nb;
+  size_t off = 0;
+  auto take = [&](size_t b) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += al(b);
+    return p;
+  };
+  const size_t chk = (size_t)2 * N * n * sizeof(double);
+  w.colchk = (double*)take(chk);
+  w.rowchk = (double*)take(chk);
+  w.gc = (double*)take(chk);
+  w.gr = (double*)take(chk);
+  w.S = (double*)take((size_t)2 * N * nb * sizeof(double));
+  w.Sa = (double*)take((size_t)2 * N * nb * sizeof(double));
+  w.Tm = (double*)take((size_t)2 * N * nb * sizeof(double));
+  w.Ta = (double*)take((size_t)2 * N * nb * sizeof(double));
+  w.tflags = (int*)take((size_t)N * N * sizeof(int));
+  w.ctr = (unsigned*)take(256);
+  w.slots = (double*)take((size_t)(1 << 20) * sizeof(double));
+  if (op == ABFT_OP_GETRF || op == ABFT_OP_GESV_MP) {
+    w.porig = (double*)take((size_t)n * nb * elem);
+    w.stage = (double*)take((size_t)2 * nb * n * elem);
+    w.moves = (int*)take((size_t)(4 * nb + 4) * sizeof(int));
+  }
+  if (op == ABFT_OP_GEQRF) {
+    w.Tfac = (double*)take((size_t)nb * nb * sizeof(double));
+    w.W = (double*)take((size_t)nb * n * sizeof(double));
+    w.W2 = (double*)take((size_t)nb * n * sizeof(double));
+    w.Wp = (double*)take((size_t)nb * nb * sizeof(double));
+    w.Wp2 = (double*)take((size_t)nb * nb * sizeof(double));
+    w.Xq = (double*)take((size_t)nb * nb * sizeof(double));
+    w.Yq = (double*)take((size_t)nb * nb * sizeof(double));
+    w.Z = (double*)take((size_t)nb * nb * sizeof(double));
+    w.Zabs = (double*)take((size_t)nb * nb * sizeof(double));
+    w.scr = (double*)take((size_t)2 * nb * nb * sizeof(double));
+    w.E = (double*)take((size_t)4 * nb * sizeof(double));
+    w.bt = (double*)take((size_t)nb * sizeof(double));
+  }
+  w.bytes = off;
+  return w;
+}
+
+int check_opts(const abft_opts* o, int64_t n, int& nb, int& protect, double& ts) {
+  if (!o) return -7;
+  nb = o->nb;
+  protect = o->protect;
+  ts = o->tau_scale > 0 ? o->tau_scale : 4.0;
+  if (nb < 1 || nb > MAXNB) return -7;
+  if (protect != ABFT_PROTECT_NONE && protect != ABFT_PROTECT_FULL) return -7;
+  (void)n;
+  return 0;
+}
+
+inline int split(int w) { return ((w / 2 + LEAFW - 1) / LEAFW) * LEAFW; }
+
+// ----------------------------------------------------------------- faults
+template <typename T>
+int apply_faults(hipStream_t s, const abft_opts* o, int iter, T* A, int64_t lda, const Ws& w, int64_t n, int N) {
+  for (int q = 0; q < o->nfaults; ++q) {
+    const abft_fault& f = o->faults[q];
+    if (f.iter != iter) continue;
+    if (f.target == 0) {
+      if (f.row < 0 || f.row >= n || f.col < 0 || f.col >= n) continue;
+      TRY(inject(s, A + f.row + f.col * lda, sizeof(T) == 4, f.bit));
+    } else if (f.target == 1 && w.colchk) {
+      if (f.row < 0 || f.row >= 2 * N || f.col < 0 || f.col >= n) continue;
+      TRY(inject(s, w.colchk + f.row + f.col * 2 * N, 0, f.bit));
+    } else if (f.target == 2 && w.rowchk) {
+      if (f.row < 0 || f.row >= n || f.col < 0 || f.col >= 2 * N) continue;
+      TRY(inject(s, w.rowchk + f.row + f.col * n, 0, f.bit));
+    }
+  }
+  return 0;
+}
+
+// ----------------------------------------------------------------- panels
+// Cholesky panel, columns [c0, c1), rows [c0, n): recursive halves; the
+// right half is updated by the left half's columns with the lower-masked
+// MFMA GEMM.
+int chol_panel(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t c0, int64_t c1, int32_t* info) {
+  const int w = (int)(c1 - c0);
+  if (w <= LEAFW) {
+    TRY(potrf_leaf(s, A, lda, c0, w, info));
+    return trsm_rlt_leaf(s, A, lda, c0 + w, n, c0, w);
+  }
+  const int h = split(w);
+  TRY(chol_panel(s, A, lda, n, c0, c0 + h, info));
+  const int64_t r = c0 + h;
+  TRY(gemm64(s, 0, 1, 0, 0, 1, (int)(n - r), (int)(c1 - r), h, -1.0, A + r + c0 * lda, lda, A + r + c0 * lda, lda,
+             1.0, A + r + r * lda, lda, 0));
+  return chol_panel(s, A, lda, n, r, c1, info);
+}
+
+// X = L^{-1} B: L unit lower at (c0, c0) of order w, B = rows [c0, c0+w) of
+// columns [j0, j1).
+int trsm_llu(hipStream_t s, double* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1) {
+  if (j1 <= j0) return 0;
+  if (w <= LEAFW) return trsm_llu_leaf(s, A, lda, c0, w, j0, j1);
+  const int h = split(w);
+  TRY(trsm_llu(s, A, lda, c0, h, j0, j1));
+  TRY(gemm64(s, 0, 0, 0, 0, 0, w - h, (int)(j1 - j0), h, -1.0, A + (c0 + h) + c0 * lda, lda, A + c0 + j0 * lda, lda,
+             1.0, A + (c0 + h) + j0 * lda, lda, 0));
+  return trsm_llu(s, A, lda, c0 + h, w - h, j0, j1);
+}
+
+struct LuCtx {
+  hipStream_t s;
+  double* A;
+  int64_t lda, n;
+  int32_t *ipiv, *info;
+  const Ws* w;
+  unsigned ctr_base;
+  abft_report* rep;
+  int maxg;
+};
+
+// LU panel, columns [c0, c1), rows [c0, n) (recursive, LAPACK getrf2 order)
+int lu_panel(LuCtx& c, int64_t c0, int64_t c1) {
+  const int w = (int)(c1 - c0);
+  if (w <= LEAFW)
+    return getrf_leaf(c.s, c.A, c.lda, c.n, c0, w, c.ipiv, c.info, c.w->slots, c.w->ctr, &c.ctr_base, c.rep, c.maxg);
+  const int h = split(w);
+  TRY(lu_panel(c, c0, c0 + h));
+  TRY(perm_build(c.s, c.ipiv, c0, h, c.w->moves));
+  TRY(laswp(c.s, c.A, c.lda, c0 + h, c1, c.w->moves, (double*)c.w->stage, (double*)nullptr, 0, 1));
+  TRY(trsm_llu(c.s, c.A, c.lda, c0, h, c0 + h, c1));
+  const int64_t r = c0 + h;
+  TRY(gemm64(c.s, 0, 0, 0, 0, 0, (int)(c.n - r), (int)(c1 - r), h, -1.0, c.A + r + c0 * c.lda, c.lda,
+             c.A + c0 + r * c.lda, c.lda, 1.0, c.A + r + r * c.lda, c.lda, 0));
+  TRY(lu_panel(c, r, c1));
+  TRY(perm_build(c.s, c.ipiv, r, w - h, c.w->moves));
+  return laswp(c.s, c.A, c.lda, c0, r, c.w->moves, (double*)c.w->stage, (double*)nullptr, 0, 1);
+}
+
+struct QrCtx {
+  hipStream_t s;
+  double* A;
+  int64_t lda, n;
+  double* tau;
+  const Ws* w;
+  int nb;
+  int64_t cb;  // first column of the current block panel
+  unsigned ctr_base;
+  abft_report* rep;
+  int maxg;
+};
+
+// Householder panel, columns [c0, c1), rows [c0, n), with its T factor at
+// Tfac[(c0-cb) + (c0-cb)*nb] (recursive; T merged as T12 = -T1 V1^T V2 T2)
+int qr_panel(QrCtx& c, int64_t c0, int64_t c1) {
+  const int w = (int)(c1 - c0);
+  const int toff = (int)(c0 - c.cb);
+  const int nb = c.nb;
+  double* A = c.A;
+  const int64_t lda = c.lda, n = c.n;
+  if (w <= LEAFW)
+    return geqrf_leaf(c.s, A, lda, n, c0, w, c.tau, c.w->Tfac, nb, toff, c.w->slots, c.w->ctr, &c.ctr_base, c.rep,
+                      c.maxg);
+  const int h = split(w);
+  TRY(qr_panel(c, c0, c0 + h));
+  const int64_t r = c0 + h;
+  double* V1 = A + c0 + c0 * lda;
+  double* T1 = c.w->Tfac + toff + (int64_t)toff * nb;
+  // apply H1^T = I - V1 T1^T V1^T to the right half
+  TRY(gemm64(c.s, 1, 0, 1, 0, 0, h, (int)(c1 - r), (int)(n - c0), 1.0, V1, lda, A + c0 + r * lda, lda, 0.0, c.w->Wp,
+             nb, 0));
+  TRY(gemm64(c.s, 1, 0, 0, 0, 0, h, (int)(c1 - r), h, 1.0, T1, nb, c.w->Wp, nb, 0.0, c.w->Wp2, nb, 0));
+  TRY(gemm64(c.s, 0, 0, 1, 0, 0, (int)(n - c0), (int)(c1 - r), h, -1.0, V1, lda, c.w->Wp2, nb, 1.0, A + c0 + r * lda,
+             lda, 0));
+  TRY(qr_panel(c, r, c1));
+  // T12 = -T1 (V1^T V2) T2 ; rows of V2 above r are zero
+  double* T2 = c.w->Tfac + (toff + h) + (int64_t)(toff + h) * nb;
+  TRY(gemm64(c.s, 1, 0, 0, 1, 0, h, w - h, (int)(n - r), 1.0, A + r + c0 * lda, lda, A + r + r * lda, lda, 0.0,
+             c.w->Xq, nb, 0));
+  TRY(gemm64(c.s, 0, 0, 0, 0, 0, h, w - h, h, 1.0, T1, nb, c.w->Xq, nb, 0.0, c.w->Yq, nb, 0));
+  return gemm64(c.s, 0, 0, 0, 0, 0, h, w - h, w - h, -1.0, c.w->Yq, nb, T2, nb, 0.0,
+                c.w->Tfac + toff + (int64_t)(toff + h) * nb, nb, 0);
+}
+
+// Column- and row-side checksum carry of an update C -= X Y over tile-rows
+// [I0, N) and tile-columns [J0, N):
+//   colchk(2I.., j) -= S(2I.., :) Y(:, j)      gc = Sa |Y|
+//   rowchk(i, 2J..) -= X(i, :) Tm(:, 2J..)      gr = |X| Ta
+// X(i,p) = Xp[i + p*ldx] for rows [xr0, n) (fx: operand mode of X),
+// Y(p,j) = Yp[p + j*ldy] (ty = 0) or Yp[j + p*ldy] (ty = 1) for columns
+// [yc0, n); the row-side matrices are Tm / Ta (nb x 2N) or, with tS = 1,
+// the transposes of S / Sa (symmetric update, Y = X^T).
+int carry(hipStream_t s, const Ws& w, int64_t n, int nb, int I0, int J0, int kw, const double* Xp, int64_t ldx,
+          int64_t xr0, int fx, const double* Yp, int64_t ldy, int ty, int64_t yc0, int tS) {
+  const int N = (int)((n + nb - 1) / nb);
+  const int ldS = 2 * N;
+  const int mr = 2 * (N - I0), ncol = (int)(n - yc0);
+  // column side
+  TRY(gemm64(s, 0, ty, 0, 0, 0, mr, ncol, kw, -1.0, w.S + 2 * I0, ldS, Yp, ldy, 1.0, w.colchk + 2 * I0 + yc0 * ldS,
+             ldS, 0));
+  TRY(gemm64(s, 0, ty, 0, 2, 0, mr, ncol, kw, 1.0, w.Sa + 2 * I0, ldS, Yp, ldy, 0.0, w.gc + 2 * I0 + yc0 * ldS, ldS,
+             0));
+  // row side
+  const int nr = (int)(n - xr0), mc = 2 * (N - J0);
+  const double* Bm = tS ? w.S + 2 * J0 : w.Tm + (int64_t)2 * J0 * nb;
+  const double* Ba = tS ? w.Sa + 2 * J0 : w.Ta + (int64_t)2 * J0 * nb;
+  const int64_t ldb = tS ? ldS : nb;
+  TRY(gemm64(s, 0, tS, fx, 0, 0, nr, mc, kw, -1.0, Xp, ldx, Bm, ldb, 1.0, w.rowchk + xr0 + (int64_t)2 * J0 * n, n, 0));
+  return gemm64(s, 0, tS, fx == 1 ? 3 : 2, 0, 0, nr, mc, kw, 1.0, Xp, ldx, Ba, ldb, 0.0,
+                w.gr + xr0 + (int64_t)2 * J0 * n, n, 0);
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+int abft_create(abft_handle* h, void* stream) {
+  if (!h) return -1;
+  abft_handle p = (abft_handle)calloc(1, sizeof(abft_handle_s));
+  if (!p) return ABFT_ERR_HIP;
+  p->stream = (hipStream_t)stream;
+  if (hipGetDevice(&p->device) != hipSuccess) { free(p); return ABFT_ERR_HIP; }
+  if (hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
+    free(p);
+    return ABFT_ERR_HIP;
+  }
+  *h = p;
+  return 0;
+}
+
+int abft_destroy(abft_handle h) {
+  free(h);
+  return 0;
+}
+
+int abft_set_stream(abft_handle h, void* stream) {
+  if (!h) return -1;
+  h->stream = (hipStream_t)stream;
+  return 0;
+}
+
+int abft_workspace_size(abft_handle h, int op, int64_t n, int32_t batch, const abft_opts* opts, size_t* bytes) {
+  (void)h;
+  (void)batch;
+  if (!bytes) return -6;
+  if (n < 0) return -3;
+  int nb, protect;
+  double ts;
+  TRY(check_opts(opts, n, nb, protect, ts));
+  if (op < ABFT_OP_POTRF || op > ABFT_OP_GEQRF) return ABFT_ERR_UNSUPPORTED;
+  Ws w = carve(nullptr, n, nb, op, sizeof(double));
+  *bytes = w.bytes;
+  return 0;
+}
+
+int abft_potrf(abft_handle h, int64_t n, double* dA, int64_t lda, void* dwork, size_t work_bytes,
+               const abft_opts* opts, int32_t* dinfo, abft_report* drep) {
+  if (!h) return -1;
+  if (n < 0) return -2;
+  if (!dA && n > 0) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  int nb, protect;
+  double ts;
+  TRY(check_opts(opts, n, nb, protect, ts));
+  if (!dinfo) return -8;
+  hipStream_t s = h->stream;
+  Ws w = carve((char*)dwork, n, nb, ABFT_OP_POTRF, sizeof(double));
+  if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
+  TRY(report_init(s, drep, dinfo));
+  if (n == 0) return report_fini(s, drep);
+  const int N = (int)((n + nb - 1) / nb);
+  const int ldc = 2 * N;
+  const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);
+  if (protect)
+    TRY(verify_tiles<double>(s, dA, lda, n, n, nb, 0, 0, 1, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu,
+                             nullptr, nullptr, -1));
+  for (int k = 0; k < N; ++k) {
+    const int64_t c0 = (int64_t)k * nb;
+    const int kw = (int)std::min<int64_t>(nb, n - c0);
+    const int64_t c1 = c0 + kw;
+    TRY(chol_panel(s, dA, lda, n, c0, c1, dinfo));
+    if (protect) {
+      TRY(xsums<double>(s, dA, lda, n, nb, k, c0, kw, k, 1, w.S, w.Sa, ldc, 0));
+      // e^T A_Ik = (e^T L_I) L_kk^T:  M(p, j) = L(c0 + j, c0 + p), p <= j
+      TRY(panel_check(s, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, lda, 1, 1, 0, 1.0, nullptr, nullptr, nullptr, -1,
+                      w.colchk, ldc, c0, kw, tsu_p, drep, k, nb));
+    }
+    if (c1 >= n) break;
+    const int64_t m = n - c1;
+    double* L21 = dA + c1 + c0 * lda;
+    TRY(gemm64(s, 0, 1, 0, 0, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0));
+    if (protect) TRY(carry(s, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, L21, lda, 1, c1, 1));
+    if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N));
+    if (protect) {
+      TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                               w.tflags, drep, k));
+      TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                                w.tflags, drep, k));
+    }
+  }
+  return report_fini(s, drep);
+}
+
+int abft_getrf(abft_handle h, int64_t n, double* dA, int64_t lda, int32_t* dipiv, void* dwork, size_t work_bytes,
+               const abft_opts* opts, int32_t* dinfo, abft_report* drep) {
+  if (!h) return -1;
+  if (n < 0) return -2;
+  if (!dA && n > 0) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  if (!dipiv && n > 0) return -5;
+  int nb, protect;
+  double ts;
+  TRY(check_opts(opts, n, nb, protect, ts));
+  if (!dinfo) return -9;
+  hipStream_t s = h->stream;
+  Ws w = carve((char*)dwork, n, nb, ABFT_OP_GETRF, sizeof(double));
+  if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
+  TRY(report_init(s, drep, dinfo));
+  if (n == 0) return report_fini(s, drep);
+  TRY(fill_zero(s, w.ctr, 256));
+  const int N = (int)((n + nb - 1) / nb);
+  const int ldc = 2 * N;
+  const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);
+  if (protect)
+    TRY(verify_tiles<double>(s, dA, lda, n, n, nb, 0, 0, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu,
+                             nullptr, nullptr, -1));
+  LuCtx c{s, dA, lda, n, dipiv, dinfo, &w, 0u, drep, std::min(h->cus, 256)};
+  double* porig = w.porig;
+  for (int k = 0; k < N; ++k) {
+    const int64_t c0 = (int64_t)k * nb;
+    const int kw = (int)std::min<int64_t>(nb, n - c0);
+    const int64_t c1 = c0 + kw;
+    if (protect)
+      if (hipMemcpy2DAsync(porig, n * sizeof(double), dA + c0 + c0 * lda, lda * sizeof(double),
+                           (n - c0) * sizeof(double), kw, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return ABFT_ERR_HIP;
+    TRY(lu_panel(c, c0, c1));
+    TRY(perm_build(s, dipiv, c0, kw, w.moves));
+    TRY(laswp(s, dA, lda, 0, c0, w.moves, w.stage, (double*)nullptr, 0, nb));
+    TRY(laswp(s, dA, lda, c1, n, w.moves, w.stage, protect ? w.colchk : (double*)nullptr, ldc, nb));
+    if (protect) {
+      // column checksums of the panel follow the interchanges of the original panel values
+      TRY(laswp(s, porig - c0, n, 0, kw, w.moves, w.stage, w.colchk + c0 * ldc, ldc, nb));
+      TRY(laswp(s, w.rowchk, n, 0, 2 * N, w.moves, w.stage, (double*)nullptr, 0, nb));
+      TRY(xsums<double>(s, dA, lda, n, nb, k, c0, kw, k, 2, w.S, w.Sa, ldc, 0));
+      // e^T (P A)_I = (e^T L_I) U_kk
+      TRY(panel_check(s, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, 1, lda, 1, 0, 1.0, nullptr, nullptr, nullptr, -1,
+                      w.colchk, ldc, c0, kw, tsu_p, drep, k, nb));
+    }
+    if (c1 >= n) break;
+    TRY(trsm_llu(s, dA, lda, c0, kw, c1, n));
+    if (protect)  // (e^T L_kk) U12 = e^T A12 on tile-row k
+      TRY(panel_check(s, w.S, w.Sa, ldc, k, k + 1, kw, dA + c0 + c1 * lda, 1, lda, 0, 0, 1.0, nullptr, nullptr, nullptr,
+                      -1, w.colchk, ldc, c1, (int)(n - c1), tsu_p, drep, k, nb));
+    const int64_t m = n - c1;
+    double* L21 = dA + c1 + c0 * lda;
+    double* U12 = dA + c0 + c1 * lda;
+    TRY(gemm64(s, 0, 0, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0));
+    if (protect) {
+      TRY(ysums<double>(s, dA + c0, lda, n, nb, k + 1, kw, w.Tm, w.Ta, nb, 0));
+      TRY(carry(s, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, U12, lda, 0, c1, 0));
+    }
+    if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N));
+    if (protect) {
+      TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                               w.tflags, drep, k));
+      TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                                w.tflags, drep, k));
+    }
+  }
+  return report_fini(s, drep);
+}
+
+int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, void* dwork, size_t work_bytes,
+               const abft_opts* opts, int32_t* dinfo, abft_report* drep) {
+  if (!h) return -1;
+  if (n < 0) return -2;
+  if (!dA && n > 0) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  if (!dtau && n > 0) return -5;
+  int nb, protect;
+  double ts;
+  TRY(check_opts(opts, n, nb, protect, ts));
+  if (!dinfo) return -9;
+  hipStream_t s = h->stream;
+  Ws w = carve((char*)dwork, n, nb, ABFT_OP_GEQRF, sizeof(double));
+  if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
+  TRY(report_init(s, drep, dinfo));
+  if (n == 0) return report_fini(s, drep);
+  TRY(fill_zero(s, w.ctr, 256));
+  const int N = (int)((n + nb - 1) / nb);
+  const int ldc = 2 * N;
+  const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);
+  if (protect)
+    TRY(verify_tiles<double>(s, dA, lda, n, n, nb, 0, 0, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu,
+                             nullptr, nullptr, -1));
+  QrCtx c{s, dA, lda, n, dtau, &w, nb, 0, 0u, drep, std::min(h->cus, 256)};
+  for (int k = 0; k < N; ++k) {
+    const int64_t c0 = (int64_t)k * nb;
+    const int kw = (int)std::min<int64_t>(nb, n - c0);
+    const int64_t c1 = c0 + kw;
+    c.cb = c0;
+    TRY(fill_zero(s, w.Tfac, (size_t)nb * nb * sizeof(double)));
+    TRY(qr_panel(c, c0, c1));
+    if (protect) {
+      TRY(xsums<double>(s, dA, lda, n, nb, k, c0, kw, k, 2, w.S, w.Sa, ldc, 0));
+      TRY(qr_check_prep(s, dA, lda, c0, kw, n - c0, w.Tfac, nb, w.scr, w.Z, w.Zabs, w.E, w.bt));
+      // e^T A_I = [I==k] e^T R - (e^T V_I) T V1^T R
+      TRY(panel_check(s, w.S, w.Sa, ldc, k, N, kw, w.Z, 1, kw, 0, 0, -1.0, w.Zabs, w.E, w.bt, k, w.colchk, ldc, c0, kw,
+                      tsu_p, drep, k, nb));
+    }
+    if (c1 >= n) break;
+    const int64_t m = n - c1;
+    double* V = dA + c0 + c0 * lda;
+    double* C = dA + c0 + c1 * lda;
+    TRY(gemm64(s, 1, 0, 1, 0, 0, kw, (int)m, (int)(n - c0), 1.0, V, lda, C, lda, 0.0, w.W, nb, 0));
+    TRY(gemm64(s, 1, 0, 0, 0, 0, kw, (int)m, kw, 1.0, w.Tfac, nb, w.W, nb, 0.0, w.W2, nb, 0));
+    TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)m, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0));
+    if (protect) {
+      TRY(ysums<double>(s, w.W2 - c1 * nb, nb, n, nb, k + 1, kw, w.Tm, w.Ta, nb, 0));
+      TRY(carry(s, w, n, nb, k, k + 1, kw, V, lda, c0, 1, w.W2, nb, 0, c1, 0));
+    }
+    if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N));
+    if (protect) {
+      TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                               w.tflags, drep, k));
+      TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                                w.tflags, drep, k));
+    }
+  }
+  return report_fini(s, drep);
+}
+
+int abft_encode(abft_handle h, int64_t m, int64_t n, const double* dA, int64_t lda, int32_t nb, double* dcolchk,
+                int64_t ldc, double* drowchk, int64_t ldr) {
+  if (!h) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -5;
+  if (nb < 1 || nb > MAXNB) return -6;
+  const int64_t Tr = (m + nb - 1) / nb;
+  if (ldc < std::max<int64_t>(1, 2 * Tr)) return -8;
+  if (ldr < std::max<int64_t>(1, m)) return -10;
+  if (m == 0 || n == 0) return 0;
+  return verify_tiles<double>(h->stream, dA, lda, m, n, nb, 0, 0, 0, 0, dcolchk, ldc, drowchk, ldr, nullptr, nullptr,
+                              0.0, nullptr, nullptr, -1);
+}
+
+int abft_verify(abft_handle h, int64_t m, int64_t n, double* dA, int64_t lda, int32_t nb, double* dcolchk,
+                int64_t ldc, double* drowchk, int64_t ldr, double tau_scale, int32_t correct, int32_t* dflags,
+                abft_report* drep) {
+  if (!h) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (lda < std::max<int64_t>(1, m)) return -5;
+  if (nb < 1 || nb > MAXNB) return -6;
+  const int64_t Tr = (m + nb - 1) / nb;
+  if (ldc < std::max<int64_t>(1, 2 * Tr)) return -8;
+  if (ldr < std::max<int64_t>(1, m)) return -10;
+  if (correct && !dflags) return -13;
+  hipStream_t s = h->stream;
+  TRY(report_init(s, drep, nullptr));
+  if (m == 0 || n == 0) return report_fini(s, drep);
+  const double tsu = (tau_scale > 0 ? tau_scale : 4.0) * U64;
+  TRY(verify_tiles<double>(s, dA, lda, m, n, nb, 0, 0, 0, correct ? 1 : 2, dcolchk, ldc, drowchk, ldr, nullptr,
+                           nullptr, tsu, dflags, drep, 0));
+  if (correct)
+    TRY(correct_tiles<double>(s, dA, lda, m, n, nb, 0, 0, 0, dcolchk, ldc, drowchk, ldr, nullptr, nullptr, tsu, dflags,
+                              drep, 0));
+  return report_fini(s, drep);
+}
+
+int abft_gesv_mp(abft_handle, int64_t, const double*, int64_t, const double*, double*, int32_t, int32_t, void*, size_t,
+                 const abft_opts*, abft_ir_report*, abft_report*) {
+  return ABFT_ERR_UNSUPPORTED;
+}
+int abft_posv_mp(abft_handle, int64_t, const double*, int64_t, const double*, double*, int32_t, int32_t, void*, size_t,
+                 const abft_opts*, abft_ir_report*, abft_report*) {
+  return ABFT_ERR_UNSUPPORTED;
+}
+int abft_potrf_batched(abft_handle, int32_t, int32_t, const int32_t*, void* const*, const int32_t*, int32_t, void*,
+                       size_t, const abft_opts*, int32_t*, abft_report*) {
+  return ABFT_ERR_UNSUPPORTED;
+}
+int abft_getrf_batched(abft_handle, int32_t, int32_t, const int32_t*, void* const*, const int32_t*, int32_t* const*,
+                       int32_t, void*, size_t, const abft_opts*, int32_t*, abft_report*) {
+  return ABFT_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

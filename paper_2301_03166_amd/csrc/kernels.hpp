@@ -1,0 +1,67 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/abft.h"
+
+namespace abft {
+
+// C = beta*C + alpha*op(A)*op(B) on FP64 MFMA.  ta/tb: 0 = N, 1 = T.  fa/fb:
+// 0 plain, 1 unit-lower mask on the stored operand, 2 absolute values,
+// 3 unit-lower mask then absolute values.
+// lower: write only C(i,j) with i + doff >= j.  atype/btype: 0 double,
+// 1 float (rounded to bf16 / fp16 when rnd = 1 / 2).
+int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int n, int k, double alpha, const void* A,
+           int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int atype = 0,
+           int btype = 0, int rnd = 0);
+
+// binary32 data GEMM for the mixed-precision trailing update:
+// C -= op(A) op(B) with C, A, B float; op in FP32 MFMA (prec ABFT_F32) or
+// bf16 / fp16 MFMA with FP32 accumulation (ABFT_BF16 / ABFT_F16).
+int gemm32(hipStream_t s, int prec, int ta, int tb, int lower, int m, int n, int k, float alpha, const float* A,
+           int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int64_t doff);
+
+template <typename T>
+int verify_tiles(hipStream_t s, const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
+                 int mode, double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc,
+                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter);
+template <typename T>
+int correct_tiles(hipStream_t s, T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
+                  double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc, const double* gr,
+                  double tsu, const int* tflags, abft_report* rep, int iter);
+template <typename T>
+int xsums(hipStream_t s, const T* A, int64_t lda, int64_t n, int nb, int I0, int64_t xc0, int kw, int dI, int mode,
+          double* S, double* Sa, int ldS, int rnd);
+template <typename T>
+int ysums(hipStream_t s, const T* Y, int64_t ldy, int64_t n, int nb, int J0, int kw, double* Tm, double* Ta, int ldT,
+          int rnd);
+int panel_check(hipStream_t s, const double* S, const double* Sa, int ldS, int I0, int I1, int kw, const double* Mp,
+                int64_t msp, int64_t msj, int tri, int pjoff, double mscale, const double* Mabs, const double* E,
+                const double* bt, int Ik, const double* colchk, int64_t ldc, int64_t cj0, int ncols, double tsu_p,
+                abft_report* rep, int iter, int nb);
+int qr_check_prep(hipStream_t s, const double* A, int64_t lda, int64_t c0, int w, int64_t m, const double* T, int ldt,
+                  double* scratch, double* Z, double* Zabs, double* E, double* bt);
+int inject(hipStream_t s, void* p, int is_float, int bit);
+int report_init(hipStream_t s, abft_report* r, int32_t* info);
+int report_fini(hipStream_t s, abft_report* r);
+
+template <typename T>
+int potrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int32_t* info);
+template <typename T>
+int trsm_rlt_leaf(hipStream_t s, T* A, int64_t lda, int64_t r0, int64_t r1, int64_t c0, int w);
+template <typename T>
+int trsm_llu_leaf(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1);
+template <typename T>
+int getrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int w, int32_t* ipiv, int32_t* info,
+               double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg);
+int geqrf_leaf(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t c0, int w, double* tau, double* Tm, int ldt,
+               int toff, double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg);
+int perm_build(hipStream_t s, const int32_t* ipiv, int64_t c0, int w, int* moves);
+template <typename T>
+int laswp(hipStream_t s, T* A, int64_t lda, int64_t j0, int64_t j1, const int* moves, T* stage, double* colchk,
+          int64_t ldc, int nb);
+
+int fill_zero(hipStream_t s, void* p, size_t bytes);
+
+}  // namespace abft

@@ -1,0 +1,580 @@
+// Panel kernels: Cholesky diagonal leaf, the two triangular-solve leaves,
+// the cooperative LU and Householder leaves, and the row-interchange kernels.
+//
+// Leaves are at most 32 columns wide; the host recursion (panel.cpp side of
+// the driver) splits wider panels and applies the updates between halves with
+// the MFMA GEMM, so the work inside a leaf is small and latency-bound.
+//
+// The LU and QR leaves hold the whole m x 32 leaf in the LDS of G co-resident
+// workgroups (cooperative launch); each column costs one grid barrier: every
+// workgroup publishes its candidate (pivot) or its partial Gram row (QR) to
+// a slot array, waits at the barrier, then all of them reduce the slots in
+// the same fixed order, so every workgroup takes the same decision.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace abft {
+
+constexpr int LEAF = 32;
+
+template <typename T>
+__device__ __forceinline__ T fms(T a, T b, T c) {  // a - b*c as the reference arithmetic does it
+  return a - b * c;
+}
+template <>
+__device__ __forceinline__ float fms<float>(float a, float b, float c) {
+  return __fmaf_rn(-b, c, a);
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky of the w x w diagonal block at (c0, c0), w <= 32, right-looking in
+// LDS.  info records the first non-positive pivot (global column + 1).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_leaf(T* A, int64_t lda, int64_t c0, int w, int32_t* info) {
+  __shared__ T L[LEAF][LEAF + 1];
+  __shared__ int fail;
+  const int tid = threadIdx.x;
+  if (tid == 0) fail = 0;
+  for (int idx = tid; idx < w * w; idx += blockDim.x) {
+    int i = idx % w, j = idx / w;
+    if (i >= j) L[i][j] = A[(c0 + i) + (c0 + j) * lda];
+  }
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    if (tid == 0) {
+      T d = L[j][j];
+      if (!(d > (T)0)) {
+        if (!fail && info) atomicCAS(info, 0, (int32_t)(c0 + j + 1));
+        fail = 1;
+      }
+      L[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < w; i += blockDim.x) L[i][j] = L[i][j] / L[j][j];
+    __syncthreads();
+    const int r = w - j - 1;
+    for (int idx = tid; idx < r * r; idx += blockDim.x) {
+      int i = j + 1 + idx % r, jj = j + 1 + idx / r;
+      if (i >= jj) L[i][jj] = fms(L[i][jj], L[i][j], L[jj][j]);
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < w * w; idx += blockDim.x) {
+    int i = idx % w, j = idx / w;
+    if (i >= j) A[(c0 + i) + (c0 + j) * lda] = L[i][j];
+  }
+}
+
+// X = B L^{-T} for rows [r0, r1) and columns [c0, c0+w): L the factored
+// diagonal block at (c0, c0) (non-unit lower).  One thread per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm_rlt_leaf(T* A, int64_t lda, int64_t r0, int64_t r1, int64_t c0, int w) {
+  __shared__ T L[LEAF][LEAF + 1];
+  __shared__ T B[256][LEAF + 1];
+  const int tid = threadIdx.x;
+  const int64_t rb = r0 + (int64_t)blockIdx.x * 256;
+  for (int idx = tid; idx < w * w; idx += 256) {
+    int i = idx % w, j = idx / w;
+    L[i][j] = (i >= j) ? A[(c0 + i) + (c0 + j) * lda] : (T)0;
+  }
+  for (int idx = tid; idx < 256 * w; idx += 256) {
+    int i = idx % 256, j = idx / 256;
+    if (rb + i < r1) B[i][j] = A[(rb + i) + (c0 + j) * lda];
+  }
+  __syncthreads();
+  if (rb + tid < r1) {
+    for (int j = 0; j < w; ++j) {
+      T s = B[tid][j];
+      for (int p = 0; p < j; ++p) s = fms(s, B[tid][p], L[j][p]);
+      B[tid][j] = s / L[j][j];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 256 * w; idx += 256) {
+    int i = idx % 256, j = idx / 256;
+    if (rb + i < r1) A[(rb + i) + (c0 + j) * lda] = B[i][j];
+  }
+}
+
+// X = L^{-1} B for the w rows [c0, c0+w) of columns [j0, j1): L unit lower at
+// (c0, c0).  One thread per column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm_llu_leaf(T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1) {
+  __shared__ T L[LEAF][LEAF + 1];
+  __shared__ T B[256][LEAF + 1];
+  const int tid = threadIdx.x;
+  const int64_t jb = j0 + (int64_t)blockIdx.x * 256;
+  for (int idx = tid; idx < w * w; idx += 256) {
+    int i = idx % w, j = idx / w;
+    L[i][j] = (i > j) ? A[(c0 + i) + (c0 + j) * lda] : (T)0;
+  }
+  for (int idx = tid; idx < 256 * w; idx += 256) {
+    int i = idx % w, c = idx / w;
+    if (jb + c < j1) B[c][i] = A[(c0 + i) + (jb + c) * lda];
+  }
+  __syncthreads();
+  if (jb + tid < j1) {
+    for (int i = 0; i < w; ++i) {
+      T s = B[tid][i];
+      for (int p = 0; p < i; ++p) s = fms(s, L[i][p], B[tid][p]);
+      B[tid][i] = s;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 256 * w; idx += 256) {
+    int i = idx % w, c = idx / w;
+    if (jb + c < j1) A[(c0 + i) + (jb + c) * lda] = B[c][i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative LU leaf: columns [c0, c0+w), rows [c0, m); workgroup g owns
+// rows [c0 + g R, c0 + (g+1) R) in LDS.  Partial pivoting with the first
+// index on ties; row interchanges inside the leaf columns only (the caller
+// applies them to the other columns).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ bool better(double a, int64_t ia, double b, int64_t ib) {
+  return a > b || (a == b && ia < ib);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m, int64_t c0, int w, int R,
+                                                    int32_t* ipiv, int32_t* info, double* slots, unsigned* ctr,
+                                                    unsigned ctr_base, abft_report* rep) {
+  extern __shared__ unsigned char smem_raw[];
+  T* Ld = reinterpret_cast<T*>(smem_raw);  // R x (w+1)
+  const int ldl = w + 1;
+  __shared__ double prow[LEAF], orow[LEAF];
+  __shared__ double wv_val[4];
+  __shared__ int64_t wv_idx[4];
+  __shared__ int64_t s_piv, s_loc;
+  __shared__ int s_pg;
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t rbeg = c0 + (int64_t)g * R;
+  const int rows = (int)max((int64_t)0, min((int64_t)R, m - rbeg));
+  const int slot_stride = G * (w + 2) + w;
+
+  for (int idx = tid; idx < rows * w; idx += 256) {
+    int i = idx % rows, j = idx / rows;
+    Ld[i * ldl + j] = A[(rbeg + i) + (c0 + j) * lda];
+  }
+  __syncthreads();
+
+  for (int j = 0; j < w; ++j) {
+    const int64_t d = c0 + j;  // diagonal row
+    double* sj = slots + (size_t)j * slot_stride;
+    // local argmax of |a(i, j)| over owned rows i >= d
+    double bv = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int i = tid; i < rows; i += 256) {
+      int64_t gi = rbeg + i;
+      if (gi < d) continue;
+      double v = fabs((double)Ld[i * ldl + j]);
+      if (better<T>(v, gi, bv, bi)) { bv = v; bi = gi; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      double ov = __shfl_xor(bv, o);
+      int64_t oi = __shfl_xor(bi, o);
+      if (better<T>(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { wv_val[wv] = bv; wv_idx[wv] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      for (int q = 1; q < 4; ++q)
+        if (better<T>(wv_val[q], wv_idx[q], bv, bi)) { bv = wv_val[q]; bi = wv_idx[q]; }
+      sj[g * (w + 2) + 0] = bv;
+      sj[g * (w + 2) + 1] = (double)bi;
+      s_loc = bi;
+    }
+    __syncthreads();
+    // candidate row (values of the leaf columns) and, from workgroup 0, row d
+    if (tid < w) {
+      const int64_t bl = s_loc;
+      double val = 0.0;
+      if (bl != INT64_MAX) val = (double)Ld[(bl - rbeg) * ldl + tid];
+      sj[g * (w + 2) + 2 + tid] = val;
+      if (g == 0) sj[G * (w + 2) + tid] = (double)Ld[(d - rbeg) * ldl + tid];
+    }
+    grid_barrier(ctr, ctr_base + (unsigned)(j + 1) * G, rep, nullptr);
+    // every workgroup picks the same winner by scanning the slots in order
+    if (tid == 0) {
+      double best = -1.0;
+      int64_t bidx = INT64_MAX;
+      int bg = 0;
+      for (int q = 0; q < G; ++q) {
+        double v = sj[q * (w + 2) + 0];
+        if (v < 0) continue;
+        int64_t ii = (int64_t)sj[q * (w + 2) + 1];
+        if (better<T>(v, ii, best, bidx)) { best = v; bidx = ii; bg = q; }
+      }
+      if (bidx == INT64_MAX) { bidx = d; bg = 0; }
+      s_piv = bidx;
+      s_pg = bg;
+    }
+    __syncthreads();
+    const int64_t p = s_piv;
+    const int pg = s_pg;
+    if (tid < w) {
+      prow[tid] = sj[pg * (w + 2) + 2 + tid];
+      orow[tid] = sj[G * (w + 2) + tid];
+    }
+    __syncthreads();
+    if (p != d) {
+      if (g == 0 && tid < w) Ld[(d - rbeg) * ldl + tid] = (T)prow[tid];
+      if (p >= rbeg && p < rbeg + rows && tid < w) Ld[(p - rbeg) * ldl + tid] = (T)orow[tid];
+    }
+    __syncthreads();
+    if (g == 0 && tid == 0) {
+      ipiv[d] = (int32_t)(p + 1);
+      if (prow[j] == 0.0 && info) atomicCAS(info, 0, (int32_t)(d + 1));
+    }
+    const T piv = (T)prow[j];
+    if (piv != (T)0) {
+      for (int i = tid; i < rows; i += 256) {
+        int64_t gi = rbeg + i;
+        if (gi <= d) continue;
+        T l = Ld[i * ldl + j] / piv;
+        Ld[i * ldl + j] = l;
+        for (int c = j + 1; c < w; ++c) Ld[i * ldl + c] = fms(Ld[i * ldl + c], l, (T)prow[c]);
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < rows * w; idx += 256) {
+    int i = idx % rows, j = idx / rows;
+    A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative Householder leaf: columns [c0, c0+w), rows [c0, m) (LAPACK
+// dlarfg convention), plus the leaf's triangular factor T (forward,
+// columnwise) written at T[toff + toff*ldt].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int64_t m, int64_t c0, int w, int R,
+                                                    double* tau, double* Tm, int ldt, int toff, double* slots,
+                                                    unsigned* ctr, unsigned ctr_base, abft_report* rep) {
+  extern __shared__ unsigned char smem_raw[];
+  double* Ld = reinterpret_cast<double*>(smem_raw);  // R x (w+1)
+  const int ldl = w + 1;
+  __shared__ double part[4][LEAF];
+  __shared__ double svec[LEAF], orow[LEAF], fvec[LEAF];
+  __shared__ double s_beta, s_tau, s_scale;
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t rbeg = c0 + (int64_t)g * R;
+  const int rows = (int)max((int64_t)0, min((int64_t)R, m - rbeg));
+  const int slot_stride = G * w + w;
+
+  for (int idx = tid; idx < rows * w; idx += 256) {
+    int i = idx % rows, j = idx / rows;
+    Ld[i * ldl + j] = A[(rbeg + i) + (c0 + j) * lda];
+  }
+  __syncthreads();
+
+  for (int j = 0; j < w; ++j) {
+    const int64_t d = c0 + j;
+    double* sj = slots + (size_t)j * slot_stride;
+    // partial Gram row: s_c = sum_{i > d} a(i,j) a(i,c), c = j..w-1
+    for (int c = j; c < w; ++c) {
+      double acc = 0.0;
+      for (int i = tid; i < rows; i += 256) {
+        if (rbeg + i <= d) continue;
+        acc += Ld[i * ldl + j] * Ld[i * ldl + c];
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) part[wv][c] = acc;
+    }
+    __syncthreads();
+    if (tid < w) {
+      double v = 0.0;
+      if (tid >= j) v = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+      sj[g * w + tid] = v;
+      if (g == 0) sj[G * w + tid] = Ld[(d - rbeg) * ldl + tid];
+    }
+    grid_barrier(ctr, ctr_base + (unsigned)(j + 1) * G, rep, nullptr);
+    if (tid < w) {
+      double s = 0.0;
+      for (int q = 0; q < G; ++q) s += sj[q * w + tid];
+      svec[tid] = s;
+      orow[tid] = sj[G * w + tid];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double alpha = orow[j], s2 = svec[j];
+      if (s2 == 0.0) {
+        s_tau = 0.0; s_scale = 0.0; s_beta = alpha;
+      } else {
+        double beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+        s_tau = (beta - alpha) / beta;
+        s_scale = 1.0 / (alpha - beta);
+        s_beta = beta;
+      }
+      if (g == 0) tau[d] = s_tau;
+    }
+    __syncthreads();
+    const double t = s_tau, sc = s_scale;
+    if (t != 0.0) {
+      if (tid < w && tid > j) fvec[tid] = t * (orow[tid] + sc * svec[tid]);
+      __syncthreads();
+      for (int i = tid; i < rows; i += 256) {
+        int64_t gi = rbeg + i;
+        if (gi < d) continue;
+        if (gi == d) {
+          Ld[i * ldl + j] = s_beta;
+          for (int c = j + 1; c < w; ++c) Ld[i * ldl + c] -= fvec[c];
+        } else {
+          double v = Ld[i * ldl + j] * sc;
+          Ld[i * ldl + j] = v;
+          for (int c = j + 1; c < w; ++c) Ld[i * ldl + c] -= fvec[c] * v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // T factor of the leaf from the Gram matrix of V (unit diagonal, zeros above)
+  double* sg = slots + (size_t)w * slot_stride;  // G x (w*w) partial Gram matrices
+  for (int e = tid; e < w * w; e += 256) {
+    int q = e % w, jj = e / w;
+    double acc = 0.0;
+    if (q < jj) {
+      for (int i = 0; i < rows; ++i) {
+        int64_t li = rbeg + i - c0;  // row index relative to the leaf top
+        double vq = (li < q) ? 0.0 : (li == q ? 1.0 : Ld[i * ldl + q]);
+        double vj = (li < jj) ? 0.0 : (li == jj ? 1.0 : Ld[i * ldl + jj]);
+        acc += vq * vj;
+      }
+    }
+    sg[(size_t)g * w * w + e] = acc;
+  }
+  grid_barrier(ctr, ctr_base + (unsigned)(w + 1) * G, rep, nullptr);
+  if (g == 0) {
+    __shared__ double Gm[LEAF][LEAF + 1];
+    __shared__ double Tl[LEAF][LEAF + 1];
+    for (int e = tid; e < w * w; e += 256) {
+      double s = 0.0;
+      for (int q = 0; q < G; ++q) s += sg[(size_t)q * w * w + e];
+      Gm[e % w][e / w] = s;
+      Tl[e % w][e / w] = 0.0;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < w; ++jj) {
+      double tj = tau[c0 + jj];
+      if (tid == 0) Tl[jj][jj] = tj;
+      if (tid < jj) {
+        double s = 0.0;
+        for (int q = tid; q < jj; ++q) s += Tl[tid][q] * Gm[q][jj];
+        Tl[tid][jj] = -tj * s;
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < w * w; e += 256) Tm[(toff + e % w) + (int64_t)(toff + e / w) * ldt] = Tl[e % w][e / w];
+  }
+  for (int idx = tid; idx < rows * w; idx += 256) {
+    int i = idx % rows, j = idx / rows;
+    A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row interchanges.  k_perm_build turns the interchanges ipiv[c0..c0+w) into
+// the list of moved rows (dst <- src), sorted by dst.  k_laswp applies the
+// moves to columns [j0, j1) through a staging buffer; with a column-checksum
+// array it also adds, per tile-row, the change of the column sums and of the
+// weighted column sums (compensated, in the moves' fixed order).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_perm_build(const int32_t* ipiv, int64_t c0, int w, int* moves) {
+  __shared__ int64_t outk[512];
+  __shared__ int64_t outc[512];
+  __shared__ int64_t inside[512];
+  __shared__ int nout;
+  const int tid = threadIdx.x;
+  // outside rows (>= c0 + w) referenced by the interchanges
+  if (tid == 0) {
+    int cnt = 0;
+    for (int t = 0; t < w; ++t) {
+      int64_t p = ipiv[c0 + t] - 1;
+      if (p >= c0 + w) outk[cnt++] = p;
+    }
+    // insertion sort + dedupe (w <= 512)
+    for (int a = 1; a < cnt; ++a) {
+      int64_t x = outk[a];
+      int b = a - 1;
+      while (b >= 0 && outk[b] > x) { outk[b + 1] = outk[b]; --b; }
+      outk[b + 1] = x;
+    }
+    int u = 0;
+    for (int a = 0; a < cnt; ++a)
+      if (u == 0 || outk[u - 1] != outk[a]) outk[u++] = outk[a];
+    nout = u;
+  }
+  __syncthreads();
+  for (int t = tid; t < w; t += 256) inside[t] = c0 + t;
+  for (int q = tid; q < nout; q += 256) outc[q] = outk[q];
+  __syncthreads();
+  if (tid == 0) {
+    for (int t = 0; t < w; ++t) {
+      int64_t p = ipiv[c0 + t] - 1;
+      if (p == c0 + t) continue;
+      int64_t* slot;
+      if (p < c0 + w) {
+        slot = &inside[p - c0];
+      } else {
+        int lo = 0, hi = nout - 1;
+        while (lo < hi) {
+          int mid = (lo + hi) >> 1;
+          if (outk[mid] < p) lo = mid + 1; else hi = mid;
+        }
+        slot = &outc[lo];
+      }
+      int64_t tmp = inside[t];
+      inside[t] = *slot;
+      *slot = tmp;
+    }
+    int nm = 0;
+    for (int t = 0; t < w; ++t)
+      if (inside[t] != c0 + t) { moves[1 + 2 * nm] = (int)(c0 + t); moves[2 + 2 * nm] = (int)inside[t]; ++nm; }
+    for (int q = 0; q < nout; ++q)
+      if (outc[q] != outk[q]) { moves[1 + 2 * nm] = (int)outk[q]; moves[2 + 2 * nm] = (int)outc[q]; ++nm; }
+    moves[0] = nm;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_laswp(T* A, int64_t lda, int64_t j0, int64_t j1, const int* moves, T* stage,
+                                               double* colchk, int64_t ldc, int nb) {
+  const int64_t j = j0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= j1) return;
+  const int nm = moves[0];
+  const int64_t nc = j1 - j0, jj = j - j0;
+  T* col = A + j * lda;
+  acc2 e{0, 0}, ww{0, 0};
+  int curI = -1;
+  for (int t = 0; t < nm; ++t) {
+    const int dst = moves[1 + 2 * t], src = moves[2 + 2 * t];
+    T vs = col[src], vd = col[dst];
+    stage[(int64_t)t * nc + jj] = vs;
+    if (colchk) {
+      int I = dst / nb;
+      if (I != curI) {
+        if (curI >= 0) {
+          acc2 c0{colchk[2 * curI + j * ldc], 0}, c1{colchk[2 * curI + 1 + j * ldc], 0};
+          cmerge(c0, e);
+          cmerge(c1, ww);
+          colchk[2 * curI + j * ldc] = cval(c0);
+          colchk[2 * curI + 1 + j * ldc] = cval(c1);
+        }
+        curI = I;
+        e = {0, 0};
+        ww = {0, 0};
+      }
+      double delta = (double)vs - (double)vd;
+      cadd(e, (double)vs);
+      cadd(e, -(double)vd);
+      double wr = (double)(dst - I * nb + 1);
+      cfma(ww, wr, (double)vs);
+      cfma(ww, -wr, (double)vd);
+      (void)delta;
+    }
+  }
+  if (colchk && curI >= 0) {
+    acc2 c0{colchk[2 * curI + j * ldc], 0}, c1{colchk[2 * curI + 1 + j * ldc], 0};
+    cmerge(c0, e);
+    cmerge(c1, ww);
+    colchk[2 * curI + j * ldc] = cval(c0);
+    colchk[2 * curI + 1 + j * ldc] = cval(c1);
+  }
+  for (int t = 0; t < nm; ++t) col[moves[1 + 2 * t]] = stage[(int64_t)t * nc + jj];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+#define CHECK_LAUNCH() return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP
+
+template <typename T>
+int potrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int32_t* info) {
+  hipLaunchKernelGGL(k_potrf_leaf<T>, dim3(1), dim3(256), 0, s, A, lda, c0, w, info);
+  CHECK_LAUNCH();
+}
+template <typename T>
+int trsm_rlt_leaf(hipStream_t s, T* A, int64_t lda, int64_t r0, int64_t r1, int64_t c0, int w) {
+  if (r1 <= r0) return 0;
+  hipLaunchKernelGGL(k_trsm_rlt_leaf<T>, dim3((unsigned)((r1 - r0 + 255) / 256)), dim3(256), 0, s, A, lda, r0, r1, c0, w);
+  CHECK_LAUNCH();
+}
+template <typename T>
+int trsm_llu_leaf(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1) {
+  if (j1 <= j0) return 0;
+  hipLaunchKernelGGL(k_trsm_llu_leaf<T>, dim3((unsigned)((j1 - j0 + 255) / 256)), dim3(256), 0, s, A, lda, c0, w, j0, j1);
+  CHECK_LAUNCH();
+}
+
+// rows per workgroup of a cooperative leaf: enough workgroups to spread m
+// rows, at least w rows in workgroup 0, at most `maxg` workgroups
+static inline void coop_shape(int64_t rows, int w, int maxg, int max_rows, int& G, int& R) {
+  int64_t r = (rows + maxg - 1) / maxg;
+  if (r < 256) r = 256;
+  if (r < w) r = w;
+  if (r > max_rows) r = max_rows;
+  G = (int)((rows + r - 1) / r);
+  if (G < 1) G = 1;
+  R = (int)r;
+}
+
+template <typename T>
+int getrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int w, int32_t* ipiv, int32_t* info,
+               double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg) {
+  int G, R;
+  const int max_rows = (int)((120 * 1024) / ((w + 1) * sizeof(T)));
+  coop_shape(m - c0, w, maxg, max_rows, G, R);
+  if ((int64_t)G * R < m - c0) return ABFT_ERR_UNSUPPORTED;
+  size_t shm = (size_t)R * (w + 1) * sizeof(T);
+  void* args[] = {&A, &lda, &m, &c0, &w, &R, &ipiv, &info, &slots, &ctr, ctr_base, &rep};
+  hipError_t e = hipLaunchCooperativeKernel((const void*)k_getrf_leaf<T>, dim3(G), dim3(256), args, shm, s);
+  *ctr_base += (unsigned)w * G;
+  return e == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
+int geqrf_leaf(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t c0, int w, double* tau, double* Tm, int ldt,
+               int toff, double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg) {
+  int G, R;
+  const int max_rows = (int)((100 * 1024) / ((w + 1) * sizeof(double)));
+  coop_shape(m - c0, w, maxg, max_rows, G, R);
+  if ((int64_t)G * R < m - c0) return ABFT_ERR_UNSUPPORTED;
+  size_t shm = (size_t)R * (w + 1) * sizeof(double);
+  void* args[] = {&A, &lda, &m, &c0, &w, &R, &tau, &Tm, &ldt, &toff, &slots, &ctr, ctr_base, &rep};
+  hipError_t e = hipLaunchCooperativeKernel((const void*)k_geqrf_leaf, dim3(G), dim3(256), args, shm, s);
+  *ctr_base += (unsigned)(w + 1) * G;
+  return e == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
+int perm_build(hipStream_t s, const int32_t* ipiv, int64_t c0, int w, int* moves) {
+  hipLaunchKernelGGL(k_perm_build, dim3(1), dim3(256), 0, s, ipiv, c0, w, moves);
+  CHECK_LAUNCH();
+}
+template <typename T>
+int laswp(hipStream_t s, T* A, int64_t lda, int64_t j0, int64_t j1, const int* moves, T* stage, double* colchk,
+          int64_t ldc, int nb) {
+  if (j1 <= j0) return 0;
+  hipLaunchKernelGGL(k_laswp<T>, dim3((unsigned)((j1 - j0 + 255) / 256)), dim3(256), 0, s, A, lda, j0, j1, moves, stage,
+                     colchk, ldc, nb);
+  CHECK_LAUNCH();
+}
+
+template int potrf_leaf<double>(hipStream_t, double*, int64_t, int64_t, int, int32_t*);
+template int potrf_leaf<float>(hipStream_t, float*, int64_t, int64_t, int, int32_t*);
+template int trsm_rlt_leaf<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int64_t, int);
+template int trsm_rlt_leaf<float>(hipStream_t, float*, int64_t, int64_t, int64_t, int64_t, int);
+template int trsm_llu_leaf<double>(hipStream_t, double*, int64_t, int64_t, int, int64_t, int64_t);
+template int trsm_llu_leaf<float>(hipStream_t, float*, int64_t, int64_t, int, int64_t, int64_t);
+template int getrf_leaf<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int, int32_t*, int32_t*, double*,
+                                unsigned*, unsigned*, abft_report*, int);
+template int getrf_leaf<float>(hipStream_t, float*, int64_t, int64_t, int64_t, int, int32_t*, int32_t*, double*,
+                               unsigned*, unsigned*, abft_report*, int);
+template int laswp<double>(hipStream_t, double*, int64_t, int64_t, int64_t, const int*, double*, double*, int64_t, int);
+template int laswp<float>(hipStream_t, float*, int64_t, int64_t, int64_t, const int*, float*, double*, int64_t, int);
+
+}  // namespace abft
