@@ -109,8 +109,21 @@ typedef struct {
   double tau_scale;    /* threshold scale (default 4.0 when <= 0) */
   const abft_fault* faults; /* host array of fault plans (test use), may be NULL */
   int32_t nfaults;
-  int32_t flags;       /* reserved, 0 */
+  int32_t flags;       /* ABFT_FLAG_* bits */
 } abft_opts;
+
+/* opts.flags: time the phases of the call with HIP events on the handle's
+   stream (the call then waits for its own completion before returning). */
+enum { ABFT_FLAG_PROFILE = 1 };
+
+/* Phase times of the last call made with ABFT_FLAG_PROFILE, with the
+   algorithmic work of the timed trailing-update GEMMs and verify passes. */
+typedef struct {
+  double ms_total, ms_panel, ms_tmu, ms_carry, ms_verify;
+  double tmu_flops;    /* flops of the trailing-update GEMMs (2 m n k each) */
+  double verify_bytes; /* bytes of matrix data streamed by the verify passes */
+  int32_t tmu_launches, iters;
+} abft_profile;
 
 typedef struct {
   int32_t iters, converged, failed_reason, info; /* reason: 0 ok, 1 no contraction, 2 non-finite, 3 max iter, 4 factorization info */
@@ -122,6 +135,9 @@ typedef struct {
 int abft_create(abft_handle* h, void* stream);
 int abft_destroy(abft_handle h);
 int abft_set_stream(abft_handle h, void* stream);
+
+/* Copy the phase profile of the handle's last ABFT_FLAG_PROFILE call. */
+int abft_get_profile(abft_handle h, abft_profile* out);
 
 /* Bytes of device workspace needed by operation `op` on an n x n problem
    (for the batched ops: n = the largest matrix order, `batch` matrices). */

@@ -46,6 +46,15 @@ class IRReport(C.Structure):
                 ("resid_norm", C.c_double), ("x_norm", C.c_double), ("a_norm", C.c_double), ("last_dx", C.c_double)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("ms_total", C.c_double), ("ms_panel", C.c_double), ("ms_tmu", C.c_double),
+                ("ms_carry", C.c_double), ("ms_verify", C.c_double), ("tmu_flops", C.c_double),
+                ("verify_bytes", C.c_double), ("tmu_launches", C.c_int32), ("iters", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("protect", C.c_int32), ("tau_scale", C.c_double),
                 ("faults", C.POINTER(Fault)), ("nfaults", C.c_int32), ("flags", C.c_int32)]
@@ -69,6 +78,7 @@ def lib():
         L.abft_create.argtypes = [C.POINTER(P), P]
         L.abft_destroy.argtypes = [P]
         L.abft_set_stream.argtypes = [P, P]
+        L.abft_get_profile.argtypes = [P, C.POINTER(Profile)]
         L.abft_workspace_size.argtypes = [P, C.c_int, i64, i32, C.POINTER(Opts), C.POINTER(sz)]
         L.abft_potrf.argtypes = [P, i64, P, i64, P, sz, C.POINTER(Opts), P, P]
         L.abft_getrf.argtypes = [P, i64, P, i64, P, P, sz, C.POINTER(Opts), P, P]
@@ -94,14 +104,25 @@ def colmajor(t):
 
 
 def _ld(A):
-    if A.dim() != 2 or A.stride(0) != 1:
-        raise AbftError("matrices must be column-major 2-D tensors (stride(0) == 1)")
-    return max(A.stride(1), A.shape[0], 1)
+    """Leading dimension of a column-major 2-D tensor (size-1 dimensions carry no stride)."""
+    if A.dim() != 2:
+        raise AbftError("matrices must be 2-D tensors")
+    m, n = A.shape
+    if m > 1 and A.stride(0) != 1:
+        raise AbftError("matrices must be column-major (stride(0) == 1)")
+    lda = A.stride(1) if n > 1 else m
+    if lda < max(m, 1):
+        raise AbftError("column stride smaller than the number of rows")
+    return max(lda, 1)
 
 
-def make_opts(nb, protect=True, tau_scale=4.0, faults=None):
+FLAG_PROFILE = 1
+
+
+def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False):
     o = Opts()
     o.nb, o.protect, o.tau_scale = int(nb), PROTECT_FULL if protect else PROTECT_NONE, float(tau_scale)
+    o.flags = FLAG_PROFILE if profile else 0
     keep = None
     if faults:
         keep = (Fault * len(faults))()
@@ -154,31 +175,40 @@ class Handle:
         return Report.from_buffer_copy(raw)
 
     # ------------------------------------------------------------ factorizations
-    def potrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True):
+    def potrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True,
+              profile=False):
         """In-place Cholesky (lower) of column-major A; returns (info, Report) when sync."""
-        return self._factor(OP_POTRF, A, nb, protect, tau_scale, faults, report, info, sync)
+        return self._factor(OP_POTRF, A, nb, protect, tau_scale, faults, report, info, sync, profile=profile)
 
-    def getrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, ipiv=None, report=None, info=None, sync=True):
+    def getrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, ipiv=None, report=None, info=None, sync=True,
+              profile=False):
         torch = self.torch
         if ipiv is None:
             ipiv = torch.zeros(A.shape[0], dtype=torch.int32, device=self.device)
-        out = self._factor(OP_GETRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=ipiv)
+        out = self._factor(OP_GETRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=ipiv, profile=profile)
         return (ipiv,) + out if sync else ipiv
 
-    def geqrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, tau=None, report=None, info=None, sync=True):
+    def geqrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, tau=None, report=None, info=None, sync=True,
+              profile=False):
         torch = self.torch
         if tau is None:
             tau = torch.zeros(A.shape[0], dtype=torch.float64, device=self.device)
-        out = self._factor(OP_GEQRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=tau)
+        out = self._factor(OP_GEQRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=tau, profile=profile)
         return (tau,) + out if sync else tau
 
-    def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None):
+    def profile(self):
+        """Phase profile of the last call made with profile=True."""
+        p = Profile()
+        _check(lib().abft_get_profile(self._h, C.byref(p)), "abft_get_profile")
+        return p.as_dict()
+
+    def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None, profile=False):
         torch = self.torch
         n = A.shape[0]
         if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
             raise AbftError("expected a square float64 device matrix")
         lda = _ld(A)
-        opts, keep = make_opts(nb, protect, tau_scale, faults)
+        opts, keep = make_opts(nb, protect, tau_scale, faults, profile)
         ws, wbytes = self.workspace(op, n, opts)
         rep = report if report is not None else self.new_report()
         inf = info if info is not None else torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -199,6 +229,80 @@ class Handle:
             return ()
         torch.cuda.synchronize(self.device)
         return int(inf.item()), self.read_report(rep)
+
+    # ------------------------------------------------------------ mixed precision
+    def gesv_mp(self, A, b, prec, nb=256, max_iter=30, chol=False, protect=True, tau_scale=4.0, faults=None,
+                x=None, report=None, ir=None, sync=True, profile=False):
+        """Solve A x = b: binary32 factorization (trailing update in `prec`) + FP64 refinement,
+        or the FP64 factorization and direct solve when prec == F64.  Returns (x, IRReport, Report)."""
+        torch = self.torch
+        n = A.shape[0]
+        if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
+            raise AbftError("expected a square float64 device matrix")
+        lda = _ld(A)
+        bb = b.contiguous()
+        if x is None:
+            x = torch.zeros(n, dtype=torch.float64, device=self.device)
+        op = OP_POSV_MP if chol else OP_GESV_MP
+        opts, keep = make_opts(nb, protect, tau_scale, faults, profile)
+        ws, wbytes = self.workspace(op, n, opts)
+        rep = report if report is not None else self.new_report()
+        irb = ir if ir is not None else torch.zeros(C.sizeof(IRReport), dtype=torch.uint8, device=self.device)
+        self._sync_stream()
+        fn = lib().abft_posv_mp if chol else lib().abft_gesv_mp
+        rc = fn(self._h, n, A.data_ptr(), lda, bb.data_ptr(), x.data_ptr(), int(prec), int(max_iter), ws.data_ptr(),
+                wbytes, C.byref(opts), irb.data_ptr(), rep.data_ptr())
+        del keep
+        _check(rc, "abft_gesv_mp")
+        if not sync:
+            return x
+        torch.cuda.synchronize(self.device)
+        return x, IRReport.from_buffer_copy(bytes(irb.cpu().numpy().tobytes())), self.read_report(rep)
+
+    # ------------------------------------------------------------ batched
+    def batched(self, mats, chol, protect=True, tau_scale=4.0, faults=None, nmax=None, sync=True, state=None):
+        """Factor a list of column-major square matrices (all float64 or all float32) in place with one
+        batched call (block / tile size 32).  Returns (infos, ipivs, reports) when sync; `state` keeps the
+        device argument arrays alive for graph capture and replay."""
+        torch = self.torch
+        batch = len(mats)
+        prec = F64 if mats[0].dtype == torch.float64 else F32
+        if state is None:
+            state = self.batched_args(mats, chol)
+        ns, ptrs, ldas, ipivs, piv_ptrs, infos, reps = state
+        opts, keep = make_opts(32, protect, tau_scale, faults)
+        op = OP_POTRF_BATCHED if chol else OP_GETRF_BATCHED
+        ws, wbytes = self.workspace(op, 0, opts, batch=batch)
+        nm = int(nmax if nmax is not None else max(m.shape[0] for m in mats))
+        self._sync_stream()
+        if chol:
+            rc = lib().abft_potrf_batched(self._h, batch, nm, ns.data_ptr(), ptrs.data_ptr(), ldas.data_ptr(), prec,
+                                          ws.data_ptr(), wbytes, C.byref(opts), infos.data_ptr(), reps.data_ptr())
+        else:
+            rc = lib().abft_getrf_batched(self._h, batch, nm, ns.data_ptr(), ptrs.data_ptr(), ldas.data_ptr(),
+                                          piv_ptrs.data_ptr(), prec, ws.data_ptr(), wbytes, C.byref(opts),
+                                          infos.data_ptr(), reps.data_ptr())
+        del keep
+        _check(rc, "abft_batched")
+        if not sync:
+            return state
+        torch.cuda.synchronize(self.device)
+        rsz = C.sizeof(Report)
+        raw = reps.cpu().numpy().tobytes()
+        reports = [Report.from_buffer_copy(raw[i * rsz:(i + 1) * rsz]) for i in range(batch)]
+        return infos.cpu().numpy(), ipivs, reports
+
+    def batched_args(self, mats, chol):
+        torch = self.torch
+        dev = self.device
+        ns = torch.tensor([m.shape[0] for m in mats], dtype=torch.int32, device=dev)
+        ptrs = torch.tensor([m.data_ptr() for m in mats], dtype=torch.int64, device=dev)
+        ldas = torch.tensor([_ld(m) for m in mats], dtype=torch.int32, device=dev)
+        ipivs = None if chol else [torch.zeros(max(m.shape[0], 1), dtype=torch.int32, device=dev) for m in mats]
+        piv_ptrs = None if chol else torch.tensor([p.data_ptr() for p in ipivs], dtype=torch.int64, device=dev)
+        infos = torch.zeros(len(mats), dtype=torch.int32, device=dev)
+        reps = torch.zeros(len(mats) * C.sizeof(Report), dtype=torch.uint8, device=dev)
+        return ns, ptrs, ldas, ipivs, piv_ptrs, infos, reps
 
     # ------------------------------------------------------------ checksums
     def encode(self, A, nb):

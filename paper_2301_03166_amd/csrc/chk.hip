@@ -11,165 +11,13 @@
 // recomputed entries; verification streams every trailing tile once.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tile.hpp"
 
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
 
 namespace abft {
-
-constexpr int MAXNB = 512;
-constexpr int QROWS = MAXNB / 64;
-
-template <typename T>
-__device__ __forceinline__ double ld(const T* p) {
-  return (double)*p;
-}
-
-// LDS scratch of one tile's sums (40 KB)
-struct TileSums {
-  double ce[MAXNB], cw[MAXNB], ca[MAXNB], cwa[MAXNB];
-  double res[MAXNB], rec[MAXNB], rws[MAXNB], rwc[MAXNB], ra[MAXNB], rwa[MAXNB];
-};
-
-// All column and row sums of tile (r0, c0, h x w); in the symmetric view an
-// element above the diagonal is read from its mirror below it.  Waves take
-// columns round-robin and lanes walk the rows (coalesced); each lane keeps
-// its rows' partial row sums, merged across waves in a fixed order.
-template <typename T>
-__device__ void tile_sums(const T* A, int64_t lda, int64_t r0, int64_t c0, int h, int w, bool sym, TileSums& ts) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  acc2 pe[QROWS], pw[QROWS];
-  double pa[QROWS], pwa[QROWS];
-#pragma unroll
-  for (int q = 0; q < QROWS; ++q) { pe[q] = {0, 0}; pw[q] = {0, 0}; pa[q] = 0; pwa[q] = 0; }
-  for (int j = wv; j < w; j += 4) {
-    acc2 se{0, 0}, sw{0, 0};
-    double sa = 0, swa = 0;
-    const double wj = (double)(j + 1);
-#pragma unroll
-    for (int q = 0; q < QROWS; ++q) {
-      int i = lane + 64 * q;
-      if (i < h) {
-        double v = (sym && i < j) ? ld(A + (r0 + j) + (c0 + i) * lda) : ld(A + (r0 + i) + (c0 + j) * lda);
-        double wi = (double)(i + 1), av = fabs(v);
-        cadd(se, v);
-        cfma(sw, wi, v);
-        sa += av;
-        swa += wi * av;
-        cadd(pe[q], v);
-        cfma(pw[q], wj, v);
-        pa[q] += av;
-        pwa[q] += wj * av;
-      }
-    }
-    se = wave_csum(se);
-    sw = wave_csum(sw);
-    sa = wave_sum(sa);
-    swa = wave_sum(swa);
-    if (lane == 0) {
-      ts.ce[j] = cval(se);
-      ts.cw[j] = cval(sw);
-      ts.ca[j] = sa;
-      ts.cwa[j] = swa;
-    }
-  }
-  for (int s = 0; s < 4; ++s) {
-    if (wv == s) {
-#pragma unroll
-      for (int q = 0; q < QROWS; ++q) {
-        int i = lane + 64 * q;
-        if (i < h) {
-          if (s == 0) {
-            ts.res[i] = pe[q].s; ts.rec[i] = pe[q].c;
-            ts.rws[i] = pw[q].s; ts.rwc[i] = pw[q].c;
-            ts.ra[i] = pa[q]; ts.rwa[i] = pwa[q];
-          } else {
-            acc2 e{ts.res[i], ts.rec[i]}, ww{ts.rws[i], ts.rwc[i]};
-            cmerge(e, pe[q]);
-            cmerge(ww, pw[q]);
-            ts.res[i] = e.s; ts.rec[i] = e.c;
-            ts.rws[i] = ww.s; ts.rwc[i] = ww.c;
-            ts.ra[i] += pa[q]; ts.rwa[i] += pwa[q];
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < h; i += blockDim.x) {
-    ts.res[i] = ts.res[i] + ts.rec[i];
-    ts.rws[i] = ts.rws[i] + ts.rwc[i];
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ void tile_geom(int bid, int I0, int J0, int nI, int nb, int64_t nr, int64_t nc, int& I,
-                                          int& J, int& h, int& w) {
-  I = I0 + bid % nI;
-  J = J0 + bid / nI;
-  h = (int)min((int64_t)nb, nr - (int64_t)I * nb);
-  w = (int)min((int64_t)nb, nc - (int64_t)J * nb);
-}
-
-// write the sums of a tile into the checksum arrays
-__device__ void store_sums(const TileSums& ts, int I, int J, int nb, int h, int w, double* colchk, int64_t ldc,
-                           double* rowchk, int64_t ldr) {
-  int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
-  for (int j = threadIdx.x; j < w; j += blockDim.x) {
-    colchk[2 * I + (c0 + j) * ldc] = ts.ce[j];
-    colchk[2 * I + 1 + (c0 + j) * ldc] = ts.cw[j];
-  }
-  for (int i = threadIdx.x; i < h; i += blockDim.x) {
-    rowchk[(r0 + i) + (2 * J) * ldr] = ts.res[i];
-    rowchk[(r0 + i) + (2 * J + 1) * ldr] = ts.rws[i];
-  }
-}
-
-// flags of every column / row of a tile against the carried checksums
-struct TileFlags {
-  double de[MAXNB], dw[MAXNB], he[MAXNB], hw[MAXNB];
-  unsigned char fe[MAXNB], fw[MAXNB], ge[MAXNB], gw[MAXNB];
-  int nflag;
-  double maxr;
-};
-
-__device__ void tile_compare(const TileSums& ts, TileFlags& tf, int I, int J, int nb, int h, int w,
-                             const double* colchk, int64_t ldc, const double* rowchk, int64_t ldr, const double* gc,
-                             const double* gr, double tsu) {
-  int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
-  if (threadIdx.x == 0) { tf.nflag = 0; tf.maxr = 0.0; }
-  __syncthreads();
-  int nfl = 0;
-  double mr = 0.0;
-  for (int j = threadIdx.x; j < w; j += blockDim.x) {
-    int64_t o = 2 * I + (c0 + j) * ldc;
-    double de = ts.ce[j] - colchk[o], dw = ts.cw[j] - colchk[o + 1];
-    double te = tau_verify(tsu, ts.ca[j], gc ? gc[o] : 0.0), tw = tau_verify(tsu, ts.cwa[j], gc ? gc[o + 1] : 0.0);
-    bool be = bad(de, te), bw = bad(dw, tw);
-    tf.de[j] = de; tf.dw[j] = dw; tf.fe[j] = be; tf.fw[j] = bw;
-    nfl += be + bw;
-    if (!be && te > 0) mr = fmax(mr, fabs(de) / te);
-    if (!bw && tw > 0) mr = fmax(mr, fabs(dw) / tw);
-  }
-  for (int i = threadIdx.x; i < h; i += blockDim.x) {
-    int64_t o = (r0 + i) + (2 * J) * ldr;
-    double de = ts.res[i] - rowchk[o], dw = ts.rws[i] - rowchk[o + ldr];
-    double te = tau_verify(tsu, ts.ra[i], gr ? gr[o] : 0.0), tw = tau_verify(tsu, ts.rwa[i], gr ? gr[o + ldr] : 0.0);
-    bool be = bad(de, te), bw = bad(dw, tw);
-    tf.he[i] = de; tf.hw[i] = dw; tf.ge[i] = be; tf.gw[i] = bw;
-    nfl += be + bw;
-    if (!be && te > 0) mr = fmax(mr, fabs(de) / te);
-    if (!bw && tw > 0) mr = fmax(mr, fabs(dw) / tw);
-  }
-  if (nfl) atomicAdd(&tf.nflag, nfl);
-  // max over the workgroup: wave max then one LDS atomic per wave (order-free)
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mr = fmax(mr, __shfl_xor(mr, o));
-  if ((threadIdx.x & 63) == 0 && mr > 0)
-    atomicMax(reinterpret_cast<unsigned long long*>(&tf.maxr), (unsigned long long)__double_as_longlong(mr));
-  __syncthreads();
-}
 
 // mode 0: encode (write sums); mode 1: verify (flag, refresh clean tiles);
 // mode 2: verify only
@@ -204,16 +52,6 @@ __global__ __launch_bounds__(256) void k_verify(const T* A, int64_t lda, int64_t
   }
 }
 
-__device__ __forceinline__ int ratio_index(double dw, double de, int len) {
-  if (!(de != 0.0)) return -1;
-  double r = dw / de;
-  if (!(fabs(r) <= 1.79e308)) return -1;
-  double k = floor(r + 0.5);
-  if (fabs(r - k) > 0.25) return -1;
-  if (k < 1.0 || k > (double)len) return -1;
-  return (int)k - 1;
-}
-
 // Locate and correct a flagged tile (one fault per tile per iteration).
 // Decision rules are those of the reference description: intersection of a
 // single flagged column and row; a single flagged line located by the ratio
@@ -227,111 +65,14 @@ __global__ __launch_bounds__(256) void k_correct(T* A, int64_t lda, int64_t nr, 
                                                  const int* tflags, abft_report* rep, int iter) {
   __shared__ TileSums ts;
   __shared__ TileFlags tf;
-  __shared__ int s_ci, s_cj, s_kind;
-  __shared__ double s_old;
+  __shared__ CorrState cs;
   int I, J, h, w;
   tile_geom(blockIdx.x, I0, J0, nI, nb, nr, nc, I, J, h, w);
   const int tile = I + J * (int)((nr + nb - 1) / nb);
   if (sym && I < J) return;
   if (!tflags[tile]) return;
-  const int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
-  const bool diag = sym && I == J;
-  tile_sums(A, lda, r0, c0, h, w, diag, ts);
-  tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu);
-  if (threadIdx.x == 0) {
-    int nFe = 0, nGe = 0, nFw = 0, nGw = 0, jf0 = -1, jf1 = -1, ig = -1;
-    for (int j = 0; j < w; ++j) {
-      if (tf.fe[j]) {
-        if (nFe == 0) jf0 = j; else if (nFe == 1) jf1 = j;
-        nFe++;
-      }
-      nFw += tf.fw[j];
-    }
-    for (int i = 0; i < h; ++i) {
-      if (tf.ge[i]) { ig = i; nGe++; }
-      nGw += tf.gw[i];
-    }
-    int ci = -1, cj = -1, repair = 0;
-    if (tf.nflag == 0) {
-      repair = -1;  // nothing left to do (flag raised by a concurrent writer)
-    } else if (diag) {
-      if (nFe == 1) {
-        int i = ratio_index(tf.dw[jf0], tf.de[jf0], h);
-        if (i == jf0) { ci = i; cj = i; }
-      } else if (nFe == 2) {
-        if (ratio_index(tf.dw[jf0], tf.de[jf0], h) == jf1 && ratio_index(tf.dw[jf1], tf.de[jf1], h) == jf0) {
-          ci = jf1; cj = jf0;
-        }
-      } else if (nFe == 0) {
-        repair = 1;
-      }
-    } else {
-      if (nFe == 1 && nGe == 1) {
-        ci = ig; cj = jf0;
-      } else if (nFe == 1 && nGe == 0) {
-        int i = ratio_index(tf.dw[jf0], tf.de[jf0], h);
-        if (i >= 0) { ci = i; cj = jf0; } else if (nGw == 0) repair = 1;
-      } else if (nFe == 0 && nGe == 1) {
-        int j = ratio_index(tf.hw[ig], tf.he[ig], w);
-        if (j >= 0) { ci = ig; cj = j; } else if (nFw == 0) repair = 1;
-      } else if (nFe == 0 && nGe == 0) {
-        repair = 1;
-      }
-    }
-    s_ci = ci; s_cj = cj;
-    s_kind = (repair == -1) ? 0 : (ci >= 0 ? 1 : (repair ? 2 : 3));
-  }
-  __syncthreads();
-  if (s_kind == 1) {
-    // recompute the element from the carried column-e checksum of column cj
-    const int ci = s_ci, cj = s_cj;
-    if (threadIdx.x < 64) {
-      acc2 s{0, 0};
-      for (int i = threadIdx.x; i < h; i += 64) {
-        if (i == ci) continue;
-        double v = (diag && i < cj) ? ld(A + (r0 + cj) + (c0 + i) * lda) : ld(A + (r0 + i) + (c0 + cj) * lda);
-        cadd(s, v);
-      }
-      s = wave_csum(s);
-      if (threadIdx.x == 0) {
-        double val = colchk[2 * I + (c0 + cj) * ldc] - cval(s);
-        T* p = A + (r0 + ci) + (c0 + cj) * lda;
-        s_old = ld(p);
-        *p = (T)val;
-      }
-    }
-    __syncthreads();
-    __threadfence_block();
-    tile_sums(A, lda, r0, c0, h, w, diag, ts);
-    tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu);
-    if (tf.nflag != 0) {
-      if (threadIdx.x == 0) {
-        A[(r0 + ci) + (c0 + cj) * lda] = (T)s_old;
-        s_kind = 3;
-      }
-      __syncthreads();
-      __threadfence_block();
-    }
-  }
-  if (s_kind == 0) return;
-  // refresh the tile's checksums from the (corrected) data
-  tile_sums(A, lda, r0, c0, h, w, diag, ts);
-  store_sums(ts, I, J, nb, h, w, colchk, ldc, rowchk, ldr);
-  if (threadIdx.x == 0 && rep) {
-    if (s_kind == 1) {
-      atomicAdd((unsigned long long*)&rep->corrected, 1ull);
-      atomicOr(&rep->status, (int)ABFT_ST_CORRECTED);
-      rep_event(rep, iter, 1, r0 + s_ci, c0 + s_cj);
-    } else if (s_kind == 2) {
-      atomicAdd((unsigned long long*)&rep->checksum_repaired, 1ull);
-      atomicOr(&rep->status, (int)ABFT_ST_REPAIRED);
-      rep_event(rep, iter, 2, r0, c0);
-    } else {
-      atomicAdd((unsigned long long*)&rep->uncorrectable, 1ull);
-      atomicOr(&rep->status, (int)ABFT_ST_UNCORRECTABLE);
-      rep_event(rep, iter, 3, r0, c0);
-    }
-  }
+  correct_tile_dev(A, lda, I, J, nb, h, w, sym && I == J, colchk, ldc, rowchk, ldr, gc, gr, tsu, rep, iter, ts, tf,
+                   cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -427,8 +168,9 @@ __global__ __launch_bounds__(256) void k_ysums(const T* Y, int64_t ldy, int64_t 
 // QR adds, for tile-row Ik, the e/w sums of R(:, j) (E[4*j + 0..3]) and for
 // every tile-row the backward-error allowance bt[j].
 // ---------------------------------------------------------------------------
+template <typename MT>
 __global__ __launch_bounds__(256) void k_panel_check(const double* S, const double* Sa, int ldS, int I0, int I1, int kw,
-                                                     const double* Mp, int64_t msp, int64_t msj, int tri, int pjoff,
+                                                     const MT* Mp, int64_t msp, int64_t msj, int tri, int pjoff,
                                                      double mscale, const double* Mabs, const double* E,
                                                      const double* bt, int Ik, const double* colchk, int64_t ldc,
                                                      int64_t cj0, int ncols, double tsu_p, abft_report* rep,
@@ -445,7 +187,7 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
     double ge = 0, gw = 0;
     int pmax = tri ? min(kw, j + pjoff + 1) : kw;
     for (int p = 0; p < pmax; ++p) {
-      double m = mscale * Mp[p * msp + j * msj];
+      double m = mscale * (double)Mp[p * msp + j * msj];
       double ma = Mabs ? Mabs[p * msp + j * msj] : fabs(m);
       cfma(xe, -S[2 * I + p * (int64_t)ldS], m);
       cfma(xw, -S[2 * I + 1 + p * (int64_t)ldS], m);
@@ -630,16 +372,23 @@ template int xsums<float>(hipStream_t, const float*, int64_t, int64_t, int, int,
 template int ysums<double>(hipStream_t, const double*, int64_t, int64_t, int, int, int, double*, double*, int, int);
 template int ysums<float>(hipStream_t, const float*, int64_t, int64_t, int, int, int, double*, double*, int, int);
 
-int panel_check(hipStream_t s, const double* S, const double* Sa, int ldS, int I0, int I1, int kw, const double* Mp,
+template <typename MT>
+int panel_check(hipStream_t s, const double* S, const double* Sa, int ldS, int I0, int I1, int kw, const MT* Mp,
                 int64_t msp, int64_t msj, int tri, int pjoff, double mscale, const double* Mabs, const double* E,
                 const double* bt, int Ik, const double* colchk, int64_t ldc, int64_t cj0, int ncols, double tsu_p,
                 abft_report* rep, int iter, int nb) {
   if (I1 <= I0 || ncols <= 0) return 0;
   dim3 grid((ncols + 255) / 256, I1 - I0);
-  hipLaunchKernelGGL(k_panel_check, grid, dim3(256), 0, s, S, Sa, ldS, I0, I1, kw, Mp, msp, msj, tri, pjoff, mscale,
-                     Mabs, E, bt, Ik, colchk, ldc, cj0, ncols, tsu_p, rep, iter, nb);
+  hipLaunchKernelGGL(k_panel_check<MT>, grid, dim3(256), 0, s, S, Sa, ldS, I0, I1, kw, Mp, msp, msj, tri, pjoff,
+                     mscale, Mabs, E, bt, Ik, colchk, ldc, cj0, ncols, tsu_p, rep, iter, nb);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
+template int panel_check<double>(hipStream_t, const double*, const double*, int, int, int, int, const double*, int64_t,
+                                 int64_t, int, int, double, const double*, const double*, const double*, int,
+                                 const double*, int64_t, int64_t, int, double, abft_report*, int, int);
+template int panel_check<float>(hipStream_t, const double*, const double*, int, int, int, int, const float*, int64_t,
+                                int64_t, int, int, double, const double*, const double*, const double*, int,
+                                const double*, int64_t, int64_t, int, double, abft_report*, int, int);
 
 int qr_check_prep(hipStream_t s, const double* A, int64_t lda, int64_t c0, int w, int64_t m, const double* T, int ldt,
                   double* scratch, double* Z, double* Zabs, double* E, double* bt) {

@@ -21,6 +21,9 @@ struct abft_handle_s {
   hipStream_t stream;
   int device;
   int cus;
+  abft_profile prof;
+  hipEvent_t* ev;  // event pool for profiled calls
+  int nev;
 };
 
 namespace {
@@ -37,6 +40,59 @@ constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
   } while (0)
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Phase timer of profiled calls: event pairs recorded on the stream, summed
+// per phase after one synchronisation at the end of the call.
+enum { PH_PANEL = 0, PH_TMU = 1, PH_CARRY = 2, PH_VERIFY = 3, PH_N = 4 };
+struct Prof {
+  abft_handle h;
+  bool on;
+  int used;
+  int tags[8192];
+  double tmu_flops = 0, verify_bytes = 0;
+  int tmu_launches = 0, iters = 0;
+  explicit Prof(abft_handle hh, const abft_opts* o) : h(hh), on(o && (o->flags & ABFT_FLAG_PROFILE)), used(0) {
+    if (!on) return;
+    if (!h->ev) {
+      h->nev = 8192;
+      h->ev = (hipEvent_t*)calloc(h->nev, sizeof(hipEvent_t));
+      for (int i = 0; i < h->nev; ++i) (void)hipEventCreate(&h->ev[i]);
+    }
+  }
+  int begin(int tag) {
+    if (!on || used + 2 > h->nev) return -1;
+    int i = used;
+    used += 2;
+    tags[i / 2] = tag;
+    (void)hipEventRecord(h->ev[i], h->stream);
+    return i;
+  }
+  void end(int i) {
+    if (i >= 0) (void)hipEventRecord(h->ev[i + 1], h->stream);
+  }
+  void finish() {
+    if (!on) return;
+    abft_profile p;
+    memset(&p, 0, sizeof(p));
+    if (used) {
+      (void)hipEventSynchronize(h->ev[used - 1]);
+      float ms;
+      double ph[PH_N] = {0, 0, 0, 0};
+      for (int i = 0; i < used; i += 2)
+        if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) ph[tags[i / 2]] += ms;
+      if (hipEventElapsedTime(&ms, h->ev[0], h->ev[used - 1]) == hipSuccess) p.ms_total = ms;
+      p.ms_panel = ph[PH_PANEL];
+      p.ms_tmu = ph[PH_TMU];
+      p.ms_carry = ph[PH_CARRY];
+      p.ms_verify = ph[PH_VERIFY];
+    }
+    p.tmu_flops = tmu_flops;
+    p.verify_bytes = verify_bytes;
+    p.tmu_launches = tmu_launches;
+    p.iters = iters;
+    h->prof = p;
+  }
+};
 
 // Workspace carve-up shared by the three factorizations.
 struct Ws {
@@ -127,10 +183,30 @@ int apply_faults(hipStream_t s, const abft_opts* o, int iter, T* A, int64_t lda,
 }
 
 // ----------------------------------------------------------------- panels
+// GEMM on the data type of the factorization: FP64 MFMA for double data;
+// for binary32 data FP32 MFMA, or bf16 / fp16 products with FP32
+// accumulation when prec asks for them (trailing update only).
+inline int gemmT(hipStream_t s, int prec, int ta, int tb, int lower, int m, int n, int k, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                 int64_t doff) {
+  (void)prec;
+  return gemm64(s, ta, tb, 0, 0, lower, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, doff);
+}
+inline int gemmT(hipStream_t s, int prec, int ta, int tb, int lower, int m, int n, int k, double alpha,
+                 const float* A, int64_t lda, const float* B, int64_t ldb, double beta, float* C, int64_t ldc,
+                 int64_t doff) {
+  return gemm32(s, prec, ta, tb, lower, m, n, k, (float)alpha, A, lda, B, ldb, (float)beta, C, ldc, doff);
+}
+template <typename T>
+constexpr int panel_prec() {
+  return sizeof(T) == 8 ? ABFT_F64 : ABFT_F32;
+}
+
 // Cholesky panel, columns [c0, c1), rows [c0, n): recursive halves; the
 // right half is updated by the left half's columns with the lower-masked
 // MFMA GEMM.
-int chol_panel(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t c0, int64_t c1, int32_t* info) {
+template <typename T>
+int chol_panel(hipStream_t s, T* A, int64_t lda, int64_t n, int64_t c0, int64_t c1, int32_t* info) {
   const int w = (int)(c1 - c0);
   if (w <= LEAFW) {
     TRY(potrf_leaf(s, A, lda, c0, w, info));
@@ -139,26 +215,28 @@ int chol_panel(hipStream_t s, double* A, int64_t lda, int64_t n, int64_t c0, int
   const int h = split(w);
   TRY(chol_panel(s, A, lda, n, c0, c0 + h, info));
   const int64_t r = c0 + h;
-  TRY(gemm64(s, 0, 1, 0, 0, 1, (int)(n - r), (int)(c1 - r), h, -1.0, A + r + c0 * lda, lda, A + r + c0 * lda, lda,
-             1.0, A + r + r * lda, lda, 0));
+  TRY(gemmT(s, panel_prec<T>(), 0, 1, 1, (int)(n - r), (int)(c1 - r), h, -1.0, A + r + c0 * lda, lda,
+            A + r + c0 * lda, lda, 1.0, A + r + r * lda, lda, 0));
   return chol_panel(s, A, lda, n, r, c1, info);
 }
 
 // X = L^{-1} B: L unit lower at (c0, c0) of order w, B = rows [c0, c0+w) of
 // columns [j0, j1).
-int trsm_llu(hipStream_t s, double* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1) {
+template <typename T>
+int trsm_llu(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1) {
   if (j1 <= j0) return 0;
   if (w <= LEAFW) return trsm_llu_leaf(s, A, lda, c0, w, j0, j1);
   const int h = split(w);
   TRY(trsm_llu(s, A, lda, c0, h, j0, j1));
-  TRY(gemm64(s, 0, 0, 0, 0, 0, w - h, (int)(j1 - j0), h, -1.0, A + (c0 + h) + c0 * lda, lda, A + c0 + j0 * lda, lda,
-             1.0, A + (c0 + h) + j0 * lda, lda, 0));
+  TRY(gemmT(s, panel_prec<T>(), 0, 0, 0, w - h, (int)(j1 - j0), h, -1.0, A + (c0 + h) + c0 * lda, lda,
+            A + c0 + j0 * lda, lda, 1.0, A + (c0 + h) + j0 * lda, lda, 0));
   return trsm_llu(s, A, lda, c0 + h, w - h, j0, j1);
 }
 
+template <typename T>
 struct LuCtx {
   hipStream_t s;
-  double* A;
+  T* A;
   int64_t lda, n;
   int32_t *ipiv, *info;
   const Ws* w;
@@ -168,21 +246,22 @@ struct LuCtx {
 };
 
 // LU panel, columns [c0, c1), rows [c0, n) (recursive, LAPACK getrf2 order)
-int lu_panel(LuCtx& c, int64_t c0, int64_t c1) {
+template <typename T>
+int lu_panel(LuCtx<T>& c, int64_t c0, int64_t c1) {
   const int w = (int)(c1 - c0);
   if (w <= LEAFW)
     return getrf_leaf(c.s, c.A, c.lda, c.n, c0, w, c.ipiv, c.info, c.w->slots, c.w->ctr, &c.ctr_base, c.rep, c.maxg);
   const int h = split(w);
   TRY(lu_panel(c, c0, c0 + h));
   TRY(perm_build(c.s, c.ipiv, c0, h, c.w->moves));
-  TRY(laswp(c.s, c.A, c.lda, c0 + h, c1, c.w->moves, (double*)c.w->stage, (double*)nullptr, 0, 1));
+  TRY(laswp(c.s, c.A, c.lda, c0 + h, c1, c.w->moves, (T*)c.w->stage, (double*)nullptr, 0, 1));
   TRY(trsm_llu(c.s, c.A, c.lda, c0, h, c0 + h, c1));
   const int64_t r = c0 + h;
-  TRY(gemm64(c.s, 0, 0, 0, 0, 0, (int)(c.n - r), (int)(c1 - r), h, -1.0, c.A + r + c0 * c.lda, c.lda,
-             c.A + c0 + r * c.lda, c.lda, 1.0, c.A + r + r * c.lda, c.lda, 0));
+  TRY(gemmT(c.s, panel_prec<T>(), 0, 0, 0, (int)(c.n - r), (int)(c1 - r), h, -1.0, c.A + r + c0 * c.lda, c.lda,
+            c.A + c0 + r * c.lda, c.lda, 1.0, c.A + r + r * c.lda, c.lda, 0));
   TRY(lu_panel(c, r, c1));
   TRY(perm_build(c.s, c.ipiv, r, w - h, c.w->moves));
-  return laswp(c.s, c.A, c.lda, c0, r, c.w->moves, (double*)c.w->stage, (double*)nullptr, 0, 1);
+  return laswp(c.s, c.A, c.lda, c0, r, c.w->moves, (T*)c.w->stage, (double*)nullptr, 0, 1);
 }
 
 struct QrCtx {
@@ -238,24 +317,333 @@ int qr_panel(QrCtx& c, int64_t c0, int64_t c1) {
 // Y(p,j) = Yp[p + j*ldy] (ty = 0) or Yp[j + p*ldy] (ty = 1) for columns
 // [yc0, n); the row-side matrices are Tm / Ta (nb x 2N) or, with tS = 1,
 // the transposes of S / Sa (symmetric update, Y = X^T).
-int carry(hipStream_t s, const Ws& w, int64_t n, int nb, int I0, int J0, int kw, const double* Xp, int64_t ldx,
-          int64_t xr0, int fx, const double* Yp, int64_t ldy, int ty, int64_t yc0, int tS) {
+template <typename T>
+int carry(hipStream_t s, const Ws& w, int64_t n, int nb, int I0, int J0, int kw, const T* Xp, int64_t ldx,
+          int64_t xr0, int fx, const T* Yp, int64_t ldy, int ty, int64_t yc0, int tS, int rnd = 0) {
   const int N = (int)((n + nb - 1) / nb);
   const int ldS = 2 * N;
+  const int isf = sizeof(T) == 4;
   const int mr = 2 * (N - I0), ncol = (int)(n - yc0);
   // column side
   TRY(gemm64(s, 0, ty, 0, 0, 0, mr, ncol, kw, -1.0, w.S + 2 * I0, ldS, Yp, ldy, 1.0, w.colchk + 2 * I0 + yc0 * ldS,
-             ldS, 0));
+             ldS, 0, 0, isf, rnd));
   TRY(gemm64(s, 0, ty, 0, 2, 0, mr, ncol, kw, 1.0, w.Sa + 2 * I0, ldS, Yp, ldy, 0.0, w.gc + 2 * I0 + yc0 * ldS, ldS,
-             0));
+             0, 0, isf, rnd));
   // row side
   const int nr = (int)(n - xr0), mc = 2 * (N - J0);
   const double* Bm = tS ? w.S + 2 * J0 : w.Tm + (int64_t)2 * J0 * nb;
   const double* Ba = tS ? w.Sa + 2 * J0 : w.Ta + (int64_t)2 * J0 * nb;
   const int64_t ldb = tS ? ldS : nb;
-  TRY(gemm64(s, 0, tS, fx, 0, 0, nr, mc, kw, -1.0, Xp, ldx, Bm, ldb, 1.0, w.rowchk + xr0 + (int64_t)2 * J0 * n, n, 0));
+  TRY(gemm64(s, 0, tS, fx, 0, 0, nr, mc, kw, -1.0, Xp, ldx, Bm, ldb, 1.0, w.rowchk + xr0 + (int64_t)2 * J0 * n, n, 0,
+             isf, 0, rnd));
   return gemm64(s, 0, tS, fx == 1 ? 3 : 2, 0, 0, nr, mc, kw, 1.0, Xp, ldx, Ba, ldb, 0.0,
-                w.gr + xr0 + (int64_t)2 * J0 * n, n, 0);
+                w.gr + xr0 + (int64_t)2 * J0 * n, n, 0, isf, 0, rnd);
+}
+
+
+inline int op_rnd(int prec) { return prec == ABFT_BF16 ? 1 : (prec == ABFT_F16 ? 2 : 0); }
+
+// Blocked right-looking Cholesky (lower) with per-tile full checksums.
+// T = double (prec ABFT_F64) or float (ABFT_F32 / ABFT_BF16 / ABFT_F16).
+template <typename T>
+int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const abft_opts* opts, int nb, int protect,
+               double ts, int prec, int32_t* dinfo, abft_report* drep) {
+  hipStream_t s = h->stream;
+  TRY(report_init(s, drep, dinfo));
+  if (n == 0) return report_fini(s, drep);
+  const int N = (int)((n + nb - 1) / nb);
+  const int ldc = 2 * N;
+  const double u = sizeof(T) == 8 ? U64 : U32;
+  const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
+  const int rnd = op_rnd(prec);
+  Prof pf(h, opts);
+  int t = pf.begin(PH_VERIFY);
+  if (protect)
+    TRY(verify_tiles<T>(s, dA, lda, n, n, nb, 0, 0, 1, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
+                        nullptr, -1));
+  pf.end(t);
+  for (int k = 0; k < N; ++k) {
+    const int64_t c0 = (int64_t)k * nb;
+    const int kw = (int)std::min<int64_t>(nb, n - c0);
+    const int64_t c1 = c0 + kw;
+    pf.iters++;
+    t = pf.begin(PH_PANEL);
+    TRY(chol_panel(s, dA, lda, n, c0, c1, dinfo));
+    if (protect) {
+      TRY(xsums<T>(s, dA, lda, n, nb, k, c0, kw, k, 1, w.S, w.Sa, ldc, 0));
+      // e^T A_Ik = (e^T L_I) L_kk^T:  M(p, j) = L(c0 + j, c0 + p), p <= j
+      TRY(panel_check<T>(s, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, lda, 1, 1, 0, 1.0, nullptr, nullptr, nullptr,
+                         -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb));
+    }
+    pf.end(t);
+    if (c1 >= n) break;
+    const int64_t m = n - c1;
+    T* L21 = dA + c1 + c0 * lda;
+    t = pf.begin(PH_TMU);
+    TRY(gemmT(s, prec, 0, 1, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0));
+    pf.end(t);
+    pf.tmu_flops += (double)m * (double)(m + 1) * kw;
+    pf.tmu_launches++;
+    if (protect) {
+      t = pf.begin(PH_CARRY);
+      if (rnd) TRY(xsums<T>(s, dA, lda, n, nb, k + 1, c0, kw, k, 1, w.S, w.Sa, ldc, rnd));
+      TRY(carry<T>(s, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, L21, lda, 1, c1, 1, rnd));
+      pf.end(t);
+    }
+    if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N));
+    if (protect) {
+      t = pf.begin(PH_VERIFY);
+      TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                          w.tflags, drep, k));
+      TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                           w.tflags, drep, k));
+      pf.end(t);
+      const double mt = (double)m / nb;
+      pf.verify_bytes += (double)sizeof(T) * nb * nb * (mt * (mt + 1) / 2);
+    }
+  }
+  TRY(report_fini(s, drep));
+  pf.finish();
+  return 0;
+}
+
+// Blocked right-looking LU with partial pivoting and per-tile full checksums.
+template <typename T>
+int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, const Ws& w, const abft_opts* opts,
+               int nb, int protect, double ts, int prec, int32_t* dinfo, abft_report* drep) {
+  hipStream_t s = h->stream;
+  TRY(report_init(s, drep, dinfo));
+  if (n == 0) return report_fini(s, drep);
+  TRY(fill_zero(s, w.ctr, 256));
+  const int N = (int)((n + nb - 1) / nb);
+  const int ldc = 2 * N;
+  const double u = sizeof(T) == 8 ? U64 : U32;
+  const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
+  const int rnd = op_rnd(prec);
+  Prof pf(h, opts);
+  int t = pf.begin(PH_VERIFY);
+  if (protect)
+    TRY(verify_tiles<T>(s, dA, lda, n, n, nb, 0, 0, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
+                        nullptr, -1));
+  pf.end(t);
+  LuCtx<T> c{s, dA, lda, n, dipiv, dinfo, &w, 0u, drep, std::min(h->cus, 256)};
+  T* porig = (T*)w.porig;
+  T* stage = (T*)w.stage;
+  for (int k = 0; k < N; ++k) {
+    const int64_t c0 = (int64_t)k * nb;
+    const int kw = (int)std::min<int64_t>(nb, n - c0);
+    const int64_t c1 = c0 + kw;
+    pf.iters++;
+    t = pf.begin(PH_PANEL);
+    if (protect)
+      if (hipMemcpy2DAsync(porig, n * sizeof(T), dA + c0 + c0 * lda, lda * sizeof(T), (n - c0) * sizeof(T), kw,
+                           hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return ABFT_ERR_HIP;
+    TRY(lu_panel(c, c0, c1));
+    TRY(perm_build(s, dipiv, c0, kw, w.moves));
+    TRY(laswp(s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
+    TRY(laswp(s, dA, lda, c1, n, w.moves, stage, protect ? w.colchk : (double*)nullptr, ldc, nb));
+    if (protect) {
+      // column checksums of the panel follow the interchanges of the original panel values
+      TRY(laswp(s, porig - c0, n, 0, kw, w.moves, stage, w.colchk + c0 * ldc, ldc, nb));
+      TRY(laswp(s, w.rowchk, n, 0, 2 * N, w.moves, (double*)w.stage, (double*)nullptr, 0, nb));
+      TRY(xsums<T>(s, dA, lda, n, nb, k, c0, kw, k, 2, w.S, w.Sa, ldc, 0));
+      // e^T (P A)_I = (e^T L_I) U_kk
+      TRY(panel_check<T>(s, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, 1, lda, 1, 0, 1.0, nullptr, nullptr, nullptr,
+                         -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb));
+    }
+    if (c1 >= n) {
+      pf.end(t);
+      break;
+    }
+    TRY(trsm_llu(s, dA, lda, c0, kw, c1, n));
+    if (protect)  // (e^T L_kk) U12 = e^T A12 on tile-row k
+      TRY(panel_check<T>(s, w.S, w.Sa, ldc, k, k + 1, kw, dA + c0 + c1 * lda, 1, lda, 0, 0, 1.0, nullptr, nullptr,
+                         nullptr, -1, w.colchk, ldc, c1, (int)(n - c1), tsu_p, drep, k, nb));
+    pf.end(t);
+    const int64_t m = n - c1;
+    T* L21 = dA + c1 + c0 * lda;
+    T* U12 = dA + c0 + c1 * lda;
+    t = pf.begin(PH_TMU);
+    TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0));
+    pf.end(t);
+    pf.tmu_flops += 2.0 * (double)m * (double)m * kw;
+    pf.tmu_launches++;
+    if (protect) {
+      t = pf.begin(PH_CARRY);
+      if (rnd) TRY(xsums<T>(s, dA, lda, n, nb, k + 1, c0, kw, k, 2, w.S, w.Sa, ldc, rnd));
+      TRY(ysums<T>(s, dA + c0, lda, n, nb, k + 1, kw, w.Tm, w.Ta, nb, rnd));
+      TRY(carry<T>(s, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, U12, lda, 0, c1, 0, rnd));
+      pf.end(t);
+    }
+    if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N));
+    if (protect) {
+      t = pf.begin(PH_VERIFY);
+      TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                          w.tflags, drep, k));
+      TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                           w.tflags, drep, k));
+      pf.end(t);
+      pf.verify_bytes += (double)sizeof(T) * (double)m * (double)m;
+    }
+  }
+  TRY(report_fini(s, drep));
+  pf.finish();
+  return 0;
+}
+
+
+// ------------------------------------------------------------ mixed precision
+// Extra workspace of the mixed-precision solve, after the factorization's.
+struct MpWs {
+  void* F;          // factor copy (float, or double for the FP64 reference)
+  int32_t *ipiv, *perm, *info, *ready;
+  unsigned* counter;
+  double *r, *xd, *part, *norms;
+  float* d32;
+  size_t bytes;
+};
+constexpr int NSPLIT = 32;
+
+MpWs carve_mp(char* base, size_t off, int64_t n, int elem) {
+  MpWs m;
+  memset(&m, 0, sizeof(m));
+  auto take = [&](size_t b) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += al(b);
+    return p;
+  };
+  m.F = take((size_t)n * n * elem);
+  m.ipiv = (int32_t*)take((size_t)n * 4);
+  m.perm = (int32_t*)take((size_t)n * 4);
+  m.info = (int32_t*)take(256);
+  m.counter = (unsigned*)take(256);
+  m.ready = (int32_t*)take((size_t)(n / 64 + 2) * 4);
+  m.r = (double*)take((size_t)n * 8);
+  m.xd = (double*)take((size_t)n * 8);
+  m.part = (double*)take((size_t)NSPLIT * n * 8);
+  m.norms = (double*)take(256);
+  m.d32 = (float*)take((size_t)n * 4);
+  m.bytes = off;
+  return m;
+}
+
+int read_norms(hipStream_t s, const double* dn, double* hn, int cnt) {
+  if (hipMemcpyAsync(hn, dn, cnt * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return ABFT_ERR_HIP;
+  return hipStreamSynchronize(s) == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
+// x := M^{-1} P x for the factor of the solve (float or double data)
+template <typename T>
+int solve_factor(hipStream_t s, const T* F, int64_t n, const int* perm, int chol, T* x, const MpWs& m,
+                 abft_report* rep) {
+  (void)perm;
+  TRY(trsv<T>(s, F, n, (int)n, chol ? 2 : 0, x, m.counter, m.ready, rep));
+  return trsv<T>(s, F, n, (int)n, chol ? 3 : 1, x, m.counter, m.ready, rep);
+}
+
+int gesv_mp_impl(abft_handle h, int64_t n, const double* dA, int64_t lda, const double* db, double* dx, int prec,
+                 int max_iter, void* dwork, size_t work_bytes, const abft_opts* opts, abft_ir_report* dir,
+                 abft_report* drep, int chol) {
+  if (!h) return -1;
+  if (n < 0) return -2;
+  if (!dA && n > 0) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  if (!db && n > 0) return -5;
+  if (!dx && n > 0) return -6;
+  if (prec < ABFT_F64 || prec > ABFT_F16) return -7;
+  if (max_iter < 0) return -8;
+  int nb, protect;
+  double ts;
+  TRY(check_opts(opts, n, nb, protect, ts));
+  if (n > 40000) return ABFT_ERR_UNSUPPORTED;
+  hipStream_t s = h->stream;
+  const int elem = prec == ABFT_F64 ? 8 : 4;
+  Ws w = carve((char*)dwork, n, nb, chol ? ABFT_OP_POTRF : ABFT_OP_GETRF, elem);
+  MpWs m = carve_mp((char*)dwork, w.bytes, n, elem);
+  if (!dwork || work_bytes < m.bytes) return ABFT_ERR_WORKSPACE;
+  abft_ir_report ir;
+  memset(&ir, 0, sizeof(ir));
+  auto finish = [&]() -> int {
+    if (dir && hipMemcpyAsync(dir, &ir, sizeof(ir), hipMemcpyHostToDevice, s) != hipSuccess) return ABFT_ERR_HIP;
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : ABFT_ERR_HIP;
+  };
+  if (n == 0) {
+    TRY(report_init(s, drep, m.info));
+    TRY(report_fini(s, drep));
+    ir.converged = 1;
+    return finish();
+  }
+  const int ni = (int)n;
+  double hn[8];
+  // factorization of a working copy
+  if (prec == ABFT_F64) {
+    if (hipMemcpy2DAsync(m.F, n * 8, dA, lda * 8, n * 8, n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return ABFT_ERR_HIP;
+    if (chol) TRY(potrf_impl<double>(h, n, (double*)m.F, n, w, opts, nb, protect, ts, prec, m.info, drep));
+    else TRY(getrf_impl<double>(h, n, (double*)m.F, n, m.ipiv, w, opts, nb, protect, ts, prec, m.info, drep));
+  } else {
+    TRY(convert_f64_f32(s, dA, lda, (float*)m.F, n, n, n));
+    if (chol) TRY(potrf_impl<float>(h, n, (float*)m.F, n, w, opts, nb, protect, ts, prec, m.info, drep));
+    else TRY(getrf_impl<float>(h, n, (float*)m.F, n, m.ipiv, w, opts, nb, protect, ts, prec, m.info, drep));
+  }
+  TRY(fill_zero(s, m.norms, 64));
+  TRY(anorm(s, dA, lda, ni, m.norms));
+  if (hipMemcpyAsync(&ir.info, m.info, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return ABFT_ERR_HIP;
+  TRY(read_norms(s, m.norms, hn, 8));
+  ir.a_norm = hn[4];
+  if (ir.info != 0) {
+    ir.failed_reason = 4;
+    return finish();
+  }
+  const int* perm = nullptr;
+  if (!chol) {
+    TRY(perm_vector(s, m.ipiv, ni, m.perm));
+    perm = m.perm;
+  }
+  const double u = U64;
+  if (prec == ABFT_F64) {
+    // direct FP64 solve (reference method)
+    TRY(gather64(s, db, perm, m.xd, ni));
+    TRY(solve_factor<double>(s, (const double*)m.F, n, perm, chol, m.xd, m, drep));
+    TRY(copy_f64(s, m.xd, dx, ni));
+    TRY(fill_zero(s, m.norms, 32));
+    TRY(residual(s, dA, lda, ni, dx, db, m.r, m.part, NSPLIT, m.norms));
+    TRY(read_norms(s, m.norms, hn, 2));
+    ir.resid_norm = hn[0];
+    ir.x_norm = hn[1];
+    ir.converged = 1;
+    return finish();
+  }
+  // x0 from the low-precision factors
+  TRY(gather_scale(s, db, perm, 1.0, m.d32, ni));
+  TRY(solve_factor<float>(s, (const float*)m.F, n, perm, chol, m.d32, m, drep));
+  TRY(f32_to_f64(s, m.d32, dx, ni));
+  double prev = INFINITY;
+  for (int it = 1; it <= max_iter; ++it) {
+    TRY(fill_zero(s, m.norms, 32));
+    TRY(residual(s, dA, lda, ni, dx, db, m.r, m.part, NSPLIT, m.norms));
+    TRY(read_norms(s, m.norms, hn, 2));
+    const double rn = hn[0], xn = hn[1];
+    ir.resid_norm = rn;
+    ir.x_norm = xn;
+    if (!(rn <= 1.79e308) || !(xn <= 1.79e308)) { ir.failed_reason = 2; break; }
+    if (rn <= u * ir.a_norm * xn) { ir.converged = 1; break; }
+    const double sc = rn > 0 ? rn : 1.0;
+    TRY(gather_scale(s, m.r, perm, 1.0 / sc, m.d32, ni));
+    TRY(solve_factor<float>(s, (const float*)m.F, n, perm, chol, m.d32, m, drep));
+    TRY(update_x(s, dx, m.d32, sc, ni, m.norms));
+    TRY(read_norms(s, m.norms, hn, 4));
+    const double dn = hn[2], xn2 = hn[3];
+    ir.last_dx = dn;
+    ir.iters = it;
+    if (!(dn <= 1.79e308)) { ir.failed_reason = 2; break; }
+    if (dn <= u * xn2) { ir.converged = 1; break; }
+    if (it >= 2 && dn > 0.5 * prev && dn > 1e3 * u * xn2) { ir.failed_reason = 1; break; }
+    prev = dn;
+  }
+  if (!ir.converged && !ir.failed_reason) ir.failed_reason = 3;
+  return finish();
 }
 
 }  // namespace
@@ -278,6 +666,10 @@ int abft_create(abft_handle* h, void* stream) {
 }
 
 int abft_destroy(abft_handle h) {
+  if (h && h->ev) {
+    for (int i = 0; i < h->nev; ++i) (void)hipEventDestroy(h->ev[i]);
+    free(h->ev);
+  }
   free(h);
   return 0;
 }
@@ -285,6 +677,13 @@ int abft_destroy(abft_handle h) {
 int abft_set_stream(abft_handle h, void* stream) {
   if (!h) return -1;
   h->stream = (hipStream_t)stream;
+  return 0;
+}
+
+int abft_get_profile(abft_handle h, abft_profile* out) {
+  if (!h) return -1;
+  if (!out) return -2;
+  *out = h->prof;
   return 0;
 }
 
@@ -296,6 +695,17 @@ int abft_workspace_size(abft_handle h, int op, int64_t n, int32_t batch, const a
   int nb, protect;
   double ts;
   TRY(check_opts(opts, n, nb, protect, ts));
+  if (op == ABFT_OP_POTRF_BATCHED || op == ABFT_OP_GETRF_BATCHED) {
+    if (batch < 0) return -4;
+    *bytes = batched_ws_bytes(batch);
+    return 0;
+  }
+  if (op == ABFT_OP_GESV_MP || op == ABFT_OP_POSV_MP) {
+    // sized for the largest precision (the FP64 reference solve)
+    Ws w = carve(nullptr, n, nb, op == ABFT_OP_POSV_MP ? ABFT_OP_POTRF : ABFT_OP_GETRF, sizeof(double));
+    *bytes = carve_mp(nullptr, w.bytes, n, sizeof(double)).bytes;
+    return 0;
+  }
   if (op < ABFT_OP_POTRF || op > ABFT_OP_GEQRF) return ABFT_ERR_UNSUPPORTED;
   Ws w = carve(nullptr, n, nb, op, sizeof(double));
   *bytes = w.bytes;
@@ -312,42 +722,9 @@ int abft_potrf(abft_handle h, int64_t n, double* dA, int64_t lda, void* dwork, s
   double ts;
   TRY(check_opts(opts, n, nb, protect, ts));
   if (!dinfo) return -8;
-  hipStream_t s = h->stream;
   Ws w = carve((char*)dwork, n, nb, ABFT_OP_POTRF, sizeof(double));
   if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
-  TRY(report_init(s, drep, dinfo));
-  if (n == 0) return report_fini(s, drep);
-  const int N = (int)((n + nb - 1) / nb);
-  const int ldc = 2 * N;
-  const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);
-  if (protect)
-    TRY(verify_tiles<double>(s, dA, lda, n, n, nb, 0, 0, 1, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu,
-                             nullptr, nullptr, -1));
-  for (int k = 0; k < N; ++k) {
-    const int64_t c0 = (int64_t)k * nb;
-    const int kw = (int)std::min<int64_t>(nb, n - c0);
-    const int64_t c1 = c0 + kw;
-    TRY(chol_panel(s, dA, lda, n, c0, c1, dinfo));
-    if (protect) {
-      TRY(xsums<double>(s, dA, lda, n, nb, k, c0, kw, k, 1, w.S, w.Sa, ldc, 0));
-      // e^T A_Ik = (e^T L_I) L_kk^T:  M(p, j) = L(c0 + j, c0 + p), p <= j
-      TRY(panel_check(s, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, lda, 1, 1, 0, 1.0, nullptr, nullptr, nullptr, -1,
-                      w.colchk, ldc, c0, kw, tsu_p, drep, k, nb));
-    }
-    if (c1 >= n) break;
-    const int64_t m = n - c1;
-    double* L21 = dA + c1 + c0 * lda;
-    TRY(gemm64(s, 0, 1, 0, 0, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0));
-    if (protect) TRY(carry(s, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, L21, lda, 1, c1, 1));
-    if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N));
-    if (protect) {
-      TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                               w.tflags, drep, k));
-      TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                                w.tflags, drep, k));
-    }
-  }
-  return report_fini(s, drep);
+  return potrf_impl<double>(h, n, dA, lda, w, opts, nb, protect, ts, ABFT_F64, dinfo, drep);
 }
 
 int abft_getrf(abft_handle h, int64_t n, double* dA, int64_t lda, int32_t* dipiv, void* dwork, size_t work_bytes,
@@ -361,63 +738,9 @@ int abft_getrf(abft_handle h, int64_t n, double* dA, int64_t lda, int32_t* dipiv
   double ts;
   TRY(check_opts(opts, n, nb, protect, ts));
   if (!dinfo) return -9;
-  hipStream_t s = h->stream;
   Ws w = carve((char*)dwork, n, nb, ABFT_OP_GETRF, sizeof(double));
   if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
-  TRY(report_init(s, drep, dinfo));
-  if (n == 0) return report_fini(s, drep);
-  TRY(fill_zero(s, w.ctr, 256));
-  const int N = (int)((n + nb - 1) / nb);
-  const int ldc = 2 * N;
-  const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);
-  if (protect)
-    TRY(verify_tiles<double>(s, dA, lda, n, n, nb, 0, 0, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu,
-                             nullptr, nullptr, -1));
-  LuCtx c{s, dA, lda, n, dipiv, dinfo, &w, 0u, drep, std::min(h->cus, 256)};
-  double* porig = w.porig;
-  for (int k = 0; k < N; ++k) {
-    const int64_t c0 = (int64_t)k * nb;
-    const int kw = (int)std::min<int64_t>(nb, n - c0);
-    const int64_t c1 = c0 + kw;
-    if (protect)
-      if (hipMemcpy2DAsync(porig, n * sizeof(double), dA + c0 + c0 * lda, lda * sizeof(double),
-                           (n - c0) * sizeof(double), kw, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return ABFT_ERR_HIP;
-    TRY(lu_panel(c, c0, c1));
-    TRY(perm_build(s, dipiv, c0, kw, w.moves));
-    TRY(laswp(s, dA, lda, 0, c0, w.moves, w.stage, (double*)nullptr, 0, nb));
-    TRY(laswp(s, dA, lda, c1, n, w.moves, w.stage, protect ? w.colchk : (double*)nullptr, ldc, nb));
-    if (protect) {
-      // column checksums of the panel follow the interchanges of the original panel values
-      TRY(laswp(s, porig - c0, n, 0, kw, w.moves, w.stage, w.colchk + c0 * ldc, ldc, nb));
-      TRY(laswp(s, w.rowchk, n, 0, 2 * N, w.moves, w.stage, (double*)nullptr, 0, nb));
-      TRY(xsums<double>(s, dA, lda, n, nb, k, c0, kw, k, 2, w.S, w.Sa, ldc, 0));
-      // e^T (P A)_I = (e^T L_I) U_kk
-      TRY(panel_check(s, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, 1, lda, 1, 0, 1.0, nullptr, nullptr, nullptr, -1,
-                      w.colchk, ldc, c0, kw, tsu_p, drep, k, nb));
-    }
-    if (c1 >= n) break;
-    TRY(trsm_llu(s, dA, lda, c0, kw, c1, n));
-    if (protect)  // (e^T L_kk) U12 = e^T A12 on tile-row k
-      TRY(panel_check(s, w.S, w.Sa, ldc, k, k + 1, kw, dA + c0 + c1 * lda, 1, lda, 0, 0, 1.0, nullptr, nullptr, nullptr,
-                      -1, w.colchk, ldc, c1, (int)(n - c1), tsu_p, drep, k, nb));
-    const int64_t m = n - c1;
-    double* L21 = dA + c1 + c0 * lda;
-    double* U12 = dA + c0 + c1 * lda;
-    TRY(gemm64(s, 0, 0, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0));
-    if (protect) {
-      TRY(ysums<double>(s, dA + c0, lda, n, nb, k + 1, kw, w.Tm, w.Ta, nb, 0));
-      TRY(carry(s, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, U12, lda, 0, c1, 0));
-    }
-    if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N));
-    if (protect) {
-      TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                               w.tflags, drep, k));
-      TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                                w.tflags, drep, k));
-    }
-  }
-  return report_fini(s, drep);
+  return getrf_impl<double>(h, n, dA, lda, dipiv, w, opts, nb, protect, ts, ABFT_F64, dinfo, drep);
 }
 
 int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, void* dwork, size_t work_bytes,
@@ -444,11 +767,15 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     TRY(verify_tiles<double>(s, dA, lda, n, n, nb, 0, 0, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu,
                              nullptr, nullptr, -1));
   QrCtx c{s, dA, lda, n, dtau, &w, nb, 0, 0u, drep, std::min(h->cus, 256)};
+  Prof pf(h, opts);
+  int t;
   for (int k = 0; k < N; ++k) {
     const int64_t c0 = (int64_t)k * nb;
     const int kw = (int)std::min<int64_t>(nb, n - c0);
     const int64_t c1 = c0 + kw;
     c.cb = c0;
+    pf.iters++;
+    t = pf.begin(PH_PANEL);
     TRY(fill_zero(s, w.Tfac, (size_t)nb * nb * sizeof(double)));
     TRY(qr_panel(c, c0, c1));
     if (protect) {
@@ -458,26 +785,38 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
       TRY(panel_check(s, w.S, w.Sa, ldc, k, N, kw, w.Z, 1, kw, 0, 0, -1.0, w.Zabs, w.E, w.bt, k, w.colchk, ldc, c0, kw,
                       tsu_p, drep, k, nb));
     }
+    pf.end(t);
     if (c1 >= n) break;
     const int64_t m = n - c1;
     double* V = dA + c0 + c0 * lda;
     double* C = dA + c0 + c1 * lda;
+    t = pf.begin(PH_TMU);
     TRY(gemm64(s, 1, 0, 1, 0, 0, kw, (int)m, (int)(n - c0), 1.0, V, lda, C, lda, 0.0, w.W, nb, 0));
     TRY(gemm64(s, 1, 0, 0, 0, 0, kw, (int)m, kw, 1.0, w.Tfac, nb, w.W, nb, 0.0, w.W2, nb, 0));
     TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)m, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0));
+    pf.end(t);
+    pf.tmu_flops += 4.0 * (double)(n - c0) * (double)m * kw + 2.0 * (double)kw * kw * m;
+    pf.tmu_launches += 3;
     if (protect) {
+      t = pf.begin(PH_CARRY);
       TRY(ysums<double>(s, w.W2 - c1 * nb, nb, n, nb, k + 1, kw, w.Tm, w.Ta, nb, 0));
       TRY(carry(s, w, n, nb, k, k + 1, kw, V, lda, c0, 1, w.W2, nb, 0, c1, 0));
+      pf.end(t);
     }
     if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N));
     if (protect) {
+      t = pf.begin(PH_VERIFY);
       TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                                w.tflags, drep, k));
       TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                                 w.tflags, drep, k));
+      pf.end(t);
+      pf.verify_bytes += 8.0 * (double)(n - c0) * (double)m;
     }
   }
-  return report_fini(s, drep);
+  TRY(report_fini(s, drep));
+  pf.finish();
+  return 0;
 }
 
 int abft_encode(abft_handle h, int64_t m, int64_t n, const double* dA, int64_t lda, int32_t nb, double* dcolchk,
@@ -519,21 +858,45 @@ int abft_verify(abft_handle h, int64_t m, int64_t n, double* dA, int64_t lda, in
   return report_fini(s, drep);
 }
 
-int abft_gesv_mp(abft_handle, int64_t, const double*, int64_t, const double*, double*, int32_t, int32_t, void*, size_t,
-                 const abft_opts*, abft_ir_report*, abft_report*) {
-  return ABFT_ERR_UNSUPPORTED;
+int abft_gesv_mp(abft_handle h, int64_t n, const double* dA, int64_t lda, const double* db, double* dx, int32_t prec,
+                 int32_t max_iter, void* dwork, size_t work_bytes, const abft_opts* opts, abft_ir_report* dir,
+                 abft_report* drep) {
+  return gesv_mp_impl(h, n, dA, lda, db, dx, prec, max_iter, dwork, work_bytes, opts, dir, drep, 0);
 }
-int abft_posv_mp(abft_handle, int64_t, const double*, int64_t, const double*, double*, int32_t, int32_t, void*, size_t,
-                 const abft_opts*, abft_ir_report*, abft_report*) {
-  return ABFT_ERR_UNSUPPORTED;
+int abft_posv_mp(abft_handle h, int64_t n, const double* dA, int64_t lda, const double* db, double* dx, int32_t prec,
+                 int32_t max_iter, void* dwork, size_t work_bytes, const abft_opts* opts, abft_ir_report* dir,
+                 abft_report* drep) {
+  return gesv_mp_impl(h, n, dA, lda, db, dx, prec, max_iter, dwork, work_bytes, opts, dir, drep, 1);
 }
-int abft_potrf_batched(abft_handle, int32_t, int32_t, const int32_t*, void* const*, const int32_t*, int32_t, void*,
-                       size_t, const abft_opts*, int32_t*, abft_report*) {
-  return ABFT_ERR_UNSUPPORTED;
+static int batched_common(abft_handle h, int chol, int32_t batch, int32_t nmax, const int32_t* dn, void* const* dA,
+                          const int32_t* dlda, int32_t* const* dipiv, int32_t prec, void* dwork, size_t work_bytes,
+                          const abft_opts* opts, int32_t* dinfo, abft_report* dreps) {
+  if (!h) return -1;
+  if (batch < 0) return -2;
+  if (nmax < 0 || nmax > 512) return -3;
+  if (batch > 0 && (!dn || !dA || !dlda)) return -4;
+  if (!chol && batch > 0 && !dipiv) return -7;
+  if (prec != ABFT_F64 && prec != ABFT_F32) return ABFT_ERR_UNSUPPORTED;
+  int nb, protect;
+  double ts;
+  TRY(check_opts(opts, nmax, nb, protect, ts));
+  if (nb != 32) return ABFT_ERR_UNSUPPORTED;  // the batched kernels use 32-wide blocks and tiles
+  if (batch == 0) return 0;
+  if (!dinfo || !dreps) return -11;
+  if (!dwork || work_bytes < batched_ws_bytes(batch)) return ABFT_ERR_WORKSPACE;
+  return batched_factor(h->stream, chol, prec, batch, dn, dA, dlda, dipiv, dwork, protect, ts, opts->faults,
+                        opts->faults ? opts->nfaults : 0, dinfo, dreps, h->cus);
 }
-int abft_getrf_batched(abft_handle, int32_t, int32_t, const int32_t*, void* const*, const int32_t*, int32_t* const*,
-                       int32_t, void*, size_t, const abft_opts*, int32_t*, abft_report*) {
-  return ABFT_ERR_UNSUPPORTED;
+
+int abft_potrf_batched(abft_handle h, int32_t batch, int32_t nmax, const int32_t* dn, void* const* dA,
+                       const int32_t* dlda, int32_t prec, void* dwork, size_t work_bytes, const abft_opts* opts,
+                       int32_t* dinfo, abft_report* dreps) {
+  return batched_common(h, 1, batch, nmax, dn, dA, dlda, nullptr, prec, dwork, work_bytes, opts, dinfo, dreps);
+}
+int abft_getrf_batched(abft_handle h, int32_t batch, int32_t nmax, const int32_t* dn, void* const* dA,
+                       const int32_t* dlda, int32_t* const* dipiv, int32_t prec, void* dwork, size_t work_bytes,
+                       const abft_opts* opts, int32_t* dinfo, abft_report* dreps) {
+  return batched_common(h, 0, batch, nmax, dn, dA, dlda, dipiv, prec, dwork, work_bytes, opts, dinfo, dreps);
 }
 
 }  // extern "C"

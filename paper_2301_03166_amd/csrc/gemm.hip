@@ -4,10 +4,11 @@
 // 2x2 arrangement (64x64 each, 4x4 blocks of v_mfma_f64_16x16x4_f64).  K is
 // walked in steps of 16 through double-buffered LDS: the next step's global
 // loads are in flight while the current step's MFMAs run.  The MFMA's
-// row/column roles are swapped (its "A" operand is the B tile) so that each
-// lane's four accumulator rows land on four columns of C and sixteen lanes
-// write sixteen consecutive rows: every store instruction writes 128-byte
-// column segments.
+// row/column roles are swapped (its "A" operand is the B tile): the
+// instruction's result D[i][j] sits in lane j + 16 (i % 4), register i / 4
+// (measured on gfx950), so with D = C^T each register of a lane maps to one
+// column of C and sixteen lanes write sixteen consecutive rows -- every store
+// instruction writes 128-byte column segments.
 //
 // Operand options (template): transposition, a unit-lower mask on the stored
 // operand (Householder vectors with their implicit unit diagonal), |.| of the
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, double alph
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int gi = m0 + wm * 64 + ri * 16 + il;
-        int gj = n0 + wn * 64 + ci * 16 + 4 * kl + r;
+        int gj = n0 + wn * 64 + ci * 16 + 4 * r + kl;
         if (gi < M && gj < N && (!LOWER || (int64_t)gi + doff >= (int64_t)gj)) {
           double* p = C + gi + (int64_t)gj * ldc;
           double v = alpha * acc[ci][ri][r];

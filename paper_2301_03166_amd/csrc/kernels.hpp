@@ -36,7 +36,8 @@ int xsums(hipStream_t s, const T* A, int64_t lda, int64_t n, int nb, int I0, int
 template <typename T>
 int ysums(hipStream_t s, const T* Y, int64_t ldy, int64_t n, int nb, int J0, int kw, double* Tm, double* Ta, int ldT,
           int rnd);
-int panel_check(hipStream_t s, const double* S, const double* Sa, int ldS, int I0, int I1, int kw, const double* Mp,
+template <typename MT>
+int panel_check(hipStream_t s, const double* S, const double* Sa, int ldS, int I0, int I1, int kw, const MT* Mp,
                 int64_t msp, int64_t msj, int tri, int pjoff, double mscale, const double* Mabs, const double* E,
                 const double* bt, int Ik, const double* colchk, int64_t ldc, int64_t cj0, int ncols, double tsu_p,
                 abft_report* rep, int iter, int nb);
@@ -63,5 +64,26 @@ int laswp(hipStream_t s, T* A, int64_t lda, int64_t j0, int64_t j1, const int* m
           int64_t ldc, int nb);
 
 int fill_zero(hipStream_t s, void* p, size_t bytes);
+
+// mixed-precision solve helpers
+int convert_f64_f32(hipStream_t s, const double* A, int64_t lda, float* B, int64_t ldb, int64_t m, int64_t n);
+int perm_vector(hipStream_t s, const int32_t* ipiv, int n, int* perm);
+int gather_scale(hipStream_t s, const double* x, const int* perm, double scale, float* y, int n);
+int gather64(hipStream_t s, const double* x, const int* perm, double* y, int n);
+template <typename T>
+int trsv(hipStream_t s, const T* F, int64_t ld, int n, int kind, T* x, unsigned* counter, int* ready,
+         abft_report* rep);
+int residual(hipStream_t s, const double* A, int64_t lda, int n, const double* x, const double* b, double* r,
+             double* part, int nsplit, double* norms);
+int update_x(hipStream_t s, double* x, const float* d32, double scale, int n, double* norms);
+int anorm(hipStream_t s, const double* A, int64_t lda, int n, double* norms);
+int copy_f64(hipStream_t s, const double* a, double* b, int n);
+
+// batched factorizations (one persistent kernel)
+size_t batched_ws_bytes(int batch);
+int batched_factor(hipStream_t s, int chol, int prec, int batch, const int32_t* dn, void* const* dA,
+                   const int32_t* dlda, int32_t* const* dipiv, void* dwork, int protect, double ts,
+                   const abft_fault* hfaults, int nfaults, int32_t* dinfo, abft_report* dreps, int cus);
+int f32_to_f64(hipStream_t s, const float* a, double* b, int n);
 
 }  // namespace abft

@@ -1,0 +1,268 @@
+// Kernels of the mixed-precision solve with FP64 iterative refinement:
+// precision conversion, the row permutation of LU, blocked triangular solves
+// (one launch per solve, sync-free between row blocks), the FP64 residual
+// r = b - A x and the vector updates / infinity norms the refinement reads.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace abft {
+
+constexpr int TB = 64;  // rows per block of the triangular solves
+
+__global__ void k_convert(const double* __restrict__ A, int64_t lda, float* __restrict__ B, int64_t ldb, int64_t m,
+                          int64_t n) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    B[i + j * ldb] = (float)A[i + j * lda];
+}
+
+// final row permutation of the LU interchanges: row i of P A is row perm[i] of A
+__global__ void k_perm_vector(const int32_t* ipiv, int n, int* perm) {
+  extern __shared__ int pv[];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) pv[i] = i;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < n; ++j) {
+      int q = ipiv[j] - 1;
+      int t = pv[j];
+      pv[j] = pv[q];
+      pv[q] = t;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = pv[i];
+}
+
+// y[i] = (float) (x[perm[i]] * scale)   (perm may be null)
+__global__ void k_gather_scale(const double* x, const int* perm, double scale, float* y, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    y[i] = (float)(x[perm ? perm[i] : i] * scale);
+}
+__global__ void k_gather64(const double* x, const int* perm, double* y, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] = x[perm ? perm[i] : i];
+}
+
+// Triangular solve x := M^{-1} x in place (M n x n, stored in the factor
+// array F): kind 0 = unit lower (LU's L), 1 = upper (LU's U), 2 = lower
+// (Cholesky L), 3 = upper given as the transpose of the stored lower
+// Cholesky factor.  Workgroups take 64-row blocks in solve order from a
+// counter; a block first waits for, and subtracts, every earlier block of
+// the solution (published with a release flag), then solves its diagonal
+// block in LDS.  The accumulation order is fixed, so results are
+// reproducible.
+template <typename T>
+__device__ __forceinline__ T melem(const T* F, int64_t ld, int kind, int64_t i, int64_t j) {
+  return kind == 3 ? F[j + i * ld] : F[i + j * ld];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv(const T* __restrict__ F, int64_t ld, int n, int kind, T* x,
+                                              unsigned* counter, int* ready, abft_report* rep) {
+  __shared__ T part[4][TB];
+  __shared__ T xb[TB];
+  __shared__ T D[TB][TB + 1];
+  __shared__ int s_blk;
+  const int nblk = (n + TB - 1) / TB;
+  const bool lower = (kind == 0 || kind == 2);
+  if (threadIdx.x == 0) s_blk = (int)atomicAdd(counter, 1u);
+  __syncthreads();
+  const int ord = s_blk;
+  if (ord >= nblk) return;
+  const int b = lower ? ord : nblk - 1 - ord;
+  const int64_t r0 = (int64_t)b * TB;
+  const int rows = (int)min((int64_t)TB, (int64_t)n - r0);
+  const int r = threadIdx.x & (TB - 1), q = threadIdx.x >> 6;
+  T acc = (T)0;
+  // contributions of the blocks solved before this one
+  for (int k = 0; k < ord; ++k) {
+    const int c = lower ? k : nblk - 1 - k;
+    if (threadIdx.x == 0) {
+      long spins = 0;
+      while (__hip_atomic_load(&ready[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1L << 22)) {
+          if (rep) atomicOr(&rep->status, (int)ABFT_ST_INTERNAL);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int64_t c0 = (int64_t)c * TB;
+    const int cols = (int)min((int64_t)TB, (int64_t)n - c0);
+    if (r < rows) {
+      for (int jj = q; jj < cols; jj += 4) acc += melem(F, ld, kind, r0 + r, c0 + jj) * x[c0 + jj];
+    }
+  }
+  part[q][r] = acc;
+  for (int idx = threadIdx.x; idx < rows * rows; idx += blockDim.x) {
+    int i = idx % rows, j = idx / rows;
+    D[i][j] = melem(F, ld, kind, r0 + i, r0 + j);
+  }
+  __syncthreads();
+  if (threadIdx.x < rows) xb[r] = x[r0 + r] - (((part[0][r] + part[1][r]) + part[2][r]) + part[3][r]);
+  __syncthreads();
+  // diagonal block, sequential in LDS
+  for (int j = 0; j < rows; ++j) {
+    const int jj = lower ? j : rows - 1 - j;
+    if (threadIdx.x == 0 && kind != 0) xb[jj] = xb[jj] / D[jj][jj];
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (lower ? (t > jj && t < rows) : (t < jj)) xb[t] -= D[t][jj] * xb[jj];
+    __syncthreads();
+  }
+  if (threadIdx.x < rows) x[r0 + r] = xb[r];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(&ready[b], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// residual partials: part[s][i] = sum over column chunk s of A(i, j) x(j)
+__global__ __launch_bounds__(256) void k_resid_part(const double* __restrict__ A, int64_t lda, int n,
+                                                    const double* __restrict__ x, int chunk, double* part) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y;
+  const int j0 = s * chunk, j1 = min(n, j0 + chunk);
+  __shared__ double xs[256];
+  double acc = 0.0;
+  for (int jb = j0; jb < j1; jb += 256) {
+    __syncthreads();
+    if (jb + threadIdx.x < j1) xs[threadIdx.x] = x[jb + threadIdx.x];
+    __syncthreads();
+    const int je = min(256, j1 - jb);
+    if (i < n)
+      for (int jj = 0; jj < je; ++jj) acc += A[i + (int64_t)(jb + jj) * lda] * xs[jj];
+  }
+  if (i < n) part[(int64_t)s * n + i] = acc;
+}
+
+__device__ __forceinline__ void max_bits(double* p, double v) {
+  if (!(v <= 1.79e308)) v = __longlong_as_double(0x7ff0000000000000ll);  // NaN / Inf -> +Inf
+  atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+// r = b - sum_s part[s]; norms[0] = max |r|, norms[1] = max |x|
+__global__ void k_resid_fin(const double* part, int nsplit, const double* b, const double* x, double* r, int n,
+                            double* norms) {
+  double mr = 0.0, mx = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < nsplit; ++q) s += part[(int64_t)q * n + i];
+    double v = b[i] - s;
+    r[i] = v;
+    mr = fmax(mr, fabs(v));
+    if (!(fabs(v) <= 1.79e308)) mr = __longlong_as_double(0x7ff0000000000000ll);
+    mx = fmax(mx, fabs(x[i]));
+    if (!(fabs(x[i]) <= 1.79e308)) mx = __longlong_as_double(0x7ff0000000000000ll);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mr = fmax(mr, __shfl_xor(mr, o));
+    mx = fmax(mx, __shfl_xor(mx, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    max_bits(&norms[0], mr);
+    max_bits(&norms[1], mx);
+  }
+}
+
+// x += scale * (double) d32; norms[2] = max |scale d|, norms[3] = max |x|
+__global__ void k_update(double* x, const float* d32, double scale, int n, double* norms) {
+  double md = 0.0, mx = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double d = scale * (double)d32[i];
+    double v = x[i] + d;
+    x[i] = v;
+    md = fmax(md, fabs(d));
+    if (!(fabs(d) <= 1.79e308)) md = __longlong_as_double(0x7ff0000000000000ll);
+    mx = fmax(mx, fabs(v));
+    if (!(fabs(v) <= 1.79e308)) mx = __longlong_as_double(0x7ff0000000000000ll);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    md = fmax(md, __shfl_xor(md, o));
+    mx = fmax(mx, __shfl_xor(mx, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    max_bits(&norms[2], md);
+    max_bits(&norms[3], mx);
+  }
+}
+
+// infinity norm of A (max row |.|-sum) into norms[4]
+__global__ __launch_bounds__(256) void k_anorm(const double* __restrict__ A, int64_t lda, int n, double* norms) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (i < n)
+    for (int j = 0; j < n; ++j) s += fabs(A[i + (int64_t)j * lda]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s = fmax(s, __shfl_xor(s, o));
+  if ((threadIdx.x & 63) == 0) max_bits(&norms[4], s);
+}
+
+__global__ void k_copy_f64(const double* a, double* b, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = a[i];
+}
+__global__ void k_f32_to_f64(const float* a, double* b, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = (double)a[i];
+}
+
+// ---------------------------------------------------------------------------
+#define LAUNCH_OK return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP
+static inline unsigned g1(int64_t n) { return (unsigned)std::min<int64_t>(4096, (n + 255) / 256); }
+
+int convert_f64_f32(hipStream_t s, const double* A, int64_t lda, float* B, int64_t ldb, int64_t m, int64_t n) {
+  if (m <= 0 || n <= 0) return 0;
+  hipLaunchKernelGGL(k_convert, dim3(g1(m), (unsigned)n), dim3(256), 0, s, A, lda, B, ldb, m, n);
+  LAUNCH_OK;
+}
+int perm_vector(hipStream_t s, const int32_t* ipiv, int n, int* perm) {
+  if ((size_t)n * sizeof(int) > 150 * 1024) return ABFT_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL(k_perm_vector, dim3(1), dim3(256), (size_t)n * sizeof(int), s, ipiv, n, perm);
+  LAUNCH_OK;
+}
+int gather_scale(hipStream_t s, const double* x, const int* perm, double scale, float* y, int n) {
+  hipLaunchKernelGGL(k_gather_scale, dim3(g1(n)), dim3(256), 0, s, x, perm, scale, y, n);
+  LAUNCH_OK;
+}
+int gather64(hipStream_t s, const double* x, const int* perm, double* y, int n) {
+  hipLaunchKernelGGL(k_gather64, dim3(g1(n)), dim3(256), 0, s, x, perm, y, n);
+  LAUNCH_OK;
+}
+template <typename T>
+int trsv(hipStream_t s, const T* F, int64_t ld, int n, int kind, T* x, unsigned* counter, int* ready,
+         abft_report* rep) {
+  const int nblk = (n + TB - 1) / TB;
+  if (fill_zero(s, counter, 4)) return ABFT_ERR_HIP;
+  if (fill_zero(s, ready, (size_t)nblk * sizeof(int))) return ABFT_ERR_HIP;
+  hipLaunchKernelGGL(k_trsv<T>, dim3(nblk), dim3(256), 0, s, F, ld, n, kind, x, counter, ready, rep);
+  LAUNCH_OK;
+}
+template int trsv<float>(hipStream_t, const float*, int64_t, int, int, float*, unsigned*, int*, abft_report*);
+template int trsv<double>(hipStream_t, const double*, int64_t, int, int, double*, unsigned*, int*, abft_report*);
+
+int residual(hipStream_t s, const double* A, int64_t lda, int n, const double* x, const double* b, double* r,
+             double* part, int nsplit, double* norms) {
+  const int chunk = (n + nsplit - 1) / nsplit;
+  hipLaunchKernelGGL(k_resid_part, dim3((n + 255) / 256, nsplit), dim3(256), 0, s, A, lda, n, x, chunk, part);
+  if (hipGetLastError() != hipSuccess) return ABFT_ERR_HIP;
+  hipLaunchKernelGGL(k_resid_fin, dim3(g1(n)), dim3(256), 0, s, part, nsplit, b, x, r, n, norms);
+  LAUNCH_OK;
+}
+int update_x(hipStream_t s, double* x, const float* d32, double scale, int n, double* norms) {
+  hipLaunchKernelGGL(k_update, dim3(g1(n)), dim3(256), 0, s, x, d32, scale, n, norms);
+  LAUNCH_OK;
+}
+int anorm(hipStream_t s, const double* A, int64_t lda, int n, double* norms) {
+  hipLaunchKernelGGL(k_anorm, dim3((n + 255) / 256), dim3(256), 0, s, A, lda, n, norms);
+  LAUNCH_OK;
+}
+int copy_f64(hipStream_t s, const double* a, double* b, int n) {
+  hipLaunchKernelGGL(k_copy_f64, dim3(g1(n)), dim3(256), 0, s, a, b, n);
+  LAUNCH_OK;
+}
+int f32_to_f64(hipStream_t s, const float* a, double* b, int n) {
+  hipLaunchKernelGGL(k_f32_to_f64, dim3(g1(n)), dim3(256), 0, s, a, b, n);
+  LAUNCH_OK;
+}
+
+}  // namespace abft

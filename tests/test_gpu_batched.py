@@ -1,0 +1,107 @@
+"""GPU parity of the batched protected factorizations (one persistent
+kernel, block and tile size 32) against the oracle, matrix by matrix."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_03166_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    from paper_2301_03166_amd import abft
+    return abft.Handle()
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.asfortranarray(a)).cuda()
+    return t if dtype is None else t.to(dtype)
+
+
+SIZES = [1, 5, 31, 32, 33, 64, 100, 129, 200, 255, 300, 512]
+
+
+@pytest.mark.parametrize("chol", [True, False])
+def test_batched_fp64_matches_oracle(h, chol):
+    mats0 = [gen.spd(n, 100 + n) if chol else gen.general(n, 100 + n) for n in SIZES]
+    mats = [dev(a) for a in mats0]
+    infos, ipivs, reps = h.batched(mats, chol)
+    for q, (n, a0) in enumerate(zip(SIZES, mats0)):
+        g = mats[q].cpu().numpy()
+        o = a0.copy(order="F")
+        if chol:
+            oinfo, orep = oracle.potrf(o, 32)
+            g, o = np.tril(g), np.tril(o)
+        else:
+            opiv, oinfo, orep = oracle.getrf(o, 32)
+            assert np.array_equal(ipivs[q].cpu().numpy()[:n], opiv), n
+        assert infos[q] == oinfo == 0, n
+        assert np.linalg.norm(g - o) <= 1e-12 * np.linalg.norm(o), n
+        assert reps[q].status == 0 and reps[q].flagged_tiles == 0, n
+        assert reps[q].max_ratio < 0.5
+
+
+@pytest.mark.parametrize("chol", [True, False])
+def test_batched_exact_integer_cases(h, chol):
+    sizes = [7, 32, 70, 160]
+    made = [gen.chol_exact(n, n) if chol else gen.lu_exact(n, n) for n in sizes]
+    mats = [dev(m[0]) for m in made]
+    infos, ipivs, reps = h.batched(mats, chol)
+    for q, n in enumerate(sizes):
+        g = mats[q].cpu().numpy()
+        if chol:
+            assert np.array_equal(np.tril(g), made[q][1])
+        else:
+            assert np.array_equal(np.tril(g, -1) + np.eye(n), made[q][2])
+            assert np.array_equal(np.triu(g), made[q][3])
+        assert reps[q].max_ratio == 0.0 and reps[q].status == 0
+
+
+def test_batched_fp32(h):
+    import torch
+    sizes = [40, 96, 257]
+    mats0 = [gen.general(n, 7 + n) for n in sizes]
+    mats = [dev(a, torch.float32) for a in mats0]
+    infos, ipivs, reps = h.batched(mats, chol=False)
+    for q, n in enumerate(sizes):
+        g = mats[q].cpu().numpy().astype(np.float64)
+        P = np.arange(n)
+        for j, p in enumerate(ipivs[q].cpu().numpy()[:n]):
+            P[j], P[p - 1] = P[p - 1], P[j]
+        L, U = np.tril(g, -1) + np.eye(n), np.triu(g)
+        assert np.linalg.norm(mats0[q][P] - L @ U) / np.linalg.norm(mats0[q]) < 1e-5
+        assert reps[q].status == 0
+
+
+@pytest.mark.parametrize("chol", [True, False])
+def test_batched_faults_corrected(h, chol):
+    sizes = [128, 200, 256, 96]
+    mats0 = [gen.spd(n, 3 + n) if chol else gen.general(n, 3 + n) for n in sizes]
+    faults = []
+    for q, n in enumerate(sizes):
+        f = gen.fault_plan("chol" if chol else "lu", n, 32, seed=77 + q)
+        f["bit"] = 60 - q
+        f["matrix"] = q
+        faults.append(f)
+    clean = [dev(a) for a in mats0]
+    h.batched(clean, chol)
+    mats = [dev(a) for a in mats0]
+    infos, ipivs, reps = h.batched(mats, chol, faults=faults)
+    for q, n in enumerate(sizes):
+        f = faults[q]
+        assert reps[q].corrected == 1, (q, reps[q].status)
+        assert reps[q].events()[0] == (f["iter"], 1, f["row"], f["col"])
+        o = mats0[q].copy(order="F")
+        ff = dict(f)
+        if chol:
+            _, orep = oracle.potrf(o, 32, faults=[ff])
+        else:
+            _, _, orep = oracle.getrf(o, 32, faults=[ff])
+        assert orep.corrected == 1 and orep.events()[0] == reps[q].events()[0]
+        g, c = mats[q].cpu().numpy(), clean[q].cpu().numpy()
+        if chol:
+            g, c = np.tril(g), np.tril(c)
+        assert np.max(np.abs(g - c)) <= 1e-12 * np.max(np.abs(c))
