@@ -312,8 +312,30 @@ static inline double tau_panel(const ctx_t* c, double mag) { return (2.0 * c->ts
 
 typedef struct { int fe[1024], fw[1024], ge[1024], gw[1024]; double de[1024], dw[1024], he[1024], hw[1024]; } tflags_t;
 
-/* compare recomputed sums with carried checksums; returns number of flags */
-static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, double* maxr) {
+/* A rebuilt element (tile-relative ci, cj) is known only to the tolerance of
+   the column checksum it was rebuilt from, te_c.  When a tile is rechecked
+   after a correction, every sum that contains the element (twice in the
+   symmetric view of a diagonal tile: at (ci, cj) and at its mirror) may
+   differ by its weight in that sum times te_c.  These give the weight of the
+   element in column j / row i of the tile, 0 where it does not occur. */
+typedef struct { int ci, cj, diag; double tec; } slack_t;
+static double slack_col(const slack_t* s, int j) {
+  if (!s) return 0.0;
+  if (j == s->cj) return (s->ci + 1) * s->tec;
+  if (s->diag && j == s->ci) return (s->cj + 1) * s->tec;
+  return 0.0;
+}
+static double slack_row(const slack_t* s, int i) {
+  if (!s) return 0.0;
+  if (i == s->ci) return (s->cj + 1) * s->tec;
+  if (s->diag && i == s->cj) return (s->ci + 1) * s->tec;
+  return 0.0;
+}
+static double slack_one(const slack_t* s, int hit) { return (s && hit) ? s->tec : 0.0; }
+
+/* compare recomputed sums with carried checksums; returns number of flags.
+   sl (may be NULL) widens the comparisons that contain a rebuilt element. */
+static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, double* maxr, const slack_t* sl) {
   int r0 = I * c->nb, h = tlen(c, I), c0 = J * c->nb, w = tlen(c, J);
   int nflag = 0;
   for (int j = 0; j < w; ++j) {
@@ -321,6 +343,9 @@ static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, dou
     double dw = t->cw[j] - AT(c->cc, 2 * I + 1, c0 + j, c->ldc);
     double te = tau_of(c, t->ca[j], AT(c->gc, 2 * I, c0 + j, c->ldc));
     double tw = tau_of(c, t->cwa[j], AT(c->gc, 2 * I + 1, c0 + j, c->ldc));
+    double sw = slack_col(sl, j);
+    te += slack_one(sl, sw > 0.0);
+    tw += sw;
     f->de[j] = de;
     f->dw[j] = dw;
     f->fe[j] = bad(de, te);
@@ -336,6 +361,9 @@ static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, dou
     double dw = t->rw[i] - AT(c->rc, r0 + i, 2 * J + 1, c->ldr);
     double te = tau_of(c, t->ra[i], AT(c->gr, r0 + i, 2 * J, c->ldr));
     double tw = tau_of(c, t->rwa[i], AT(c->gr, r0 + i, 2 * J + 1, c->ldr));
+    double sw = slack_row(sl, i);
+    te += slack_one(sl, sw > 0.0);
+    tw += sw;
     f->he[i] = de;
     f->hw[i] = dw;
     f->ge[i] = bad(de, te);
@@ -368,7 +396,7 @@ static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
   static tsums_t t;
   static tflags_t f;
   tile_sums(c, A, lda, I, J, &t);
-  int nf = tile_flags(c, I, J, &t, &f, NULL);
+  int nf = tile_flags(c, I, J, &t, &f, NULL, NULL);
   if (nf == 0) return;
   int nFe = 0, nGe = 0, nFw = 0, nGw = 0, jf[2] = {-1, -1}, ig = -1;
   for (int j = 0; j < w; ++j) {
@@ -417,7 +445,8 @@ static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
     double old = AT(A, r0 + ci, c0 + cj, lda);
     AT(A, r0 + ci, c0 + cj, lda) = s;
     tile_sums(c, A, lda, I, J, &t);
-    if (tile_flags(c, I, J, &t, &f, NULL) == 0) {
+    slack_t sl = {ci, cj, diag, tau_of(c, t.ca[cj], AT(c->gc, 2 * I, c0 + cj, c->ldc))};
+    if (tile_flags(c, I, J, &t, &f, NULL, &sl) == 0) {
       kind = 1;
     } else {
       AT(A, r0 + ci, c0 + cj, lda) = old;
@@ -443,7 +472,7 @@ static void verify_region(ctx_t* c, double* A, int lda, int Ia, int Ja) {
       if (c->sym && I < J) continue;
       tile_sums(c, A, lda, I, J, &t);
       double mr = c->rep->max_ratio;
-      int nf = tile_flags(c, I, J, &t, &f, &mr);
+      int nf = tile_flags(c, I, J, &t, &f, &mr, NULL);
       if (nf) {
         c->rep->flagged_tiles++;
         note_flag(c);

@@ -34,11 +34,19 @@ __device__ void tile_sums(const T* A, int64_t lda, int64_t r0, int64_t c0, int h
     acc2 se{0, 0}, sw{0, 0};
     double sa = 0, swa = 0;
     const double wj = (double)(j + 1);
+    double vq[QROWS];
+    // all loads of the column first (QROWS independent requests in flight)
+#pragma unroll
+    for (int q = 0; q < QROWS; ++q) {
+      int i = lane + 64 * q;
+      vq[q] = 0.0;
+      if (i < h) vq[q] = (sym && i < j) ? ld(A + (r0 + j) + (c0 + i) * lda) : ld(A + (r0 + i) + (c0 + j) * lda);
+    }
 #pragma unroll
     for (int q = 0; q < QROWS; ++q) {
       int i = lane + 64 * q;
       if (i < h) {
-        double v = (sym && i < j) ? ld(A + (r0 + j) + (c0 + i) * lda) : ld(A + (r0 + i) + (c0 + j) * lda);
+        const double v = vq[q];
         double wi = (double)(i + 1), av = fabs(v);
         cadd(se, v);
         cfma(sw, wi, v);
@@ -121,18 +129,36 @@ struct TileFlags {
   double maxr;
 };
 
+// A rebuilt element (tile-relative sci, scj) is known only to the tolerance
+// tec of the column checksum it was rebuilt from; after a correction every
+// sum containing it (twice in the symmetric view of a diagonal tile: the
+// element and its mirror) may differ by its weight in that sum times tec.
+__device__ __forceinline__ double slack_w(int line, int a, int b, bool sdiag, double tec) {
+  if (line == b) return (a + 1) * tec;
+  if (sdiag && line == a) return (b + 1) * tec;
+  return 0.0;
+}
+
+// sci < 0: plain comparison; otherwise widen the sums that hold element
+// (sci, scj) as described above
 __device__ void tile_compare(const TileSums& ts, TileFlags& tf, int I, int J, int nb, int h, int w,
                              const double* colchk, int64_t ldc, const double* rowchk, int64_t ldr, const double* gc,
-                             const double* gr, double tsu) {
+                             const double* gr, double tsu, int sci = -1, int scj = -1, bool sdiag = false) {
   int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
   if (threadIdx.x == 0) { tf.nflag = 0; tf.maxr = 0.0; }
   __syncthreads();
+  const double tec =
+      sci >= 0 ? tau_verify(tsu, ts.ca[scj], gc ? gc[2 * I + (c0 + scj) * ldc] : 0.0) : 0.0;
   int nfl = 0;
   double mr = 0.0;
   for (int j = threadIdx.x; j < w; j += blockDim.x) {
     int64_t o = 2 * I + (c0 + j) * ldc;
     double de = ts.ce[j] - colchk[o], dw = ts.cw[j] - colchk[o + 1];
     double te = tau_verify(tsu, ts.ca[j], gc ? gc[o] : 0.0), tw = tau_verify(tsu, ts.cwa[j], gc ? gc[o + 1] : 0.0);
+    if (sci >= 0) {
+      const double sw = slack_w(j, sci, scj, sdiag, tec);
+      if (sw > 0.0) { te += tec; tw += sw; }
+    }
     bool be = bad(de, te), bw = bad(dw, tw);
     tf.de[j] = de; tf.dw[j] = dw; tf.fe[j] = be; tf.fw[j] = bw;
     nfl += be + bw;
@@ -143,6 +169,10 @@ __device__ void tile_compare(const TileSums& ts, TileFlags& tf, int I, int J, in
     int64_t o = (r0 + i) + (2 * J) * ldr;
     double de = ts.res[i] - rowchk[o], dw = ts.rws[i] - rowchk[o + ldr];
     double te = tau_verify(tsu, ts.ra[i], gr ? gr[o] : 0.0), tw = tau_verify(tsu, ts.rwa[i], gr ? gr[o + ldr] : 0.0);
+    if (sci >= 0) {
+      const double sw = slack_w(i, scj, sci, sdiag, tec);
+      if (sw > 0.0) { te += tec; tw += sw; }
+    }
     bool be = bad(de, te), bw = bad(dw, tw);
     tf.he[i] = de; tf.hw[i] = dw; tf.ge[i] = be; tf.gw[i] = bw;
     nfl += be + bw;
@@ -230,6 +260,12 @@ __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h,
     cs.ci = ci;
     cs.cj = cj;
     cs.kind = (repair == -1) ? 0 : (ci >= 0 ? 1 : (repair ? 2 : 3));
+#ifdef ABFT_DEBUG_CORRECT
+    printf("correct I=%d J=%d diag=%d nflag=%d nFe=%d nGe=%d nFw=%d nGw=%d jf0=%d jf1=%d ig=%d -> ci=%d cj=%d kind=%d\n",
+           I, J, (int)diag, tf.nflag, nFe, nGe, nFw, nGw, jf0, jf1, ig, ci, cj, cs.kind);
+    for (int j = 0; j < w; ++j)
+      if (tf.fe[j] || tf.fw[j]) printf("  col %d de=%g dw=%g fe=%d fw=%d\n", j, tf.de[j], tf.dw[j], tf.fe[j], tf.fw[j]);
+#endif
   }
   __syncthreads();
   if (cs.kind == 1) {
@@ -251,8 +287,17 @@ __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h,
     }
     __syncthreads();
     tile_sums(A, lda, r0, c0, h, w, diag, ts);
-    tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu);
+    tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu, ci, cj, diag);
     if (tf.nflag != 0) {
+#ifdef ABFT_DEBUG_CORRECT
+      if (threadIdx.x == 0) {
+        printf("recheck failed: nflag=%d\n", tf.nflag);
+        for (int j = 0; j < w; ++j)
+          if (tf.fe[j] || tf.fw[j]) printf("  col %d de=%g dw=%g\n", j, tf.de[j], tf.dw[j]);
+        for (int i = 0; i < h; ++i)
+          if (tf.ge[i] || tf.gw[i]) printf("  row %d de=%g dw=%g\n", i, tf.he[i], tf.hw[i]);
+      }
+#endif
       if (threadIdx.x == 0) {
         A[(r0 + ci) + (c0 + cj) * lda] = (T)cs.old;
         cs.kind = 3;

@@ -105,3 +105,23 @@ def test_batched_faults_corrected(h, chol):
         if chol:
             g, c = np.tril(g), np.tril(c)
         assert np.max(np.abs(g - c)) <= 1e-12 * np.max(np.abs(c))
+
+
+def test_batched_chol_diagonal_tile_flips(h):
+    """Flips inside Cholesky diagonal tiles, one per matrix, including the far
+    corner (nb-1, 0) of a tile; each is corrected as the oracle corrects it."""
+    n = 128
+    pos = [(95, 64), (87, 64), (70, 70), (63, 32)]
+    mats0 = [gen.spd(n, 0) for _ in pos]
+    faults = [{"iter": (p[1] // 32) - 1, "row": p[0], "col": p[1], "bit": 57, "matrix": q} for q, p in enumerate(pos)]
+    clean = [dev(a) for a in mats0]
+    h.batched(clean, True)
+    mats = [dev(a) for a in mats0]
+    infos, ipivs, reps = h.batched(mats, True, faults=faults)
+    for q, f in enumerate(faults):
+        o = mats0[q].copy(order="F")
+        _, orep = oracle.potrf(o, 32, faults=[{k: v for k, v in f.items() if k != "matrix"}])
+        assert orep.status == 1 and reps[q].status == 1, (q, orep.status, reps[q].status)
+        assert reps[q].events()[0] == orep.events()[0] == (f["iter"], 1, f["row"], f["col"])
+        g, c = np.tril(mats[q].cpu().numpy()), np.tril(clean[q].cpu().numpy())
+        assert np.max(np.abs(g - c)) <= 1e-12 * np.max(np.abs(c))

@@ -244,3 +244,18 @@ def test_two_flips_one_tile_uncorrectable(h):
     G, rep = _gpu(h, "lu", A, nb, faults=fs)
     _, orep = _orc("lu", A, nb, faults=fs)
     assert rep.status & 4 and orep.status & 4
+
+
+@pytest.mark.parametrize("pos", [(95, 64), (87, 64), (70, 70), (80, 79)])
+def test_chol_diagonal_tile_flip(h, pos):
+    """Flips inside a Cholesky diagonal tile, including its far corner, where
+    the rebuilt element's rounding is weighted by nb-1 in the recheck."""
+    n, nb = 128, 32
+    A = gen.spd(n, 0)
+    f = {"iter": 1, "row": pos[0], "col": pos[1], "bit": 57}
+    clean, _ = _gpu(h, "chol", A, nb)
+    G, rep = _gpu(h, "chol", A, nb, faults=[f])
+    O, orep = _orc("chol", A, nb, faults=[f])
+    assert rep.status == orep.status == 1
+    assert rep.events() == orep.events() == [(1, 1, pos[0], pos[1])]
+    assert np.max(np.abs(G - clean)) <= 1e-11 * np.max(np.abs(clean))

@@ -269,6 +269,28 @@ def test_single_flip_detected_and_corrected(kind, bit):
         assert np.allclose(aux[k], aux0[k], rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("pos", [(87, 64), (95, 64), (70, 70), (95, 95), (80, 79)])
+@pytest.mark.parametrize("bit", [57, 55])
+def test_chol_diagonal_tile_flip_corrected(pos, bit):
+    """Cholesky keeps one triangle of a diagonal tile; a flip anywhere in it
+    shows in two columns (the element and its mirror) and is corrected.  The
+    rebuilt element carries the column checksum's rounding, which the
+    recheck sees multiplied by the element's row weight (up to nb): the far
+    corner (nb-1, 0) of the tile is the case that exercises that allowance."""
+    n, nb = 128, 32
+    A0 = gen.spd(n, 0)
+    clean = A0.copy(order="F")
+    oracle.potrf(clean, nb)
+    f = {"iter": 1, "row": pos[0], "col": pos[1], "bit": bit}
+    A = A0.copy(order="F")
+    info, rep = oracle.potrf(A, nb, faults=[f])
+    assert info == 0
+    assert rep.status & oracle.ST_CORRECTED and not rep.status & oracle.ST_UNCORRECTABLE
+    assert rep.events()[0] == (1, 1, pos[0], pos[1])
+    L, L0 = np.tril(A), np.tril(clean)
+    assert np.max(np.abs(L - L0)) <= 1e-12 * np.max(np.abs(L0))
+
+
 @pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
 def test_low_bit_flip_harmless(kind):
     """Bit 0 changes an element by one ulp: undetectable by any floating-point
