@@ -13,7 +13,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libabft.so")
+LIB_PATH = os.environ.get("ABFT_LIB") or os.path.join(HERE, "libabft.so")
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
 PROTECT_NONE, PROTECT_FULL = 0, 2

@@ -76,13 +76,17 @@ __device__ __forceinline__ void rep_flag_iter(abft_report* r, int iter) { atomic
 
 // ---------------------------------------------------------------------------
 // Grid-wide barrier for cooperative launches (every workgroup resident).
+// Only thread 0 fences: its release (L2 write-back) covers the whole
+// workgroup's completed stores, its acquire (L2 invalidate) the whole
+// workgroup's following loads.
 // A monotonically increasing counter: workgroup g waits until the counter
 // reaches `target` = (barrier index + 1) * gridDim.x.  The wait is bounded;
 // on expiry the workgroup records ABFT_ST_INTERNAL and carries on, so every
 // wave always reaches the end of the kernel.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned target, abft_report* rep, int* err) {
-  __threadfence();
+  // the workgroup barrier completes every wave's stores; thread 0's
+  // agent-scope release then publishes them before the arrival is counted
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);

@@ -40,6 +40,7 @@ constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
   } while (0)
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t SPLITK_ELEMS = (size_t)1 << 22;  // split-K partials (32 MB)
 
 // Phase timer of profiled calls: event pairs recorded on the stream, summed
 // per phase after one synchronisation at the end of the call.
@@ -98,7 +99,7 @@ struct Prof {
 struct Ws {
   double *colchk, *rowchk, *gc, *gr, *S, *Sa, *Tm, *Ta;
   double *Tfac, *W, *W2, *Wp, *Wp2, *Xq, *Yq, *Z, *Zabs, *E, *bt, *scr;
-  double *porig, *stage, *slots;
+  double *porig, *stage, *slots, *splitk;
   int *tflags, *moves;
   unsigned* ctr;
   size_t bytes;
@@ -132,6 +133,7 @@ Ws carve(char* base, int64_t n, int nb, int op, int elem) {
     w.moves = (int*)take((size_t)(4 * nb + 4) * sizeof(int));
   }
   if (op == ABFT_OP_GEQRF) {
+    w.splitk = (double*)take((size_t)SPLITK_ELEMS * sizeof(double));
     w.Tfac = (double*)take((size_t)nb * nb * sizeof(double));
     w.W = (double*)take((size_t)nb * n * sizeof(double));
     w.W2 = (double*)take((size_t)nb * n * sizeof(double));
@@ -253,14 +255,14 @@ int lu_panel(LuCtx<T>& c, int64_t c0, int64_t c1) {
     return getrf_leaf(c.s, c.A, c.lda, c.n, c0, w, c.ipiv, c.info, c.w->slots, c.w->ctr, &c.ctr_base, c.rep, c.maxg);
   const int h = split(w);
   TRY(lu_panel(c, c0, c0 + h));
-  TRY(perm_build(c.s, c.ipiv, c0, h, c.w->moves));
+  TRY(perm_build(c.s, c.ipiv, c0, h, c.n, c.w->moves));
   TRY(laswp(c.s, c.A, c.lda, c0 + h, c1, c.w->moves, (T*)c.w->stage, (double*)nullptr, 0, 1));
   TRY(trsm_llu(c.s, c.A, c.lda, c0, h, c0 + h, c1));
   const int64_t r = c0 + h;
   TRY(gemmT(c.s, panel_prec<T>(), 0, 0, 0, (int)(c.n - r), (int)(c1 - r), h, -1.0, c.A + r + c0 * c.lda, c.lda,
             c.A + c0 + r * c.lda, c.lda, 1.0, c.A + r + r * c.lda, c.lda, 0));
   TRY(lu_panel(c, r, c1));
-  TRY(perm_build(c.s, c.ipiv, r, w - h, c.w->moves));
+  TRY(perm_build(c.s, c.ipiv, r, w - h, c.n, c.w->moves));
   return laswp(c.s, c.A, c.lda, c0, r, c.w->moves, (T*)c.w->stage, (double*)nullptr, 0, 1);
 }
 
@@ -295,7 +297,7 @@ int qr_panel(QrCtx& c, int64_t c0, int64_t c1) {
   double* T1 = c.w->Tfac + toff + (int64_t)toff * nb;
   // apply H1^T = I - V1 T1^T V1^T to the right half
   TRY(gemm64(c.s, 1, 0, 1, 0, 0, h, (int)(c1 - r), (int)(n - c0), 1.0, V1, lda, A + c0 + r * lda, lda, 0.0, c.w->Wp,
-             nb, 0));
+             nb, 0, 0, 0, 0, c.w->splitk, SPLITK_ELEMS));
   TRY(gemm64(c.s, 1, 0, 0, 0, 0, h, (int)(c1 - r), h, 1.0, T1, nb, c.w->Wp, nb, 0.0, c.w->Wp2, nb, 0));
   TRY(gemm64(c.s, 0, 0, 1, 0, 0, (int)(n - c0), (int)(c1 - r), h, -1.0, V1, lda, c.w->Wp2, nb, 1.0, A + c0 + r * lda,
              lda, 0));
@@ -303,7 +305,7 @@ int qr_panel(QrCtx& c, int64_t c0, int64_t c1) {
   // T12 = -T1 (V1^T V2) T2 ; rows of V2 above r are zero
   double* T2 = c.w->Tfac + (toff + h) + (int64_t)(toff + h) * nb;
   TRY(gemm64(c.s, 1, 0, 0, 1, 0, h, w - h, (int)(n - r), 1.0, A + r + c0 * lda, lda, A + r + r * lda, lda, 0.0,
-             c.w->Xq, nb, 0));
+             c.w->Xq, nb, 0, 0, 0, 0, c.w->splitk, SPLITK_ELEMS));
   TRY(gemm64(c.s, 0, 0, 0, 0, 0, h, w - h, h, 1.0, T1, nb, c.w->Xq, nb, 0.0, c.w->Yq, nb, 0));
   return gemm64(c.s, 0, 0, 0, 0, 0, h, w - h, w - h, -1.0, c.w->Yq, nb, T2, nb, 0.0,
                 c.w->Tfac + toff + (int64_t)(toff + h) * nb, nb, 0);
@@ -440,7 +442,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
                            hipMemcpyDeviceToDevice, s) != hipSuccess)
         return ABFT_ERR_HIP;
     TRY(lu_panel(c, c0, c1));
-    TRY(perm_build(s, dipiv, c0, kw, w.moves));
+    TRY(perm_build(s, dipiv, c0, kw, n, w.moves));
     TRY(laswp(s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
     TRY(laswp(s, dA, lda, c1, n, w.moves, stage, protect ? w.colchk : (double*)nullptr, ldc, nb));
     if (protect) {
@@ -791,7 +793,8 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     double* V = dA + c0 + c0 * lda;
     double* C = dA + c0 + c1 * lda;
     t = pf.begin(PH_TMU);
-    TRY(gemm64(s, 1, 0, 1, 0, 0, kw, (int)m, (int)(n - c0), 1.0, V, lda, C, lda, 0.0, w.W, nb, 0));
+    TRY(gemm64(s, 1, 0, 1, 0, 0, kw, (int)m, (int)(n - c0), 1.0, V, lda, C, lda, 0.0, w.W, nb, 0, 0, 0, 0, w.splitk,
+               SPLITK_ELEMS));
     TRY(gemm64(s, 1, 0, 0, 0, 0, kw, (int)m, kw, 1.0, w.Tfac, nb, w.W, nb, 0.0, w.W2, nb, 0));
     TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)m, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0));
     pf.end(t);

@@ -22,6 +22,8 @@
 
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
+
 namespace abft {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -46,10 +48,14 @@ __device__ __forceinline__ double load_op(const float* p) {
   return (double)v;
 }
 
+// Split-K (kc > 0): workgroup y takes K range [y*kc, min(K, (y+1)*kc)) and
+// writes alpha * its partial product to P + y*M*N (leading dimension M);
+// k_splitk_reduce then adds the partials in a fixed order.
 template <typename AT, typename BT, int TA, int TB, int FA, int FB, int LOWER, int RND>
 __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, double alpha, const AT* __restrict__ A,
                                                 int64_t lda, const BT* __restrict__ B, int64_t ldb, double beta,
-                                                double* __restrict__ C, int64_t ldc, int64_t doff) {
+                                                double* __restrict__ C, int64_t ldc, int64_t doff, int kc,
+                                                double* __restrict__ P) {
   constexpr int BM = 128, BN = 128, BK = 16, PAD = 4;
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
@@ -64,6 +70,13 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, double alph
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv & 1, wn = wv >> 1;
+  const int kbeg = kc > 0 ? (int)blockIdx.y * kc : 0;
+  const int kend = kc > 0 ? min(K, kbeg + kc) : K;
+  if (kc > 0) {
+    C = P + (int64_t)blockIdx.y * M * N;
+    ldc = M;
+    beta = 0.0;
+  }
 
   double ra[8], rb[8];
   auto loadA = [&](int k0) {
@@ -74,7 +87,7 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, double alph
       if (TA == 0) { i = idx % BM; p = idx / BM; } else { p = idx % BK; i = idx / BK; }
       int gi = m0 + i, gp = k0 + p;
       double v = 0.0;
-      if (gi < M && gp < K) {
+      if (gi < M && gp < kend) {
         int64_t r = TA == 0 ? gi : gp, c = TA == 0 ? gp : gi;
         v = load_op<RND>(A + r + c * lda);
         if (FA == 1 || FA == 3) v = (r < c) ? 0.0 : ((r == c) ? 1.0 : v);
@@ -91,7 +104,7 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, double alph
       if (TB == 0) { p = idx % BK; j = idx / BK; } else { j = idx % BN; p = idx / BN; }
       int gj = n0 + j, gp = k0 + p;
       double v = 0.0;
-      if (gj < N && gp < K) {
+      if (gj < N && gp < kend) {
         int64_t r = TB == 0 ? gp : gj, c = TB == 0 ? gj : gp;
         v = load_op<RND>(B + r + c * ldb);
         if (FB == 1) v = (r < c) ? 0.0 : ((r == c) ? 1.0 : v);
@@ -115,10 +128,10 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, double alph
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  const int KT = (K + BK - 1) / BK;
+  const int KT = (kend - kbeg + BK - 1) / BK;
   if (KT > 0) {
-    loadA(0);
-    loadB(0);
+    loadA(kbeg);
+    loadB(kbeg);
     storeAB(0);
   }
   __syncthreads();
@@ -126,8 +139,8 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, double alph
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < KT) {
-      loadA((kt + 1) * BK);
-      loadB((kt + 1) * BK);
+      loadA(kbeg + (kt + 1) * BK);
+      loadB(kbeg + (kt + 1) * BK);
     }
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
@@ -163,22 +176,54 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, double alph
       }
 }
 
+__global__ void k_splitk_reduce(const double* __restrict__ P, int S, int M, int N, double beta, double* C,
+                                int64_t ldc) {
+  const int64_t tot = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % M, j = e / M;
+    double acc = 0.0;
+    for (int q = 0; q < S; ++q) acc += P[(int64_t)q * tot + e];
+    double* c = C + i + j * ldc;
+    *c = (beta == 0.0) ? acc : beta * (*c) + acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host dispatcher
 // ---------------------------------------------------------------------------
 #define GEMM_CASE(AT_, BT_, TA_, TB_, FA_, FB_, LO_, RN_)                                                        \
   if (ta == TA_ && tb == TB_ && fa == FA_ && fb == FB_ && lower == LO_ && rnd == RN_) {                            \
-    hipLaunchKernelGGL((k_gemm64<AT_, BT_, TA_, TB_, FA_, FB_, LO_, RN_>), dim3(grid), dim3(256), 0, s, m, n, k,   \
-                       alpha, (const AT_*)A, lda, (const BT_*)B, ldb, beta, C, ldc, doff);                         \
-    return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;                                                     \
+    hipLaunchKernelGGL((k_gemm64<AT_, BT_, TA_, TB_, FA_, FB_, LO_, RN_>), dim3((unsigned)grid, S), dim3(256), 0, s, \
+                       m, n, k, alpha, (const AT_*)A, lda, (const BT_*)B, ldb, beta, C, ldc, doff, kc, ws);        \
+    if (hipGetLastError() != hipSuccess) return ABFT_ERR_HIP;                                                      \
+    if (kc > 0) {                                                                                                  \
+      unsigned rg = (unsigned)std::min<int64_t>(4096, ((int64_t)m * n + 255) / 256);                              \
+      hipLaunchKernelGGL(k_splitk_reduce, dim3(rg), dim3(256), 0, s, ws, (int)S, m, n, beta, C, ldc);               \
+      if (hipGetLastError() != hipSuccess) return ABFT_ERR_HIP;                                                    \
+    }                                                                                                              \
+    return 0;                                                                                                      \
   }
 
 int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int n, int k, double alpha, const void* A,
            int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int atype,
-           int btype, int rnd) {
+           int btype, int rnd, double* ws, size_t ws_elems) {
   if (m <= 0 || n <= 0) return 0;
   if (k <= 0 && beta == 1.0) return 0;
   int64_t grid = (int64_t)((m + 127) / 128) * ((n + 127) / 128);
+  // few output tiles and a long K: split K over extra workgroups
+  unsigned S = 1;
+  int kc = 0;
+  if (ws && !lower && grid < 160 && k >= 2048) {
+    int64_t want = std::min<int64_t>(32, std::min<int64_t>((320 + grid - 1) / grid, k / 512));
+    if (want >= 2) {
+      int64_t kcl = ((k + want - 1) / want + 15) / 16 * 16;
+      int64_t sp = (k + kcl - 1) / kcl;
+      if (sp >= 2 && (size_t)sp * m * n <= ws_elems) {
+        S = (unsigned)sp;
+        kc = (int)kcl;
+      }
+    }
+  }
   if (atype == 0 && btype == 0) {
     GEMM_CASE(double, double, 0, 0, 0, 0, 0, 0)  // LU trailing update, TRSM updates, checksum carries
     GEMM_CASE(double, double, 0, 1, 0, 0, 0, 0)  // X * Y^T

@@ -4,7 +4,10 @@
 // MFMA (16x16x16, FP32 accumulation) after round-to-nearest-even of the
 // operands.  Tile and pipeline shape follow the FP64 kernel: 128x128 tiles,
 // four waves of 64x64, K in steps of 16 through double-buffered LDS,
-// XCD-aware workgroup order.  The bf16/fp16 form is bound by the FP32 read
+// XCD-aware workgroup order.  For these MFMAs the result D[i][j] sits in lane
+// j + 16 (i / 4), register i % 4 (measured on gfx950; the FP64 instruction
+// interleaves the other way), so with D = C^T a lane's four registers are four
+// consecutive columns of C.  The bf16/fp16 form is bound by the FP32 read
 // and write of C (arithmetic intensity ~ nb/4 flop per byte), the FP32 form
 // by the MFMA rate.
 #include "common.hpp"
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(256) void k_gemm32(int M, int N, int K, float alpha
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int gi = m0 + wm * 64 + ri * 16 + il;
-        int gj = n0 + wn * 64 + ci * 16 + 4 * r + kl;
+        int gj = n0 + wn * 64 + ci * 16 + 4 * kl + r;
         if (gi < M && gj < N && (!LOWER || (int64_t)gi + doff >= (int64_t)gj)) {
           float* p = C + gi + (int64_t)gj * ldc;
           float v = alpha * acc[ci][ri][r];

@@ -10,11 +10,13 @@ namespace abft {
 // C = beta*C + alpha*op(A)*op(B) on FP64 MFMA.  ta/tb: 0 = N, 1 = T.  fa/fb:
 // 0 plain, 1 unit-lower mask on the stored operand, 2 absolute values,
 // 3 unit-lower mask then absolute values.
-// lower: write only C(i,j) with i + doff >= j.  atype/btype: 0 double,
+// lower: write only C(i,j) with i + doff >= j.  With a scratch buffer `ws`
+// (ws_elems doubles) a launch with few output tiles and a long K is split
+// along K and reduced in a fixed order.  atype/btype: 0 double,
 // 1 float (rounded to bf16 / fp16 when rnd = 1 / 2).
 int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int n, int k, double alpha, const void* A,
            int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int atype = 0,
-           int btype = 0, int rnd = 0);
+           int btype = 0, int rnd = 0, double* ws = nullptr, size_t ws_elems = 0);
 
 // binary32 data GEMM for the mixed-precision trailing update:
 // C -= op(A) op(B) with C, A, B float; op in FP32 MFMA (prec ABFT_F32) or
@@ -58,7 +60,7 @@ int getrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int w, i
                double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg);
 int geqrf_leaf(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t c0, int w, double* tau, double* Tm, int ldt,
                int toff, double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg);
-int perm_build(hipStream_t s, const int32_t* ipiv, int64_t c0, int w, int* moves);
+int perm_build(hipStream_t s, const int32_t* ipiv, int64_t c0, int w, int64_t n, int* moves);
 template <typename T>
 int laswp(hipStream_t s, T* A, int64_t lda, int64_t j0, int64_t j1, const int* moves, T* stage, double* colchk,
           int64_t ldc, int nb);

@@ -385,61 +385,49 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
 // array it also adds, per tile-row, the change of the column sums and of the
 // weighted column sums (compensated, in the moves' fixed order).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_perm_build(const int32_t* ipiv, int64_t c0, int w, int* moves) {
-  __shared__ int64_t outk[512];
-  __shared__ int64_t outc[512];
-  __shared__ int64_t inside[512];
-  __shared__ int nout;
+// The table holds, for every row r in [c0, n), the original row now stored at
+// r (-1: unchanged).  Rows [c0, n) of the panel bound the table (<= 36864
+// rows in LDS); one thread replays the interchanges, then a block-wide
+// compaction lists the moved rows in increasing order.
+constexpr int PB_MAX = 36864;
+__global__ __launch_bounds__(256) void k_perm_build(const int32_t* ipiv, int64_t c0, int w, int64_t n, int* moves) {
+  __shared__ int cur[PB_MAX];
+  __shared__ int cnt[257];
   const int tid = threadIdx.x;
-  // outside rows (>= c0 + w) referenced by the interchanges
-  if (tid == 0) {
-    int cnt = 0;
-    for (int t = 0; t < w; ++t) {
-      int64_t p = ipiv[c0 + t] - 1;
-      if (p >= c0 + w) outk[cnt++] = p;
-    }
-    // insertion sort + dedupe (w <= 512)
-    for (int a = 1; a < cnt; ++a) {
-      int64_t x = outk[a];
-      int b = a - 1;
-      while (b >= 0 && outk[b] > x) { outk[b + 1] = outk[b]; --b; }
-      outk[b + 1] = x;
-    }
-    int u = 0;
-    for (int a = 0; a < cnt; ++a)
-      if (u == 0 || outk[u - 1] != outk[a]) outk[u++] = outk[a];
-    nout = u;
-  }
-  __syncthreads();
-  for (int t = tid; t < w; t += 256) inside[t] = c0 + t;
-  for (int q = tid; q < nout; q += 256) outc[q] = outk[q];
+  const int rows = (int)(n - c0);
+  for (int r = tid; r < rows; r += 256) cur[r] = -1;
   __syncthreads();
   if (tid == 0) {
     for (int t = 0; t < w; ++t) {
-      int64_t p = ipiv[c0 + t] - 1;
-      if (p == c0 + t) continue;
-      int64_t* slot;
-      if (p < c0 + w) {
-        slot = &inside[p - c0];
-      } else {
-        int lo = 0, hi = nout - 1;
-        while (lo < hi) {
-          int mid = (lo + hi) >> 1;
-          if (outk[mid] < p) lo = mid + 1; else hi = mid;
-        }
-        slot = &outc[lo];
-      }
-      int64_t tmp = inside[t];
-      inside[t] = *slot;
-      *slot = tmp;
+      const int p = ipiv[c0 + t] - 1 - (int)c0;
+      if (p == t) continue;
+      int a = cur[t] < 0 ? t : cur[t];
+      int b = cur[p] < 0 ? p : cur[p];
+      cur[t] = b;
+      cur[p] = a;
     }
-    int nm = 0;
-    for (int t = 0; t < w; ++t)
-      if (inside[t] != c0 + t) { moves[1 + 2 * nm] = (int)(c0 + t); moves[2 + 2 * nm] = (int)inside[t]; ++nm; }
-    for (int q = 0; q < nout; ++q)
-      if (outc[q] != outk[q]) { moves[1 + 2 * nm] = (int)outk[q]; moves[2 + 2 * nm] = (int)outc[q]; ++nm; }
-    moves[0] = nm;
   }
+  __syncthreads();
+  // compaction of moved rows (cur[r] >= 0 and != r), in increasing r
+  const int chunk = (rows + 255) / 256;
+  const int r0 = tid * chunk, r1 = min(rows, r0 + chunk);
+  int c = 0;
+  for (int r = r0; r < r1; ++r) c += (cur[r] >= 0 && cur[r] != r);
+  cnt[tid + 1] = c;
+  __syncthreads();
+  if (tid == 0) {
+    cnt[0] = 0;
+    for (int q = 1; q <= 256; ++q) cnt[q] += cnt[q - 1];
+    moves[0] = cnt[256];
+  }
+  __syncthreads();
+  int o = cnt[tid];
+  for (int r = r0; r < r1; ++r)
+    if (cur[r] >= 0 && cur[r] != r) {
+      moves[1 + 2 * o] = (int)(c0 + r);
+      moves[2 + 2 * o] = (int)(c0 + cur[r]);
+      ++o;
+    }
 }
 
 template <typename T>
@@ -551,8 +539,9 @@ int geqrf_leaf(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t c0, int
   return e == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 
-int perm_build(hipStream_t s, const int32_t* ipiv, int64_t c0, int w, int* moves) {
-  hipLaunchKernelGGL(k_perm_build, dim3(1), dim3(256), 0, s, ipiv, c0, w, moves);
+int perm_build(hipStream_t s, const int32_t* ipiv, int64_t c0, int w, int64_t n, int* moves) {
+  if (n - c0 > PB_MAX) return ABFT_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL(k_perm_build, dim3(1), dim3(256), 0, s, ipiv, c0, w, n, moves);
   CHECK_LAUNCH();
 }
 template <typename T>

@@ -35,8 +35,12 @@ def test_mp_solve_matches_oracle(h, chol, prec, kappa):
     b = gen.rhs(n, seed=24)
     x, ir, rep = h.gesv_mp(dev(A), dev(b), PRECS[prec], nb=nb, chol=chol)
     xo, info, oir = oracle.gesv_mp(A, b, PRECS[prec], nb=nb, chol=chol)
-    assert ir.info == 0 and info == 0
-    assert bool(ir.converged) == bool(oir.converged), (ir.failed_reason, oir.failed_reason)
+    # at kappa = 1e10 the binary32 copy of an SPD matrix may lose definiteness:
+    # a failed factorization (info > 0) and a refinement that does not converge
+    # are the same outcome class
+    assert bool(ir.converged) == bool(oir.converged), (ir.failed_reason, oir.failed_reason, ir.info, info)
+    if kappa < 1e8:
+        assert ir.info == 0 and info == 0
     assert not rep.status & 4 and rep.flagged_tiles == 0
     if ir.converged:
         xr = oracle.solve_ref(A, b)
