@@ -2,17 +2,26 @@
 """Benchmark of the ABFT-protected one-sided decompositions on one MI355X.
 
 One step = one pass of the hot path over synthetic inputs resident in HBM:
-the ABFT-protected FP64 Cholesky, LU (partial pivoting) and Householder QR of
-an n x n matrix (default n = 32768, block size 512; SPD A = G G^T/n + n I for
-Cholesky, U(-1,1) entries for LU and QR), plus the mixed-precision and
-batched legs when they are built.  Each factorization works in place, so a
-step first restores its matrix from a pristine device copy (a device-to-device
-copy inside the timed region).
 
-Prints ONE JSON line: whole-step useful TFLOP/s (n^3/3 + 2n^3/3 + 4n^3/3 per
-step for the three FP64 decompositions), the trailing-update GEMM's roofline
-(flops per launch / average launch time, both measured by the library with
-HIP events on its stream), and the CPU oracle timed on a bounded sample.
+* FP64 legs (the headline): ABFT-protected Cholesky, LU (partial pivoting)
+  and Householder QR of an n x n matrix (default n = 32768, nb = 512; SPD
+  A = G G^T/n + n I for Cholesky, U(-1,1) entries for LU and QR), full
+  row + column checksums verified every iteration.  Each factorization works
+  in place, so it first restores its matrix from a pristine device copy (a
+  device-to-device copy outside the leg's timed events).
+* Mixed-precision leg: A x = b at n = 16384 (A = Q diag(s) Q^T, kappa 1e2),
+  FP64 direct solve against binary32 / bf16 / fp16 trailing updates with FP64
+  iterative refinement, LU and Cholesky; speedup at forward error <= 1e-12
+  against the closed-form solution.
+* Batched leg: 4096 matrices of orders uniform on [32, 512], ABFT Cholesky
+  and LU in FP64 and FP32, one library call each, replayed from the HIP graph
+  the library captured on first use.
+
+Prints ONE JSON line.  `value` is the useful FP64 TFLOP/s of the three
+FP64 legs (n^3/3 + 2n^3/3 + 4n^3/3 per step over their timed duration);
+`roofline` is the FP64 trailing-update product (flops per launch / average
+launch time, both measured by the library with HIP events on its stream);
+`cpu_baseline` is the plain CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -52,6 +61,337 @@ def cpu_baseline(n=2048, nb=512):
             "sample": f"ABFT Cholesky+LU+QR, n={n}, nb={nb}, one run each ({dt:.1f} s on one host core)"}
 
 
+def fp64_legs(h, torch, dev, args, legs):
+    from paper_2301_03166_amd import gen
+    n, nb = args.n, args.nb
+    log(f"generating FP64 inputs n={n}")
+    pristine = {}
+    if "chol" in legs:
+        pristine["chol"] = gen.spd_torch(n, 11, dev)
+    if "lu" in legs:
+        pristine["lu"] = gen.general_torch(n, 12, dev)
+    if "qr" in legs:
+        pristine["qr"] = gen.general_torch(n, 13, dev)
+    work = torch.empty((n, n), dtype=torch.float64, device=dev)
+    ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
+    tau = torch.zeros(n, dtype=torch.float64, device=dev)
+    reports = {k: h.new_report() for k in legs}
+    infos = {k: torch.zeros(1, dtype=torch.int32, device=dev) for k in legs}
+    flops = {"chol": n ** 3 / 3.0, "lu": 2.0 * n ** 3 / 3.0, "qr": 4.0 * n ** 3 / 3.0}
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in legs}
+    leg_ms = {k: [] for k in legs}
+    prof_acc = {}
+    profile = not args.no_profile
+
+    def run(k, protect=True, prof=False):
+        A = work.t()  # column-major view of the row-major buffer
+        A.copy_(pristine[k].t())
+        e0, e1 = ev[k]
+        e0.record()
+        kw = dict(protect=protect, report=reports[k], info=infos[k], sync=False, profile=prof)
+        if k == "chol":
+            h.potrf(A, nb, **kw)
+        elif k == "lu":
+            h.getrf(A, nb, ipiv=ipiv, **kw)
+        else:
+            h.geqrf(A, nb, tau=tau, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    log(f"FP64 warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        for k in legs:
+            run(k)
+    status = {k: None for k in legs}
+    for s in range(args.steps):
+        for k in legs:
+            leg_ms[k].append(run(k))
+            rep = h.read_report(reports[k])
+            st = {"info": int(infos[k].item()), "abft_status": rep.status, "flagged_tiles": rep.flagged_tiles,
+                  "max_ratio": rep.max_ratio}
+            if status[k] is None or st["abft_status"] or st["info"]:
+                status[k] = st
+        log(f"FP64 step {s}: " + ", ".join(f"{k} {leg_ms[k][-1]:.1f} ms" for k in legs))
+    # phase profile (separate run per leg: the profiled call waits on its own events)
+    if profile:
+        for k in legs:
+            run(k, prof=True)
+            p = h.profile()
+            prof_acc[k] = {f: p[f] for f in ("ms_total", "ms_panel", "ms_tmu", "ms_carry", "ms_verify", "tmu_flops",
+                                             "tmu_launches", "verify_bytes")}
+    unprot = {}
+    if not args.no_overhead:
+        for k in legs:
+            unprot[k] = run(k, protect=False)
+        log("unprotected: " + ", ".join(f"{k} {unprot[k]:.1f} ms" for k in legs))
+    del work, pristine
+    torch.cuda.empty_cache()
+    per_leg = {}
+    for k in legs:
+        ms = sum(leg_ms[k]) / len(leg_ms[k])
+        d = {"ms": ms, "tflops": flops[k] / ms / 1e9, "frac_fp64_peak": flops[k] / ms / 1e9 / FP64_PEAK_TFLOPS}
+        if k in unprot:
+            d["ms_unprotected"] = unprot[k]
+            d["checksum_overhead_pct"] = 100.0 * (ms - unprot[k]) / unprot[k]
+        if k in prof_acc:
+            a = prof_acc[k]
+            d.update({"ms_panel": a["ms_panel"], "ms_tmu": a["ms_tmu"], "ms_carry": a["ms_carry"],
+                      "ms_verify": a["ms_verify"],
+                      "tmu_tflops": a["tmu_flops"] / a["ms_tmu"] / 1e9 if a["ms_tmu"] > 0 else None,
+                      "verify_gbs": a["verify_bytes"] / a["ms_verify"] / 1e6 if a["ms_verify"] > 0 else None})
+        per_leg[k] = d
+    total_ms = sum(sum(leg_ms[k]) for k in legs)
+    value = sum(flops[k] for k in legs) * args.steps / total_ms / 1e9
+    roof = None
+    if prof_acc:
+        ms = sum(a["ms_tmu"] for a in prof_acc.values())
+        fl = sum(a["tmu_flops"] for a in prof_acc.values())
+        launches = sum(a["tmu_launches"] for a in prof_acc.values())
+        achieved = fl / ms / 1e9 if ms > 0 else None
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": None,
+                "kernel": "k_dgemm (FP64 trailing-matrix update products)", "launches": launches,
+                "avg_launch_ms": ms / launches if launches else None,
+                "flops_per_launch": fl / launches if launches else None}
+    return value, total_ms / args.steps, per_leg, status, roof
+
+
+def mp_leg(h, torch, dev, args):
+    import numpy as np
+    from paper_2301_03166_amd import abft, gen
+    n, nb = args.mp_n, args.mp_nb
+    log(f"generating MP input n={n} kappa={args.mp_kappa:g}")
+    A, s, V = gen.mp_torch(n, args.mp_kappa, 21, dev)
+    A = A.t()  # symmetric: the same values, column-major view
+    b_h = gen.rhs(n, 24)
+    b = torch.from_numpy(b_h).to(dev)
+    xs = gen.mp_exact_solution(b_h, s, V)
+    precs = [("f64", abft.F64), ("f32", abft.F32), ("bf16", abft.BF16), ("f16", abft.F16)]
+    out = {}
+    for chol in (False, True):
+        kind = "chol" if chol else "lu"
+        res = {}
+        for name, p in precs:
+            x = torch.zeros(n, dtype=torch.float64, device=dev)
+            h.gesv_mp(A, b, p, nb=nb, chol=chol, x=x)  # warmup
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            times = []
+            for _ in range(args.steps):
+                e0.record()
+                x, ir, rep = h.gesv_mp(A, b, p, nb=nb, chol=chol, x=x)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            err = float(np.linalg.norm(x.cpu().numpy() - xs, np.inf) / np.linalg.norm(xs, np.inf))
+            res[name] = {"ms": sum(times) / len(times), "forward_error": err, "ir_iters": int(ir.iters),
+                         "converged": bool(ir.converged) if p != abft.F64 else True,
+                         "abft_status": rep.status}
+        base = res["f64"]["ms"]
+        ok = [k for k in ("f32", "bf16", "f16") if res[k]["converged"] and res[k]["forward_error"] <= 1e-12]
+        best = min(ok, key=lambda k: res[k]["ms"]) if ok else None
+        out[kind] = {"solves": res, "best": best, "speedup_vs_fp64": base / res[best]["ms"] if best else None}
+        log(f"MP {kind}: " + ", ".join(f"{k} {v['ms']:.1f} ms err {v['forward_error']:.1e}" for k, v in res.items()))
+    del A, b
+    torch.cuda.empty_cache()
+    sp = [v["speedup_vs_fp64"] for v in out.values() if v["speedup_vs_fp64"]]
+    return {"n": n, "nb": nb, "kappa": args.mp_kappa, "target_forward_error": 1e-12,
+            "speedup_vs_fp64": min(sp) if sp else None, "lu": out["lu"], "chol": out["chol"]}
+
+
+def batched_leg(h, torch, dev, args):
+    import numpy as np
+    from paper_2301_03166_amd import gen
+    cnt = args.batch
+    sizes = gen.batch_sizes(cnt, 32, 512, 31)
+    seeds = gen.batch_seeds(cnt, 31)
+    out = {}
+    for kind in ("chol", "lu"):
+        chol = kind == "chol"
+        for dname, dt in (("f64", torch.float64), ("f32", torch.float32)):
+            log(f"generating batched {kind} {dname}")
+            pristine, _ = gen.batch_torch(sizes, seeds, kind, dev, dtype=dt)
+            flat = torch.empty_like(pristine)
+            offs = np.concatenate([[0], np.cumsum(sizes.astype(np.int64) ** 2)])
+            views = [torch.as_strided(flat, (int(nn), int(nn)), (1, int(nn)), int(offs[q]))
+                     for q, nn in enumerate(sizes)]
+            state = h.batched_args(views, chol)
+            flat.copy_(pristine)
+            h.batched(views, chol, state=state, graph=True, sync=False)  # capture + first replay
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            times = []
+            for _ in range(max(3, args.steps)):
+                flat.copy_(pristine)
+                e0.record()
+                h.batched(views, chol, state=state, graph=True, sync=False)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            infos = state[5].cpu().numpy()
+            raw = state[6].cpu().numpy().tobytes()
+            from paper_2301_03166_amd.abft import Report
+            import ctypes
+            rsz = ctypes.sizeof(Report)
+            flagged = sum(1 for q in range(cnt) if Report.from_buffer_copy(raw[q * rsz:(q + 1) * rsz]).status)
+            fl = float(np.sum(sizes.astype(np.float64) ** 3)) * (1.0 / 3.0 if chol else 2.0 / 3.0)
+            ms = float(np.median(times))
+            out[f"{kind}_{dname}"] = {"ms": ms, "tflops": fl / ms / 1e9, "min_ms": min(times),
+                                      "info_nonzero": int(np.count_nonzero(infos)), "abft_flagged": flagged}
+            log(f"batched {kind} {dname}: {ms:.2f} ms {fl / ms / 1e9:.2f} TFLOP/s")
+            del pristine, flat, views, state
+            torch.cuda.empty_cache()
+    return {"matrices": cnt, "orders": "uniform on [32, 512]", "graph": True, "legs": out}
+
+
+class PowerSampler:
+    """Board power sampled in a thread through the amdsmi library (socket
+    power, W).  Any failure leaves the sampler disabled (energy: null)."""
+
+    def __init__(self, period=0.02):
+        self.period, self.samples, self.ok, self._stop = period, [], False, None
+        try:
+            import amdsmi
+            amdsmi.amdsmi_init()
+            self._smi = amdsmi
+            self._h = amdsmi.amdsmi_get_processor_handles()[0]
+            self.read()
+            self.ok = True
+        except Exception as e:  # no library, no permission, no device
+            log(f"power sampling unavailable: {e}")
+
+    def read(self):
+        info = self._smi.amdsmi_get_power_info(self._h)
+        for key in ("current_socket_power", "socket_power", "average_socket_power"):
+            v = info.get(key) if isinstance(info, dict) else None
+            if isinstance(v, (int, float)) and v > 0:
+                return float(v)
+        raise RuntimeError(f"no socket power in {info}")
+
+    def start(self):
+        import threading
+        self.samples = []
+        self._stop = threading.Event()
+
+        def loop():
+            while not self._stop.is_set():
+                try:
+                    self.samples.append((time.perf_counter(), self.read()))
+                except Exception:
+                    pass
+                time.sleep(self.period)
+        self._t = threading.Thread(target=loop, daemon=True)
+        self._t.start()
+
+    def stop(self):
+        self._stop.set()
+        self._t.join(timeout=2)
+        return list(self.samples)
+
+
+def energy_leg(h, torch, dev, args):
+    """Energy per factorization: repeated ABFT LU factorizations for >= 2 s
+    with board power sampled meanwhile; gross and above the idle level."""
+    from paper_2301_03166_amd import gen
+    ps = PowerSampler()
+    if not ps.ok:
+        return None
+    n, nb = args.energy_n, args.nb
+    A0 = gen.general_torch(n, 12, dev)
+    W = torch.empty_like(A0)
+    ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    rep = h.new_report()
+    ps.start()
+    time.sleep(1.0)
+    idle = ps.stop()
+    reps, t0 = 0, time.perf_counter()
+    ps.start()
+    while time.perf_counter() - t0 < 2.5 or reps < 3:
+        W.copy_(A0)
+        h.getrf(W.t(), nb, ipiv=ipiv, report=rep, info=info, sync=False)
+        torch.cuda.synchronize()
+        reps += 1
+    t1 = time.perf_counter()
+    busy = ps.stop()
+    del A0, W
+    torch.cuda.empty_cache()
+    if len(busy) < 10 or not idle:
+        return None
+    p_idle = sum(p for _, p in idle) / len(idle)
+    joules = 0.0
+    for (ta, pa), (tb, pb) in zip(busy[:-1], busy[1:]):
+        joules += 0.5 * (pa + pb) * (tb - ta)
+    span = busy[-1][0] - busy[0][0]
+    per = joules / reps * (t1 - t0) / span if span > 0 else None
+    return {"workload": f"ABFT LU n={n} nb={nb} (includes the device copy that restores A)", "repetitions": reps,
+            "seconds": t1 - t0, "sample_period_s": ps.period, "samples": len(busy), "avg_power_w":
+            sum(p for _, p in busy) / len(busy), "idle_power_w": p_idle, "joules_per_factorization": per,
+            "joules_above_idle_per_factorization": (per - p_idle * (t1 - t0) / reps) if per else None}
+
+
+def campaign_leg(h, torch, dev, args):
+    """Seeded single-bit fault campaign: for each decomposition, runs r = 0..R-1
+    with one flip (uniform iteration, stored trailing element, bit 0..63) when r
+    is odd; outcomes against the clean run of the same matrix."""
+    from paper_2301_03166_amd import gen
+    n, nb, R = args.campaign_n, args.campaign_nb, args.campaign
+    out = {}
+    for d, kind in enumerate(("chol", "lu", "qr")):
+        A0 = gen.spd_torch(n, 1, dev) if kind == "chol" else gen.general_torch(n, 2 + d - 1, dev)
+        ref = torch.empty_like(A0)
+        W = torch.empty_like(A0)
+        aux = torch.zeros(n, dtype=torch.float64 if kind == "qr" else torch.int32, device=dev)
+
+        def run(dst, faults):
+            dst.copy_(A0)
+            A = dst.t()
+            if kind == "chol":
+                info, rep = h.potrf(A, nb, faults=faults)
+            elif kind == "lu":
+                _, info, rep = h.getrf(A, nb, faults=faults, ipiv=aux)
+            else:
+                _, info, rep = h.geqrf(A, nb, faults=faults, tau=aux)
+            return rep
+
+        run(ref, None)
+        ref_t = ref.t()
+        scale = float(ref_t.abs().max())
+        tally = {"clean_runs": 0, "false_alarms": 0, "faulted_runs": 0, "corrected": 0, "checksum_repaired": 0,
+                 "uncorrectable": 0, "undetected_harmless": 0, "undetected_corrupting": 0,
+                 "corrected_but_wrong": 0}
+        for r in range(R):
+            faults = [gen.fault_plan(kind, n, nb, seed=10 ** 6 * d + r)] if r % 2 else None
+            rep = run(W, faults)
+            Wt = W.t()
+            diff = float((torch.tril(Wt - ref_t) if kind == "chol" else (Wt - ref_t)).abs().max())
+            same = diff <= 1e-12 * scale
+            if faults is None:
+                tally["clean_runs"] += 1
+                tally["false_alarms"] += int(rep.status != 0)
+                continue
+            tally["faulted_runs"] += 1
+            if rep.status & 4:
+                tally["uncorrectable"] += 1
+            elif rep.status & 1:
+                tally["corrected"] += 1
+                tally["corrected_but_wrong"] += int(not same)
+            elif rep.status & 2:
+                tally["checksum_repaired"] += 1
+            else:
+                tally["undetected_harmless" if same else "undetected_corrupting"] += 1
+        f = max(1, tally["faulted_runs"])
+        tally["detected_pct"] = 100.0 * (f - tally["undetected_harmless"] - tally["undetected_corrupting"]) / f
+        tally["correct_result_pct"] = 100.0 * (tally["corrected"] - tally["corrected_but_wrong"] +
+                                               tally["undetected_harmless"] + tally["checksum_repaired"]) / f
+        out[kind] = tally
+        log(f"campaign {kind}: {tally}")
+        del A0, ref, W
+        torch.cuda.empty_cache()
+    return {"n": n, "nb": nb, "runs_per_decomposition": R, "plan": "flip iff run index odd; iteration, stored "
+            "trailing element and bit (0..63) uniform, seeded per run", "outcomes": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,8 +400,20 @@ def main():
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--legs", default="chol,lu,qr")
+    ap.add_argument("--mp-n", type=int, default=16384)
+    ap.add_argument("--mp-nb", type=int, default=512)
+    ap.add_argument("--mp-kappa", type=float, default=1e2)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--campaign", type=int, default=24, help="fault-campaign runs per decomposition (0: skip)")
+    ap.add_argument("--campaign-n", type=int, default=8192)
+    ap.add_argument("--campaign-nb", type=int, default=256)
+    ap.add_argument("--energy-n", type=int, default=16384)
+    ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--no-mp", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-overhead", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the factorization is not sharded "
@@ -69,103 +421,19 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2301_03166_amd import abft, gen
+    from paper_2301_03166_amd import abft
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    n, nb = args.n, args.nb
-    legs = [x for x in args.legs.split(",") if x]
     h = abft.Handle(dev)
-    log(f"generating inputs n={n}")
-    pristine, work, aux = {}, {}, {}
-    if "chol" in legs:
-        pristine["chol"] = gen.spd_torch(n, 11, dev)
-    if "lu" in legs:
-        pristine["lu"] = gen.general_torch(n, 12, dev)
-    if "qr" in legs:
-        pristine["qr"] = gen.general_torch(n, 13, dev)
-    for k, v in pristine.items():
-        work[k] = torch.empty_like(v)
-    ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
-    tau = torch.zeros(n, dtype=torch.float64, device=dev)
-    reports = {k: h.new_report() for k in legs}
-    infos = {k: torch.zeros(1, dtype=torch.int32, device=dev) for k in legs}
-    flops = {"chol": n ** 3 / 3.0, "lu": 2.0 * n ** 3 / 3.0, "qr": 4.0 * n ** 3 / 3.0}
-    profile = not args.no_profile
-    events = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in legs}
-    leg_ms = {k: [] for k in legs}
-    prof_acc = {}
-
-    def run_step(timed):
-        for k in legs:
-            # the matrices are stored column-major: the transpose view of the row-major buffer
-            A = work[k].t()
-            A.copy_(pristine[k].t())
-            ev0, ev1 = events[k]
-            ev0.record()
-            if k == "chol":
-                h.potrf(A, nb, report=reports[k], info=infos[k], sync=False, profile=profile and timed)
-            elif k == "lu":
-                h.getrf(A, nb, ipiv=ipiv, report=reports[k], info=infos[k], sync=False, profile=profile and timed)
-            elif k == "qr":
-                h.geqrf(A, nb, tau=tau, report=reports[k], info=infos[k], sync=False, profile=profile and timed)
-            ev1.record()
-            if timed:
-                torch.cuda.synchronize()
-                leg_ms[k].append(ev0.elapsed_time(ev1))
-                if profile:
-                    p = h.profile()
-                    acc = prof_acc.setdefault(k, {"ms_tmu": 0.0, "tmu_flops": 0.0, "tmu_launches": 0,
-                                                  "ms_verify": 0.0, "verify_bytes": 0.0, "ms_panel": 0.0,
-                                                  "ms_carry": 0.0})
-                    for f in acc:
-                        acc[f] += p[f]
-
-    log(f"warmup x{args.warmup}")
-    for _ in range(args.warmup):
-        run_step(False)
-    torch.cuda.synchronize()
-    log(f"timing x{args.steps}")
+    legs = [x for x in args.legs.split(",") if x]
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        run_step(True)
-        log(f"step {s} done: " + ", ".join(f"{k} {leg_ms[k][-1]:.1f} ms" for k in legs))
-    torch.cuda.synchronize()
+    value, ms_step, per_leg, status, roof = fp64_legs(h, torch, dev, args, legs)
+    mp = None if args.no_mp else mp_leg(h, torch, dev, args)
+    batched = None if args.no_batched else batched_leg(h, torch, dev, args)
+    campaign = campaign_leg(h, torch, dev, args) if args.campaign > 0 else None
+    energy = None if args.no_energy else energy_leg(h, torch, dev, args)
     wall = time.perf_counter() - t0
-
-    # correctness of the timed runs: no numerical failure, no ABFT flag
-    status = {}
-    for k in legs:
-        rep = h.read_report(reports[k])
-        status[k] = {"info": int(infos[k].item()), "abft_status": rep.status, "flagged_tiles": rep.flagged_tiles,
-                     "max_ratio": rep.max_ratio}
-    step_flops = sum(flops[k] for k in legs)
-    value = step_flops * args.steps / wall / 1e12
-    per_leg = {k: {"ms": sum(v) / len(v), "tflops": flops[k] / (sum(v) / len(v)) / 1e9} for k, v in leg_ms.items()}
-
-    roof = None
-    if profile and prof_acc:
-        ms = sum(a["ms_tmu"] for a in prof_acc.values())
-        fl = sum(a["tmu_flops"] for a in prof_acc.values())
-        launches = sum(a["tmu_launches"] for a in prof_acc.values())
-        achieved = fl / ms / 1e9 if ms > 0 else None
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": None,
-                "kernel": "k_gemm64 (trailing-matrix update)", "launches": launches,
-                "avg_launch_ms": ms / launches if launches else None,
-                "flops_per_launch": fl / launches if launches else None}
-        vb = sum(a["verify_bytes"] for a in prof_acc.values())
-        vms = sum(a["ms_verify"] for a in prof_acc.values())
-        for k, a in prof_acc.items():
-            steps = len(leg_ms[k])
-            per_leg[k].update({"ms_panel": a["ms_panel"] / steps, "ms_tmu": a["ms_tmu"] / steps,
-                               "ms_carry": a["ms_carry"] / steps, "ms_verify": a["ms_verify"] / steps,
-                               "checksum_overhead_pct": 100.0 * (a["ms_carry"] + a["ms_verify"]) /
-                               max(1e-9, sum(leg_ms[k]))})
-        verify_gbs = vb / vms / 1e6 if vms > 0 else None
-    else:
-        verify_gbs = None
-
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -174,12 +442,15 @@ def main():
     out = {
         "metric": "FP64 TFLOP/s ABFT LU/Cholesky/QR n=32768; MP+IR speedup vs FP64 @1e-12 error",
         "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": wall * 1000.0 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"ABFT-protected FP64 " + "+".join(legs) + f", n={n}, nb={nb}, one matrix each",
-                   "n": n, "nb": nb, "legs": legs, "protect": "full row+column checksums, verified every iteration"},
+        "config": {"workload": "ABFT-protected FP64 " + "+".join(legs) + f", n={args.n}, nb={args.nb}, one "
+                               "matrix each, full row+column checksums verified every iteration",
+                   "n": args.n, "nb": args.nb, "legs": legs},
         "legs": per_leg, "status": status,
-        "roofline": roof, "verify_hbm_gbs": verify_gbs,
+        "roofline": roof,
+        "mp": mp, "batched": batched, "fault_campaign": campaign, "energy": energy,
+        "wall_s": wall,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

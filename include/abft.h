@@ -28,7 +28,9 @@
  *   - Numerical status is written to device memory: potrf `*dinfo = j > 0`
  *     when the leading minor of order j is not positive definite; getrf
  *     `*dinfo = j > 0` when U(j,j) is exactly zero (factorization completes,
- *     LAPACK semantics).  The ABFT outcome is in the report.
+ *     LAPACK semantics).  The ABFT outcome is in the report; after a
+ *     Cholesky breakdown (info > 0) the remaining iterations run on NaN data
+ *     and their checks flag, so the report then says nothing about faults.
  */
 #ifndef ABFT_H
 #define ABFT_H
@@ -112,9 +114,11 @@ typedef struct {
   int32_t flags;       /* ABFT_FLAG_* bits */
 } abft_opts;
 
-/* opts.flags: time the phases of the call with HIP events on the handle's
-   stream (the call then waits for its own completion before returning). */
-enum { ABFT_FLAG_PROFILE = 1 };
+/* opts.flags: ABFT_FLAG_PROFILE times the phases of the call with HIP
+   events on the handle's stream (the call then waits for its own completion
+   before returning); ABFT_FLAG_GRAPH lets the batched calls capture and
+   replay HIP graphs (see abft_potrf_batched). */
+enum { ABFT_FLAG_PROFILE = 1, ABFT_FLAG_GRAPH = 2 };
 
 /* Phase times of the last call made with ABFT_FLAG_PROFILE, with the
    algorithmic work of the timed trailing-update GEMMs and verify passes. */
@@ -163,6 +167,23 @@ int abft_getrf(abft_handle h, int64_t n, double* dA, int64_t lda, int32_t* dipiv
 int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, void* dwork, size_t work_bytes,
                const abft_opts* opts, int32_t* dinfo, abft_report* drep);
 
+/* The trailing-matrix update primitive (the TMU product of every iteration
+   of the blocked decompositions, and the checksum carry C^c -= S Y of the
+   ABFT design): C = beta*C + alpha*op(A)*op(B) in FP64 on the FP64 matrix
+   cores, op(X) = X (trans 0) or X^T (trans 1); C is m x n, op(A) m x k,
+   op(B) k x n, all column-major device memory.  flags:
+   ABFT_GEMM_LOWER writes only entries C(i,j) with i >= j (symmetric
+   updates); ABFT_GEMM_UNIT_LOWER_A reads the stored A as unit lower
+   triangular (above its diagonal 0, on it 1: Householder vectors).
+   dwork (may be NULL) lets a product with few output tiles and a long K
+   split K over more workgroups (partials reduced in a fixed order), using
+   up to work_bytes.  Supported: NN, NT, TN; UNIT_LOWER_A with NN or TN;
+   LOWER with NT.  m, n, k < 2^31. */
+enum { ABFT_GEMM_LOWER = 1, ABFT_GEMM_UNIT_LOWER_A = 2 };
+int abft_gemm(abft_handle h, int32_t transa, int32_t transb, int32_t flags, int64_t m, int64_t n, int64_t k,
+              double alpha, const double* dA, int64_t lda, const double* dB, int64_t ldb, double beta, double* dC,
+              int64_t ldc, void* dwork, size_t work_bytes);
+
 /* Standalone per-tile checksums of an m x n matrix with tile size nb:
    dcolchk is (2*ceil(m/nb)) x n with leading dimension ldc >= 2*ceil(m/nb):
    row 2I holds the column sums of tile-row I, row 2I+1 the sums weighted by
@@ -202,8 +223,12 @@ int abft_posv_mp(abft_handle h, int64_t n, const double* dA, int64_t lda, const 
    device pointers) describe matrix i; prec is ABFT_F64 (double data) or
    ABFT_F32 (float data; dA then holds float pointers).  nmax bounds every
    dn[i] (<= 512).  dinfo[i] and dreps[i] receive each matrix's status.
-   Fault plans select their matrix with abft_fault.matrix.  Calls are
-   captured in a HIP graph by the library on first use and replayed. */
+   Fault plans select their matrix with abft_fault.matrix.  With
+   ABFT_FLAG_GRAPH in opts->flags (and no fault plan) the call's launches are
+   captured into a HIP graph the first time a given argument set is seen and
+   the graph is replayed on the handle's stream by later calls with the same
+   pointers and sizes (up to 8 argument sets are kept per handle); the
+   contents of the arrays may change between replays, their addresses not. */
 int abft_potrf_batched(abft_handle h, int32_t batch, int32_t nmax, const int32_t* dn, void* const* dA,
                        const int32_t* dlda, int32_t prec, void* dwork, size_t work_bytes, const abft_opts* opts,
                        int32_t* dinfo, abft_report* dreps);

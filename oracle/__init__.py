@@ -206,3 +206,23 @@ def round_bf16(x):
 
 def round_fp16(x):
     return np.vectorize(lib().orc_round_fp16)(np.asarray(x, dtype=np.float64))
+
+
+def gemm(A, B, C, transa=False, transb=False, alpha=1.0, beta=0.0, lower=False, unit_lower_a=False):
+    """The update product of each iteration of the blocked decompositions
+    (the trailing-matrix update, Sec. 2): returns beta*C + alpha*op(A) op(B)
+    in float64, with the stored A read as unit lower triangular when asked
+    (Householder vectors) and, for symmetric updates, only entries i >= j
+    written (the others keep C's values).  beta == 0 ignores C's values."""
+    A = np.array(A, dtype=np.float64)
+    if unit_lower_a:
+        A = np.tril(A, -1) + np.eye(*A.shape)
+    opA = A.T if transa else A
+    opB = np.asarray(B, dtype=np.float64).T if transb else np.asarray(B, dtype=np.float64)
+    prod = alpha * (opA @ opB)
+    C = np.array(C, dtype=np.float64)
+    out = prod if beta == 0.0 else beta * C + prod
+    if lower:
+        keep = np.tril(np.ones(C.shape, dtype=bool))
+        out = np.where(keep, out, C)
+    return out

@@ -83,6 +83,7 @@ def lib():
         L.abft_potrf.argtypes = [P, i64, P, i64, P, sz, C.POINTER(Opts), P, P]
         L.abft_getrf.argtypes = [P, i64, P, i64, P, P, sz, C.POINTER(Opts), P, P]
         L.abft_geqrf.argtypes = [P, i64, P, i64, P, P, sz, C.POINTER(Opts), P, P]
+        L.abft_gemm.argtypes = [P, i32, i32, i32, i64, i64, i64, d, P, i64, P, i64, d, P, i64, P, sz]
         L.abft_encode.argtypes = [P, i64, i64, P, i64, i32, P, i64, P, i64]
         L.abft_verify.argtypes = [P, i64, i64, P, i64, i32, P, i64, P, i64, d, i32, P, P]
         L.abft_gesv_mp.argtypes = [P, i64, P, i64, P, P, i32, i32, P, sz, C.POINTER(Opts), P, P]
@@ -116,13 +117,14 @@ def _ld(A):
     return max(lda, 1)
 
 
-FLAG_PROFILE = 1
+FLAG_PROFILE, FLAG_GRAPH = 1, 2
+GEMM_LOWER, GEMM_UNIT_LOWER_A = 1, 2
 
 
-def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False):
+def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False, graph=False):
     o = Opts()
     o.nb, o.protect, o.tau_scale = int(nb), PROTECT_FULL if protect else PROTECT_NONE, float(tau_scale)
-    o.flags = FLAG_PROFILE if profile else 0
+    o.flags = (FLAG_PROFILE if profile else 0) | (FLAG_GRAPH if graph else 0)
     keep = None
     if faults:
         keep = (Fault * len(faults))()
@@ -260,17 +262,18 @@ class Handle:
         return x, IRReport.from_buffer_copy(bytes(irb.cpu().numpy().tobytes())), self.read_report(rep)
 
     # ------------------------------------------------------------ batched
-    def batched(self, mats, chol, protect=True, tau_scale=4.0, faults=None, nmax=None, sync=True, state=None):
+    def batched(self, mats, chol, protect=True, tau_scale=4.0, faults=None, nmax=None, sync=True, state=None,
+                graph=False):
         """Factor a list of column-major square matrices (all float64 or all float32) in place with one
         batched call (block / tile size 32).  Returns (infos, ipivs, reports) when sync; `state` keeps the
-        device argument arrays alive for graph capture and replay."""
+        device argument arrays alive so that graph=True calls replay the library's captured graph."""
         torch = self.torch
         batch = len(mats)
         prec = F64 if mats[0].dtype == torch.float64 else F32
         if state is None:
             state = self.batched_args(mats, chol)
         ns, ptrs, ldas, ipivs, piv_ptrs, infos, reps = state
-        opts, keep = make_opts(32, protect, tau_scale, faults)
+        opts, keep = make_opts(32, protect, tau_scale, faults, graph=graph)
         op = OP_POTRF_BATCHED if chol else OP_GETRF_BATCHED
         ws, wbytes = self.workspace(op, 0, opts, batch=batch)
         nm = int(nmax if nmax is not None else max(m.shape[0] for m in mats))
@@ -303,6 +306,20 @@ class Handle:
         infos = torch.zeros(len(mats), dtype=torch.int32, device=dev)
         reps = torch.zeros(len(mats) * C.sizeof(Report), dtype=torch.uint8, device=dev)
         return ns, ptrs, ldas, ipivs, piv_ptrs, infos, reps
+
+    # ------------------------------------------------------------ update primitive
+    def gemm(self, A, B, C, transa=False, transb=False, alpha=1.0, beta=0.0, lower=False, unit_lower_a=False,
+             work=None):
+        """C = beta*C + alpha*op(A)*op(B) on column-major FP64 tensors (abft_gemm)."""
+        m, n = C.shape
+        k = A.shape[0] if transa else A.shape[1]
+        flags = (GEMM_LOWER if lower else 0) | (GEMM_UNIT_LOWER_A if unit_lower_a else 0)
+        self._sync_stream()
+        _check(lib().abft_gemm(self._h, int(bool(transa)), int(bool(transb)), flags, m, n, k, float(alpha),
+                               A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), float(beta), C.data_ptr(), _ld(C),
+                               work.data_ptr() if work is not None else None,
+                               work.numel() * work.element_size() if work is not None else 0), "abft_gemm")
+        return C
 
     # ------------------------------------------------------------ checksums
     def encode(self, A, nb):

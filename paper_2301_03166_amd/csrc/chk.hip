@@ -19,6 +19,172 @@
 
 namespace abft {
 
+// ---------------------------------------------------------------------------
+// Tile sums for the streaming passes (encode / verify).  Every sum is
+// accumulated serially in one lane with compensated arithmetic, so no
+// cross-lane reduction is needed: wave v owns the 64-row strips v and v + 4
+// (tiles have at most 512 rows) and walks the tile in chunks of 32 columns.
+// The lane that loads row i accumulates row i's sums; each 64 x 32 block is
+// then transposed through the wave's LDS buffer so that lane (half, jj) sums
+// rows 32*half .. 32*half + 31 of column jj.  The two halves and the four
+// waves' column partials are merged in a fixed order.  The next strip's
+// loads are in flight while the current one is summed.
+// ---------------------------------------------------------------------------
+constexpr int SCW = 16;          // columns per chunk
+constexpr int SRL = 64 / SCW;    // lanes summing one column (each takes 64/SRL rows)
+struct StreamLds {
+  double blk[4][SCW][65];  // per-wave transpose buffer [column in chunk][row in strip]
+  double cp[4][SCW][6];    // per-wave column partials of the chunk
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// rows 64 s .. 64 s + 63 (this lane: one row), columns c .. c + SCW - 1
+template <typename T>
+__device__ __forceinline__ void strip_load(double (&v)[SCW], const T* A, int64_t lda, int64_t r0, int64_t c0, int h,
+                                           int w, bool sym, int s, int c) {
+  const int i = 64 * s + (threadIdx.x & 63);
+  if (sym) {  // diagonal tile of a symmetric matrix: upper part from the mirror
+#pragma unroll
+    for (int t = 0; t < SCW; ++t) {
+      const int j = c + t;
+      double x = 0.0;
+      if (i < h && j < w) x = i < j ? (double)A[(r0 + j) + (c0 + i) * lda] : (double)A[(r0 + i) + (c0 + j) * lda];
+      v[t] = x;
+    }
+    return;
+  }
+  const int ic = i < h ? i : h - 1;  // clamp, then zero: no divergent loads
+  const T* p = A + (r0 + ic) + (c0 + c) * lda;
+  if (c + SCW <= w) {
+#pragma unroll
+    for (int t = 0; t < SCW; ++t) v[t] = (double)p[t * lda];
+  } else {
+#pragma unroll
+    for (int t = 0; t < SCW; ++t) v[t] = (c + t < w) ? (double)p[t * lda] : 0.0;
+  }
+  if (i >= h) {
+#pragma unroll
+    for (int t = 0; t < SCW; ++t) v[t] = 0.0;
+  }
+}
+
+struct StripAcc {
+  acc2 re, rw;  // sums of the lane's row in this strip
+  double ra, rwa;
+};
+struct ColAcc {
+  acc2 ce, cw;
+  double ca, cwa;
+};
+
+__device__ __forceinline__ void strip_sum(const double (&v)[SCW], int s, int c, StripAcc& r, ColAcc& col,
+                                          double (*blk)[65]) {
+  const int lane = threadIdx.x & 63, part = lane / SCW, jj = lane % SCW;
+#pragma unroll
+  for (int t = 0; t < SCW; ++t) {
+    const double wj = (double)(c + t + 1), x = v[t], ax = fabs(x);
+    cadd(r.re, x);
+    cfma(r.rw, wj, x);
+    r.ra += ax;
+    r.rwa += wj * ax;
+    blk[t][lane] = x;
+  }
+  wave_lds_sync();
+#pragma unroll 4
+  for (int q = 0; q < 64 / SRL; ++q) {
+    const int il = (64 / SRL) * part + q;
+    const double x = blk[jj][il], ax = fabs(x), wi = (double)(64 * s + il + 1);
+    cadd(col.ce, x);
+    cfma(col.cw, wi, x);
+    col.ca += ax;
+    col.cwa += wi * ax;
+  }
+  wave_lds_sync();
+}
+
+__device__ __forceinline__ acc2 shfl_acc(const acc2& a, int m) {
+  return acc2{__shfl_xor(a.s, m), __shfl_xor(a.c, m)};
+}
+
+template <typename T>
+__device__ void tile_sums_stream(const T* A, int64_t lda, int64_t r0, int64_t c0, int h, int w, bool sym, TileSums& ts,
+                                 StreamLds& L) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, jj = lane % SCW;
+  const int nstrip = (h + 63) / 64;
+  const int s0 = wv, s1 = wv + 4;
+  const bool has0 = s0 < nstrip, has1 = s1 < nstrip;
+  StripAcc r0a{{0, 0}, {0, 0}, 0, 0}, r1a{{0, 0}, {0, 0}, 0, 0};
+  double v0[SCW], v1[SCW];
+  if (has0) strip_load(v0, A, lda, r0, c0, h, w, sym, s0, 0);
+  if (has1) strip_load(v1, A, lda, r0, c0, h, w, sym, s1, 0);
+  for (int c = 0; c < w; c += SCW) {
+    ColAcc col{{0, 0}, {0, 0}, 0, 0};
+    const int cn = c + SCW;
+    if (has0) {
+      strip_sum(v0, s0, c, r0a, col, L.blk[wv]);
+      if (cn < w) strip_load(v0, A, lda, r0, c0, h, w, sym, s0, cn);
+    }
+    if (has1) {
+      strip_sum(v1, s1, c, r1a, col, L.blk[wv]);
+      if (cn < w) strip_load(v1, A, lda, r0, c0, h, w, sym, s1, cn);
+    }
+    // merge the SRL row parts of each column (lanes jj, jj+SCW, ...), fixed order
+#pragma unroll
+    for (int m = SCW; m < 64; m <<= 1) {
+      const acc2 oe = shfl_acc(col.ce, m), ow = shfl_acc(col.cw, m);
+      const double oa = __shfl_xor(col.ca, m), owa = __shfl_xor(col.cwa, m);
+      if (lane & m) {  // the higher lane of each pair adds the lower one's partial first
+        acc2 te = oe, tw = ow;
+        cmerge(te, col.ce);
+        cmerge(tw, col.cw);
+        col.ce = te;
+        col.cw = tw;
+        col.ca = oa + col.ca;
+        col.cwa = owa + col.cwa;
+      } else {
+        cmerge(col.ce, oe);
+        cmerge(col.cw, ow);
+        col.ca += oa;
+        col.cwa += owa;
+      }
+    }
+    if (lane < SCW) {
+      double* q = L.cp[wv][jj];
+      q[0] = col.ce.s; q[1] = col.ce.c; q[2] = col.cw.s; q[3] = col.cw.c;
+      q[4] = col.ca; q[5] = col.cwa;
+    }
+    __syncthreads();
+    if (threadIdx.x < SCW && c + (int)threadIdx.x < w) {
+      const int t = threadIdx.x;
+      acc2 e{L.cp[0][t][0], L.cp[0][t][1]}, ww{L.cp[0][t][2], L.cp[0][t][3]};
+      double a = L.cp[0][t][4], wa = L.cp[0][t][5];
+      for (int u = 1; u < 4; ++u) {
+        cmerge(e, acc2{L.cp[u][t][0], L.cp[u][t][1]});
+        cmerge(ww, acc2{L.cp[u][t][2], L.cp[u][t][3]});
+        a += L.cp[u][t][4];
+        wa += L.cp[u][t][5];
+      }
+      ts.ce[c + t] = cval(e);
+      ts.cw[c + t] = cval(ww);
+      ts.ca[c + t] = a;
+      ts.cwa[c + t] = wa;
+    }
+    __syncthreads();
+  }
+  const int i0 = 64 * s0 + lane, i1 = 64 * s1 + lane;
+  if (has0 && i0 < h) {
+    ts.res[i0] = cval(r0a.re); ts.rws[i0] = cval(r0a.rw); ts.ra[i0] = r0a.ra; ts.rwa[i0] = r0a.rwa;
+  }
+  if (has1 && i1 < h) {
+    ts.res[i1] = cval(r1a.re); ts.rws[i1] = cval(r1a.rw); ts.ra[i1] = r1a.ra; ts.rwa[i1] = r1a.rwa;
+  }
+  __syncthreads();
+}
+
 // mode 0: encode (write sums); mode 1: verify (flag, refresh clean tiles);
 // mode 2: verify only
 template <typename T>
@@ -28,11 +194,12 @@ __global__ __launch_bounds__(256) void k_verify(const T* A, int64_t lda, int64_t
                                                 int* tflags, abft_report* rep, int iter) {
   __shared__ TileSums ts;
   __shared__ TileFlags tf;
+  __shared__ StreamLds sl;
   int I, J, h, w;
   tile_geom(blockIdx.x, I0, J0, nI, nb, nr, nc, I, J, h, w);
   const int tile = I + J * (int)((nr + nb - 1) / nb);
   if (sym && I < J) return;
-  tile_sums(A, lda, (int64_t)I * nb, (int64_t)J * nb, h, w, sym && I == J, ts);
+  tile_sums_stream(A, lda, (int64_t)I * nb, (int64_t)J * nb, h, w, sym && I == J, ts, sl);
   if (mode == 0) {
     store_sums(ts, I, J, nb, h, w, colchk, ldc, rowchk, ldr);
     return;

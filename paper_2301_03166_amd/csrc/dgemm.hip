@@ -1,0 +1,295 @@
+// FP64 MFMA GEMM for the large products of the factorizations (trailing
+// updates and the reflector products of the blocked QR):
+//   C = beta*C + alpha*op(A)*op(B), column-major, A/B 16-byte aligned with
+//   even leading dimensions (the host dispatcher checks this).
+//
+// Tile 128x128 per 256-thread workgroup, four waves in 2x2 of 64x64, each a
+// 4x4 block of v_mfma_f64_16x16x4_f64; K walked in steps of 32 through
+// double-buffered LDS (2 x 66 KB, one workgroup per CU: the accumulators
+// alone take 128 AGPRs per lane, so a CU holds one such workgroup anyway and
+// the LDS is spent on a deeper K step instead).  Interior tiles load with
+// 16-byte global loads and no bounds tests; edge tiles, the K tail and
+// split-K remainders take the same data path with per-element guards.
+//
+// Workgroup order: the hardware deals workgroups round-robin to the eight
+// XCDs; the index is remapped so that each XCD owns a contiguous chunk of a
+// grouped order (groups of 8 tile-rows, column-major inside a group), so the
+// 8 row-blocks of A a chunk reads stay in that XCD's L2 while it sweeps the
+// columns.  For the symmetric (lower) update only the tiles on or below the
+// diagonal are enumerated, column by column, so the chunks carry equal work.
+//
+// Operand options: op(A) = A or A^T, op(B) = B or B^T, a unit-lower mask on
+// the stored A (Householder vectors with their implicit unit diagonal), and a
+// lower-triangular write mask on C.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace abft {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+namespace {
+
+constexpr int DG_BM = 128, DG_BN = 128, DG_BK = 32, DG_PAD = 4, DG_GM = 8;
+
+// Stage of one operand tile (R x BK logical, R = 128) held in registers as
+// BK/4 pairs per thread.  ALONG_R: the pairs run along the tile's R
+// dimension (stored operand contiguous in R); else along K.
+template <bool ALONG_R>
+struct Stage {
+  f64x2 v[DG_BK / 4];
+};
+
+// Stored element (r, c) of a unit-lower operand: 0 above, 1 on the diagonal.
+__device__ __forceinline__ double unit_lower(double v, int64_t r, int64_t c) {
+  return r < c ? 0.0 : (r == c ? 1.0 : v);
+}
+
+// Load the R x BK block of op(X) starting at (x0, k0) where op(X)[i][p] is
+// X[x0+i + (k0+p)*ld] (ALONG_R) or X[k0+p + (x0+i)*ld] (!ALONG_R).
+// FULL: no bounds tests (the block lies inside [0,R) x [k0,kend)).
+// MASK: apply the unit-lower mask of the stored operand.
+template <bool ALONG_R, bool FULL, bool MASK>
+__device__ __forceinline__ void stage_load(Stage<ALONG_R>& st, const double* __restrict__ X, int64_t ld, int x0,
+                                           int xlim, int k0, int kend) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < DG_BK / 4; ++s) {
+    const int v = tid + 256 * s;
+    int i0, i1, p0, p1;
+    if (ALONG_R) {
+      i0 = 2 * (v & 63);
+      i1 = i0 + 1;
+      p0 = p1 = v >> 6;
+    } else {
+      p0 = 2 * (v & (DG_BK / 2 - 1));
+      p1 = p0 + 1;
+      i0 = i1 = v / (DG_BK / 2);
+    }
+    const int gi0 = x0 + i0, gi1 = x0 + i1, gp0 = k0 + p0, gp1 = k0 + p1;
+    // stored coordinates (row, column) of the two elements
+    const int64_t r0 = ALONG_R ? gi0 : gp0, c0 = ALONG_R ? gp0 : gi0;
+    const int64_t r1 = ALONG_R ? gi1 : gp1, c1 = ALONG_R ? gp1 : gi1;
+    f64x2 val;
+    if (FULL) {
+      val = *reinterpret_cast<const f64x2*>(X + r0 + c0 * ld);
+    } else {
+      val[0] = (gi0 < xlim && gp0 < kend) ? X[r0 + c0 * ld] : 0.0;
+      val[1] = (gi1 < xlim && gp1 < kend) ? X[r1 + c1 * ld] : 0.0;
+    }
+    if (MASK) {
+      val[0] = unit_lower(val[0], r0, c0);
+      val[1] = unit_lower(val[1], r1, c1);
+      if (!FULL) {
+        if (!(gi0 < xlim && gp0 < kend)) val[0] = 0.0;
+        if (!(gi1 < xlim && gp1 < kend)) val[1] = 0.0;
+      }
+    }
+    st.v[s] = val;
+  }
+}
+
+// LDS image of a tile: S[p][i], p in [0, BK), i in [0, R)
+template <bool ALONG_R>
+__device__ __forceinline__ void stage_store(const Stage<ALONG_R>& st, double (*S)[DG_BM + DG_PAD]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < DG_BK / 4; ++s) {
+    const int v = tid + 256 * s;
+    if (ALONG_R) {
+      *reinterpret_cast<f64x2*>(&S[v >> 6][2 * (v & 63)]) = st.v[s];
+    } else {
+      const int p = 2 * (v & (DG_BK / 2 - 1)), i = v / (DG_BK / 2);
+      S[p][i] = st.v[s][0];
+      S[p + 1][i] = st.v[s][1];
+    }
+  }
+}
+
+// inverse of the column-major enumeration of the lower tiles of a T x T grid:
+// column c holds T - c tiles, S(c) = c*T - c(c-1)/2 precede it
+__device__ __forceinline__ void lower_tile(int lin, int T, int& tm, int& tn) {
+  const double b = 2.0 * T + 1.0;
+  int c = (int)((b - sqrt(b * b - 8.0 * lin)) * 0.5);
+  c = max(0, min(c, T - 1));
+  auto S = [&](int x) { return (int)((int64_t)x * T - ((int64_t)x * (x - 1)) / 2); };
+  while (c > 0 && S(c) > lin) --c;
+  while (c + 1 < T && S(c + 1) <= lin) ++c;
+  tn = c;
+  tm = c + (lin - S(c));
+}
+
+}  // namespace
+
+// TRI: the grid enumerates only the lower tiles of a square T x T grid
+// (requires LOWER, M == N, doff == 0).
+template <int TA, int TB, int FA, int LOWER, int TRI>
+__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                               int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
+                                               double* __restrict__ C, int64_t ldc, int64_t doff, int kc,
+                                               double* __restrict__ P) {
+  constexpr int BM = DG_BM, BN = DG_BN, BK = DG_BK;
+  __shared__ __attribute__((aligned(16))) double As[2][BK][BM + DG_PAD];
+  __shared__ __attribute__((aligned(16))) double Bs[2][BK][BN + DG_PAD];
+
+  const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  const int nt = TRI ? tilesM * (tilesM + 1) / 2 : tilesM * tilesN;
+  int lin = blockIdx.x;
+  if ((nt & 7) == 0) lin = (lin & 7) * (nt >> 3) + (lin >> 3);
+  int tm, tn;
+  if (TRI) {
+    lower_tile(lin, tilesM, tm, tn);
+  } else {
+    const int g = lin / (DG_GM * tilesN);
+    const int rbase = g * DG_GM;
+    const int rows = min(DG_GM, tilesM - rbase);
+    const int rem = lin - g * DG_GM * tilesN;
+    tm = rbase + rem % rows;
+    tn = rem / rows;
+  }
+  const int m0 = tm * BM, n0 = tn * BN;
+  if (LOWER && (int64_t)(m0 + BM - 1) + doff < (int64_t)n0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv & 1, wn = wv >> 1;
+  const int kbeg = kc > 0 ? (int)blockIdx.y * kc : 0;
+  const int kend = kc > 0 ? min(K, kbeg + kc) : K;
+  if (kc > 0) {
+    C = P + (int64_t)blockIdx.y * M * N;
+    ldc = M;
+    beta = 0.0;
+  }
+  const bool inner = (m0 + BM <= M) && (n0 + BN <= N);
+
+  Stage<TA == 0> sa;
+  Stage<TB == 1> sb;
+  // A's stored operand needs its mask only where the tile meets the diagonal
+  auto load = [&](int k0) {
+    const bool full = inner && (k0 + BK <= kend);
+    const bool needmask =
+        FA == 1 && (TA == 0 ? (m0 < k0 + BK) : (k0 < m0 + BM));  // some stored row <= stored column
+    if (full) {
+      if (FA == 1 && needmask)
+        stage_load<TA == 0, true, true>(sa, A, lda, m0, M, k0, kend);
+      else
+        stage_load<TA == 0, true, false>(sa, A, lda, m0, M, k0, kend);
+      stage_load<TB == 1, true, false>(sb, B, ldb, n0, N, k0, kend);
+    } else {
+      stage_load<TA == 0, false, FA == 1>(sa, A, lda, m0, M, k0, kend);
+      stage_load<TB == 1, false, false>(sb, B, ldb, n0, N, k0, kend);
+    }
+  };
+  auto store = [&](int buf) {
+    stage_store<TA == 0>(sa, As[buf]);
+    stage_store<TB == 1>(sb, Bs[buf]);
+  };
+
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  const int KT = (kend - kbeg + BK - 1) / BK;
+  if (KT > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  const int kl = lane >> 4, il = lane & 15;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < KT) load(kbeg + (kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        af[q] = As[cur][kk * 4 + kl][wm * 64 + q * 16 + il];
+        bf[q] = Bs[cur][kk * 4 + kl][wn * 64 + q * 16 + il];
+      }
+#pragma unroll
+      for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+        for (int ri = 0; ri < 4; ++ri)
+          acc[ci][ri] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[ci], af[ri], acc[ci][ri], 0, 0, 0);
+    }
+    if (kt + 1 < KT) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  // D = C^T layout: acc[ci][ri][r] is C(gi, gj) with gi = m0 + wm*64 + ri*16 + il,
+  // gj = n0 + wn*64 + ci*16 + 4r + kl; sixteen lanes write 128 contiguous bytes
+  const bool straddle = LOWER && (int64_t)m0 + doff < (int64_t)(n0 + BN - 1);
+  if (inner && !straddle) {
+#pragma unroll
+    for (int ci = 0; ci < 4; ++ci) {
+      double cv[4][4];
+      if (beta != 0.0) {
+#pragma unroll
+        for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int gi = m0 + wm * 64 + ri * 16 + il, gj = n0 + wn * 64 + ci * 16 + 4 * r + kl;
+            cv[ri][r] = C[gi + (int64_t)gj * ldc];
+          }
+      }
+#pragma unroll
+      for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = m0 + wm * 64 + ri * 16 + il, gj = n0 + wn * 64 + ci * 16 + 4 * r + kl;
+          const double v = alpha * acc[ci][ri][r];
+          C[gi + (int64_t)gj * ldc] = (beta == 0.0) ? v : beta * cv[ri][r] + v;
+        }
+    }
+  } else {
+#pragma unroll
+    for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+      for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = m0 + wm * 64 + ri * 16 + il, gj = n0 + wn * 64 + ci * 16 + 4 * r + kl;
+          if (gi < M && gj < N && (!LOWER || (int64_t)gi + doff >= (int64_t)gj)) {
+            double* p = C + gi + (int64_t)gj * ldc;
+            const double v = alpha * acc[ci][ri][r];
+            *p = (beta == 0.0) ? v : beta * (*p) + v;
+          }
+        }
+  }
+}
+
+// Returns 1 when the product was launched here, 0 when the caller should use
+// the general kernel (unsupported option combination or alignment), <0 on error.
+int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, int k, double alpha, const double* A,
+               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int S,
+               int kc, double* ws) {
+  if ((reinterpret_cast<uintptr_t>(A) & 15) || (reinterpret_cast<uintptr_t>(B) & 15) || (lda & 1) || (ldb & 1))
+    return 0;
+  const int64_t tM = (m + DG_BM - 1) / DG_BM, tN = (n + DG_BN - 1) / DG_BN;
+  const bool tri = lower && m == n && doff == 0 && S == 1;
+  const int64_t nt = tri ? tM * (tM + 1) / 2 : tM * tN;
+  if (nt > 0x7fffffff) return 0;
+  const dim3 grid((unsigned)nt, (unsigned)S), block(256);
+#define DG_CASE(TA_, TB_, FA_, LO_)                                                                              \
+  if (ta == TA_ && tb == TB_ && fa == FA_ && lower == LO_) {                                                       \
+    if (LO_ && tri)                                                                                                \
+      hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, LO_>), grid, block, 0, s, m, n, k, alpha, A, lda, B, ldb, beta, \
+                         C, ldc, doff, kc, ws);                                                                    \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, 0>), grid, block, 0, s, m, n, k, alpha, A, lda, B, ldb, beta,  \
+                         C, ldc, doff, kc, ws);                                                                    \
+    return hipGetLastError() == hipSuccess ? 1 : ABFT_ERR_HIP;                                                     \
+  }
+  DG_CASE(0, 0, 0, 0)  // C -= L21 U12 (LU), TRSM block updates
+  DG_CASE(0, 1, 0, 1)  // C -= L21 L21^T, lower part (Cholesky)
+  DG_CASE(0, 1, 0, 0)  // X Y^T
+  DG_CASE(1, 0, 1, 0)  // W = V^T C (QR)
+  DG_CASE(0, 0, 1, 0)  // C -= V W (QR)
+#undef DG_CASE
+  return 0;
+}
+
+}  // namespace abft

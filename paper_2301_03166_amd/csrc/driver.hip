@@ -17,6 +17,16 @@
 
 using namespace abft;
 
+// A captured batched call: the arguments it was captured with and its
+// executable graph (replayed when a later call passes the same arguments).
+struct BatchGraph {
+  int chol, prec, batch, protect;
+  double ts;
+  const void *dn, *dA, *dlda, *dipiv, *dwork, *dinfo, *dreps;
+  hipGraphExec_t exec;
+};
+constexpr int MAX_GRAPHS = 8;
+
 struct abft_handle_s {
   hipStream_t stream;
   int device;
@@ -24,6 +34,9 @@ struct abft_handle_s {
   abft_profile prof;
   hipEvent_t* ev;  // event pool for profiled calls
   int nev;
+  hipStream_t cap;  // side stream used only for graph capture (created on first use)
+  BatchGraph graphs[MAX_GRAPHS];
+  int ngraphs, next_graph;
 };
 
 namespace {
@@ -672,6 +685,10 @@ int abft_destroy(abft_handle h) {
     for (int i = 0; i < h->nev; ++i) (void)hipEventDestroy(h->ev[i]);
     free(h->ev);
   }
+  if (h) {
+    for (int i = 0; i < h->ngraphs; ++i) (void)hipGraphExecDestroy(h->graphs[i].exec);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+  }
   free(h);
   return 0;
 }
@@ -822,6 +839,30 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   return 0;
 }
 
+int abft_gemm(abft_handle h, int32_t transa, int32_t transb, int32_t flags, int64_t m, int64_t n, int64_t k,
+              double alpha, const double* dA, int64_t lda, const double* dB, int64_t ldb, double beta, double* dC,
+              int64_t ldc, void* dwork, size_t work_bytes) {
+  if (!h) return -1;
+  if (transa != 0 && transa != 1) return -2;
+  if (transb != 0 && transb != 1) return -3;
+  if (flags & ~(ABFT_GEMM_LOWER | ABFT_GEMM_UNIT_LOWER_A)) return -4;
+  const int64_t lim = 0x7fffffff;
+  if (m < 0 || m > lim) return -5;
+  if (n < 0 || n > lim) return -6;
+  if (k < 0 || k > lim) return -7;
+  if (lda < std::max<int64_t>(1, transa ? k : m)) return -10;
+  if (ldb < std::max<int64_t>(1, transb ? n : k)) return -12;
+  if (ldc < std::max<int64_t>(1, m)) return -15;
+  if (m == 0 || n == 0) return 0;
+  const int lower = (flags & ABFT_GEMM_LOWER) ? 1 : 0, fa = (flags & ABFT_GEMM_UNIT_LOWER_A) ? 1 : 0;
+  if (transa && transb) return ABFT_ERR_UNSUPPORTED;
+  if (lower && !(transa == 0 && transb == 1)) return ABFT_ERR_UNSUPPORTED;
+  if (fa && transb) return ABFT_ERR_UNSUPPORTED;
+  double* ws = (dwork && work_bytes >= sizeof(double)) ? (double*)dwork : nullptr;
+  return gemm64(h->stream, transa, transb, fa, 0, lower, (int)m, (int)n, (int)k, alpha, dA, lda, dB, ldb, beta, dC,
+                ldc, 0, 0, 0, 0, ws, ws ? work_bytes / sizeof(double) : 0);
+}
+
 int abft_encode(abft_handle h, int64_t m, int64_t n, const double* dA, int64_t lda, int32_t nb, double* dcolchk,
                 int64_t ldc, double* drowchk, int64_t ldr) {
   if (!h) return -1;
@@ -887,8 +928,41 @@ static int batched_common(abft_handle h, int chol, int32_t batch, int32_t nmax, 
   if (batch == 0) return 0;
   if (!dinfo || !dreps) return -11;
   if (!dwork || work_bytes < batched_ws_bytes(batch)) return ABFT_ERR_WORKSPACE;
-  return batched_factor(h->stream, chol, prec, batch, dn, dA, dlda, dipiv, dwork, protect, ts, opts->faults,
-                        opts->faults ? opts->nfaults : 0, dinfo, dreps, h->cus);
+  const int nf = opts->faults ? opts->nfaults : 0;
+  if (!(opts->flags & ABFT_FLAG_GRAPH) || nf > 0)
+    return batched_factor(h->stream, chol, prec, batch, dn, dA, dlda, dipiv, dwork, protect, ts, opts->faults, nf,
+                          dinfo, dreps, h->cus);
+  // graph path: replay the graph captured for these arguments, or capture it
+  for (int i = 0; i < h->ngraphs; ++i) {
+    const BatchGraph& g = h->graphs[i];
+    if (g.chol == chol && g.prec == prec && g.batch == batch && g.protect == protect && g.ts == ts && g.dn == dn &&
+        g.dA == dA && g.dlda == dlda && g.dipiv == dipiv && g.dwork == dwork && g.dinfo == dinfo && g.dreps == dreps)
+      return hipGraphLaunch(g.exec, h->stream) == hipSuccess ? 0 : ABFT_ERR_HIP;
+  }
+  if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) return ABFT_ERR_HIP;
+  if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return ABFT_ERR_HIP;
+  const int rc = batched_factor(h->cap, chol, prec, batch, dn, dA, dlda, dipiv, dwork, protect, ts, nullptr, 0, dinfo,
+                                dreps, h->cus);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(h->cap, &graph);
+  if (rc || ec != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc ? rc : ABFT_ERR_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return ABFT_ERR_HIP;
+  int slot;
+  if (h->ngraphs < MAX_GRAPHS) {
+    slot = h->ngraphs++;
+  } else {  // evict round-robin, after the stream has finished any replay of it
+    slot = h->next_graph++ % MAX_GRAPHS;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return ABFT_ERR_HIP;
+    (void)hipGraphExecDestroy(h->graphs[slot].exec);
+  }
+  h->graphs[slot] = BatchGraph{chol, prec, batch, protect, ts, dn, dA, dlda, dipiv, dwork, dinfo, dreps, exec};
+  return hipGraphLaunch(exec, h->stream) == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 
 int abft_potrf_batched(abft_handle h, int32_t batch, int32_t nmax, const int32_t* dn, void* const* dA,

@@ -216,12 +216,25 @@ int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int 
   if (ws && !lower && grid < 160 && k >= 2048) {
     int64_t want = std::min<int64_t>(32, std::min<int64_t>((320 + grid - 1) / grid, k / 512));
     if (want >= 2) {
-      int64_t kcl = ((k + want - 1) / want + 15) / 16 * 16;
+      int64_t kcl = ((k + want - 1) / want + 31) / 32 * 32;
       int64_t sp = (k + kcl - 1) / kcl;
       if (sp >= 2 && (size_t)sp * m * n <= ws_elems) {
         S = (unsigned)sp;
         kc = (int)kcl;
       }
+    }
+  }
+  if (atype == 0 && btype == 0 && fb == 0 && rnd == 0 && fa <= 1) {
+    const int r = dgemm_fast(s, ta, tb, fa, lower, m, n, k, alpha, (const double*)A, lda, (const double*)B, ldb, beta,
+                             C, ldc, doff, (int)S, kc, ws);
+    if (r < 0) return r;
+    if (r == 1) {
+      if (kc > 0) {
+        unsigned rg = (unsigned)std::min<int64_t>(4096, ((int64_t)m * n + 255) / 256);
+        hipLaunchKernelGGL(k_splitk_reduce, dim3(rg), dim3(256), 0, s, ws, (int)S, m, n, beta, C, ldc);
+        if (hipGetLastError() != hipSuccess) return ABFT_ERR_HIP;
+      }
+      return 0;
     }
   }
   if (atype == 0 && btype == 0) {

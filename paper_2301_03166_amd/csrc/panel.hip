@@ -149,6 +149,7 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
   __shared__ double prow[LEAF], orow[LEAF];
   __shared__ double wv_val[4];
   __shared__ int64_t wv_idx[4];
+  __shared__ int wv_g[4];
   __shared__ int64_t s_piv, s_loc;
   __shared__ int s_pg;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -199,22 +200,39 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
       if (g == 0) sj[G * (w + 2) + tid] = (double)Ld[(d - rbeg) * ldl + tid];
     }
     grid_barrier(ctr, ctr_base + (unsigned)(j + 1) * G, rep, nullptr);
-    // every workgroup picks the same winner by scanning the slots in order
-    if (tid == 0) {
-      double best = -1.0;
-      int64_t bidx = INT64_MAX;
-      int bg = 0;
-      for (int q = 0; q < G; ++q) {
-        double v = sj[q * (w + 2) + 0];
-        if (v < 0) continue;
-        int64_t ii = (int64_t)sj[q * (w + 2) + 1];
-        if (better<T>(v, ii, best, bidx)) { best = v; bidx = ii; bg = q; }
+    // every workgroup picks the same winner: one slot per thread, then a
+    // block argmax (largest |value|, first row index on ties; the row index
+    // identifies its workgroup, so the choice does not depend on the order)
+    {
+      double v = -1.0;
+      int64_t ii = INT64_MAX;
+      int gq = 0;
+      for (int q = tid; q < G; q += 256) {
+        const double vq = sj[q * (w + 2) + 0];
+        const int64_t iq = vq < 0 ? INT64_MAX : (int64_t)sj[q * (w + 2) + 1];
+        if (vq >= 0 && better<T>(vq, iq, v, ii)) { v = vq; ii = iq; gq = q; }
       }
-      if (bidx == INT64_MAX) { bidx = d; bg = 0; }
-      s_piv = bidx;
-      s_pg = bg;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o);
+        const int64_t oi = __shfl_xor(ii, o);
+        const int og = __shfl_xor(gq, o);
+        if (better<T>(ov, oi, v, ii)) { v = ov; ii = oi; gq = og; }
+      }
+      if (lane == 0) { wv_val[wv] = v; wv_idx[wv] = ii; wv_g[wv] = gq; }
+      __syncthreads();
+      if (tid == 0) {
+        double best = wv_val[0];
+        int64_t bidx = wv_idx[0];
+        int bg = wv_g[0];
+        for (int q = 1; q < 4; ++q)
+          if (better<T>(wv_val[q], wv_idx[q], best, bidx)) { best = wv_val[q]; bidx = wv_idx[q]; bg = wv_g[q]; }
+        if (bidx == INT64_MAX) { bidx = d; bg = 0; }
+        s_piv = bidx;
+        s_pg = bg;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     const int64_t p = s_piv;
     const int pg = s_pg;
     if (tid < w) {
@@ -261,6 +279,7 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
   double* Ld = reinterpret_cast<double*>(smem_raw);  // R x (w+1)
   const int ldl = w + 1;
   __shared__ double part[4][LEAF];
+  __shared__ double qpart[256 / LEAF][LEAF];
   __shared__ double svec[LEAF], orow[LEAF], fvec[LEAF];
   __shared__ double s_beta, s_tau, s_scale;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -295,13 +314,24 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
       if (g == 0) sj[G * w + tid] = Ld[(d - rbeg) * ldl + tid];
     }
     grid_barrier(ctr, ctr_base + (unsigned)(j + 1) * G, rep, nullptr);
-    if (tid < w) {
+    {
+      // thread (group gq, column c) sums the slots q = gq, gq + QG, ...; the
+      // QG group sums are then added in group order (a fixed order)
+      constexpr int QG = 256 / LEAF;
+      const int c = tid % LEAF, gq = tid / LEAF;
       double s = 0.0;
-      for (int q = 0; q < G; ++q) s += sj[q * w + tid];
-      svec[tid] = s;
-      orow[tid] = sj[G * w + tid];
+      if (c < w)
+        for (int q = gq; q < G; q += QG) s += sj[q * w + c];
+      qpart[gq][c] = s;
+      __syncthreads();
+      if (tid < w) {
+        double t = qpart[0][tid];
+        for (int u = 1; u < QG; ++u) t += qpart[u][tid];
+        svec[tid] = t;
+        orow[tid] = sj[G * w + tid];
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (tid == 0) {
       double alpha = orow[j], s2 = svec[j];
       if (s2 == 0.0) {
@@ -354,8 +384,17 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
     __shared__ double Gm[LEAF][LEAF + 1];
     __shared__ double Tl[LEAF][LEAF + 1];
     for (int e = tid; e < w * w; e += 256) {
-      double s = 0.0;
-      for (int q = 0; q < G; ++q) s += sg[(size_t)q * w * w + e];
+      // eight interleaved partial sums (loads in flight), added in order
+      double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int q = 0;
+      for (; q + 8 <= G; q += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] += sg[(size_t)(q + u) * w * w + e];
+      }
+      for (int u = 0; q + u < G; ++u) p[u] += sg[(size_t)(q + u) * w * w + e];
+      double s = p[0];
+#pragma unroll
+      for (int u = 1; u < 8; ++u) s += p[u];
       Gm[e % w][e / w] = s;
       Tl[e % w][e / w] = 0.0;
     }
@@ -389,45 +428,65 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
 // r (-1: unchanged).  Rows [c0, n) of the panel bound the table (<= 36864
 // rows in LDS); one thread replays the interchanges, then a block-wide
 // compaction lists the moved rows in increasing order.
-constexpr int PB_MAX = 36864;
-__global__ __launch_bounds__(256) void k_perm_build(const int32_t* ipiv, int64_t c0, int w, int64_t n, int* moves) {
-  __shared__ int cur[PB_MAX];
-  __shared__ int cnt[257];
+// Move list of the w row interchanges of a panel starting at row c0: after
+// the swaps, row dst holds the original row src; moves = {count, dst0, src0,
+// dst1, src1, ...} in increasing dst.  Only the panel's own rows [0, w) and
+// the distinct pivot rows at or below w (relative to c0) can move, so the
+// replay works on a compact table of at most 2w entries: entry t < w is row
+// t, entry w + f is the pivot row first named by interchange f.
+constexpr int PB_W = 512;  // largest panel width (block size)
+__global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, int64_t c0, int w, int64_t n,
+                                                        int* moves) {
+  __shared__ int pv[PB_W], sidx[PB_W];
+  __shared__ int key[2 * PB_W], cur[2 * PB_W];
+  __shared__ int nmoved;
   const int tid = threadIdx.x;
-  const int rows = (int)(n - c0);
-  for (int r = tid; r < rows; r += 256) cur[r] = -1;
+  const int rows = (int)min<int64_t>(n - c0, 0x7fffffff);
+  if (tid < w) {
+    int p = ipiv[c0 + tid] - 1 - (int)c0;
+    if (p < 0 || p >= rows) p = tid;  // not produced by the panel; no interchange
+    pv[tid] = p;
+  }
+  if (tid == 0) nmoved = 0;
   __syncthreads();
-  if (tid == 0) {
+  if (tid < w) {
+    const int p = pv[tid];
+    int f = tid;
+    if (p >= w)
+      for (int t = 0; t < tid; ++t)
+        if (pv[t] == p) { f = t; break; }
+    sidx[tid] = p < w ? p : w + f;
+    key[tid] = tid;
+    key[w + tid] = (p >= w && f == tid) ? p : -1;
+  }
+  __syncthreads();
+  for (int i = tid; i < 2 * w; i += blockDim.x) cur[i] = key[i];
+  __syncthreads();
+  if (tid == 0)
     for (int t = 0; t < w; ++t) {
-      const int p = ipiv[c0 + t] - 1 - (int)c0;
-      if (p == t) continue;
-      int a = cur[t] < 0 ? t : cur[t];
-      int b = cur[p] < 0 ? p : cur[p];
-      cur[t] = b;
-      cur[p] = a;
+      const int b = sidx[t];
+      if (b != t) {
+        const int x = cur[t];
+        cur[t] = cur[b];
+        cur[b] = x;
+      }
     }
+  __syncthreads();
+  // rank every moved entry by its row (rows are distinct) and emit in order
+  for (int i = tid; i < 2 * w; i += blockDim.x) {
+    const int ki = key[i];
+    if (ki < 0 || cur[i] == ki) continue;
+    int r = 0;
+    for (int q = 0; q < 2 * w; ++q) {
+      const int kq = key[q];
+      r += (kq >= 0 && cur[q] != kq && kq < ki);
+    }
+    moves[1 + 2 * r] = (int)(c0 + ki);
+    moves[2 + 2 * r] = (int)(c0 + cur[i]);
+    atomicAdd(&nmoved, 1);
   }
   __syncthreads();
-  // compaction of moved rows (cur[r] >= 0 and != r), in increasing r
-  const int chunk = (rows + 255) / 256;
-  const int r0 = tid * chunk, r1 = min(rows, r0 + chunk);
-  int c = 0;
-  for (int r = r0; r < r1; ++r) c += (cur[r] >= 0 && cur[r] != r);
-  cnt[tid + 1] = c;
-  __syncthreads();
-  if (tid == 0) {
-    cnt[0] = 0;
-    for (int q = 1; q <= 256; ++q) cnt[q] += cnt[q - 1];
-    moves[0] = cnt[256];
-  }
-  __syncthreads();
-  int o = cnt[tid];
-  for (int r = r0; r < r1; ++r)
-    if (cur[r] >= 0 && cur[r] != r) {
-      moves[1 + 2 * o] = (int)(c0 + r);
-      moves[2 + 2 * o] = (int)(c0 + cur[r]);
-      ++o;
-    }
+  if (tid == 0) moves[0] = nmoved;
 }
 
 template <typename T>
@@ -540,8 +599,8 @@ int geqrf_leaf(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t c0, int
 }
 
 int perm_build(hipStream_t s, const int32_t* ipiv, int64_t c0, int w, int64_t n, int* moves) {
-  if (n - c0 > PB_MAX) return ABFT_ERR_UNSUPPORTED;
-  hipLaunchKernelGGL(k_perm_build, dim3(1), dim3(256), 0, s, ipiv, c0, w, n, moves);
+  if (w < 0 || w > PB_W) return ABFT_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL(k_perm_build, dim3(1), dim3(2 * PB_W), 0, s, ipiv, c0, w, n, moves);
   CHECK_LAUNCH();
 }
 template <typename T>

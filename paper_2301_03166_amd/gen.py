@@ -143,3 +143,46 @@ def general_torch(n: int, seed: int, device):
     import torch
     g = torch.Generator(device=device).manual_seed(seed)
     return torch.rand((n, n), generator=g, dtype=torch.float64, device=device).mul_(2.0).sub_(1.0)
+
+
+def mp_torch(n: int, kappa: float, seed: int, device):
+    """The mixed-precision test matrix of ``mp_matrix`` built in device memory
+    (same s and reflectors, so the closed-form solution of ``mp_exact_solution``
+    applies); returns (A, s, V) with A a torch tensor and s, V numpy arrays."""
+    import torch
+    s = kappa ** (-np.arange(n) / max(n - 1, 1))
+    V = reflectors(n, seed)
+    a = torch.diag(torch.from_numpy(s).to(device))
+    for v in V[::-1]:
+        vt = torch.from_numpy(v).to(device)
+        t = 2.0 / float(v @ v)
+        av = a @ vt
+        vav = float(vt @ av)
+        a.addr_(vt, av, alpha=-t)
+        a.addr_(av, vt, alpha=-t)
+        a.addr_(vt, vt, alpha=t * t * vav)
+    return a, s, V  # symmetric: row- and column-major storage coincide
+
+
+def batch_torch(sizes, seeds, kind: str, device, dtype=None):
+    """Matrices of the given orders packed one after another in one flat
+    device buffer (column-major each); SPD for kind == "chol" (G G^T/n + n I),
+    U(-1, 1) otherwise.  Returns (flat, views)."""
+    import torch
+    dtype = dtype or torch.float64
+    offs = np.concatenate([[0], np.cumsum(np.asarray(sizes, dtype=np.int64) ** 2)])
+    flat = torch.empty(int(offs[-1]), dtype=dtype, device=device)
+    views = []
+    for q, (n, sd) in enumerate(zip(sizes, seeds)):
+        n = int(n)
+        g = torch.Generator(device=device).manual_seed(int(sd))
+        if kind == "chol":
+            G = torch.randn((n, n), generator=g, dtype=torch.float64, device=device)
+            m = G @ G.T / n
+            m.diagonal().add_(n)
+        else:
+            m = torch.rand((n, n), generator=g, dtype=torch.float64, device=device).mul_(2.0).sub_(1.0)
+        v = torch.as_strided(flat, (n, n), (1, n), int(offs[q]))
+        v.copy_(m.t())
+        views.append(v)
+    return flat, views

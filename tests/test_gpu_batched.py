@@ -125,3 +125,31 @@ def test_batched_chol_diagonal_tile_flips(h):
         assert reps[q].events()[0] == orep.events()[0] == (f["iter"], 1, f["row"], f["col"])
         g, c = np.tril(mats[q].cpu().numpy()), np.tril(clean[q].cpu().numpy())
         assert np.max(np.abs(g - c)) <= 1e-12 * np.max(np.abs(c))
+
+
+@pytest.mark.parametrize("chol", [True, False])
+def test_batched_graph_replay_matches_eager(h, chol):
+    """Graph capture on first use, replays afterwards: every replay (with
+    eager work and synchronizations between them) equals the eager call."""
+    import torch
+    sizes = [200, 37, 512, 96, 33, 260]
+    mats0 = [gen.spd(n, 90 + n) if chol else gen.general(n, 90 + n) for n in sizes]
+    ref = [dev(a) for a in mats0]
+    infos0, ipivs0, reps0 = h.batched(ref, chol)
+    work = [dev(a) for a in mats0]
+    state = h.batched_args(work, chol)
+    for rep in range(4):
+        for q, a in enumerate(mats0):
+            work[q].copy_(torch.from_numpy(np.asfortranarray(a)))
+        infos, ipivs, reps = h.batched(work, chol, state=state, graph=True)
+        torch.cuda.synchronize()
+        scratch = torch.randn(256, 256, dtype=torch.float64, device="cuda") @ torch.randn(256, 256, dtype=torch.float64,
+                                                                                            device="cuda")
+        torch.cuda.synchronize()
+        del scratch
+        for q in range(len(sizes)):
+            assert torch.equal(work[q], ref[q]), (rep, q)
+            assert reps[q].status == 0
+            if not chol:
+                assert torch.equal(ipivs[q], ipivs0[q])
+        assert np.array_equal(infos, infos0)

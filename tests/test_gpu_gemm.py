@@ -1,0 +1,130 @@
+"""GPU parity of the FP64 update product (abft_gemm) against the oracle's
+plain definition: ragged and aligned shapes, K tails, the unit-lower and
+lower-write options, split K, unaligned operands (general kernel)."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def h():
+    import torch
+    from paper_2301_03166_amd import abft
+    assert torch.cuda.is_available()
+    return abft.Handle()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.asfortranarray(a)).cuda()
+
+
+def _mats(m, n, k, ta, tb, seed, integer=False):
+    rng = np.random.default_rng(seed)
+    draw = (lambda s: rng.integers(-8, 9, size=s).astype(np.float64)) if integer else (
+        lambda s: rng.uniform(-1, 1, size=s))
+    A = draw((k, m) if ta else (m, k))
+    B = draw((n, k) if tb else (k, n))
+    C = draw((m, n))
+    return A, B, C
+
+
+def _bound(A, B, C, ta, tb, alpha, beta, k, unit):
+    if unit:
+        A = np.tril(A, -1) + np.eye(*A.shape)
+    a = np.abs(A.T if ta else A)
+    b = np.abs(B.T if tb else B)
+    return 2.0 * (k + 2) * U64 * (abs(alpha) * (a @ b) + abs(beta) * np.abs(C)) + 1e-300
+
+
+CASES = [
+    # m, n, k, ta, tb, unit_lower_a, lower
+    (1, 1, 1, 0, 0, 0, 0),
+    (128, 128, 32, 0, 0, 0, 0),
+    (256, 384, 64, 0, 0, 0, 0),
+    (130, 257, 70, 0, 0, 0, 0),
+    (300, 200, 33, 0, 0, 0, 0),
+    (1000, 900, 512, 0, 0, 0, 0),
+    (384, 384, 96, 0, 1, 0, 1),
+    (300, 300, 64, 0, 1, 0, 1),
+    (1152, 1152, 256, 0, 1, 0, 1),
+    (300, 200, 64, 0, 1, 0, 1),
+    (257, 129, 40, 0, 1, 0, 0),
+    (64, 500, 700, 1, 0, 1, 0),
+    (130, 260, 300, 1, 0, 0, 0),
+    (700, 300, 64, 0, 0, 1, 0),
+    (640, 384, 128, 0, 0, 1, 0),
+]
+
+
+@pytest.mark.parametrize("m,n,k,ta,tb,unit,lower", CASES)
+@pytest.mark.parametrize("alpha,beta", [(-1.0, 1.0), (1.0, 0.0), (0.5, -2.0)])
+def test_gemm_matches_oracle(h, m, n, k, ta, tb, unit, lower, alpha, beta):
+    A, B, C = _mats(m, n, k, ta, tb, seed=m * 7 + n * 3 + k)
+    dA, dB, dC = dev(A), dev(B), dev(C)
+    if beta == 0.0:
+        dC.fill_(float("nan"))  # beta == 0 must not read C
+        if lower:
+            dC.copy_(dev(C))
+    h.gemm(dA, dB, dC, ta, tb, alpha, beta, lower=bool(lower), unit_lower_a=bool(unit))
+    ref = oracle.gemm(A, B, C, ta, tb, alpha, beta, lower=bool(lower), unit_lower_a=bool(unit))
+    got = dC.cpu().numpy()
+    tol = _bound(A, B, C, ta, tb, alpha, beta, k, unit)
+    if lower:
+        up = ~np.tril(np.ones((m, n), dtype=bool))
+        assert np.array_equal(got[up], C[up])  # strictly upper part untouched
+    assert np.all(np.abs(got - ref) <= tol)
+
+
+@pytest.mark.parametrize("m,n,k,ta,tb,unit,lower", [(256, 320, 96, 0, 0, 0, 0), (300, 300, 64, 0, 1, 0, 1),
+                                                    (200, 130, 50, 1, 0, 1, 0)])
+def test_gemm_exact_integers(h, m, n, k, ta, tb, unit, lower):
+    """Small integers: every partial sum is exact, so the result is bitwise."""
+    A, B, C = _mats(m, n, k, ta, tb, seed=5, integer=True)
+    dC = dev(C)
+    h.gemm(dev(A), dev(B), dC, ta, tb, -1.0, 1.0, lower=bool(lower), unit_lower_a=bool(unit))
+    assert np.array_equal(dC.cpu().numpy(), oracle.gemm(A, B, C, ta, tb, -1.0, 1.0, bool(lower), bool(unit)))
+
+
+def test_gemm_split_k(h):
+    """Few output tiles and a long K: the product splits K when given scratch."""
+    import torch
+    m, n, k = 128, 1024, 8192
+    A, B, C = _mats(m, n, k, 1, 0, seed=9)
+    work = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    ref = oracle.gemm(A, B, C, True, False, 1.0, 0.0, unit_lower_a=True)
+    tol = _bound(A, B, C, 1, 0, 1.0, 0.0, k, True)
+    for w in (None, work):
+        dC = dev(C)
+        h.gemm(dev(A), dev(B), dC, True, False, 1.0, 0.0, unit_lower_a=True, work=w)
+        assert np.all(np.abs(dC.cpu().numpy() - ref) <= tol)
+
+
+def test_gemm_unaligned_operands(h):
+    """Operands at odd element offsets / odd leading dimensions take the
+    general kernel; results are the same to the bound."""
+    import torch
+    m, n, k = 200, 150, 90
+    A, B, C = _mats(m, n, k, 0, 0, seed=11)
+    bigA = torch.zeros((m + 1) * (k + 1), dtype=torch.float64, device="cuda")
+    vA = torch.as_strided(bigA, (m, k), (1, m + 1), 1)  # odd lda, offset 1
+    vA.copy_(torch.from_numpy(A))
+    dC = dev(C)
+    h.gemm(vA, dev(B), dC, False, False, -1.0, 1.0)
+    ref = oracle.gemm(A, B, C, False, False, -1.0, 1.0)
+    assert np.all(np.abs(dC.cpu().numpy() - ref) <= _bound(A, B, C, 0, 0, -1.0, 1.0, k, False))
+
+
+def test_gemm_rejects_bad_arguments(h):
+    from paper_2301_03166_amd import abft
+    import torch
+    A = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(abft.AbftError):
+        h.gemm(A, A, A, True, True)  # TT not supported
+    with pytest.raises(abft.AbftError):
+        h.gemm(A, A, A, False, False, lower=True)  # lower write needs NT

@@ -41,7 +41,10 @@ def test_mp_solve_matches_oracle(h, chol, prec, kappa):
     assert bool(ir.converged) == bool(oir.converged), (ir.failed_reason, oir.failed_reason, ir.info, info)
     if kappa < 1e8:
         assert ir.info == 0 and info == 0
-    assert not rep.status & 4 and rep.flagged_tiles == 0
+    if ir.info == 0:
+        # past a Cholesky breakdown the factor holds NaN and every later check
+        # flags; the report describes faults only for a completed factorization
+        assert not rep.status & 4 and rep.flagged_tiles == 0
     if ir.converged:
         xr = oracle.solve_ref(A, b)
         err = np.linalg.norm(x.cpu().numpy() - xr, np.inf) / np.linalg.norm(xr, np.inf)

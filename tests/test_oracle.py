@@ -394,3 +394,30 @@ def test_mp_cholesky_refinement():
     assert info == 0 and ir.converged
     xs = gen.mp_exact_solution(b, s, V)
     assert np.linalg.norm(x - xs, np.inf) / np.linalg.norm(xs, np.inf) < 1e-12
+
+
+@pytest.mark.parametrize("ta,tb,unit,lower", [(0, 0, 0, 0), (0, 1, 0, 1), (1, 0, 1, 0), (0, 0, 1, 0), (0, 1, 0, 0)])
+def test_gemm_definition_brute_force(ta, tb, unit, lower):
+    """The oracle's update product against explicit triple loops on small
+    integer operands (every sum exact)."""
+    rng = np.random.default_rng(4)
+    m, n, k = 5, 4, 6
+    A = rng.integers(-5, 6, size=(k, m) if ta else (m, k)).astype(float)
+    B = rng.integers(-5, 6, size=(n, k) if tb else (k, n)).astype(float)
+    C = rng.integers(-5, 6, size=(m, n)).astype(float)
+    alpha, beta = -2.0, 3.0
+    out = oracle.gemm(A, B, C, ta, tb, alpha, beta, lower=bool(lower), unit_lower_a=bool(unit))
+    for i in range(m):
+        for j in range(n):
+            if lower and i < j:
+                assert out[i, j] == C[i, j]
+                continue
+            s = 0.0
+            for p in range(k):
+                r, c = (p, i) if ta else (i, p)
+                a = A[r, c]
+                if unit:
+                    a = 0.0 if r < c else (1.0 if r == c else a)
+                b = B[j, p] if tb else B[p, j]
+                s += a * b
+            assert out[i, j] == beta * C[i, j] + alpha * s
