@@ -106,12 +106,14 @@ typedef struct {
 } abft_report;
 
 typedef struct {
-  int32_t nb;          /* block size = checksum tile size (1..1024) */
+  int32_t nb;          /* block size = checksum tile size (1..512; batched: 32) */
   int32_t protect;     /* ABFT_PROTECT_NONE or ABFT_PROTECT_FULL */
   double tau_scale;    /* threshold scale (default 4.0 when <= 0) */
   const abft_fault* faults; /* host array of fault plans (test use), may be NULL */
   int32_t nfaults;
   int32_t flags;       /* ABFT_FLAG_* bits */
+  int32_t wgs_per_cu;  /* batched: persistent workgroups per compute unit (0: 1; at most 4) */
+  int32_t reserved;
 } abft_opts;
 
 /* opts.flags: ABFT_FLAG_PROFILE times the phases of the call with HIP

@@ -57,7 +57,8 @@ class Profile(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("protect", C.c_int32), ("tau_scale", C.c_double),
-                ("faults", C.POINTER(Fault)), ("nfaults", C.c_int32), ("flags", C.c_int32)]
+                ("faults", C.POINTER(Fault)), ("nfaults", C.c_int32), ("flags", C.c_int32),
+                ("wgs_per_cu", C.c_int32), ("reserved", C.c_int32)]
 
 
 class AbftError(RuntimeError):
@@ -121,8 +122,9 @@ FLAG_PROFILE, FLAG_GRAPH = 1, 2
 GEMM_LOWER, GEMM_UNIT_LOWER_A = 1, 2
 
 
-def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False, graph=False):
+def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False, graph=False, wgs_per_cu=0):
     o = Opts()
+    o.wgs_per_cu = int(wgs_per_cu)
     o.nb, o.protect, o.tau_scale = int(nb), PROTECT_FULL if protect else PROTECT_NONE, float(tau_scale)
     o.flags = (FLAG_PROFILE if profile else 0) | (FLAG_GRAPH if graph else 0)
     keep = None
@@ -210,6 +212,9 @@ class Handle:
         if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
             raise AbftError("expected a square float64 device matrix")
         lda = _ld(A)
+        if nb is None or nb == "auto":  # the autotuned block size for this operation and size class
+            from . import autotune
+            nb = autotune.lookup_nb({OP_POTRF: "potrf", OP_GETRF: "getrf"}.get(op, "geqrf"), n)
         opts, keep = make_opts(nb, protect, tau_scale, faults, profile)
         ws, wbytes = self.workspace(op, n, opts)
         rep = report if report is not None else self.new_report()
@@ -263,7 +268,7 @@ class Handle:
 
     # ------------------------------------------------------------ batched
     def batched(self, mats, chol, protect=True, tau_scale=4.0, faults=None, nmax=None, sync=True, state=None,
-                graph=False):
+                graph=False, wgs_per_cu=None):
         """Factor a list of column-major square matrices (all float64 or all float32) in place with one
         batched call (block / tile size 32).  Returns (infos, ipivs, reports) when sync; `state` keeps the
         device argument arrays alive so that graph=True calls replay the library's captured graph."""
@@ -273,7 +278,10 @@ class Handle:
         if state is None:
             state = self.batched_args(mats, chol)
         ns, ptrs, ldas, ipivs, piv_ptrs, infos, reps = state
-        opts, keep = make_opts(32, protect, tau_scale, faults, graph=graph)
+        if wgs_per_cu is None:  # the autotuned choice for this operation and precision
+            from . import autotune
+            wgs_per_cu = autotune.lookup_wgs("potrf" if chol else "getrf", "f64" if prec == F64 else "f32")
+        opts, keep = make_opts(32, protect, tau_scale, faults, graph=graph, wgs_per_cu=wgs_per_cu)
         op = OP_POTRF_BATCHED if chol else OP_GETRF_BATCHED
         ws, wbytes = self.workspace(op, 0, opts, batch=batch)
         nm = int(nmax if nmax is not None else max(m.shape[0] for m in mats))

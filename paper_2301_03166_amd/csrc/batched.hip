@@ -482,7 +482,7 @@ size_t batched_ws_bytes(int batch) {
 
 int batched_factor(hipStream_t s, int chol, int prec, int batch, const int32_t* dn, void* const* dA,
                    const int32_t* dlda, int32_t* const* dipiv, void* dwork, int protect, double ts,
-                   const abft_fault* hfaults, int nfaults, int32_t* dinfo, abft_report* dreps, int cus) {
+                   const abft_fault* hfaults, int nfaults, int32_t* dinfo, abft_report* dreps, int wgs) {
   if (batch > 8192) return ABFT_ERR_UNSUPPORTED;
   char* base = (char*)dwork;
   double* chk = (double*)base;
@@ -502,7 +502,7 @@ int batched_factor(hipStream_t s, int chol, int prec, int batch, const int32_t* 
   const size_t elem = prec == ABFT_F64 ? 8 : 4;
   size_t shm = std::max((size_t)BMAX * (BNB + 1) * elem + (size_t)BNB * 65 * elem, sizeof(TileSums) + sizeof(TileFlags));
   shm = (shm + 255) & ~(size_t)255;
-  dim3 grid(std::min(batch, cus));
+  dim3 grid(std::min(batch, wgs));  // persistent workgroups; extra ones wait for a free CU
 #define BLAUNCH(T_, C_)                                                                                            \
   hipLaunchKernelGGL((k_batched<T_, C_>), grid, dim3(256), shm, s, batch, dn, dA, dlda, dipiv, order, queue, chk,   \
                      protect, ts * u, nfaults ? dfaults : nullptr, nfaults, dinfo, dreps)

@@ -272,7 +272,9 @@ __global__ __launch_bounds__(256) void k_xsums(const T* A, int64_t lda, int64_t 
   const int64_t r0 = (int64_t)I * nb;
   const int h = (int)min((int64_t)nb, n - r0);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int p = wv; p < kw; p += 4) {
+  // workgroup y takes columns [16 y, 16 y + 16), four per wave
+  const int pe = min(kw, (int)blockIdx.y * 16 + 16);
+  for (int p = (int)blockIdx.y * 16 + wv; p < pe; p += 4) {
     acc2 se{0, 0}, sw{0, 0};
     double sa = 0, swa = 0;
     for (int i = lane; i < h; i += 64) {
@@ -305,19 +307,40 @@ __global__ __launch_bounds__(256) void k_xsums(const T* A, int64_t lda, int64_t 
 template <typename T, int RND>
 __global__ __launch_bounds__(256) void k_ysums(const T* Y, int64_t ldy, int64_t n, int nb, int J0, int kw,
                                                double* Tm, double* Ta, int ldT) {
+  // workgroup (J, y): rows p in [64 y, 64 y + 64); thread (ph, pl) sums the
+  // columns j = ph, ph + 4, ...; the four phases are merged in order
+  __shared__ double part[4][64][4];
   const int J = J0 + blockIdx.x;
   const int64_t c0 = (int64_t)J * nb;
   const int w = (int)min((int64_t)nb, n - c0);
-  for (int p = threadIdx.x; p < kw; p += blockDim.x) {
-    acc2 se{0, 0}, sw{0, 0};
-    double sa = 0, swa = 0;
-    for (int j = 0; j < w; ++j) {
+  const int pl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int p = (int)blockIdx.y * 64 + pl;
+  acc2 se{0, 0}, sw{0, 0};
+  double sa = 0, swa = 0;
+  if (p < kw) {
+    for (int j = ph; j < w; j += 4) {
       double v = opval<T, RND>(Y + p + (c0 + j) * ldy);
       double wj = (double)(j + 1);
       cadd(se, v);
       cfma(sw, wj, v);
       sa += fabs(v);
       swa += wj * fabs(v);
+    }
+  }
+  part[ph][pl][0] = se.s;
+  part[ph][pl][1] = se.c;
+  part[ph][pl][2] = sw.s;
+  part[ph][pl][3] = sw.c;
+  __shared__ double pa[4][64][2];
+  pa[ph][pl][0] = sa;
+  pa[ph][pl][1] = swa;
+  __syncthreads();
+  if (ph == 0 && p < kw) {
+    for (int q = 1; q < 4; ++q) {
+      cmerge(se, acc2{part[q][pl][0], part[q][pl][1]});
+      cmerge(sw, acc2{part[q][pl][2], part[q][pl][3]});
+      sa += pa[q][pl][0];
+      swa += pa[q][pl][1];
     }
     Tm[p + (2 * J) * (int64_t)ldT] = cval(se);
     Tm[p + (2 * J + 1) * (int64_t)ldT] = cval(sw);
@@ -335,6 +358,9 @@ __global__ __launch_bounds__(256) void k_ysums(const T* Y, int64_t ldy, int64_t 
 // QR adds, for tile-row Ik, the e/w sums of R(:, j) (E[4*j + 0..3]) and for
 // every tile-row the backward-error allowance bt[j].
 // ---------------------------------------------------------------------------
+// Workgroup = 64 columns x 4 tile-rows; M and S/Sa are staged through LDS
+// in chunks of 32 values of p (coalesced loads, one stage shared by the four
+// tile-rows); the accumulation runs over p in increasing order.
 template <typename MT>
 __global__ __launch_bounds__(256) void k_panel_check(const double* S, const double* Sa, int ldS, int I0, int I1, int kw,
                                                      const MT* Mp, int64_t msp, int64_t msj, int tri, int pjoff,
@@ -342,25 +368,58 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
                                                      const double* bt, int Ik, const double* colchk, int64_t ldc,
                                                      int64_t cj0, int ncols, double tsu_p, abft_report* rep,
                                                      int iter, int nb) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int I = I0 + blockIdx.y;
-  __shared__ int flag;
+  constexpr int PC = 32;
+  __shared__ double Mc[PC][65], Ma[PC][65];
+  __shared__ double Sc[4][PC][4];
+  __shared__ int flag[4], fcol[4];
   __shared__ unsigned long long smax;
-  if (threadIdx.x == 0) { flag = 0; smax = 0; }
-  __syncthreads();
-  if (j < ncols && I < I1) {
-    double ce = colchk[2 * I + (cj0 + j) * ldc], cw = colchk[2 * I + 1 + (cj0 + j) * ldc];
-    acc2 xe{ce, 0}, xw{cw, 0};
-    double ge = 0, gw = 0;
-    int pmax = tri ? min(kw, j + pjoff + 1) : kw;
-    for (int p = 0; p < pmax; ++p) {
-      double m = mscale * (double)Mp[p * msp + j * msj];
-      double ma = Mabs ? Mabs[p * msp + j * msj] : fabs(m);
-      cfma(xe, -S[2 * I + p * (int64_t)ldS], m);
-      cfma(xw, -S[2 * I + 1 + p * (int64_t)ldS], m);
-      ge += Sa[2 * I + p * (int64_t)ldS] * ma;
-      gw += Sa[2 * I + 1 + p * (int64_t)ldS] * ma;
+  const int tid = threadIdx.x, jl = tid & 63, il = tid >> 6;
+  const int j0 = blockIdx.x * 64, j = j0 + jl;
+  const int Ib = I0 + blockIdx.y * 4, I = Ib + il;
+  if (tid < 4) { flag[tid] = 0; fcol[tid] = 0x7fffffff; }
+  if (tid == 0) smax = 0;
+  const bool live = j < ncols && I < I1;
+  double ce = 0, cw = 0;
+  if (live) { ce = colchk[2 * I + (cj0 + j) * ldc]; cw = colchk[2 * I + 1 + (cj0 + j) * ldc]; }
+  acc2 xe{ce, 0}, xw{cw, 0};
+  double ge = 0, gw = 0;
+  for (int p0 = 0; p0 < kw; p0 += PC) {
+    __syncthreads();
+    // stage M(p0 .. p0+31, j0 .. j0+63), along whichever index is contiguous
+    for (int e = tid; e < PC * 64; e += 256) {
+      int pl, jc;
+      if (msp == 1) { pl = e % PC; jc = e / PC; } else { jc = e % 64; pl = e / 64; }
+      const int pp = p0 + pl, jj = j0 + jc;
+      double m = 0.0, ma = 0.0;
+      if (pp < kw && jj < ncols && (!tri || pp <= jj + pjoff)) {
+        m = mscale * (double)Mp[pp * msp + jj * msj];
+        ma = Mabs ? Mabs[pp * msp + jj * msj] : fabs(m);
+      }
+      Mc[pl][jc] = m;
+      Ma[pl][jc] = ma;
     }
+    if (tid < 4 * PC) {
+      const int q = tid / PC, pl = tid % PC, II = Ib + q, pp = p0 + pl;
+      const bool ok = II < I1 && pp < kw;
+      Sc[q][pl][0] = ok ? S[2 * II + pp * (int64_t)ldS] : 0.0;
+      Sc[q][pl][1] = ok ? S[2 * II + 1 + pp * (int64_t)ldS] : 0.0;
+      Sc[q][pl][2] = ok ? Sa[2 * II + pp * (int64_t)ldS] : 0.0;
+      Sc[q][pl][3] = ok ? Sa[2 * II + 1 + pp * (int64_t)ldS] : 0.0;
+    }
+    __syncthreads();
+    if (live) {
+      const int pend = min(PC, kw - p0);
+      const int plim = tri ? min(pend, j + pjoff + 1 - p0) : pend;  // masked products are skipped
+      for (int pl = 0; pl < plim; ++pl) {
+        const double m = Mc[pl][jl], ma = Ma[pl][jl];
+        cfma(xe, -Sc[il][pl][0], m);
+        cfma(xw, -Sc[il][pl][1], m);
+        ge += Sc[il][pl][2] * ma;
+        gw += Sc[il][pl][3] * ma;
+      }
+    }
+  }
+  if (live) {
     if (E) {
       if (I == Ik) {
         cadd(xe, -E[4 * j + 0]);
@@ -374,7 +433,8 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
     double de = cval(xe), dw = cval(xw);
     double te = tsu_p * (fabs(ce) + ge), tw = tsu_p * (fabs(cw) + gw);
     if (bad(de, te) || bad(dw, tw)) {
-      atomicOr(&flag, 1);
+      atomicOr(&flag[il], 1);
+      atomicMin(&fcol[il], j);
     } else {
       double r = 0;
       if (te > 0) r = fabs(de) / te;
@@ -383,14 +443,15 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0 && rep) {
+  if (tid == 0 && rep) {
     if (smax) rep_max_ratio(rep, __longlong_as_double((long long)smax));
-    if (flag) {
-      atomicAdd((unsigned long long*)&rep->panel_flags, 1ull);
-      atomicOr(&rep->status, (int)ABFT_ST_PANEL);
-      rep_flag_iter(rep, iter);
-      rep_event(rep, iter, 4, (int64_t)I * nb, cj0 + blockIdx.x * blockDim.x);
-    }
+    for (int q = 0; q < 4; ++q)
+      if (flag[q]) {
+        atomicAdd((unsigned long long*)&rep->panel_flags, 1ull);
+        atomicOr(&rep->status, (int)ABFT_ST_PANEL);
+        rep_flag_iter(rep, iter);
+        rep_event(rep, iter, 4, (int64_t)(Ib + q) * nb, cj0 + fcol[q]);
+      }
   }
 }
 
@@ -517,9 +578,10 @@ int xsums(hipStream_t s, const T* A, int64_t lda, int64_t n, int nb, int I0, int
           double* S, double* Sa, int ldS, int rnd) {
   int N = (int)((n + nb - 1) / nb);
   if (N - I0 <= 0 || kw <= 0) return 0;
-  if (rnd == 1) hipLaunchKernelGGL((k_xsums<T, 1>), dim3(N - I0), dim3(256), 0, s, A, lda, n, nb, I0, xc0, kw, dI, mode, S, Sa, ldS);
-  else if (rnd == 2) hipLaunchKernelGGL((k_xsums<T, 2>), dim3(N - I0), dim3(256), 0, s, A, lda, n, nb, I0, xc0, kw, dI, mode, S, Sa, ldS);
-  else hipLaunchKernelGGL((k_xsums<T, 0>), dim3(N - I0), dim3(256), 0, s, A, lda, n, nb, I0, xc0, kw, dI, mode, S, Sa, ldS);
+  const dim3 grid(N - I0, (kw + 15) / 16);
+  if (rnd == 1) hipLaunchKernelGGL((k_xsums<T, 1>), grid, dim3(256), 0, s, A, lda, n, nb, I0, xc0, kw, dI, mode, S, Sa, ldS);
+  else if (rnd == 2) hipLaunchKernelGGL((k_xsums<T, 2>), grid, dim3(256), 0, s, A, lda, n, nb, I0, xc0, kw, dI, mode, S, Sa, ldS);
+  else hipLaunchKernelGGL((k_xsums<T, 0>), grid, dim3(256), 0, s, A, lda, n, nb, I0, xc0, kw, dI, mode, S, Sa, ldS);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 template <typename T>
@@ -527,9 +589,10 @@ int ysums(hipStream_t s, const T* Y, int64_t ldy, int64_t n, int nb, int J0, int
           int rnd) {
   int N = (int)((n + nb - 1) / nb);
   if (N - J0 <= 0 || kw <= 0) return 0;
-  if (rnd == 1) hipLaunchKernelGGL((k_ysums<T, 1>), dim3(N - J0), dim3(256), 0, s, Y, ldy, n, nb, J0, kw, Tm, Ta, ldT);
-  else if (rnd == 2) hipLaunchKernelGGL((k_ysums<T, 2>), dim3(N - J0), dim3(256), 0, s, Y, ldy, n, nb, J0, kw, Tm, Ta, ldT);
-  else hipLaunchKernelGGL((k_ysums<T, 0>), dim3(N - J0), dim3(256), 0, s, Y, ldy, n, nb, J0, kw, Tm, Ta, ldT);
+  const dim3 grid(N - J0, (kw + 63) / 64);
+  if (rnd == 1) hipLaunchKernelGGL((k_ysums<T, 1>), grid, dim3(256), 0, s, Y, ldy, n, nb, J0, kw, Tm, Ta, ldT);
+  else if (rnd == 2) hipLaunchKernelGGL((k_ysums<T, 2>), grid, dim3(256), 0, s, Y, ldy, n, nb, J0, kw, Tm, Ta, ldT);
+  else hipLaunchKernelGGL((k_ysums<T, 0>), grid, dim3(256), 0, s, Y, ldy, n, nb, J0, kw, Tm, Ta, ldT);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 template int xsums<double>(hipStream_t, const double*, int64_t, int64_t, int, int, int64_t, int, int, int, double*,
@@ -545,7 +608,7 @@ int panel_check(hipStream_t s, const double* S, const double* Sa, int ldS, int I
                 const double* bt, int Ik, const double* colchk, int64_t ldc, int64_t cj0, int ncols, double tsu_p,
                 abft_report* rep, int iter, int nb) {
   if (I1 <= I0 || ncols <= 0) return 0;
-  dim3 grid((ncols + 255) / 256, I1 - I0);
+  dim3 grid((ncols + 63) / 64, (I1 - I0 + 3) / 4);
   hipLaunchKernelGGL(k_panel_check<MT>, grid, dim3(256), 0, s, S, Sa, ldS, I0, I1, kw, Mp, msp, msj, tri, pjoff,
                      mscale, Mabs, E, bt, Ik, colchk, ldc, cj0, ncols, tsu_p, rep, iter, nb);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;

@@ -91,8 +91,9 @@ __device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned target, abf
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
+    // poll without ordering; the acquire fence after the loop orders what follows
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
       if (++spins > (1L << 21)) {
         if (rep) atomicOr(&rep->status, (int)ABFT_ST_INTERNAL);
         if (err) atomicOr(err, 1);

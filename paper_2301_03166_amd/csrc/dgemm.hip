@@ -123,8 +123,9 @@ __device__ __forceinline__ void lower_tile(int lin, int T, int& tm, int& tn) {
 }  // namespace
 
 // TRI: the grid enumerates only the lower tiles of a square T x T grid
-// (requires LOWER, M == N, doff == 0).
-template <int TA, int TB, int FA, int LOWER, int TRI>
+// (requires LOWER, M == N, doff == 0).  ROLE only separates the launches of
+// the trailing-matrix update (1) from the other products (0) in profiles.
+template <int TA, int TB, int FA, int LOWER, int TRI, int ROLE>
 __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha, const double* __restrict__ A,
                                                int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
                                                double* __restrict__ C, int64_t ldc, int64_t doff, int kc,
@@ -198,9 +199,25 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
   }
   __syncthreads();
   const int kl = lane >> 4, il = lane & 15;
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < KT) load(kbeg + (kt + 1) * BK);
+  // D = C^T layout: acc[ci][ri][r] is C(gi, gj) with gi = m0 + wm*64 + ri*16 + il,
+  // gj = n0 + wn*64 + ci*16 + 4r + kl; sixteen lanes write 128 contiguous bytes.
+  // Interior tiles read their C values during the last K step (the epilogue
+  // then finds them in registers instead of waiting on memory).
+  const bool straddle = LOWER && (int64_t)m0 + doff < (int64_t)(n0 + BN - 1);
+  const bool fastC = inner && !straddle && beta != 0.0;
+  double cpre[4][4][4];
+  auto loadC = [&]() {
+#pragma unroll
+    for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+      for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = m0 + wm * 64 + ri * 16 + il, gj = n0 + wn * 64 + ci * 16 + 4 * r + kl;
+          cpre[ci][ri][r] = C[gi + (int64_t)gj * ldc];
+        }
+  };
+  auto step = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       double af[4], bf[4];
@@ -215,35 +232,29 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
         for (int ri = 0; ri < 4; ++ri)
           acc[ci][ri] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[ci], af[ri], acc[ci][ri], 0, 0, 0);
     }
-    if (kt + 1 < KT) store(cur ^ 1);
+  };
+  for (int kt = 0; kt + 1 < KT; ++kt) {
+    const int cur = kt & 1;
+    load(kbeg + (kt + 1) * BK);
+    step(cur);
+    store(cur ^ 1);
     __syncthreads();
   }
+  // last K step (peeled: no operand loads in flight, C's values instead)
+  if (fastC) loadC();
+  if (KT > 0) step((KT - 1) & 1);
 
-  // D = C^T layout: acc[ci][ri][r] is C(gi, gj) with gi = m0 + wm*64 + ri*16 + il,
-  // gj = n0 + wn*64 + ci*16 + 4r + kl; sixteen lanes write 128 contiguous bytes
-  const bool straddle = LOWER && (int64_t)m0 + doff < (int64_t)(n0 + BN - 1);
   if (inner && !straddle) {
 #pragma unroll
-    for (int ci = 0; ci < 4; ++ci) {
-      double cv[4][4];
-      if (beta != 0.0) {
-#pragma unroll
-        for (int ri = 0; ri < 4; ++ri)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int gi = m0 + wm * 64 + ri * 16 + il, gj = n0 + wn * 64 + ci * 16 + 4 * r + kl;
-            cv[ri][r] = C[gi + (int64_t)gj * ldc];
-          }
-      }
+    for (int ci = 0; ci < 4; ++ci)
 #pragma unroll
       for (int ri = 0; ri < 4; ++ri)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int gi = m0 + wm * 64 + ri * 16 + il, gj = n0 + wn * 64 + ci * 16 + 4 * r + kl;
           const double v = alpha * acc[ci][ri][r];
-          C[gi + (int64_t)gj * ldc] = (beta == 0.0) ? v : beta * cv[ri][r] + v;
+          C[gi + (int64_t)gj * ldc] = fastC ? beta * cpre[ci][ri][r] + v : v;
         }
-    }
   } else {
 #pragma unroll
     for (int ci = 0; ci < 4; ++ci)
@@ -265,7 +276,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
 // the general kernel (unsupported option combination or alignment), <0 on error.
 int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, int k, double alpha, const double* A,
                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int S,
-               int kc, double* ws) {
+               int kc, double* ws, int role) {
   if ((reinterpret_cast<uintptr_t>(A) & 15) || (reinterpret_cast<uintptr_t>(B) & 15) || (lda & 1) || (ldb & 1))
     return 0;
   const int64_t tM = (m + DG_BM - 1) / DG_BM, tN = (n + DG_BN - 1) / DG_BN;
@@ -273,14 +284,16 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, i
   const int64_t nt = tri ? tM * (tM + 1) / 2 : tM * tN;
   if (nt > 0x7fffffff) return 0;
   const dim3 grid((unsigned)nt, (unsigned)S), block(256);
+#define DG_LAUNCH(TA_, TB_, FA_, LO_, TRI_, RO_)                                                                  \
+  hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, TRI_, RO_>), grid, block, 0, s, m, n, k, alpha, A, lda, B, ldb, beta, \
+                     C, ldc, doff, kc, ws)
 #define DG_CASE(TA_, TB_, FA_, LO_)                                                                              \
   if (ta == TA_ && tb == TB_ && fa == FA_ && lower == LO_) {                                                       \
-    if (LO_ && tri)                                                                                                \
-      hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, LO_>), grid, block, 0, s, m, n, k, alpha, A, lda, B, ldb, beta, \
-                         C, ldc, doff, kc, ws);                                                                    \
-    else                                                                                                           \
-      hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, 0>), grid, block, 0, s, m, n, k, alpha, A, lda, B, ldb, beta,  \
-                         C, ldc, doff, kc, ws);                                                                    \
+    if (LO_ && tri) {                                                                                              \
+      if (role) DG_LAUNCH(TA_, TB_, FA_, LO_, LO_, 1); else DG_LAUNCH(TA_, TB_, FA_, LO_, LO_, 0);                 \
+    } else {                                                                                                       \
+      if (role) DG_LAUNCH(TA_, TB_, FA_, LO_, 0, 1); else DG_LAUNCH(TA_, TB_, FA_, LO_, 0, 0);                     \
+    }                                                                                                              \
     return hipGetLastError() == hipSuccess ? 1 : ABFT_ERR_HIP;                                                     \
   }
   DG_CASE(0, 0, 0, 0)  // C -= L21 U12 (LU), TRSM block updates
@@ -289,6 +302,7 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, i
   DG_CASE(1, 0, 1, 0)  // W = V^T C (QR)
   DG_CASE(0, 0, 1, 0)  // C -= V W (QR)
 #undef DG_CASE
+#undef DG_LAUNCH
   return 0;
 }
 

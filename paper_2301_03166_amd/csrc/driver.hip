@@ -20,7 +20,7 @@ using namespace abft;
 // A captured batched call: the arguments it was captured with and its
 // executable graph (replayed when a later call passes the same arguments).
 struct BatchGraph {
-  int chol, prec, batch, protect;
+  int chol, prec, batch, protect, wgs;
   double ts;
   const void *dn, *dA, *dlda, *dipiv, *dwork, *dinfo, *dreps;
   hipGraphExec_t exec;
@@ -41,7 +41,8 @@ struct abft_handle_s {
 
 namespace {
 
-constexpr int LEAFW = 32;
+constexpr int LEAFW = 32;   // leaf width of the Cholesky panel and the triangular solves
+constexpr int CLEAFW = 64;  // widest cooperative LU / QR leaf (narrower where it cannot cover the rows)
 constexpr int MAXNB = 512;
 constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
 constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
@@ -54,6 +55,10 @@ constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 constexpr size_t SPLITK_ELEMS = (size_t)1 << 22;  // split-K partials (32 MB)
+// cooperative-leaf exchange slots: per column G (w + 2) + w doubles (LU) or
+// G w + w (QR), plus G w^2 for the QR leaf's Gram partials; G <= 256, w <= 64
+constexpr size_t SLOT_DOUBLES = (size_t)3 << 20;
+constexpr size_t CTR_BYTES = 4096;  // grid-barrier counters: top + 16 groups, 128 bytes apart
 
 // Phase timer of profiled calls: event pairs recorded on the stream, summed
 // per phase after one synchronisation at the end of the call.
@@ -138,8 +143,8 @@ Ws carve(char* base, int64_t n, int nb, int op, int elem) {
   w.Tm = (double*)take((size_t)2 * N * nb * sizeof(double));
   w.Ta = (double*)take((size_t)2 * N * nb * sizeof(double));
   w.tflags = (int*)take((size_t)N * N * sizeof(int));
-  w.ctr = (unsigned*)take(256);
-  w.slots = (double*)take((size_t)(1 << 20) * sizeof(double));
+  w.ctr = (unsigned*)take(CTR_BYTES);
+  w.slots = (double*)take(SLOT_DOUBLES * sizeof(double));
   if (op == ABFT_OP_GETRF || op == ABFT_OP_GESV_MP) {
     w.porig = (double*)take((size_t)n * nb * elem);
     w.stage = (double*)take((size_t)2 * nb * n * elem);
@@ -175,7 +180,7 @@ int check_opts(const abft_opts* o, int64_t n, int& nb, int& protect, double& ts)
   return 0;
 }
 
-inline int split(int w) { return ((w / 2 + LEAFW - 1) / LEAFW) * LEAFW; }
+inline int split(int w, int leaf = LEAFW) { return ((w / 2 + leaf - 1) / leaf) * leaf; }
 
 // ----------------------------------------------------------------- faults
 template <typename T>
@@ -201,15 +206,18 @@ int apply_faults(hipStream_t s, const abft_opts* o, int iter, T* A, int64_t lda,
 // GEMM on the data type of the factorization: FP64 MFMA for double data;
 // for binary32 data FP32 MFMA, or bf16 / fp16 products with FP32
 // accumulation when prec asks for them (trailing update only).
+// role 1 marks the trailing-matrix update (its own kernel instance in profiles)
 inline int gemmT(hipStream_t s, int prec, int ta, int tb, int lower, int m, int n, int k, double alpha,
                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-                 int64_t doff) {
+                 int64_t doff, int role = 0) {
   (void)prec;
-  return gemm64(s, ta, tb, 0, 0, lower, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, doff);
+  return gemm64(s, ta, tb, 0, 0, lower, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, doff, 0, 0, 0, nullptr, 0,
+                role);
 }
 inline int gemmT(hipStream_t s, int prec, int ta, int tb, int lower, int m, int n, int k, double alpha,
                  const float* A, int64_t lda, const float* B, int64_t ldb, double beta, float* C, int64_t ldc,
-                 int64_t doff) {
+                 int64_t doff, int role = 0) {
+  (void)role;
   return gemm32(s, prec, ta, tb, lower, m, n, k, (float)alpha, A, lda, B, ldb, (float)beta, C, ldc, doff);
 }
 template <typename T>
@@ -264,9 +272,12 @@ struct LuCtx {
 template <typename T>
 int lu_panel(LuCtx<T>& c, int64_t c0, int64_t c1) {
   const int w = (int)(c1 - c0);
-  if (w <= LEAFW)
-    return getrf_leaf(c.s, c.A, c.lda, c.n, c0, w, c.ipiv, c.info, c.w->slots, c.w->ctr, &c.ctr_base, c.rep, c.maxg);
-  const int h = split(w);
+  if (w <= CLEAFW) {
+    const int rc =
+        getrf_leaf(c.s, c.A, c.lda, c.n, c0, w, c.ipiv, c.info, c.w->slots, c.w->ctr, &c.ctr_base, c.rep, c.maxg);
+    if (rc != ABFT_ERR_UNSUPPORTED || w <= LEAFW) return rc;  // else too many rows for one wide leaf: split
+  }
+  const int h = w <= CLEAFW ? split(w) : split(w, CLEAFW);
   TRY(lu_panel(c, c0, c0 + h));
   TRY(perm_build(c.s, c.ipiv, c0, h, c.n, c.w->moves));
   TRY(laswp(c.s, c.A, c.lda, c0 + h, c1, c.w->moves, (T*)c.w->stage, (double*)nullptr, 0, 1));
@@ -300,10 +311,12 @@ int qr_panel(QrCtx& c, int64_t c0, int64_t c1) {
   const int nb = c.nb;
   double* A = c.A;
   const int64_t lda = c.lda, n = c.n;
-  if (w <= LEAFW)
-    return geqrf_leaf(c.s, A, lda, n, c0, w, c.tau, c.w->Tfac, nb, toff, c.w->slots, c.w->ctr, &c.ctr_base, c.rep,
-                      c.maxg);
-  const int h = split(w);
+  if (w <= CLEAFW) {
+    const int rc = geqrf_leaf(c.s, A, lda, n, c0, w, c.tau, c.w->Tfac, nb, toff, c.w->slots, c.w->ctr, &c.ctr_base,
+                              c.rep, c.maxg);
+    if (rc != ABFT_ERR_UNSUPPORTED || w <= LEAFW) return rc;  // else too many rows for one wide leaf: split
+  }
+  const int h = w <= CLEAFW ? split(w) : split(w, CLEAFW);
   TRY(qr_panel(c, c0, c0 + h));
   const int64_t r = c0 + h;
   double* V1 = A + c0 + c0 * lda;
@@ -395,7 +408,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     const int64_t m = n - c1;
     T* L21 = dA + c1 + c0 * lda;
     t = pf.begin(PH_TMU);
-    TRY(gemmT(s, prec, 0, 1, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0));
+    TRY(gemmT(s, prec, 0, 1, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
     pf.end(t);
     pf.tmu_flops += (double)m * (double)(m + 1) * kw;
     pf.tmu_launches++;
@@ -429,7 +442,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
   hipStream_t s = h->stream;
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
-  TRY(fill_zero(s, w.ctr, 256));
+  TRY(fill_zero(s, w.ctr, CTR_BYTES));
   const int N = (int)((n + nb - 1) / nb);
   const int ldc = 2 * N;
   const double u = sizeof(T) == 8 ? U64 : U32;
@@ -480,7 +493,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
     T* L21 = dA + c1 + c0 * lda;
     T* U12 = dA + c0 + c1 * lda;
     t = pf.begin(PH_TMU);
-    TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0));
+    TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
     pf.end(t);
     pf.tmu_flops += 2.0 * (double)m * (double)m * kw;
     pf.tmu_launches++;
@@ -778,7 +791,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
-  TRY(fill_zero(s, w.ctr, 256));
+  TRY(fill_zero(s, w.ctr, CTR_BYTES));
   const int N = (int)((n + nb - 1) / nb);
   const int ldc = 2 * N;
   const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);
@@ -809,14 +822,21 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     const int64_t m = n - c1;
     double* V = dA + c0 + c0 * lda;
     double* C = dA + c0 + c1 * lda;
+    // C -= V T^T V^T C: the two products with the full panel height are the
+    // trailing update proper (timed per launch); W2 = T^T W is a small product
+    int S = 0;
     t = pf.begin(PH_TMU);
     TRY(gemm64(s, 1, 0, 1, 0, 0, kw, (int)m, (int)(n - c0), 1.0, V, lda, C, lda, 0.0, w.W, nb, 0, 0, 0, 0, w.splitk,
-               SPLITK_ELEMS));
-    TRY(gemm64(s, 1, 0, 0, 0, 0, kw, (int)m, kw, 1.0, w.Tfac, nb, w.W, nb, 0.0, w.W2, nb, 0));
-    TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)m, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0));
+               SPLITK_ELEMS, 1, &S));
     pf.end(t);
-    pf.tmu_flops += 4.0 * (double)(n - c0) * (double)m * kw + 2.0 * (double)kw * kw * m;
-    pf.tmu_launches += 3;
+    if (S > 1) TRY(splitk_reduce(s, w.splitk, S, kw, (int)m, 0.0, w.W, nb));
+    TRY(gemm64(s, 1, 0, 0, 0, 0, kw, (int)m, kw, 1.0, w.Tfac, nb, w.W, nb, 0.0, w.W2, nb, 0));
+    t = pf.begin(PH_TMU);
+    TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)m, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0, 0, 0, 0, nullptr,
+               0, 1));
+    pf.end(t);
+    pf.tmu_flops += 4.0 * (double)(n - c0) * (double)m * kw;
+    pf.tmu_launches += 2;
     if (protect) {
       t = pf.begin(PH_CARRY);
       TRY(ysums<double>(s, w.W2 - c1 * nb, nb, n, nb, k + 1, kw, w.Tm, w.Ta, nb, 0));
@@ -929,20 +949,23 @@ static int batched_common(abft_handle h, int chol, int32_t batch, int32_t nmax, 
   if (!dinfo || !dreps) return -11;
   if (!dwork || work_bytes < batched_ws_bytes(batch)) return ABFT_ERR_WORKSPACE;
   const int nf = opts->faults ? opts->nfaults : 0;
+  if (opts->wgs_per_cu < 0 || opts->wgs_per_cu > 4) return -10;
+  const int wgs = std::max(1, (int)opts->wgs_per_cu) * h->cus;
   if (!(opts->flags & ABFT_FLAG_GRAPH) || nf > 0)
     return batched_factor(h->stream, chol, prec, batch, dn, dA, dlda, dipiv, dwork, protect, ts, opts->faults, nf,
-                          dinfo, dreps, h->cus);
+                          dinfo, dreps, wgs);
   // graph path: replay the graph captured for these arguments, or capture it
   for (int i = 0; i < h->ngraphs; ++i) {
     const BatchGraph& g = h->graphs[i];
-    if (g.chol == chol && g.prec == prec && g.batch == batch && g.protect == protect && g.ts == ts && g.dn == dn &&
+    if (g.chol == chol && g.prec == prec && g.batch == batch && g.protect == protect && g.ts == ts && g.wgs == wgs &&
+        g.dn == dn &&
         g.dA == dA && g.dlda == dlda && g.dipiv == dipiv && g.dwork == dwork && g.dinfo == dinfo && g.dreps == dreps)
       return hipGraphLaunch(g.exec, h->stream) == hipSuccess ? 0 : ABFT_ERR_HIP;
   }
   if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) return ABFT_ERR_HIP;
   if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return ABFT_ERR_HIP;
   const int rc = batched_factor(h->cap, chol, prec, batch, dn, dA, dlda, dipiv, dwork, protect, ts, nullptr, 0, dinfo,
-                                dreps, h->cus);
+                                dreps, wgs);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(h->cap, &graph);
   if (rc || ec != hipSuccess || !graph) {
@@ -961,7 +984,7 @@ static int batched_common(abft_handle h, int chol, int32_t batch, int32_t nmax, 
     if (hipStreamSynchronize(h->stream) != hipSuccess) return ABFT_ERR_HIP;
     (void)hipGraphExecDestroy(h->graphs[slot].exec);
   }
-  h->graphs[slot] = BatchGraph{chol, prec, batch, protect, ts, dn, dA, dlda, dipiv, dwork, dinfo, dreps, exec};
+  h->graphs[slot] = BatchGraph{chol, prec, batch, protect, wgs, ts, dn, dA, dlda, dipiv, dwork, dinfo, dreps, exec};
   return hipGraphLaunch(exec, h->stream) == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 

@@ -188,6 +188,12 @@ __global__ void k_splitk_reduce(const double* __restrict__ P, int S, int M, int 
   }
 }
 
+int splitk_reduce(hipStream_t s, const double* P, int S, int m, int n, double beta, double* C, int64_t ldc) {
+  unsigned rg = (unsigned)std::min<int64_t>(4096, ((int64_t)m * n + 255) / 256);
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(rg), dim3(256), 0, s, P, S, m, n, beta, C, ldc);
+  return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
 // ---------------------------------------------------------------------------
 // host dispatcher
 // ---------------------------------------------------------------------------
@@ -206,15 +212,20 @@ __global__ void k_splitk_reduce(const double* __restrict__ P, int S, int M, int 
 
 int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int n, int k, double alpha, const void* A,
            int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int atype,
-           int btype, int rnd, double* ws, size_t ws_elems) {
+           int btype, int rnd, double* ws, size_t ws_elems, int role, int* split_out) {
   if (m <= 0 || n <= 0) return 0;
   if (k <= 0 && beta == 1.0) return 0;
   int64_t grid = (int64_t)((m + 127) / 128) * ((n + 127) / 128);
-  // few output tiles and a long K: split K over extra workgroups
+  // few output tiles and a long K: split K over extra workgroups (about two
+  // per CU, K ranges of at least 128, as many as the partials buffer holds)
   unsigned S = 1;
   int kc = 0;
-  if (ws && !lower && grid < 160 && k >= 2048) {
-    int64_t want = std::min<int64_t>(32, std::min<int64_t>((320 + grid - 1) / grid, k / 512));
+  // (a trailing-update launch splits only when its caller reduces the
+  // partials itself, so that the launch stays one kernel)
+  if (split_out) *split_out = 0;
+  if (ws && !lower && (!role || split_out) && grid < 512 && k >= 1024) {
+    int64_t want = std::min<int64_t>(64, std::min<int64_t>((512 + grid - 1) / grid, k / 128));
+    want = std::min<int64_t>(want, (int64_t)(ws_elems / ((size_t)m * n)));
     if (want >= 2) {
       int64_t kcl = ((k + want - 1) / want + 31) / 32 * 32;
       int64_t sp = (k + kcl - 1) / kcl;
@@ -226,13 +237,15 @@ int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int 
   }
   if (atype == 0 && btype == 0 && fb == 0 && rnd == 0 && fa <= 1) {
     const int r = dgemm_fast(s, ta, tb, fa, lower, m, n, k, alpha, (const double*)A, lda, (const double*)B, ldb, beta,
-                             C, ldc, doff, (int)S, kc, ws);
+                             C, ldc, doff, (int)S, kc, ws, role);
     if (r < 0) return r;
     if (r == 1) {
       if (kc > 0) {
-        unsigned rg = (unsigned)std::min<int64_t>(4096, ((int64_t)m * n + 255) / 256);
-        hipLaunchKernelGGL(k_splitk_reduce, dim3(rg), dim3(256), 0, s, ws, (int)S, m, n, beta, C, ldc);
-        if (hipGetLastError() != hipSuccess) return ABFT_ERR_HIP;
+        if (split_out) {
+          *split_out = (int)S;
+          return 0;
+        }
+        return splitk_reduce(s, ws, (int)S, m, n, beta, C, ldc);
       }
       return 0;
     }

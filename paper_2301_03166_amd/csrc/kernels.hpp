@@ -16,7 +16,10 @@ namespace abft {
 // 1 float (rounded to bf16 / fp16 when rnd = 1 / 2).
 int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int n, int k, double alpha, const void* A,
            int64_t lda, const void* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int atype = 0,
-           int btype = 0, int rnd = 0, double* ws = nullptr, size_t ws_elems = 0);
+           int btype = 0, int rnd = 0, double* ws = nullptr, size_t ws_elems = 0, int role = 0,
+           int* split_out = nullptr);
+// C = beta C + sum of the S split-K partials in P (m x n each, leading dimension m)
+int splitk_reduce(hipStream_t s, const double* P, int S, int m, int n, double beta, double* C, int64_t ldc);
 
 // binary32 data GEMM for the mixed-precision trailing update:
 // C -= op(A) op(B) with C, A, B float; op in FP32 MFMA (prec ABFT_F32) or
@@ -25,7 +28,7 @@ int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int 
 // if launched, 0 if the option combination is not covered, <0 on error
 int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, int k, double alpha, const double* A,
                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int S,
-               int kc, double* ws);
+               int kc, double* ws, int role);
 int gemm32(hipStream_t s, int prec, int ta, int tb, int lower, int m, int n, int k, float alpha, const float* A,
            int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int64_t doff);
 
@@ -90,7 +93,7 @@ int copy_f64(hipStream_t s, const double* a, double* b, int n);
 size_t batched_ws_bytes(int batch);
 int batched_factor(hipStream_t s, int chol, int prec, int batch, const int32_t* dn, void* const* dA,
                    const int32_t* dlda, int32_t* const* dipiv, void* dwork, int protect, double ts,
-                   const abft_fault* hfaults, int nfaults, int32_t* dinfo, abft_report* dreps, int cus);
+                   const abft_fault* hfaults, int nfaults, int32_t* dinfo, abft_report* dreps, int wgs);
 int f32_to_f64(hipStream_t s, const float* a, double* b, int n);
 
 }  // namespace abft

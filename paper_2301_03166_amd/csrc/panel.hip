@@ -15,7 +15,8 @@
 
 namespace abft {
 
-constexpr int LEAF = 32;
+constexpr int LEAF = 32;   // width of the triangular leaf kernels (potrf / trsm)
+constexpr int CLEAF = 64;  // widest cooperative LU / QR leaf
 
 template <typename T>
 __device__ __forceinline__ T fms(T a, T b, T c) {  // a - b*c as the reference arithmetic does it
@@ -24,6 +25,26 @@ __device__ __forceinline__ T fms(T a, T b, T c) {  // a - b*c as the reference a
 template <>
 __device__ __forceinline__ float fms<float>(float a, float b, float c) {
   return __fmaf_rn(-b, c, a);
+}
+
+// Row update Ld[c] -= f[c] * v for c in [cb, w) (a - b*c rounding, as the
+// reference arithmetic), eight columns per step with every load issued
+// before the first use (an LDS round trip per eight elements, not per one).
+template <typename T, typename F>
+__device__ __forceinline__ void row_axpy(T* __restrict__ x, const F* __restrict__ f, T v, int cb, int w) {
+  int c = cb;
+  for (; c + 8 <= w; c += 8) {
+    T xv[8];
+    F fv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      xv[u] = x[c + u];
+      fv[u] = f[c + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[c + u] = fms(xv[u], (T)fv[u], v);
+  }
+  for (; c < w; ++c) x[c] = fms(x[c], (T)f[c], v);
 }
 
 // ---------------------------------------------------------------------------
@@ -84,10 +105,25 @@ __global__ __launch_bounds__(256) void k_trsm_rlt_leaf(T* A, int64_t lda, int64_
   }
   __syncthreads();
   if (rb + tid < r1) {
-    for (int j = 0; j < w; ++j) {
-      T s = B[tid][j];
-      for (int p = 0; p < j; ++p) s = fms(s, B[tid][p], L[j][p]);
-      B[tid][j] = s / L[j][j];
+    if (w == LEAF) {  // the row in registers, fully unrolled (same operation order)
+      T x[LEAF];
+#pragma unroll
+      for (int j = 0; j < LEAF; ++j) x[j] = B[tid][j];
+#pragma unroll
+      for (int j = 0; j < LEAF; ++j) {
+        T s = x[j];
+#pragma unroll
+        for (int p = 0; p < j; ++p) s = fms(s, x[p], L[j][p]);
+        x[j] = s / L[j][j];
+      }
+#pragma unroll
+      for (int j = 0; j < LEAF; ++j) B[tid][j] = x[j];
+    } else {
+      for (int j = 0; j < w; ++j) {
+        T s = B[tid][j];
+        for (int p = 0; p < j; ++p) s = fms(s, B[tid][p], L[j][p]);
+        B[tid][j] = s / L[j][j];
+      }
     }
   }
   __syncthreads();
@@ -115,10 +151,25 @@ __global__ __launch_bounds__(256) void k_trsm_llu_leaf(T* A, int64_t lda, int64_
   }
   __syncthreads();
   if (jb + tid < j1) {
-    for (int i = 0; i < w; ++i) {
-      T s = B[tid][i];
-      for (int p = 0; p < i; ++p) s = fms(s, L[i][p], B[tid][p]);
-      B[tid][i] = s;
+    if (w == LEAF) {  // the column in registers, fully unrolled (same operation order)
+      T x[LEAF];
+#pragma unroll
+      for (int i = 0; i < LEAF; ++i) x[i] = B[tid][i];
+#pragma unroll
+      for (int i = 1; i < LEAF; ++i) {
+        T s = x[i];
+#pragma unroll
+        for (int p = 0; p < i; ++p) s = fms(s, L[i][p], x[p]);
+        x[i] = s;
+      }
+#pragma unroll
+      for (int i = 0; i < LEAF; ++i) B[tid][i] = x[i];
+    } else {
+      for (int i = 0; i < w; ++i) {
+        T s = B[tid][i];
+        for (int p = 0; p < i; ++p) s = fms(s, L[i][p], B[tid][p]);
+        B[tid][i] = s;
+      }
     }
   }
   __syncthreads();
@@ -134,6 +185,24 @@ __global__ __launch_bounds__(256) void k_trsm_llu_leaf(T* A, int64_t lda, int64_
 // index on ties; row interchanges inside the leaf columns only (the caller
 // applies them to the other columns).
 // ---------------------------------------------------------------------------
+#ifdef ABFT_LEAF_TIMING
+#define LT_DECL unsigned long long lt_t = __builtin_amdgcn_s_memtime(), lt_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#define LT_MARK(k)                                        \
+  do {                                                    \
+    unsigned long long lt_n = __builtin_amdgcn_s_memtime(); \
+    lt_acc[k] += lt_n - lt_t;                             \
+    lt_t = lt_n;                                          \
+  } while (0)
+#define LT_PRINT(name)                                                                                          \
+  if (blockIdx.x == 0 && threadIdx.x == 0 && c0 < 64)                                                          \
+    printf("%s c0=%ld G=%d R=%d w=%d: %llu %llu %llu %llu %llu %llu %llu %llu\n", name, (long)c0, (int)gridDim.x, R, w, \
+           lt_acc[0], lt_acc[1], lt_acc[2], lt_acc[3], lt_acc[4], lt_acc[5], lt_acc[6], lt_acc[7]);
+#else
+#define LT_DECL
+#define LT_MARK(k)
+#define LT_PRINT(name)
+#endif
+
 template <typename T>
 __device__ __forceinline__ bool better(double a, int64_t ia, double b, int64_t ib) {
   return a > b || (a == b && ia < ib);
@@ -144,9 +213,10 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
                                                     int32_t* ipiv, int32_t* info, double* slots, unsigned* ctr,
                                                     unsigned ctr_base, abft_report* rep) {
   extern __shared__ unsigned char smem_raw[];
+  LT_DECL
   T* Ld = reinterpret_cast<T*>(smem_raw);  // R x (w+1)
   const int ldl = w + 1;
-  __shared__ double prow[LEAF], orow[LEAF];
+  __shared__ double prow[CLEAF], orow[CLEAF];
   __shared__ double wv_val[4];
   __shared__ int64_t wv_idx[4];
   __shared__ int wv_g[4];
@@ -199,7 +269,9 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
       sj[g * (w + 2) + 2 + tid] = val;
       if (g == 0) sj[G * (w + 2) + tid] = (double)Ld[(d - rbeg) * ldl + tid];
     }
+    LT_MARK(0);
     grid_barrier(ctr, ctr_base + (unsigned)(j + 1) * G, rep, nullptr);
+    LT_MARK(1);
     // every workgroup picks the same winner: one slot per thread, then a
     // block argmax (largest |value|, first row index on ties; the row index
     // identifies its workgroup, so the choice does not depend on the order)
@@ -233,6 +305,7 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
       }
       __syncthreads();
     }
+    LT_MARK(2);
     const int64_t p = s_piv;
     const int pg = s_pg;
     if (tid < w) {
@@ -240,6 +313,7 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
       orow[tid] = sj[G * (w + 2) + tid];
     }
     __syncthreads();
+    LT_MARK(3);
     if (p != d) {
       if (g == 0 && tid < w) Ld[(d - rbeg) * ldl + tid] = (T)prow[tid];
       if (p >= rbeg && p < rbeg + rows && tid < w) Ld[(p - rbeg) * ldl + tid] = (T)orow[tid];
@@ -256,7 +330,7 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
         if (gi <= d) continue;
         T l = Ld[i * ldl + j] / piv;
         Ld[i * ldl + j] = l;
-        for (int c = j + 1; c < w; ++c) Ld[i * ldl + c] = fms(Ld[i * ldl + c], l, (T)prow[c]);
+        row_axpy(Ld + i * ldl, prow, l, j + 1, w);  // a(i,c) - l * u(c)
       }
     }
     __syncthreads();
@@ -265,6 +339,8 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
     int i = idx % rows, j = idx / rows;
     A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
   }
+  LT_MARK(4);
+  LT_PRINT("lu_leaf")
 }
 
 // ---------------------------------------------------------------------------
@@ -272,20 +348,23 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
 // dlarfg convention), plus the leaf's triangular factor T (forward,
 // columnwise) written at T[toff + toff*ldt].
 // ---------------------------------------------------------------------------
+
 __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int64_t m, int64_t c0, int w, int R,
                                                     double* tau, double* Tm, int ldt, int toff, double* slots,
                                                     unsigned* ctr, unsigned ctr_base, abft_report* rep) {
   extern __shared__ unsigned char smem_raw[];
+  LT_DECL
   double* Ld = reinterpret_cast<double*>(smem_raw);  // R x (w+1)
   const int ldl = w + 1;
-  __shared__ double part[4][LEAF];
-  __shared__ double qpart[256 / LEAF][LEAF];
-  __shared__ double svec[LEAF], orow[LEAF], fvec[LEAF];
+  __shared__ double part[4][CLEAF];
+  __shared__ double qpart[256 / CLEAF][CLEAF];
+  __shared__ double svec[CLEAF], orow[CLEAF], fvec[CLEAF];
   __shared__ double s_beta, s_tau, s_scale;
-  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int64_t rbeg = c0 + (int64_t)g * R;
   const int rows = (int)max((int64_t)0, min((int64_t)R, m - rbeg));
-  const int slot_stride = G * w + w;
+  // per column: G workgroup partial Gram rows, then row d (w values each)
+  const size_t slot_stride = (size_t)(G + 1) * w;
 
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
@@ -293,45 +372,79 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
   }
   __syncthreads();
 
+  // sum of the G records of len values (src + r * len) for entries e <
+  // len: QG threads share an entry (records r = gq, gq + QG, ...), eight
+  // loads in flight each; the parts are added in a fixed order.  The result
+  // goes to dst[e] (LDS).
+  constexpr int QG = 256 / CLEAF;
+  auto sum_slots = [&](const double* src, int len, double* dst) {
+    for (int e0 = 0; e0 < len; e0 += CLEAF) {
+      const int c = tid % CLEAF, gq = tid / CLEAF, e = e0 + c;
+      double pp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (e < len) {
+        int r = gq;
+        for (; r + 7 * QG < G; r += 8 * QG) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pp[u] += src[(size_t)(r + u * QG) * len + e];
+        }
+        for (int u = 0; r < G; r += QG, ++u) pp[u] += src[(size_t)r * len + e];
+      }
+      double t = pp[0];
+#pragma unroll
+      for (int u = 1; u < 8; ++u) t += pp[u];
+      qpart[gq][c] = t;
+      __syncthreads();
+      if (tid < CLEAF && e0 + tid < len) {
+        double v = qpart[0][tid];
+        for (int u = 1; u < QG; ++u) v += qpart[u][tid];
+        dst[e0 + tid] = v;
+      }
+      __syncthreads();
+    }
+  };
+
   for (int j = 0; j < w; ++j) {
     const int64_t d = c0 + j;
     double* sj = slots + (size_t)j * slot_stride;
-    // partial Gram row: s_c = sum_{i > d} a(i,j) a(i,c), c = j..w-1
-    for (int c = j; c < w; ++c) {
+    double* rowd = sj + (size_t)G * w;
+    // partial Gram row: s_c = sum_{i > d} a(i,j) a(i,c), c = j..w-1; thread
+    // (q, cl) takes column c = j + cl over the rows i = q (mod 4) of the LDS
+    // panel, and the four row classes are added in order
+    {
+      const int cl = tid & 63, q = tid >> 6, c = j + cl;
       double acc = 0.0;
-      for (int i = tid; i < rows; i += 256) {
-        if (rbeg + i <= d) continue;
-        acc += Ld[i * ldl + j] * Ld[i * ldl + c];
+      if (c < w) {
+        const int i0 = (int)max((int64_t)0, d + 1 - rbeg);
+        int i = i0 + ((q - i0 % 4) + 4) % 4;
+        for (; i + 28 < rows; i += 32) {  // eight rows per step, loads first
+          double xa[8], xb[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            xa[u] = Ld[(i + 4 * u) * ldl + j];
+            xb[u] = Ld[(i + 4 * u) * ldl + c];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += xa[u] * xb[u];
+        }
+        for (; i < rows; i += 4) acc += Ld[i * ldl + j] * Ld[i * ldl + c];
       }
-      acc = wave_sum(acc);
-      if (lane == 0) part[wv][c] = acc;
+      part[q][cl] = acc;
     }
     __syncthreads();
+    LT_MARK(0);
     if (tid < w) {
       double v = 0.0;
-      if (tid >= j) v = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
-      sj[g * w + tid] = v;
-      if (g == 0) sj[G * w + tid] = Ld[(d - rbeg) * ldl + tid];
+      if (tid >= j) v = ((part[0][tid - j] + part[1][tid - j]) + part[2][tid - j]) + part[3][tid - j];
+      sj[(size_t)g * w + tid] = v;
+      if (g == 0) rowd[tid] = Ld[(d - rbeg) * ldl + tid];
     }
+    LT_MARK(1);
     grid_barrier(ctr, ctr_base + (unsigned)(j + 1) * G, rep, nullptr);
-    {
-      // thread (group gq, column c) sums the slots q = gq, gq + QG, ...; the
-      // QG group sums are then added in group order (a fixed order)
-      constexpr int QG = 256 / LEAF;
-      const int c = tid % LEAF, gq = tid / LEAF;
-      double s = 0.0;
-      if (c < w)
-        for (int q = gq; q < G; q += QG) s += sj[q * w + c];
-      qpart[gq][c] = s;
-      __syncthreads();
-      if (tid < w) {
-        double t = qpart[0][tid];
-        for (int u = 1; u < QG; ++u) t += qpart[u][tid];
-        svec[tid] = t;
-        orow[tid] = sj[G * w + tid];
-      }
-      __syncthreads();
-    }
+    LT_MARK(2);
+    // every workgroup: Gram row = sum of the G partial rows, and row d
+    if (tid < w) orow[tid] = rowd[tid];
+    sum_slots(sj, w, svec);
+    LT_MARK(3);
     if (tid == 0) {
       double alpha = orow[j], s2 = svec[j];
       if (s2 == 0.0) {
@@ -358,63 +471,103 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
         } else {
           double v = Ld[i * ldl + j] * sc;
           Ld[i * ldl + j] = v;
-          for (int c = j + 1; c < w; ++c) Ld[i * ldl + c] -= fvec[c] * v;
+          row_axpy(Ld + i * ldl, fvec, v, j + 1, w);  // a(i,c) - f(c) * v
         }
       }
     }
     __syncthreads();
+    LT_MARK(4);
   }
   // T factor of the leaf from the Gram matrix of V (unit diagonal, zeros above)
-  double* sg = slots + (size_t)w * slot_stride;  // G x (w*w) partial Gram matrices
+  double* sg = slots + (size_t)w * slot_stride;  // G partial Gram matrices (w*w each)
   for (int e = tid; e < w * w; e += 256) {
     int q = e % w, jj = e / w;
     double acc = 0.0;
     if (q < jj) {
-      for (int i = 0; i < rows; ++i) {
+      // rows inside the leaf's top w x w block carry the unit diagonal and
+      // the zeros above it; the rows below are plain (eight per step)
+      const int itop = (int)min((int64_t)rows, max((int64_t)0, c0 + w - rbeg));
+      for (int i = 0; i < itop; ++i) {
         int64_t li = rbeg + i - c0;  // row index relative to the leaf top
         double vq = (li < q) ? 0.0 : (li == q ? 1.0 : Ld[i * ldl + q]);
         double vj = (li < jj) ? 0.0 : (li == jj ? 1.0 : Ld[i * ldl + jj]);
         acc += vq * vj;
       }
+      int i = itop;
+      for (; i + 8 <= rows; i += 8) {
+        double xa[8], xb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          xa[u] = Ld[(i + u) * ldl + q];
+          xb[u] = Ld[(i + u) * ldl + jj];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += xa[u] * xb[u];
+      }
+      for (; i < rows; ++i) acc += Ld[i * ldl + q] * Ld[i * ldl + jj];
     }
     sg[(size_t)g * w * w + e] = acc;
   }
-  grid_barrier(ctr, ctr_base + (unsigned)(w + 1) * G, rep, nullptr);
-  if (g == 0) {
-    __shared__ double Gm[LEAF][LEAF + 1];
-    __shared__ double Tl[LEAF][LEAF + 1];
-    for (int e = tid; e < w * w; e += 256) {
-      // eight interleaved partial sums (loads in flight), added in order
-      double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      int q = 0;
-      for (; q + 8 <= G; q += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) p[u] += sg[(size_t)(q + u) * w * w + e];
-      }
-      for (int u = 0; q + u < G; ++u) p[u] += sg[(size_t)(q + u) * w * w + e];
-      double s = p[0];
-#pragma unroll
-      for (int u = 1; u < 8; ++u) s += p[u];
-      Gm[e % w][e / w] = s;
-      Tl[e % w][e / w] = 0.0;
-    }
-    __syncthreads();
-    for (int jj = 0; jj < w; ++jj) {
-      double tj = tau[c0 + jj];
-      if (tid == 0) Tl[jj][jj] = tj;
-      if (tid < jj) {
-        double s = 0.0;
-        for (int q = tid; q < jj; ++q) s += Tl[tid][q] * Gm[q][jj];
-        Tl[tid][jj] = -tj * s;
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < w * w; e += 256) Tm[(toff + e % w) + (int64_t)(toff + e / w) * ldt] = Tl[e % w][e / w];
-  }
+  // the panel goes back to A first: workgroup 0 then reuses its LDS for the
+  // Gram matrix and T (2 w (w+1) doubles <= R (w+1), since R >= 2w)
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
     A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
   }
+  LT_MARK(5);
+  grid_barrier(ctr, ctr_base + (unsigned)(w + 1) * G, rep, nullptr);
+  LT_MARK(6);
+  if (g == 0) {
+    double* Gm = Ld;                 // Gm[q * ldl + j]
+    double* Tl = Ld + w * ldl;       // Tl[q * ldl + j]
+    // the Gram matrix (sum of the G partials), staged in Tl's space: one
+    // entry per thread, eight loads in flight, parts added in order
+    for (int e = tid; e < w * w; e += 256) {
+      double pp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int r = 0;
+      for (; r + 8 <= G; r += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pp[u] += sg[(size_t)(r + u) * w * w + e];
+      }
+      for (int u = 0; r < G; ++r, ++u) pp[u] += sg[(size_t)r * w * w + e];
+      double t = pp[0];
+#pragma unroll
+      for (int u = 1; u < 8; ++u) t += pp[u];
+      Tl[e] = t;
+    }
+    __syncthreads();
+    for (int e = tid; e < w * w; e += 256) {
+      Gm[(e % w) * ldl + e / w] = Tl[e];
+    }
+    __syncthreads();
+    for (int e = tid; e < w * w; e += 256) Tl[(e % w) * ldl + e / w] = 0.0;
+    __syncthreads();
+    for (int jj = 0; jj < w; ++jj) {
+      double tj = tau[c0 + jj];
+      if (tid == 0) Tl[jj * ldl + jj] = tj;
+      if (tid < jj) {
+        double sacc = 0.0;
+        int q = tid;
+        for (; q + 8 <= jj; q += 8) {
+          double ta[8], gb[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            ta[u] = Tl[tid * ldl + q + u];
+            gb[u] = Gm[(q + u) * ldl + jj];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sacc += ta[u] * gb[u];
+        }
+        for (; q < jj; ++q) sacc += Tl[tid * ldl + q] * Gm[q * ldl + jj];
+        Tl[tid * ldl + jj] = -tj * sacc;
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < w * w; e += 256)
+      Tm[(toff + e % w) + (int64_t)(toff + e / w) * ldt] = Tl[(e % w) * ldl + e / w];
+  }
+  LT_MARK(7);
+  LT_PRINT("qr_leaf")
 }
 
 // ---------------------------------------------------------------------------
@@ -489,51 +642,91 @@ __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, in
   if (tid == 0) moves[0] = nmoved;
 }
 
+// Row interchanges on columns [j0, j1).  TPC threads share a column (the
+// column's moves are dealt round-robin; TPC = 1 for wide ranges); all moved
+// values are read (in batches of independent loads) and parked in `stage`
+// before any is written, so cycles of moves need no ordering.  With colchk
+// (TPC = 1), the column checksums of every tile-row that receives a new value
+// are corrected by the plain and position-weighted differences (moves arrive
+// in increasing destination row, so each tile-row's corrections are
+// contiguous).
+constexpr int LASWP_BATCH = 16;
 template <typename T>
-__global__ __launch_bounds__(256) void k_laswp(T* A, int64_t lda, int64_t j0, int64_t j1, const int* moves, T* stage,
-                                               double* colchk, int64_t ldc, int nb) {
-  const int64_t j = j0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= j1) return;
+__global__ __launch_bounds__(256) void k_laswp(T* __restrict__ A, int64_t lda, int64_t j0, int64_t j1,
+                                               const int* __restrict__ moves, T* __restrict__ stage,
+                                               double* __restrict__ colchk, int64_t ldc, int nb, int tpc) {
+  __shared__ int mv[4 * PB_W];
   const int nm = moves[0];
+  for (int t = threadIdx.x; t < 2 * nm; t += blockDim.x) mv[t] = moves[1 + t];
+  __syncthreads();
+  const int cpb = (int)blockDim.x / tpc, sub = threadIdx.x % tpc;
+  const int64_t j = j0 + (int64_t)blockIdx.x * cpb + threadIdx.x / tpc;
+  const bool active = j < j1;
   const int64_t nc = j1 - j0, jj = j - j0;
-  T* col = A + j * lda;
+  T* __restrict__ col = A + (active ? j : j0) * lda;
   acc2 e{0, 0}, ww{0, 0};
   int curI = -1;
-  for (int t = 0; t < nm; ++t) {
-    const int dst = moves[1 + 2 * t], src = moves[2 + 2 * t];
-    T vs = col[src], vd = col[dst];
-    stage[(int64_t)t * nc + jj] = vs;
-    if (colchk) {
-      int I = dst / nb;
-      if (I != curI) {
-        if (curI >= 0) {
-          acc2 c0{colchk[2 * curI + j * ldc], 0}, c1{colchk[2 * curI + 1 + j * ldc], 0};
-          cmerge(c0, e);
-          cmerge(c1, ww);
-          colchk[2 * curI + j * ldc] = cval(c0);
-          colchk[2 * curI + 1 + j * ldc] = cval(c1);
+  auto flush = [&]() {
+    if (curI >= 0) {
+      acc2 c0{colchk[2 * curI + j * ldc], 0}, c1{colchk[2 * curI + 1 + j * ldc], 0};
+      cmerge(c0, e);
+      cmerge(c1, ww);
+      colchk[2 * curI + j * ldc] = cval(c0);
+      colchk[2 * curI + 1 + j * ldc] = cval(c1);
+    }
+  };
+  if (active) {
+    for (int t0 = sub; t0 < nm; t0 += LASWP_BATCH * tpc) {
+      T vs[LASWP_BATCH], vd[LASWP_BATCH];
+#pragma unroll
+      for (int u = 0; u < LASWP_BATCH; ++u) {
+        const int t = t0 + u * tpc;
+        if (t < nm) {
+          vs[u] = col[mv[2 * t + 1]];
+          if (colchk) vd[u] = col[mv[2 * t]];
         }
-        curI = I;
-        e = {0, 0};
-        ww = {0, 0};
       }
-      double delta = (double)vs - (double)vd;
-      cadd(e, (double)vs);
-      cadd(e, -(double)vd);
-      double wr = (double)(dst - I * nb + 1);
-      cfma(ww, wr, (double)vs);
-      cfma(ww, -wr, (double)vd);
-      (void)delta;
+#pragma unroll
+      for (int u = 0; u < LASWP_BATCH; ++u) {
+        const int t = t0 + u * tpc;
+        if (t < nm) {
+          stage[(int64_t)t * nc + jj] = vs[u];
+          if (colchk) {
+            const int dst = mv[2 * t];
+            const int I = dst / nb;
+            if (I != curI) {
+              flush();
+              curI = I;
+              e = {0, 0};
+              ww = {0, 0};
+            }
+            const double wr = (double)(dst - I * nb + 1);
+            cadd(e, (double)vs[u]);
+            cadd(e, -(double)vd[u]);
+            cfma(ww, wr, (double)vs[u]);
+            cfma(ww, -wr, (double)vd[u]);
+          }
+        }
+      }
+    }
+    if (colchk) flush();
+  }
+  if (tpc > 1) __syncthreads();  // every value of the column is staged before any is written
+  if (active) {
+    for (int t0 = sub; t0 < nm; t0 += LASWP_BATCH * tpc) {
+      T v[LASWP_BATCH];
+#pragma unroll
+      for (int u = 0; u < LASWP_BATCH; ++u) {
+        const int t = t0 + u * tpc;
+        if (t < nm) v[u] = stage[(int64_t)t * nc + jj];
+      }
+#pragma unroll
+      for (int u = 0; u < LASWP_BATCH; ++u) {
+        const int t = t0 + u * tpc;
+        if (t < nm) col[mv[2 * t]] = v[u];
+      }
     }
   }
-  if (colchk && curI >= 0) {
-    acc2 c0{colchk[2 * curI + j * ldc], 0}, c1{colchk[2 * curI + 1 + j * ldc], 0};
-    cmerge(c0, e);
-    cmerge(c1, ww);
-    colchk[2 * curI + j * ldc] = cval(c0);
-    colchk[2 * curI + 1 + j * ldc] = cval(c1);
-  }
-  for (int t = 0; t < nm; ++t) col[moves[1 + 2 * t]] = stage[(int64_t)t * nc + jj];
 }
 
 // ---------------------------------------------------------------------------
@@ -575,7 +768,7 @@ template <typename T>
 int getrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int w, int32_t* ipiv, int32_t* info,
                double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg) {
   int G, R;
-  const int max_rows = (int)((120 * 1024) / ((w + 1) * sizeof(T)));
+  const int max_rows = (int)((144 * 1024) / ((w + 1) * sizeof(T)));
   coop_shape(m - c0, w, maxg, max_rows, G, R);
   if ((int64_t)G * R < m - c0) return ABFT_ERR_UNSUPPORTED;
   size_t shm = (size_t)R * (w + 1) * sizeof(T);
@@ -588,7 +781,7 @@ int getrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int w, i
 int geqrf_leaf(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t c0, int w, double* tau, double* Tm, int ldt,
                int toff, double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg) {
   int G, R;
-  const int max_rows = (int)((100 * 1024) / ((w + 1) * sizeof(double)));
+  const int max_rows = (int)((140 * 1024) / ((w + 1) * sizeof(double)));
   coop_shape(m - c0, w, maxg, max_rows, G, R);
   if ((int64_t)G * R < m - c0) return ABFT_ERR_UNSUPPORTED;
   size_t shm = (size_t)R * (w + 1) * sizeof(double);
@@ -607,8 +800,18 @@ template <typename T>
 int laswp(hipStream_t s, T* A, int64_t lda, int64_t j0, int64_t j1, const int* moves, T* stage, double* colchk,
           int64_t ldc, int nb) {
   if (j1 <= j0) return 0;
-  hipLaunchKernelGGL(k_laswp<T>, dim3((unsigned)((j1 - j0 + 255) / 256)), dim3(256), 0, s, A, lda, j0, j1, moves, stage,
-                     colchk, ldc, nb);
+  // Every moved value is its own cache line (rows are scattered), so the
+  // work is spread over as many CUs as possible: without checksums 16
+  // threads per column (4 for wide ranges) share a column's moves; with
+  // checksums (one thread per column) 64-thread workgroups.
+  int tpc = 1, bs = 64;
+  if (!colchk) {
+    tpc = (j1 - j0) >= 4096 ? 4 : 16;
+    bs = 256;
+  }
+  const int64_t cpb = bs / tpc;
+  hipLaunchKernelGGL(k_laswp<T>, dim3((unsigned)((j1 - j0 + cpb - 1) / cpb)), dim3(bs), 0, s, A, lda, j0, j1, moves,
+                     stage, colchk, ldc, nb, tpc);
   CHECK_LAUNCH();
 }
 
