@@ -5,7 +5,7 @@
 //
 // Tile 128x128 per 256-thread workgroup, four waves in 2x2 of 64x64, each a
 // 4x4 block of v_mfma_f64_16x16x4_f64; K walked in steps of 32 through
-// double-buffered LDS (2 x 66 KB, one workgroup per CU: the accumulators
+// double-buffered LDS (2 x 72 KB, one workgroup per CU: the accumulators
 // alone take 128 AGPRs per lane, so a CU holds one such workgroup anyway and
 // the LDS is spent on a deeper K step instead).  Interior tiles load with
 // 16-byte global loads and no bounds tests; edge tiles, the K tail and
@@ -31,7 +31,7 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 namespace {
 
-constexpr int DG_BM = 128, DG_BN = 128, DG_BK = 32, DG_PAD = 4, DG_GM = 8;
+constexpr int DG_BM = 128, DG_BN = 128, DG_BK = 32, DG_PAD = 16, DG_GM = 8;  // row stride 144: conflict-free operand reads
 
 // Stage of one operand tile (R x BK logical, R = 128) held in registers as
 // BK/4 pairs per thread.  ALONG_R: the pairs run along the tile's R
