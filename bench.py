@@ -428,7 +428,8 @@ def main():
     h = abft.Handle(dev)
     legs = [x for x in args.legs.split(",") if x]
     t0 = time.perf_counter()
-    value, ms_step, per_leg, status, roof = fp64_legs(h, torch, dev, args, legs)
+    value, ms_step, per_leg, status, roof = fp64_legs(h, torch, dev, args, legs) if legs else (None, None, {}, {},
+                                                                                              None)
     mp = None if args.no_mp else mp_leg(h, torch, dev, args)
     batched = None if args.no_batched else batched_leg(h, torch, dev, args)
     campaign = campaign_leg(h, torch, dev, args) if args.campaign > 0 else None

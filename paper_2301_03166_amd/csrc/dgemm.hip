@@ -4,12 +4,13 @@
 //   even leading dimensions (the host dispatcher checks this).
 //
 // Tile 128x128 per 256-thread workgroup, four waves in 2x2 of 64x64, each a
-// 4x4 block of v_mfma_f64_16x16x4_f64; K walked in steps of 32 through
-// double-buffered LDS (2 x 72 KB, one workgroup per CU: the accumulators
-// alone take 128 AGPRs per lane, so a CU holds one such workgroup anyway and
-// the LDS is spent on a deeper K step instead).  Interior tiles load with
-// 16-byte global loads and no bounds tests; edge tiles, the K tail and
-// split-K remainders take the same data path with per-element guards.
+// 4x4 block of v_mfma_f64_16x16x4_f64; K walked through double-buffered LDS
+// in steps of BK: BK = 32 (~2 x 72 KB of LDS, one workgroup per CU, C read
+// ahead during the last K step) or BK = 16 (~2 x 36 KB and at most 256
+// registers per lane, so two workgroups share a CU and one's prologue and
+// epilogue overlap the other's products).  Interior tiles load with 16-byte
+// global loads and no bounds tests; edge tiles, the K tail and split-K
+// remainders take the same data path with per-element guards.
 //
 // Workgroup order: the hardware deals workgroups round-robin to the eight
 // XCDs; the index is remapped so that each XCD owns a contiguous chunk of a
@@ -21,6 +22,8 @@
 // Operand options: op(A) = A or A^T, op(B) = B or B^T, a unit-lower mask on
 // the stored A (Householder vectors with their implicit unit diagonal), and a
 // lower-triangular write mask on C.
+#include <cstdlib>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -31,14 +34,30 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 namespace {
 
-constexpr int DG_BM = 128, DG_BN = 128, DG_BK = 32, DG_PAD = 16, DG_GM = 8;  // row stride 144: conflict-free operand reads
+constexpr int DG_BM = 128, DG_BN = 128, DG_GM = 8;
+// LDS image of an operand tile (R = 128 rows of op(X), BK values of k): an
+// operand read from memory along R is kept k-major with row stride
+// SKR = R + 16 (its 16-byte stores are sequential, and the MFMA's reads of
+// four k-rows x 16 consecutive r fall in disjoint bank halves); an operand
+// read along K is kept r-major with row stride SRK = BK + 2 (its 16-byte
+// stores are sequential, and lane (r, k) of the MFMA read hits bank pair
+// ((BK + 2) r + k) mod 32 -- a bijection over each half-wave for BK = 16, 32).
+constexpr int SKR = DG_BM + 16;
+template <int BK, bool ALONG_R>
+__host__ __device__ constexpr int lds_elems() {
+  return ALONG_R ? BK * SKR : DG_BM * (BK + 2);
+}
+template <int BK, bool ALONG_R>
+__device__ __forceinline__ int lidx(int k, int r) {
+  return ALONG_R ? k * SKR + r : r * (BK + 2) + k;
+}
 
 // Stage of one operand tile (R x BK logical, R = 128) held in registers as
 // BK/4 pairs per thread.  ALONG_R: the pairs run along the tile's R
 // dimension (stored operand contiguous in R); else along K.
-template <bool ALONG_R>
+template <int BK, bool ALONG_R>
 struct Stage {
-  f64x2 v[DG_BK / 4];
+  f64x2 v[BK / 4];
 };
 
 // Stored element (r, c) of a unit-lower operand: 0 above, 1 on the diagonal.
@@ -50,12 +69,12 @@ __device__ __forceinline__ double unit_lower(double v, int64_t r, int64_t c) {
 // X[x0+i + (k0+p)*ld] (ALONG_R) or X[k0+p + (x0+i)*ld] (!ALONG_R).
 // FULL: no bounds tests (the block lies inside [0,R) x [k0,kend)).
 // MASK: apply the unit-lower mask of the stored operand.
-template <bool ALONG_R, bool FULL, bool MASK>
-__device__ __forceinline__ void stage_load(Stage<ALONG_R>& st, const double* __restrict__ X, int64_t ld, int x0,
+template <int BK, bool ALONG_R, bool FULL, bool MASK>
+__device__ __forceinline__ void stage_load(Stage<BK, ALONG_R>& st, const double* __restrict__ X, int64_t ld, int x0,
                                            int xlim, int k0, int kend) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int s = 0; s < DG_BK / 4; ++s) {
+  for (int s = 0; s < BK / 4; ++s) {
     const int v = tid + 256 * s;
     int i0, i1, p0, p1;
     if (ALONG_R) {
@@ -63,9 +82,9 @@ __device__ __forceinline__ void stage_load(Stage<ALONG_R>& st, const double* __r
       i1 = i0 + 1;
       p0 = p1 = v >> 6;
     } else {
-      p0 = 2 * (v & (DG_BK / 2 - 1));
+      p0 = 2 * (v & (BK / 2 - 1));
       p1 = p0 + 1;
-      i0 = i1 = v / (DG_BK / 2);
+      i0 = i1 = v / (BK / 2);
     }
     const int gi0 = x0 + i0, gi1 = x0 + i1, gp0 = k0 + p0, gp1 = k0 + p1;
     // stored coordinates (row, column) of the two elements
@@ -90,19 +109,18 @@ __device__ __forceinline__ void stage_load(Stage<ALONG_R>& st, const double* __r
   }
 }
 
-// LDS image of a tile: S[p][i], p in [0, BK), i in [0, R)
-template <bool ALONG_R>
-__device__ __forceinline__ void stage_store(const Stage<ALONG_R>& st, double (*S)[DG_BM + DG_PAD]) {
+// LDS image of a tile (layout lidx): element (p, i), p in [0, BK), i in [0, R)
+template <int BK, bool ALONG_R>
+__device__ __forceinline__ void stage_store(const Stage<BK, ALONG_R>& st, double* S) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int s = 0; s < DG_BK / 4; ++s) {
+  for (int s = 0; s < BK / 4; ++s) {
     const int v = tid + 256 * s;
     if (ALONG_R) {
-      *reinterpret_cast<f64x2*>(&S[v >> 6][2 * (v & 63)]) = st.v[s];
+      *reinterpret_cast<f64x2*>(&S[lidx<BK, true>(v >> 6, 2 * (v & 63))]) = st.v[s];
     } else {
-      const int p = 2 * (v & (DG_BK / 2 - 1)), i = v / (DG_BK / 2);
-      S[p][i] = st.v[s][0];
-      S[p + 1][i] = st.v[s][1];
+      const int p = 2 * (v & (BK / 2 - 1)), i = v / (BK / 2);
+      *reinterpret_cast<f64x2*>(&S[lidx<BK, false>(p, i)]) = st.v[s];
     }
   }
 }
@@ -125,14 +143,15 @@ __device__ __forceinline__ void lower_tile(int lin, int T, int& tm, int& tn) {
 // TRI: the grid enumerates only the lower tiles of a square T x T grid
 // (requires LOWER, M == N, doff == 0).  ROLE only separates the launches of
 // the trailing-matrix update (1) from the other products (0) in profiles.
-template <int TA, int TB, int FA, int LOWER, int TRI, int ROLE>
-__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha, const double* __restrict__ A,
-                                               int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
-                                               double* __restrict__ C, int64_t ldc, int64_t doff, int kc,
-                                               double* __restrict__ P) {
-  constexpr int BM = DG_BM, BN = DG_BN, BK = DG_BK;
-  __shared__ __attribute__((aligned(16))) double As[2][BK][BM + DG_PAD];
-  __shared__ __attribute__((aligned(16))) double Bs[2][BK][BN + DG_PAD];
+template <int TA, int TB, int FA, int LOWER, int TRI, int ROLE, int BK>
+__global__ __launch_bounds__(256, BK == 16 ? 2 : 1) void k_dgemm(int M, int N, int K, double alpha,
+                                                                 const double* __restrict__ A, int64_t lda,
+                                                                 const double* __restrict__ B, int64_t ldb,
+                                                                 double beta, double* __restrict__ C, int64_t ldc,
+                                                                 int64_t doff, int kc, double* __restrict__ P) {
+  constexpr int BM = DG_BM, BN = DG_BN;
+  __shared__ __attribute__((aligned(16))) double As[2][lds_elems<BK, TA == 0>()];
+  __shared__ __attribute__((aligned(16))) double Bs[2][lds_elems<BK, TB == 1>()];
 
   const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
   const int nt = TRI ? tilesM * (tilesM + 1) / 2 : tilesM * tilesN;
@@ -163,8 +182,8 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
   }
   const bool inner = (m0 + BM <= M) && (n0 + BN <= N);
 
-  Stage<TA == 0> sa;
-  Stage<TB == 1> sb;
+  Stage<BK, TA == 0> sa;
+  Stage<BK, TB == 1> sb;
   // A's stored operand needs its mask only where the tile meets the diagonal
   auto load = [&](int k0) {
     const bool full = inner && (k0 + BK <= kend);
@@ -172,18 +191,18 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
         FA == 1 && (TA == 0 ? (m0 < k0 + BK) : (k0 < m0 + BM));  // some stored row <= stored column
     if (full) {
       if (FA == 1 && needmask)
-        stage_load<TA == 0, true, true>(sa, A, lda, m0, M, k0, kend);
+        stage_load<BK, TA == 0, true, true>(sa, A, lda, m0, M, k0, kend);
       else
-        stage_load<TA == 0, true, false>(sa, A, lda, m0, M, k0, kend);
-      stage_load<TB == 1, true, false>(sb, B, ldb, n0, N, k0, kend);
+        stage_load<BK, TA == 0, true, false>(sa, A, lda, m0, M, k0, kend);
+      stage_load<BK, TB == 1, true, false>(sb, B, ldb, n0, N, k0, kend);
     } else {
-      stage_load<TA == 0, false, FA == 1>(sa, A, lda, m0, M, k0, kend);
-      stage_load<TB == 1, false, false>(sb, B, ldb, n0, N, k0, kend);
+      stage_load<BK, TA == 0, false, FA == 1>(sa, A, lda, m0, M, k0, kend);
+      stage_load<BK, TB == 1, false, false>(sb, B, ldb, n0, N, k0, kend);
     }
   };
   auto store = [&](int buf) {
-    stage_store<TA == 0>(sa, As[buf]);
-    stage_store<TB == 1>(sb, Bs[buf]);
+    stage_store<BK, TA == 0>(sa, As[buf]);
+    stage_store<BK, TB == 1>(sb, Bs[buf]);
   };
 
   f64x4 acc[4][4];
@@ -204,7 +223,9 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
   // Interior tiles read their C values during the last K step (the epilogue
   // then finds them in registers instead of waiting on memory).
   const bool straddle = LOWER && (int64_t)m0 + doff < (int64_t)(n0 + BN - 1);
-  const bool fastC = inner && !straddle && beta != 0.0;
+  // (read ahead only with one workgroup per CU: with two, the other one's
+  // products cover the wait, and the registers are needed)
+  const bool fastC = BK == 32 && inner && !straddle && beta != 0.0;
   double cpre[4][4][4];
   auto loadC = [&]() {
 #pragma unroll
@@ -223,8 +244,8 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
       double af[4], bf[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        af[q] = As[cur][kk * 4 + kl][wm * 64 + q * 16 + il];
-        bf[q] = Bs[cur][kk * 4 + kl][wn * 64 + q * 16 + il];
+        af[q] = As[cur][lidx<BK, TA == 0>(kk * 4 + kl, wm * 64 + q * 16 + il)];
+        bf[q] = Bs[cur][lidx<BK, TB == 1>(kk * 4 + kl, wn * 64 + q * 16 + il)];
       }
 #pragma unroll
       for (int ci = 0; ci < 4; ++ci)
@@ -253,7 +274,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
         for (int r = 0; r < 4; ++r) {
           const int gi = m0 + wm * 64 + ri * 16 + il, gj = n0 + wn * 64 + ci * 16 + 4 * r + kl;
           const double v = alpha * acc[ci][ri][r];
-          C[gi + (int64_t)gj * ldc] = fastC ? beta * cpre[ci][ri][r] + v : v;
+          C[gi + (int64_t)gj * ldc] = fastC ? beta * cpre[ci][ri][r] + v : (beta == 0.0 ? v : beta * C[gi + (int64_t)gj * ldc] + v);
         }
   } else {
 #pragma unroll
@@ -272,6 +293,16 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
   }
 }
 
+// K step of the product kernel: 16 unless ABFT_DGEMM_BK=32 in the environment
+// (read once; a tuning override)
+static int dgemm_bk() {
+  static const int bk = [] {
+    const char* e = getenv("ABFT_DGEMM_BK");
+    return (e && atoi(e) == 32) ? 32 : 16;
+  }();
+  return bk;
+}
+
 // Returns 1 when the product was launched here, 0 when the caller should use
 // the general kernel (unsupported option combination or alignment), <0 on error.
 int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, int k, double alpha, const double* A,
@@ -284,9 +315,16 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, i
   const int64_t nt = tri ? tM * (tM + 1) / 2 : tM * tN;
   if (nt > 0x7fffffff) return 0;
   const dim3 grid((unsigned)nt, (unsigned)S), block(256);
-#define DG_LAUNCH(TA_, TB_, FA_, LO_, TRI_, RO_)                                                                  \
-  hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, TRI_, RO_>), grid, block, 0, s, m, n, k, alpha, A, lda, B, ldb, beta, \
-                     C, ldc, doff, kc, ws)
+  const bool bk16 = dgemm_bk() == 16;
+#define DG_LAUNCH(TA_, TB_, FA_, LO_, TRI_, RO_)                                                                    \
+  do {                                                                                                             \
+    if (bk16)                                                                                                      \
+      hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, TRI_, RO_, 16>), grid, block, 0, s, m, n, k, alpha, A, lda, B,  \
+                         ldb, beta, C, ldc, doff, kc, ws);                                                         \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, TRI_, RO_, 32>), grid, block, 0, s, m, n, k, alpha, A, lda, B,  \
+                         ldb, beta, C, ldc, doff, kc, ws);                                                         \
+  } while (0)
 #define DG_CASE(TA_, TB_, FA_, LO_)                                                                              \
   if (ta == TA_ && tb == TB_ && fa == FA_ && lower == LO_) {                                                       \
     if (LO_ && tri) {                                                                                              \

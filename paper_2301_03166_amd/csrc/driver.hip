@@ -55,9 +55,9 @@ constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 constexpr size_t SPLITK_ELEMS = (size_t)1 << 22;  // split-K partials (32 MB)
-// cooperative-leaf exchange slots: per column G (w + 2) + w doubles (LU) or
-// G w + w (QR), plus G w^2 for the QR leaf's Gram partials; G <= 256, w <= 64
-constexpr size_t SLOT_DOUBLES = (size_t)3 << 20;
+// cooperative-leaf exchange records (SLOT_WORDS 8-byte words), two columns
+// alternating: per column 4G (3 + 2w) + 2w words (LU) or G 2w + 2w (QR);
+// G <= 256, w <= 64
 constexpr size_t CTR_BYTES = 4096;  // grid-barrier counters: top + 16 groups, 128 bytes apart
 
 // Phase timer of profiled calls: event pairs recorded on the stream, summed
@@ -144,7 +144,7 @@ Ws carve(char* base, int64_t n, int nb, int op, int elem) {
   w.Ta = (double*)take((size_t)2 * N * nb * sizeof(double));
   w.tflags = (int*)take((size_t)N * N * sizeof(int));
   w.ctr = (unsigned*)take(CTR_BYTES);
-  w.slots = (double*)take(SLOT_DOUBLES * sizeof(double));
+  w.slots = (double*)take(SLOT_WORDS * sizeof(double));
   if (op == ABFT_OP_GETRF || op == ABFT_OP_GESV_MP) {
     w.porig = (double*)take((size_t)n * nb * elem);
     w.stage = (double*)take((size_t)2 * nb * n * elem);
@@ -443,6 +443,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
   TRY(fill_zero(s, w.ctr, CTR_BYTES));
+  TRY(fill_zero(s, w.slots, SLOT_WORDS * sizeof(double)));  // leaf records: sequence numbers restart
   const int N = (int)((n + nb - 1) / nb);
   const int ldc = 2 * N;
   const double u = sizeof(T) == 8 ? U64 : U32;
@@ -616,7 +617,7 @@ int gesv_mp_impl(abft_handle h, int64_t n, const double* dA, int64_t lda, const 
     else TRY(getrf_impl<float>(h, n, (float*)m.F, n, m.ipiv, w, opts, nb, protect, ts, prec, m.info, drep));
   }
   TRY(fill_zero(s, m.norms, 64));
-  TRY(anorm(s, dA, lda, ni, m.norms));
+  TRY(anorm(s, dA, lda, ni, m.part, NSPLIT, m.norms));
   if (hipMemcpyAsync(&ir.info, m.info, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return ABFT_ERR_HIP;
   TRY(read_norms(s, m.norms, hn, 8));
   ir.a_norm = hn[4];
@@ -792,6 +793,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
   TRY(fill_zero(s, w.ctr, CTR_BYTES));
+  TRY(fill_zero(s, w.slots, SLOT_WORDS * sizeof(double)));  // leaf records: sequence numbers restart
   const int N = (int)((n + nb - 1) / nb);
   const int ldc = 2 * N;
   const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);

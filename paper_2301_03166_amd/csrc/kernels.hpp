@@ -63,6 +63,9 @@ template <typename T>
 int trsm_rlt_leaf(hipStream_t s, T* A, int64_t lda, int64_t r0, int64_t r1, int64_t c0, int w);
 template <typename T>
 int trsm_llu_leaf(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1);
+// cooperative-leaf exchange area, in 8-byte words (the LU leaf's records are
+// cleared at the start of each factorization: their sequence numbers restart)
+constexpr size_t SLOT_WORDS = (size_t)3 << 20;
 template <typename T>
 int getrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int w, int32_t* ipiv, int32_t* info,
                double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg);
@@ -86,7 +89,7 @@ int trsv(hipStream_t s, const T* F, int64_t ld, int n, int kind, T* x, unsigned*
 int residual(hipStream_t s, const double* A, int64_t lda, int n, const double* x, const double* b, double* r,
              double* part, int nsplit, double* norms);
 int update_x(hipStream_t s, double* x, const float* d32, double scale, int n, double* norms);
-int anorm(hipStream_t s, const double* A, int64_t lda, int n, double* norms);
+int anorm(hipStream_t s, const double* A, int64_t lda, int n, double* part, int nsplit, double* norms);
 int copy_f64(hipStream_t s, const double* a, double* b, int n);
 
 // batched factorizations (one persistent kernel)

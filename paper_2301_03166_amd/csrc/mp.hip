@@ -42,78 +42,142 @@ __global__ void k_gather64(const double* x, const int* perm, double* y, int n) {
 }
 
 // Triangular solve x := M^{-1} x in place (M n x n, stored in the factor
-// array F): kind 0 = unit lower (LU's L), 1 = upper (LU's U), 2 = lower
+// array F): KIND 0 = unit lower (LU's L), 1 = upper (LU's U), 2 = lower
 // (Cholesky L), 3 = upper given as the transpose of the stored lower
 // Cholesky factor.  Workgroups take 64-row blocks in solve order from a
-// counter; a block first waits for, and subtracts, every earlier block of
-// the solution (published with a release flag), then solves its diagonal
-// block in LDS.  The accumulation order is fixed, so results are
-// reproducible.
+// counter.  A block first subtracts the products of every earlier block of
+// the solution: its 64 x 64 coefficient blocks do not depend on the solution
+// and are read ahead, and each wave polls the earlier blocks' ready flags
+// itself and consumes every block it finds published in one go (one acquire
+// per group).  One wave then solves the diagonal block with its row of the
+// block in registers: substitution, one lane broadcast per step, the
+// reciprocals of the diagonal formed up front.  The accumulation order is
+// fixed, so results are reproducible.
 template <typename T>
-__device__ __forceinline__ T melem(const T* F, int64_t ld, int kind, int64_t i, int64_t j) {
-  return kind == 3 ? F[j + i * ld] : F[i + j * ld];
-}
+__device__ __forceinline__ T fmat(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fmat<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fmat<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv(const T* __restrict__ F, int64_t ld, int n, int kind, T* x,
-                                              unsigned* counter, int* ready, abft_report* rep) {
+__device__ __forceinline__ T lane_bcast(T v, int j);
+template <>
+__device__ __forceinline__ float lane_bcast<float>(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+template <>
+__device__ __forceinline__ double lane_bcast<double>(double v, int j) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, j), hi = __builtin_amdgcn_readlane((int)(u >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void k_trsv(const T* __restrict__ F, int64_t ld, int n, T* x, unsigned* counter,
+                                              int* ready, abft_report* rep) {
+  constexpr bool LOWER = KIND == 0 || KIND == 2, TR = KIND == 3;
   __shared__ T part[4][TB];
-  __shared__ T xb[TB];
   __shared__ T D[TB][TB + 1];
   __shared__ int s_blk;
   const int nblk = (n + TB - 1) / TB;
-  const bool lower = (kind == 0 || kind == 2);
   if (threadIdx.x == 0) s_blk = (int)atomicAdd(counter, 1u);
   __syncthreads();
   const int ord = s_blk;
   if (ord >= nblk) return;
-  const int b = lower ? ord : nblk - 1 - ord;
+  const int b = LOWER ? ord : nblk - 1 - ord;
   const int64_t r0 = (int64_t)b * TB;
   const int rows = (int)min((int64_t)TB, (int64_t)n - r0);
   const int r = threadIdx.x & (TB - 1), q = threadIdx.x >> 6;
+  // element (i, j) of the diagonal block of M
+  for (int idx = threadIdx.x; idx < TB * TB; idx += 256) {
+    const int i = TR ? idx / TB : idx % TB, j = TR ? idx % TB : idx / TB;
+    T v = (T)0;
+    if (i < rows && j < rows) v = TR ? F[(r0 + j) + (r0 + i) * ld] : F[(r0 + i) + (r0 + j) * ld];
+    D[i][j] = v;
+  }
+  // earlier block k of the solve order, its coefficients in row r0 + r and
+  // this wave's 16 columns [16 q, 16 q + 16)
+  auto pred = [&](int k) { return LOWER ? k : nblk - 1 - k; };
+  auto load_m = [&](int k, T(&m)[16]) {
+    const int64_t c0 = (int64_t)pred(k) * TB;
+    const int cl = (int)min((int64_t)TB, (int64_t)n - c0) - 16 * q;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int64_t col = c0 + 16 * q + s;
+      m[s] = (r < rows && s < cl) ? (TR ? F[col + (r0 + r) * ld] : F[(r0 + r) + col * ld]) : (T)0;
+    }
+  };
   T acc = (T)0;
-  // contributions of the blocks solved before this one
-  for (int k = 0; k < ord; ++k) {
-    const int c = lower ? k : nblk - 1 - k;
-    if (threadIdx.x == 0) {
-      long spins = 0;
-      while (__hip_atomic_load(&ready[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1L << 22)) {
-          if (rep) atomicOr(&rep->status, (int)ABFT_ST_INTERNAL);
-          break;
-        }
+  auto accum = [&](int k, const T(&m)[16]) {
+    const int64_t c0 = (int64_t)pred(k) * TB;
+    const int cl = (int)min((int64_t)TB, (int64_t)n - c0) - 16 * q;
+    T xs[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) xs[s] = s < cl ? x[c0 + 16 * q + s] : (T)0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = fmat(m[s], xs[s], acc);
+  };
+  T mp[16];
+  if (ord > 0) load_m(0, mp);
+  long spins = 0;
+  for (int k = 0; k < ord;) {
+    // earlier blocks k, k+1, ... already published (lane l looks at k + l)
+    int nr;
+    for (;;) {
+      const int kl = k + r;
+      int f = 1;
+      if (kl < ord) f = __hip_atomic_load(&ready[pred(kl)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long waiting = __ballot(f == 0);
+      nr = min(waiting ? (int)__builtin_ctzll(waiting) : TB, ord - k);
+      if (nr > 0) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1L << 22)) {
+        if (r == 0 && rep) atomicOr(&rep->status, (int)ABFT_ST_INTERNAL);
+        nr = ord - k;
+        break;
       }
     }
-    __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const int64_t c0 = (int64_t)c * TB;
-    const int cols = (int)min((int64_t)TB, (int64_t)n - c0);
-    if (r < rows) {
-      for (int jj = q; jj < cols; jj += 4) acc += melem(F, ld, kind, r0 + r, c0 + jj) * x[c0 + jj];
+    accum(k, mp);
+    int kk = k + 1;
+    for (; kk + 1 < k + nr; kk += 2) {
+      T m0[16], m1[16];
+      load_m(kk, m0);
+      load_m(kk + 1, m1);
+      accum(kk, m0);
+      accum(kk + 1, m1);
     }
+    if (kk < k + nr) {
+      T m0[16];
+      load_m(kk, m0);
+      accum(kk, m0);
+    }
+    k += nr;
+    if (k < ord) load_m(k, mp);
   }
   part[q][r] = acc;
-  for (int idx = threadIdx.x; idx < rows * rows; idx += blockDim.x) {
-    int i = idx % rows, j = idx / rows;
-    D[i][j] = melem(F, ld, kind, r0 + i, r0 + j);
+  __syncthreads();
+  if (q != 0) return;
+  // diagonal block: wave 0, lane r holds row r
+  T xv = (T)0, dr[TB];
+  if (r < rows) xv = x[r0 + r] - (((part[0][r] + part[1][r]) + part[2][r]) + part[3][r]);
+#pragma unroll
+  for (int j = 0; j < TB; ++j) dr[j] = D[r][j];
+  const T rd = (KIND != 0 && r < rows) ? (T)1 / D[r][r] : (T)1;
+#pragma unroll
+  for (int s = 0; s < TB; ++s) {
+    const int j = LOWER ? s : TB - 1 - s;
+    if (j < rows) {
+      T xj = lane_bcast(xv, j);
+      if (KIND != 0) xj *= lane_bcast(rd, j);
+      if (r == j) xv = xj;
+      else if (LOWER ? r > j : r < j) xv = fmat(-dr[j], xj, xv);
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < rows) xb[r] = x[r0 + r] - (((part[0][r] + part[1][r]) + part[2][r]) + part[3][r]);
-  __syncthreads();
-  // diagonal block, sequential in LDS
-  for (int j = 0; j < rows; ++j) {
-    const int jj = lower ? j : rows - 1 - j;
-    if (threadIdx.x == 0 && kind != 0) xb[jj] = xb[jj] / D[jj][jj];
-    __syncthreads();
-    const int t = threadIdx.x;
-    if (lower ? (t > jj && t < rows) : (t < jj)) xb[t] -= D[t][jj] * xb[jj];
-    __syncthreads();
-  }
-  if (threadIdx.x < rows) x[r0 + r] = xb[r];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(&ready[b], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (r < rows) x[r0 + r] = xv;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (r == 0) __hip_atomic_store(&ready[b], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // residual partials: part[s][i] = sum over column chunk s of A(i, j) x(j)
@@ -188,15 +252,34 @@ __global__ void k_update(double* x, const float* d32, double scale, int n, doubl
   }
 }
 
-// infinity norm of A (max row |.|-sum) into norms[4]
-__global__ __launch_bounds__(256) void k_anorm(const double* __restrict__ A, int64_t lda, int n, double* norms) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  double s = 0.0;
-  if (i < n)
-    for (int j = 0; j < n; ++j) s += fabs(A[i + (int64_t)j * lda]);
+// infinity norm of A (max row |.|-sum) into norms[4], in two passes: row
+// sums over column chunks (part[s][i], chunk s), then their fixed-order sums
+__global__ __launch_bounds__(256) void k_anorm_part(const double* __restrict__ A, int64_t lda, int n, int chunk,
+                                                    double* part) {
+  const int i = blockIdx.x * 256 + threadIdx.x, s = blockIdx.y;
+  const int j0 = s * chunk, j1 = min(n, j0 + chunk);
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < n) {
+    int j = j0;
+    for (; j + 7 < j1; j += 8) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s = fmax(s, __shfl_xor(s, o));
-  if ((threadIdx.x & 63) == 0) max_bits(&norms[4], s);
+      for (int u = 0; u < 8; ++u) a[u] += fabs(A[i + (int64_t)(j + u) * lda]);
+    }
+    for (int u = 0; j < j1; ++j, ++u) a[u] += fabs(A[i + (int64_t)j * lda]);
+    part[(int64_t)s * n + i] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  }
+}
+__global__ void k_anorm_fin(const double* part, int nsplit, int n, double* norms) {
+  double m = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int q = 0; q < nsplit; ++q) v += part[(int64_t)q * n + i];
+    if (!(v <= 1.79e308)) v = __longlong_as_double(0x7ff0000000000000ll);
+    m = fmax(m, v);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) max_bits(&norms[4], m);
 }
 
 __global__ void k_copy_f64(const double* a, double* b, int n) {
@@ -231,10 +314,17 @@ int gather64(hipStream_t s, const double* x, const int* perm, double* y, int n) 
 template <typename T>
 int trsv(hipStream_t s, const T* F, int64_t ld, int n, int kind, T* x, unsigned* counter, int* ready,
          abft_report* rep) {
+  if (n <= 0) return 0;
+  if (kind < 0 || kind > 3) return ABFT_ERR_UNSUPPORTED;
   const int nblk = (n + TB - 1) / TB;
   if (fill_zero(s, counter, 4)) return ABFT_ERR_HIP;
   if (fill_zero(s, ready, (size_t)nblk * sizeof(int))) return ABFT_ERR_HIP;
-  hipLaunchKernelGGL(k_trsv<T>, dim3(nblk), dim3(256), 0, s, F, ld, n, kind, x, counter, ready, rep);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL((k_trsv<T, 0>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, ready, rep); break;
+    case 1: hipLaunchKernelGGL((k_trsv<T, 1>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, ready, rep); break;
+    case 2: hipLaunchKernelGGL((k_trsv<T, 2>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, ready, rep); break;
+    default: hipLaunchKernelGGL((k_trsv<T, 3>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, ready, rep);
+  }
   LAUNCH_OK;
 }
 template int trsv<float>(hipStream_t, const float*, int64_t, int, int, float*, unsigned*, int*, abft_report*);
@@ -252,8 +342,12 @@ int update_x(hipStream_t s, double* x, const float* d32, double scale, int n, do
   hipLaunchKernelGGL(k_update, dim3(g1(n)), dim3(256), 0, s, x, d32, scale, n, norms);
   LAUNCH_OK;
 }
-int anorm(hipStream_t s, const double* A, int64_t lda, int n, double* norms) {
-  hipLaunchKernelGGL(k_anorm, dim3((n + 255) / 256), dim3(256), 0, s, A, lda, n, norms);
+int anorm(hipStream_t s, const double* A, int64_t lda, int n, double* part, int nsplit, double* norms) {
+  if (n <= 0) return 0;
+  const int chunk = (n + nsplit - 1) / nsplit;
+  hipLaunchKernelGGL(k_anorm_part, dim3((n + 255) / 256, nsplit), dim3(256), 0, s, A, lda, n, chunk, part);
+  if (hipGetLastError() != hipSuccess) return ABFT_ERR_HIP;
+  hipLaunchKernelGGL(k_anorm_fin, dim3(g1(n)), dim3(256), 0, s, part, nsplit, n, norms);
   LAUNCH_OK;
 }
 int copy_f64(hipStream_t s, const double* a, double* b, int n) {

@@ -208,10 +208,58 @@ __device__ __forceinline__ bool better(double a, int64_t ia, double b, int64_t i
   return a > b || (a == b && ia < ib);
 }
 
+// Exchange records of the LU leaf.  Every 64-bit word carries 32 bits of
+// payload (high half) and the sequence number of the column that wrote it
+// (low half), so a reader polls the very word it needs: a word is valid
+// once its sequence number matches, with no barrier or fence between
+// writer and reader (single-copy atomicity of aligned 64-bit accesses at
+// device scope).  Sequence numbers are unique within a factorization, and
+// the record area is cleared before the factorization starts.
+__device__ __forceinline__ void ll_put(uint64_t* p, uint32_t payload, uint32_t seq) {
+  __hip_atomic_store(p, ((uint64_t)payload << 32) | seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void ll_put2(uint64_t* p, double v, uint32_t seq) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  ll_put(p, (uint32_t)(u >> 32), seq);
+  ll_put(p + 1, (uint32_t)u, seq);
+}
+// bounded poll of a word already loaded once: on expiry the error is
+// recorded and whatever was read is used
+__device__ __forceinline__ void ll_poll(const uint64_t* p, uint64_t& v, uint32_t seq, abft_report* rep) {
+  long spins = 0;
+  while ((uint32_t)v != seq) {
+    __builtin_amdgcn_s_sleep(1);
+    v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (++spins > (1L << 21)) {
+      if (rep) atomicOr(&rep->status, (int)ABFT_ST_INTERNAL);
+      break;
+    }
+  }
+}
+__device__ __forceinline__ double ll_dbl(uint64_t hi, uint64_t lo) {
+  return __longlong_as_double((long long)((hi & 0xffffffff00000000ull) | (lo >> 32)));
+}
+// both words of a double: the two loads are issued before either is polled
+__device__ __forceinline__ double ll_get2b(const uint64_t* p, uint32_t seq, abft_report* rep) {
+  uint64_t hi = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t lo = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  ll_poll(p, hi, seq, rep);
+  ll_poll(p + 1, lo, seq, rep);
+  return ll_dbl(hi, lo);
+}
+constexpr uint32_t LL_NONE = 0xffffffffu;  // no candidate row in this workgroup
+
+// Records of one column: per workgroup 3 + 2w words (|pivot| candidate, its
+// row index, its row), then the 2w words of row d.  Two columns' records
+// alternate: a workgroup writes column j + 2 only after every workgroup has
+// published column j + 1, which each does only after it has read everything
+// of column j it needs.
+__host__ __device__ constexpr int64_t lu_rec_words(int G, int w) { return (int64_t)G * (3 + 2 * w) + 2 * w; }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m, int64_t c0, int w, int R,
-                                                    int32_t* ipiv, int32_t* info, double* slots, unsigned* ctr,
-                                                    unsigned ctr_base, abft_report* rep) {
+                                                    int32_t* ipiv, int32_t* info, uint64_t* recs, uint32_t seq0,
+                                                    abft_report* rep) {
   extern __shared__ unsigned char smem_raw[];
   LT_DECL
   T* Ld = reinterpret_cast<T*>(smem_raw);  // R x (w+1)
@@ -225,7 +273,8 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t rbeg = c0 + (int64_t)g * R;
   const int rows = (int)max((int64_t)0, min((int64_t)R, m - rbeg));
-  const int slot_stride = G * (w + 2) + w;
+  const int rw = 3 + 2 * w;
+  const int64_t cstride = lu_rec_words(G, w);
 
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
@@ -234,8 +283,10 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
   __syncthreads();
 
   for (int j = 0; j < w; ++j) {
-    const int64_t d = c0 + j;  // diagonal row
-    double* sj = slots + (size_t)j * slot_stride;
+    const int64_t d = c0 + j;  // diagonal row (in workgroup 0: R >= w)
+    const uint32_t seq = seq0 + (uint32_t)j;
+    uint64_t* rj = recs + (size_t)(j & 1) * cstride;
+    uint64_t* rowd = rj + (size_t)G * rw;
     // local argmax of |a(i, j)| over owned rows i >= d
     double bv = -1.0;
     int64_t bi = INT64_MAX;
@@ -253,37 +304,43 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
     }
     if (lane == 0) { wv_val[wv] = bv; wv_idx[wv] = bi; }
     __syncthreads();
+    uint64_t* mine = rj + (size_t)g * rw;
     if (tid == 0) {
       for (int q = 1; q < 4; ++q)
         if (better<T>(wv_val[q], wv_idx[q], bv, bi)) { bv = wv_val[q]; bi = wv_idx[q]; }
-      sj[g * (w + 2) + 0] = bv;
-      sj[g * (w + 2) + 1] = (double)bi;
+      ll_put2(mine, bv, seq);
+      ll_put(mine + 2, bi == INT64_MAX ? LL_NONE : (uint32_t)bi, seq);
       s_loc = bi;
     }
     __syncthreads();
     // candidate row (values of the leaf columns) and, from workgroup 0, row d
     if (tid < w) {
       const int64_t bl = s_loc;
-      double val = 0.0;
-      if (bl != INT64_MAX) val = (double)Ld[(bl - rbeg) * ldl + tid];
-      sj[g * (w + 2) + 2 + tid] = val;
-      if (g == 0) sj[G * (w + 2) + tid] = (double)Ld[(d - rbeg) * ldl + tid];
+      ll_put2(mine + 3 + 2 * tid, bl == INT64_MAX ? 0.0 : (double)Ld[(bl - rbeg) * ldl + tid], seq);
+      if (g == 0) ll_put2(rowd + 2 * tid, (double)Ld[(d - rbeg) * ldl + tid], seq);
     }
     LT_MARK(0);
-    grid_barrier(ctr, ctr_base + (unsigned)(j + 1) * G, rep, nullptr);
-    LT_MARK(1);
-    // every workgroup picks the same winner: one slot per thread, then a
-    // block argmax (largest |value|, first row index on ties; the row index
-    // identifies its workgroup, so the choice does not depend on the order)
+    // every workgroup picks the same winner: one record per thread (its three
+    // words loaded together), then a block argmax (largest |value|, first
+    // row index on ties; the row index identifies its workgroup, so the
+    // choice does not depend on the order)
     {
       double v = -1.0;
       int64_t ii = INT64_MAX;
       int gq = 0;
       for (int q = tid; q < G; q += 256) {
-        const double vq = sj[q * (w + 2) + 0];
-        const int64_t iq = vq < 0 ? INT64_MAX : (int64_t)sj[q * (w + 2) + 1];
+        const uint64_t* rq = rj + (size_t)q * rw;
+        uint64_t wd[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) wd[u] = __hip_atomic_load(rq + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) ll_poll(rq + u, wd[u], seq, rep);
+        const double vq = ll_dbl(wd[0], wd[1]);
+        const uint32_t iq32 = (uint32_t)(wd[2] >> 32);
+        const int64_t iq = iq32 == LL_NONE ? INT64_MAX : (int64_t)iq32;
         if (vq >= 0 && better<T>(vq, iq, v, ii)) { v = vq; ii = iq; gq = q; }
       }
+      LT_MARK(1);
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         const double ov = __shfl_xor(v, o);
@@ -308,15 +365,16 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
     LT_MARK(2);
     const int64_t p = s_piv;
     const int pg = s_pg;
+    const bool own_p = p != d && p >= rbeg && p < rbeg + rows;
     if (tid < w) {
-      prow[tid] = sj[pg * (w + 2) + 2 + tid];
-      orow[tid] = sj[G * (w + 2) + tid];
+      prow[tid] = ll_get2b(rj + (size_t)pg * rw + 3 + 2 * tid, seq, rep);
+      if (own_p) orow[tid] = ll_get2b(rowd + 2 * tid, seq, rep);
     }
     __syncthreads();
     LT_MARK(3);
     if (p != d) {
       if (g == 0 && tid < w) Ld[(d - rbeg) * ldl + tid] = (T)prow[tid];
-      if (p >= rbeg && p < rbeg + rows && tid < w) Ld[(p - rbeg) * ldl + tid] = (T)orow[tid];
+      if (own_p && tid < w) Ld[(p - rbeg) * ldl + tid] = (T)orow[tid];
     }
     __syncthreads();
     if (g == 0 && tid == 0) {
@@ -334,12 +392,13 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
       }
     }
     __syncthreads();
+    LT_MARK(4);
   }
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
     A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
   }
-  LT_MARK(4);
+  LT_MARK(5);
   LT_PRINT("lu_leaf")
 }
 
@@ -347,11 +406,24 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
 // Cooperative Householder leaf: columns [c0, c0+w), rows [c0, m) (LAPACK
 // dlarfg convention), plus the leaf's triangular factor T (forward,
 // columnwise) written at T[toff + toff*ldt].
+//
+// Per column j every workgroup forms the partial Gram row
+// S_c = sum over its rows i > d of a(i,j) a(i,c) for every c < w, stores it
+// (workgroup 0 also row d), and after one flag barrier adds the G partial
+// rows in one fixed order (plain loads: the records are shared through each
+// XCD's L2).  Entries c >= j give the column norm and the reflector's dot
+// products with the trailing columns; entries c < j give
+// v_c . v_j = v_c(d) + scale S_c, the inputs of T's column j, which
+// workgroup 0 stages in T's strictly upper part.  After the loop workgroup
+// 0 runs T's recurrence in LDS.  Records of two columns alternate (a
+// workgroup rewrites column j's records only after the barrier of column
+// j + 1, which every workgroup passes only after reading column j).
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int64_t qr_rec_words(int G, int w) { return (int64_t)(G + 1) * w; }
 
 __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int64_t m, int64_t c0, int w, int R,
-                                                    double* tau, double* Tm, int ldt, int toff, double* slots,
-                                                    unsigned* ctr, unsigned ctr_base, abft_report* rep) {
+                                                    double* tau, double* Tm, int ldt, int toff, double* recs,
+                                                    unsigned* flags, unsigned seq0, abft_report* rep) {
   extern __shared__ unsigned char smem_raw[];
   LT_DECL
   double* Ld = reinterpret_cast<double*>(smem_raw);  // R x (w+1)
@@ -363,8 +435,7 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int64_t rbeg = c0 + (int64_t)g * R;
   const int rows = (int)max((int64_t)0, min((int64_t)R, m - rbeg));
-  // per column: G workgroup partial Gram rows, then row d (w values each)
-  const size_t slot_stride = (size_t)(G + 1) * w;
+  const int64_t cstride = qr_rec_words(G, w);
 
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
@@ -373,25 +444,30 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
   __syncthreads();
 
   // sum of the G records of len values (src + r * len) for entries e <
-  // len: QG threads share an entry (records r = gq, gq + QG, ...), eight
+  // len: QG threads share an entry (records r = gq, gq + QG, ...), sixteen
   // loads in flight each; the parts are added in a fixed order.  The result
   // goes to dst[e] (LDS).
   constexpr int QG = 256 / CLEAF;
   auto sum_slots = [&](const double* src, int len, double* dst) {
     for (int e0 = 0; e0 < len; e0 += CLEAF) {
       const int c = tid % CLEAF, gq = tid / CLEAF, e = e0 + c;
-      double pp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      double pp[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) pp[u] = 0.0;
       if (e < len) {
         int r = gq;
-        for (; r + 7 * QG < G; r += 8 * QG) {
+        for (; r + 15 * QG < G; r += 16 * QG) {
+          double v[16];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) pp[u] += src[(size_t)(r + u * QG) * len + e];
+          for (int u = 0; u < 16; ++u) v[u] = src[(size_t)(r + u * QG) * len + e];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) pp[u] += v[u];
         }
         for (int u = 0; r < G; r += QG, ++u) pp[u] += src[(size_t)r * len + e];
       }
       double t = pp[0];
 #pragma unroll
-      for (int u = 1; u < 8; ++u) t += pp[u];
+      for (int u = 1; u < 16; ++u) t += pp[u];
       qpart[gq][c] = t;
       __syncthreads();
       if (tid < CLEAF && e0 + tid < len) {
@@ -405,18 +481,17 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
 
   for (int j = 0; j < w; ++j) {
     const int64_t d = c0 + j;
-    double* sj = slots + (size_t)j * slot_stride;
+    double* sj = recs + (size_t)(j & 1) * cstride;
     double* rowd = sj + (size_t)G * w;
-    // partial Gram row: s_c = sum_{i > d} a(i,j) a(i,c), c = j..w-1; thread
-    // (q, cl) takes column c = j + cl over the rows i = q (mod 4) of the LDS
-    // panel, and the four row classes are added in order
+    // partial Gram row: thread (q, c) takes column c over the rows i = q
+    // (mod 4) below d of the LDS panel, eight rows per step, loads first
     {
-      const int cl = tid & 63, q = tid >> 6, c = j + cl;
+      const int c = tid & 63, q = tid >> 6;
       double acc = 0.0;
       if (c < w) {
         const int i0 = (int)max((int64_t)0, d + 1 - rbeg);
         int i = i0 + ((q - i0 % 4) + 4) % 4;
-        for (; i + 28 < rows; i += 32) {  // eight rows per step, loads first
+        for (; i + 28 < rows; i += 32) {
           double xa[8], xb[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -428,29 +503,26 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
         }
         for (; i < rows; i += 4) acc += Ld[i * ldl + j] * Ld[i * ldl + c];
       }
-      part[q][cl] = acc;
+      part[q][c] = acc;
     }
     __syncthreads();
-    LT_MARK(0);
     if (tid < w) {
-      double v = 0.0;
-      if (tid >= j) v = ((part[0][tid - j] + part[1][tid - j]) + part[2][tid - j]) + part[3][tid - j];
-      sj[(size_t)g * w + tid] = v;
+      sj[(size_t)g * w + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
       if (g == 0) rowd[tid] = Ld[(d - rbeg) * ldl + tid];
     }
+    LT_MARK(0);
+    flag_barrier(flags, seq0 + (unsigned)j, rep);
     LT_MARK(1);
-    grid_barrier(ctr, ctr_base + (unsigned)(j + 1) * G, rep, nullptr);
-    LT_MARK(2);
-    // every workgroup: Gram row = sum of the G partial rows, and row d
+    // every workgroup: the same Gram row (hence the same reflector), and row d
     if (tid < w) orow[tid] = rowd[tid];
     sum_slots(sj, w, svec);
-    LT_MARK(3);
+    LT_MARK(2);
     if (tid == 0) {
-      double alpha = orow[j], s2 = svec[j];
+      const double alpha = orow[j], s2 = svec[j];
       if (s2 == 0.0) {
         s_tau = 0.0; s_scale = 0.0; s_beta = alpha;
       } else {
-        double beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+        const double beta = -copysign(sqrt(alpha * alpha + s2), alpha);
         s_tau = (beta - alpha) / beta;
         s_scale = 1.0 / (alpha - beta);
         s_beta = beta;
@@ -459,6 +531,8 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
     }
     __syncthreads();
     const double t = s_tau, sc = s_scale;
+    if (g == 0 && tid < j)  // v_c . v_j for c < j, staged in T's strictly upper part
+      Tm[(toff + tid) + (int64_t)(toff + j) * ldt] = orow[tid] + sc * svec[tid];
     if (t != 0.0) {
       if (tid < w && tid > j) fvec[tid] = t * (orow[tid] + sc * svec[tid]);
       __syncthreads();
@@ -467,7 +541,7 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
         if (gi < d) continue;
         if (gi == d) {
           Ld[i * ldl + j] = s_beta;
-          for (int c = j + 1; c < w; ++c) Ld[i * ldl + c] -= fvec[c];
+          row_axpy(Ld + i * ldl, fvec, 1.0, j + 1, w);  // a(d,c) - f(c)
         } else {
           double v = Ld[i * ldl + j] * sc;
           Ld[i * ldl + j] = v;
@@ -476,71 +550,23 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
       }
     }
     __syncthreads();
-    LT_MARK(4);
+    LT_MARK(3);
   }
-  // T factor of the leaf from the Gram matrix of V (unit diagonal, zeros above)
-  double* sg = slots + (size_t)w * slot_stride;  // G partial Gram matrices (w*w each)
-  for (int e = tid; e < w * w; e += 256) {
-    int q = e % w, jj = e / w;
-    double acc = 0.0;
-    if (q < jj) {
-      // rows inside the leaf's top w x w block carry the unit diagonal and
-      // the zeros above it; the rows below are plain (eight per step)
-      const int itop = (int)min((int64_t)rows, max((int64_t)0, c0 + w - rbeg));
-      for (int i = 0; i < itop; ++i) {
-        int64_t li = rbeg + i - c0;  // row index relative to the leaf top
-        double vq = (li < q) ? 0.0 : (li == q ? 1.0 : Ld[i * ldl + q]);
-        double vj = (li < jj) ? 0.0 : (li == jj ? 1.0 : Ld[i * ldl + jj]);
-        acc += vq * vj;
-      }
-      int i = itop;
-      for (; i + 8 <= rows; i += 8) {
-        double xa[8], xb[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          xa[u] = Ld[(i + u) * ldl + q];
-          xb[u] = Ld[(i + u) * ldl + jj];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += xa[u] * xb[u];
-      }
-      for (; i < rows; ++i) acc += Ld[i * ldl + q] * Ld[i * ldl + jj];
-    }
-    sg[(size_t)g * w * w + e] = acc;
-  }
-  // the panel goes back to A first: workgroup 0 then reuses its LDS for the
-  // Gram matrix and T (2 w (w+1) doubles <= R (w+1), since R >= 2w)
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
     A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
   }
-  LT_MARK(5);
-  grid_barrier(ctr, ctr_base + (unsigned)(w + 1) * G, rep, nullptr);
-  LT_MARK(6);
+  LT_MARK(4);
   if (g == 0) {
-    double* Gm = Ld;                 // Gm[q * ldl + j]
-    double* Tl = Ld + w * ldl;       // Tl[q * ldl + j]
-    // the Gram matrix (sum of the G partials), staged in Tl's space: one
-    // entry per thread, eight loads in flight, parts added in order
-    for (int e = tid; e < w * w; e += 256) {
-      double pp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      int r = 0;
-      for (; r + 8 <= G; r += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) pp[u] += sg[(size_t)(r + u) * w * w + e];
-      }
-      for (int u = 0; r < G; ++r, ++u) pp[u] += sg[(size_t)r * w * w + e];
-      double t = pp[0];
-#pragma unroll
-      for (int u = 1; u < 8; ++u) t += pp[u];
-      Tl[e] = t;
-    }
+    // T from the staged dot products: T(0:j, j) = -tau_j T(0:j, 0:j) z_j
     __syncthreads();
+    double* Gm = Ld;            // Gm[q * ldl + j] = v_q . v_j, q < j
+    double* Tl = Ld + w * ldl;  // Tl[q * ldl + j]
     for (int e = tid; e < w * w; e += 256) {
-      Gm[(e % w) * ldl + e / w] = Tl[e];
+      const int q = e % w, jj = e / w;
+      Gm[q * ldl + jj] = q < jj ? Tm[(toff + q) + (int64_t)(toff + jj) * ldt] : 0.0;
+      Tl[q * ldl + jj] = 0.0;
     }
-    __syncthreads();
-    for (int e = tid; e < w * w; e += 256) Tl[(e % w) * ldl + e / w] = 0.0;
     __syncthreads();
     for (int jj = 0; jj < w; ++jj) {
       double tj = tau[c0 + jj];
@@ -566,32 +592,29 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
     for (int e = tid; e < w * w; e += 256)
       Tm[(toff + e % w) + (int64_t)(toff + e / w) * ldt] = Tl[(e % w) * ldl + e / w];
   }
-  LT_MARK(7);
+  LT_MARK(5);
   LT_PRINT("qr_leaf")
 }
 
 // ---------------------------------------------------------------------------
 // Row interchanges.  k_perm_build turns the interchanges ipiv[c0..c0+w) into
 // the list of moved rows (dst <- src), sorted by dst.  k_laswp applies the
-// moves to columns [j0, j1) through a staging buffer; with a column-checksum
-// array it also adds, per tile-row, the change of the column sums and of the
-// weighted column sums (compensated, in the moves' fixed order).
+// moves to columns [j0, j1); with a column-checksum array it also adds, per
+// tile-row, the change of the column sums and of the weighted column sums
+// (compensated).
 // ---------------------------------------------------------------------------
-// The table holds, for every row r in [c0, n), the original row now stored at
-// r (-1: unchanged).  Rows [c0, n) of the panel bound the table (<= 36864
-// rows in LDS); one thread replays the interchanges, then a block-wide
-// compaction lists the moved rows in increasing order.
 // Move list of the w row interchanges of a panel starting at row c0: after
 // the swaps, row dst holds the original row src; moves = {count, dst0, src0,
 // dst1, src1, ...} in increasing dst.  Only the panel's own rows [0, w) and
 // the distinct pivot rows at or below w (relative to c0) can move, so the
-// replay works on a compact table of at most 2w entries: entry t < w is row
-// t, entry w + f is the pivot row first named by interchange f.
+// work is on a compact table of at most 2w slots: slot t < w is row t, slot
+// w + f is the pivot row first named by interchange f.  The interchanges are
+// resolved in parallel (no serial replay): see the chain rule below.
 constexpr int PB_W = 512;  // largest panel width (block size)
 __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, int64_t c0, int w, int64_t n,
                                                         int* moves) {
-  __shared__ int pv[PB_W], sidx[PB_W];
-  __shared__ int key[2 * PB_W], cur[2 * PB_W];
+  __shared__ int pv[PB_W], sidx[PB_W], ptr[PB_W];
+  __shared__ int key[2 * PB_W], mflag[2 * PB_W];
   __shared__ int nmoved;
   const int tid = threadIdx.x;
   const int rows = (int)min<int64_t>(n - c0, 0x7fffffff);
@@ -602,6 +625,7 @@ __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, in
   }
   if (tid == 0) nmoved = 0;
   __syncthreads();
+  // table slot of each step's pivot row (b_t >= t), and the row each slot starts with
   if (tid < w) {
     const int p = pv[tid];
     int f = tid;
@@ -613,119 +637,172 @@ __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, in
     key[w + tid] = (p >= w && f == tid) ? p : -1;
   }
   __syncthreads();
-  for (int i = tid; i < 2 * w; i += blockDim.x) cur[i] = key[i];
-  __syncthreads();
-  if (tid == 0)
-    for (int t = 0; t < w; ++t) {
-      const int b = sidx[t];
-      if (b != t) {
-        const int x = cur[t];
-        cur[t] = cur[b];
-        cur[b] = x;
-      }
+  // Step t swaps slots t and b_t, after which slot t never changes.  With
+  // D(t) the row in slot t just before step t: D(t) = D(t') for the last
+  // step t' < t with b_t' = t (it moved D(t') into slot t), else row t; so
+  // D(t) is the root of the chain t -> t'.  Slot t ends with D(t) when
+  // b_t = t, else with what slot b_t held before step t: D(t*) for the last
+  // step t* < t with b_t* = b_t, else that slot's first row; an outer slot
+  // ends with D of the last step that names it, else its own row.
+  int ts = -1, tl = -1;
+  if (tid < w) {
+    const int b = sidx[tid];
+    int pr = -1;
+    for (int t2 = 0; t2 < tid; ++t2) {
+      const int s2 = sidx[t2];
+      if (s2 == tid) pr = t2;
+      if (s2 == b) ts = t2;
     }
-  __syncthreads();
-  // rank every moved entry by its row (rows are distinct) and emit in order
-  for (int i = tid; i < 2 * w; i += blockDim.x) {
-    const int ki = key[i];
-    if (ki < 0 || cur[i] == ki) continue;
-    int r = 0;
-    for (int q = 0; q < 2 * w; ++q) {
-      const int kq = key[q];
-      r += (kq >= 0 && cur[q] != kq && kq < ki);
-    }
-    moves[1 + 2 * r] = (int)(c0 + ki);
-    moves[2 + 2 * r] = (int)(c0 + cur[i]);
-    atomicAdd(&nmoved, 1);
+    ptr[tid] = pr >= 0 ? pr : tid;
+  } else if (tid < 2 * w) {
+    for (int t = 0; t < w; ++t)
+      if (sidx[t] == tid) tl = t;
   }
   __syncthreads();
+  for (int r = 0; r < 10; ++r) {  // pointer jumping: chains are shorter than 2^10 > PB_W
+    const int nxt = tid < w ? ptr[ptr[tid]] : 0;
+    __syncthreads();
+    if (tid < w) ptr[tid] = nxt;
+    __syncthreads();
+  }
+  int fin = -1;
+  if (tid < w) {
+    const int b = sidx[tid];
+    fin = b == tid ? ptr[tid] : (ts >= 0 ? ptr[ts] : key[b]);
+  } else if (tid < 2 * w) {
+    fin = tl >= 0 ? ptr[tl] : key[tid];
+  }
+  const int moved = tid < 2 * w && key[tid] >= 0 && fin != key[tid];
+  mflag[tid] = moved;
+  if (moved) atomicAdd(&nmoved, 1);
+  __syncthreads();
+  // rank by destination row: the panel's own rows (slots < w, in order)
+  // come before the outer pivot rows
+  if (moved) {
+    int r = 0;
+    if (tid < w) {
+      for (int q = 0; q < tid; ++q) r += mflag[q];
+    } else {
+      for (int q = 0; q < w; ++q) r += mflag[q];
+      const int kx = key[tid];
+      for (int q = w; q < 2 * w; ++q) r += (mflag[q] && key[q] < kx);
+    }
+    moves[1 + 2 * r] = (int)(c0 + key[tid]);
+    moves[2 + 2 * r] = (int)(c0 + fin);
+  }
   if (tid == 0) moves[0] = nmoved;
 }
 
-// Row interchanges on columns [j0, j1).  TPC threads share a column (the
-// column's moves are dealt round-robin; TPC = 1 for wide ranges); all moved
-// values are read (in batches of independent loads) and parked in `stage`
-// before any is written, so cycles of moves need no ordering.  With colchk
-// (TPC = 1), the column checksums of every tile-row that receives a new value
-// are corrected by the plain and position-weighted differences (moves arrive
-// in increasing destination row, so each tile-row's corrections are
-// contiguous).
-constexpr int LASWP_BATCH = 16;
+// Row interchanges on columns [j0, j1), in one kernel with no staging in
+// HBM: a workgroup takes cpw consecutive columns and every move of each;
+// pair (move t, column c) goes to thread (t + nm c) mod 256, so the lanes of
+// a wave touch consecutive moves of one column (the panel's own rows are
+// contiguous).  Every value is loaded into registers before the workgroup
+// barrier and stored after it, so cycles of moves need no ordering.  With a
+// column-checksum array, the new and old values of the moved elements go to
+// LDS and, per column, the thread at the start of each run of moves into one
+// tile-row adds the run's plain and position-weighted differences
+// (compensated, in the moves' order: increasing destination row) to that
+// tile-row's column checksums.
+constexpr int LASWP_PAIRS = 16;                      // (move, column) pairs per thread
+constexpr int LASWP_CPW = 256 * LASWP_PAIRS / 1024;  // columns per workgroup (up to 1024 moves)
+constexpr int LASWP_NBK = 1024 / 16;                 // blocks of 16 moves per column
 template <typename T>
 __global__ __launch_bounds__(256) void k_laswp(T* __restrict__ A, int64_t lda, int64_t j0, int64_t j1,
-                                               const int* __restrict__ moves, T* __restrict__ stage,
-                                               double* __restrict__ colchk, int64_t ldc, int nb, int tpc) {
+                                               const int* __restrict__ moves, double* __restrict__ colchk,
+                                               int64_t ldc, int nb, int cpw) {
+  extern __shared__ double dl[];  // with colchk: new values [ncol][nm], then old values [ncol][nm]
   __shared__ int mv[4 * PB_W];
   const int nm = moves[0];
   for (int t = threadIdx.x; t < 2 * nm; t += blockDim.x) mv[t] = moves[1 + t];
   __syncthreads();
-  const int cpb = (int)blockDim.x / tpc, sub = threadIdx.x % tpc;
-  const int64_t j = j0 + (int64_t)blockIdx.x * cpb + threadIdx.x / tpc;
-  const bool active = j < j1;
-  const int64_t nc = j1 - j0, jj = j - j0;
-  T* __restrict__ col = A + (active ? j : j0) * lda;
-  acc2 e{0, 0}, ww{0, 0};
-  int curI = -1;
-  auto flush = [&]() {
-    if (curI >= 0) {
-      acc2 c0{colchk[2 * curI + j * ldc], 0}, c1{colchk[2 * curI + 1 + j * ldc], 0};
-      cmerge(c0, e);
-      cmerge(c1, ww);
-      colchk[2 * curI + j * ldc] = cval(c0);
-      colchk[2 * curI + 1 + j * ldc] = cval(c1);
-    }
-  };
-  if (active) {
-    for (int t0 = sub; t0 < nm; t0 += LASWP_BATCH * tpc) {
-      T vs[LASWP_BATCH], vd[LASWP_BATCH];
+  const int64_t cb = j0 + (int64_t)blockIdx.x * cpw;
+  const int ncol = (int)min((int64_t)cpw, j1 - cb);
+  const int np = nm * ncol;
+  T vs[LASWP_PAIRS], vd[LASWP_PAIRS];
 #pragma unroll
-      for (int u = 0; u < LASWP_BATCH; ++u) {
-        const int t = t0 + u * tpc;
-        if (t < nm) {
-          vs[u] = col[mv[2 * t + 1]];
-          if (colchk) vd[u] = col[mv[2 * t]];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < LASWP_BATCH; ++u) {
-        const int t = t0 + u * tpc;
-        if (t < nm) {
-          stage[(int64_t)t * nc + jj] = vs[u];
-          if (colchk) {
-            const int dst = mv[2 * t];
-            const int I = dst / nb;
-            if (I != curI) {
-              flush();
-              curI = I;
-              e = {0, 0};
-              ww = {0, 0};
-            }
-            const double wr = (double)(dst - I * nb + 1);
-            cadd(e, (double)vs[u]);
-            cadd(e, -(double)vd[u]);
-            cfma(ww, wr, (double)vs[u]);
-            cfma(ww, -wr, (double)vd[u]);
-          }
-        }
-      }
+  for (int k = 0; k < LASWP_PAIRS; ++k) {
+    const int p = threadIdx.x + 256 * k;
+    if (p < np) {
+      const int t = p % nm, c = p / nm;
+      const T* col = A + (cb + c) * lda;
+      vs[k] = col[mv[2 * t + 1]];
+      if (colchk) vd[k] = col[mv[2 * t]];
     }
-    if (colchk) flush();
   }
-  if (tpc > 1) __syncthreads();  // every value of the column is staged before any is written
-  if (active) {
-    for (int t0 = sub; t0 < nm; t0 += LASWP_BATCH * tpc) {
-      T v[LASWP_BATCH];
+  __syncthreads();  // every value of the workgroup's columns is loaded before any is written
 #pragma unroll
-      for (int u = 0; u < LASWP_BATCH; ++u) {
-        const int t = t0 + u * tpc;
-        if (t < nm) v[u] = stage[(int64_t)t * nc + jj];
-      }
-#pragma unroll
-      for (int u = 0; u < LASWP_BATCH; ++u) {
-        const int t = t0 + u * tpc;
-        if (t < nm) col[mv[2 * t]] = v[u];
+  for (int k = 0; k < LASWP_PAIRS; ++k) {
+    const int p = threadIdx.x + 256 * k;
+    if (p < np) {
+      const int t = p % nm, c = p / nm;
+      A[(cb + c) * lda + mv[2 * t]] = vs[k];
+      if (colchk) {
+        dl[c * nm + t] = (double)vs[k];
+        dl[(ncol + c) * nm + t] = (double)vd[k];
       }
     }
+  }
+  if (!colchk) return;
+  __syncthreads();
+  // Checksum fix-up.  The moves of a column are cut into blocks of 16; one
+  // thread per (column, block) sums each piece of a run (the moves into one
+  // tile-row) that lies in its block.  A run inside one block updates the
+  // checksums directly; the pieces of a run that crosses blocks are merged
+  // in block order by the thread of the block where the run starts.
+  __shared__ acc2 hd[LASWP_CPW][LASWP_NBK][2], tl[LASWP_CPW][LASWP_NBK][2];
+  const int nbk = (nm + 15) / 16;
+  auto tile_of = [&](int t) { return mv[2 * t] / nb; };
+  auto fix = [&](int c, int I, const acc2& e, const acc2& ww) {
+    const int64_t j = cb + c;
+    acc2 c0{colchk[2 * I + j * ldc], 0}, c1{colchk[2 * I + 1 + j * ldc], 0};
+    cmerge(c0, e);
+    cmerge(c1, ww);
+    colchk[2 * I + j * ldc] = cval(c0);
+    colchk[2 * I + 1 + j * ldc] = cval(c1);
+  };
+  for (int p = threadIdx.x; p < ncol * nbk; p += blockDim.x) {
+    const int c = p / nbk, b = p % nbk, t0 = 16 * b, t1 = min(nm, t0 + 16);
+    for (int t = t0; t < t1;) {
+      const int I = tile_of(t);
+      const bool from_before = t == t0 && t0 > 0 && tile_of(t0 - 1) == I;  // run begun in an earlier block
+      acc2 e{0, 0}, ww{0, 0};
+      int u = t;
+      for (; u < t1 && tile_of(u) == I; ++u) {
+        const double wr = (double)(mv[2 * u] - I * nb + 1), vn = dl[c * nm + u], vo = dl[(ncol + c) * nm + u];
+        cadd(e, vn);
+        cadd(e, -vo);
+        cfma(ww, wr, vn);
+        cfma(ww, -wr, vo);
+      }
+      const bool ends_here = u < t1 || t1 == nm || tile_of(t1) != I;
+      if (!from_before && ends_here) {
+        fix(c, I, e, ww);  // the whole run
+      } else if (from_before) {
+        hd[c][b][0] = e;  // head or middle piece of a run begun earlier
+        hd[c][b][1] = ww;
+      } else {
+        tl[c][b][0] = e;  // first piece of a run that continues
+        tl[c][b][1] = ww;
+      }
+      t = u;
+    }
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < ncol * nbk; p += blockDim.x) {
+    const int c = p / nbk, b = p % nbk, t0 = 16 * b, t1 = min(nm, t0 + 16);
+    const int I = tile_of(t1 - 1);
+    const bool continues = t1 < nm && tile_of(t1) == I;
+    const bool began_before = tile_of(t0) == I && t0 > 0 && tile_of(t0 - 1) == I;
+    if (!continues || began_before) continue;  // this block does not hold the start of a crossing run
+    acc2 e = tl[c][b][0], ww = tl[c][b][1];
+    for (int bb = b + 1; bb < nbk; ++bb) {
+      cmerge(e, hd[c][bb][0]);
+      cmerge(ww, hd[c][bb][1]);
+      const int u1 = min(nm, 16 * bb + 16);
+      if (u1 == nm || tile_of(u1) != I) break;
+    }
+    fix(c, I, e, ww);
   }
 }
 
@@ -767,14 +844,18 @@ static inline void coop_shape(int64_t rows, int w, int maxg, int max_rows, int& 
 template <typename T>
 int getrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int w, int32_t* ipiv, int32_t* info,
                double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg) {
+  (void)ctr;
   int G, R;
   const int max_rows = (int)((144 * 1024) / ((w + 1) * sizeof(T)));
   coop_shape(m - c0, w, maxg, max_rows, G, R);
   if ((int64_t)G * R < m - c0) return ABFT_ERR_UNSUPPORTED;
+  if (w > CLEAF || (size_t)(2 * lu_rec_words(G, w)) > SLOT_WORDS) return ABFT_ERR_UNSUPPORTED;
   size_t shm = (size_t)R * (w + 1) * sizeof(T);
-  void* args[] = {&A, &lda, &m, &c0, &w, &R, &ipiv, &info, &slots, &ctr, ctr_base, &rep};
+  uint64_t* recs = reinterpret_cast<uint64_t*>(slots);
+  uint32_t seq0 = *ctr_base + 1;
+  void* args[] = {&A, &lda, &m, &c0, &w, &R, &ipiv, &info, &recs, &seq0, &rep};
   hipError_t e = hipLaunchCooperativeKernel((const void*)k_getrf_leaf<T>, dim3(G), dim3(256), args, shm, s);
-  *ctr_base += (unsigned)w * G;
+  *ctr_base += (unsigned)w;
   return e == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 
@@ -784,10 +865,12 @@ int geqrf_leaf(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t c0, int
   const int max_rows = (int)((140 * 1024) / ((w + 1) * sizeof(double)));
   coop_shape(m - c0, w, maxg, max_rows, G, R);
   if ((int64_t)G * R < m - c0) return ABFT_ERR_UNSUPPORTED;
+  if (w > CLEAF || G > 256 || (size_t)(2 * qr_rec_words(G, w)) > SLOT_WORDS) return ABFT_ERR_UNSUPPORTED;
   size_t shm = (size_t)R * (w + 1) * sizeof(double);
-  void* args[] = {&A, &lda, &m, &c0, &w, &R, &tau, &Tm, &ldt, &toff, &slots, &ctr, ctr_base, &rep};
+  unsigned seq0 = *ctr_base + 1;
+  void* args[] = {&A, &lda, &m, &c0, &w, &R, &tau, &Tm, &ldt, &toff, &slots, &ctr, &seq0, &rep};
   hipError_t e = hipLaunchCooperativeKernel((const void*)k_geqrf_leaf, dim3(G), dim3(256), args, shm, s);
-  *ctr_base += (unsigned)(w + 1) * G;
+  *ctr_base += (unsigned)w;
   return e == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 
@@ -799,19 +882,15 @@ int perm_build(hipStream_t s, const int32_t* ipiv, int64_t c0, int w, int64_t n,
 template <typename T>
 int laswp(hipStream_t s, T* A, int64_t lda, int64_t j0, int64_t j1, const int* moves, T* stage, double* colchk,
           int64_t ldc, int nb) {
+  (void)stage;
   if (j1 <= j0) return 0;
-  // Every moved value is its own cache line (rows are scattered), so the
-  // work is spread over as many CUs as possible: without checksums 16
-  // threads per column (4 for wide ranges) share a column's moves; with
-  // checksums (one thread per column) 64-thread workgroups.
-  int tpc = 1, bs = 64;
-  if (!colchk) {
-    tpc = (j1 - j0) >= 4096 ? 4 : 16;
-    bs = 256;
-  }
-  const int64_t cpb = bs / tpc;
-  hipLaunchKernelGGL(k_laswp<T>, dim3((unsigned)((j1 - j0 + cpb - 1) / cpb)), dim3(bs), 0, s, A, lda, j0, j1, moves,
-                     stage, colchk, ldc, nb, tpc);
+  // the move count is on the device: size for the largest list (2 x panel
+  // width) unless the range is narrow
+  const int nmax = 2 * PB_W;
+  const int cpw = LASWP_CPW;
+  const size_t shm = colchk ? (size_t)2 * cpw * nmax * sizeof(double) : 0;
+  hipLaunchKernelGGL(k_laswp<T>, dim3((unsigned)((j1 - j0 + cpw - 1) / cpw)), dim3(256), shm, s, A, lda, j0, j1, moves,
+                     colchk, ldc, nb, cpw);
   CHECK_LAUNCH();
 }
 

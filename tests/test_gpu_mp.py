@@ -52,13 +52,17 @@ def test_mp_solve_matches_oracle(h, chol, prec, kappa):
 
 
 @pytest.mark.parametrize("chol", [False, True])
-def test_fp64_reference_solve(h, chol):
-    n = 300
+@pytest.mark.parametrize("n", [300, 1000, 2085])
+def test_fp64_reference_solve(h, chol, n):
+    # 64-row solve blocks: n = 1000 and 2085 end in a ragged block
     A, s, V = gen.mp_matrix(n, 1e2, seed=22)
     b = gen.rhs(n, seed=24)
     x, ir, rep = h.gesv_mp(dev(A), dev(b), 0, nb=64, chol=chol)
     xs = gen.mp_exact_solution(b, s, V)
     assert np.linalg.norm(x.cpu().numpy() - xs, np.inf) / np.linalg.norm(xs, np.inf) < 1e-13
+    # infinity norm of the stored matrix (the refinement's stopping test)
+    an = np.abs(A).sum(axis=1).max()
+    assert abs(ir.a_norm - an) <= 1e-13 * an
 
 
 def test_mp_factor_flip_corrected(h):

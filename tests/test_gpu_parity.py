@@ -126,7 +126,7 @@ def test_getrf_tie_break(h):
     assert info == 0 and np.array_equal(host(ipiv), np.arange(1, 101))
 
 
-@pytest.mark.parametrize("n,nb", [(300, 64), (1000, 128), (700, 256)])
+@pytest.mark.parametrize("n,nb", [(300, 64), (1000, 128), (700, 256), (1300, 512)])
 def test_getrf_random_vs_oracle(h, n, nb):
     A = gen.general(n, seed=n + 1)
     dA = dev(A)
@@ -163,7 +163,7 @@ def qr_q(F, tau):
     return Q
 
 
-@pytest.mark.parametrize("n,nb", [(1, 16), (50, 16), (300, 64), (600, 128), (520, 256)])
+@pytest.mark.parametrize("n,nb", [(1, 16), (50, 16), (300, 64), (600, 128), (520, 256), (1100, 512)])
 def test_geqrf_random_vs_oracle(h, n, nb):
     A = gen.general(n, seed=n + 2)
     dA = dev(A)
