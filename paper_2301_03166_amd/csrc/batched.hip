@@ -21,6 +21,7 @@ namespace abft {
 constexpr int BNB = 32;        // block size = checksum tile size of the batched path
 constexpr int BMAX = 512;      // largest matrix order
 constexpr int BN = BMAX / BNB; // largest number of tile rows
+constexpr int BMAXFL = BN * (BN + 1) / 2;  // most trailing tiles of one step (lower part)
 
 struct BatchChk {  // per-matrix checksum workspace (fixed stride)
   double *colchk, *rowchk, *gc, *gr, *S, *Sa, *Tm, *Ta;
@@ -84,88 +85,121 @@ __device__ __forceinline__ float fms_b<float>(float a, float b, float c) {
 
 // checksum carry of the batched trailing update  A22 -= X Y  over tile-rows
 // and tile-columns > k: X rows (i >= c1) from the LDS panel P (row i - c0),
-// Y(p, j) from ymat (LU: U12 in A; Cholesky: the transpose of X).
+// Y(p, j) from ymat (LU: U12 in A; Cholesky: the transpose of X).  The
+// per-tile-row sums of X (S, Sa), and for LU the per-tile-column sums of
+// U12 (Tm, Ta), are formed in the LDS block sl (2 x 2 BN x BNB doubles);
+// one thread per column then updates that column's checksums of every
+// tile-row (its Y column in registers), and one thread per row the row
+// checksums of every tile-column.  Sums are compensated, in index order.
 template <typename T, int CHOL>
-__device__ void batch_carry(const T* A, int64_t lda, int n, int k, int w, const T* P, int ldp, const BatchChk& c) {
+__device__ void batch_carry(const T* A, int64_t lda, int n, int k, int w, const T* P, int ldp, const BatchChk& c,
+                            double* sl) {
   const int N = (n + BNB - 1) / BNB;
   const int c0 = k * BNB, c1 = c0 + w;
   const int ldc = 2 * BN;
+  double* Sl = sl;                 // [2I + e][p]
+  double* Sal = sl + 2 * BN * BNB;  // magnitudes
   // S: sums of X over each tile-row I > k (compensated); Sa: |.|-sums
-  for (int e = threadIdx.x; e < (N - k - 1) * w; e += blockDim.x) {
-    int I = k + 1 + e / w, p = e % w;
+  for (int e = threadIdx.x; e < (N - k - 1) * BNB; e += blockDim.x) {
+    const int I = k + 1 + e / BNB, p = e % BNB;
     acc2 se{0, 0}, sw{0, 0};
     double sa = 0, swa = 0;
-    for (int i = I * BNB; i < min(n, (I + 1) * BNB); ++i) {
-      double v = (double)P[(i - c0) * ldp + p], wi = (double)(i - I * BNB + 1);
-      cadd(se, v);
-      cfma(sw, wi, v);
-      sa += fabs(v);
-      swa += wi * fabs(v);
-    }
-    c.S[2 * I + p * ldc] = cval(se);
-    c.S[2 * I + 1 + p * ldc] = cval(sw);
-    c.Sa[2 * I + p * ldc] = sa;
-    c.Sa[2 * I + 1 + p * ldc] = swa;
-  }
-  if (!CHOL) {
-    // Tm: row sums of U12 over each tile-column J > k
-    for (int e = threadIdx.x; e < (N - k - 1) * w; e += blockDim.x) {
-      int J = k + 1 + e / w, p = e % w;
-      acc2 se{0, 0}, sw{0, 0};
-      double sa = 0, swa = 0;
-      for (int j = J * BNB; j < min(n, (J + 1) * BNB); ++j) {
-        double v = (double)A[(c0 + p) + (int64_t)j * lda], wj = (double)(j - J * BNB + 1);
+    if (p < w)
+      for (int i = I * BNB; i < min(n, (I + 1) * BNB); ++i) {
+        const double v = (double)P[(i - c0) * ldp + p], wi = (double)(i - I * BNB + 1);
         cadd(se, v);
-        cfma(sw, wj, v);
+        cfma(sw, wi, v);
         sa += fabs(v);
-        swa += wj * fabs(v);
+        swa += wi * fabs(v);
       }
-      c.Tm[p + (2 * J) * BNB] = cval(se);
-      c.Tm[p + (2 * J + 1) * BNB] = cval(sw);
-      c.Ta[p + (2 * J) * BNB] = sa;
-      c.Ta[p + (2 * J + 1) * BNB] = swa;
-    }
+    Sl[(2 * I) * BNB + p] = cval(se);
+    Sl[(2 * I + 1) * BNB + p] = cval(sw);
+    Sal[(2 * I) * BNB + p] = sa;
+    Sal[(2 * I + 1) * BNB + p] = swa;
   }
   __syncthreads();
   // column side: colchk(2I+e, j) -= S(2I+e, :) y(:, j);  gc = Sa |y|
-  for (int e = threadIdx.x; e < (n - c1) * (N - k - 1); e += blockDim.x) {
-    int j = c1 + e % (n - c1), I = k + 1 + e / (n - c1);
-    if (CHOL && I < j / BNB) continue;
-    acc2 ue{c.colchk[2 * I + (int64_t)j * ldc], 0}, uw{c.colchk[2 * I + 1 + (int64_t)j * ldc], 0};
-    double ga = 0, gwa = 0;
-    for (int p = 0; p < w; ++p) {
-      double y = CHOL ? (double)P[(j - c0) * ldp + p] : (double)A[(c0 + p) + (int64_t)j * lda];
-      cfma(ue, -c.S[2 * I + p * ldc], y);
-      cfma(uw, -c.S[2 * I + 1 + p * ldc], y);
-      ga += c.Sa[2 * I + p * ldc] * fabs(y);
-      gwa += c.Sa[2 * I + 1 + p * ldc] * fabs(y);
+  for (int j = c1 + threadIdx.x; j < n; j += blockDim.x) {
+    double y[BNB];
+#pragma unroll
+    for (int p = 0; p < BNB; ++p)
+      y[p] = p < w ? (CHOL ? (double)P[(j - c0) * ldp + p] : (double)A[(c0 + p) + (int64_t)j * lda]) : 0.0;
+    for (int I = CHOL ? max(k + 1, j / BNB) : k + 1; I < N; ++I) {
+      acc2 ue{0, 0}, uw{0, 0};
+      double ga = 0, gwa = 0;
+#pragma unroll
+      for (int p = 0; p < BNB; ++p) {
+        cfma(ue, -Sl[(2 * I) * BNB + p], y[p]);
+        cfma(uw, -Sl[(2 * I + 1) * BNB + p], y[p]);
+        ga += Sal[(2 * I) * BNB + p] * fabs(y[p]);
+        gwa += Sal[(2 * I + 1) * BNB + p] * fabs(y[p]);
+      }
+      double* ce = &c.colchk[2 * I + (int64_t)j * ldc];
+      acc2 o{ce[0], 0}, ow{ce[1], 0};
+      cmerge(o, ue);
+      cmerge(ow, uw);
+      ce[0] = cval(o);
+      ce[1] = cval(ow);
+      c.gc[2 * I + (int64_t)j * ldc] = ga;
+      c.gc[2 * I + 1 + (int64_t)j * ldc] = gwa;
     }
-    c.colchk[2 * I + (int64_t)j * ldc] = cval(ue);
-    c.colchk[2 * I + 1 + (int64_t)j * ldc] = cval(uw);
-    c.gc[2 * I + (int64_t)j * ldc] = ga;
-    c.gc[2 * I + 1 + (int64_t)j * ldc] = gwa;
+  }
+  __syncthreads();
+  if (!CHOL) {
+    // Tm: row sums of U12 over each tile-column J > k (the S block is free now)
+    for (int e = threadIdx.x; e < (N - k - 1) * BNB; e += blockDim.x) {
+      const int J = k + 1 + e / BNB, p = e % BNB;
+      acc2 se{0, 0}, sw{0, 0};
+      double sa = 0, swa = 0;
+      if (p < w) {
+        const int j0 = J * BNB, jn = min(n, j0 + BNB) - j0;
+        double u[BNB];
+#pragma unroll
+        for (int t = 0; t < BNB; ++t) u[t] = t < jn ? (double)A[(c0 + p) + (int64_t)(j0 + t) * lda] : 0.0;
+#pragma unroll
+        for (int t = 0; t < BNB; ++t) {
+          if (t < jn) {
+            const double wj = (double)(t + 1);
+            cadd(se, u[t]);
+            cfma(sw, wj, u[t]);
+            sa += fabs(u[t]);
+            swa += wj * fabs(u[t]);
+          }
+        }
+      }
+      Sl[(2 * J) * BNB + p] = cval(se);
+      Sl[(2 * J + 1) * BNB + p] = cval(sw);
+      Sal[(2 * J) * BNB + p] = sa;
+      Sal[(2 * J + 1) * BNB + p] = swa;
+    }
+    __syncthreads();
   }
   // row side: rowchk(i, 2J+e) -= x(i, :) t(:, 2J+e);  gr = |x| t_abs
-  for (int e = threadIdx.x; e < (n - c1) * (N - k - 1); e += blockDim.x) {
-    int i = c1 + e % (n - c1), J = k + 1 + e / (n - c1);
-    if (CHOL && i / BNB < J) continue;
-    acc2 ue{c.rowchk[i + (int64_t)(2 * J) * BMAX], 0}, uw{c.rowchk[i + (int64_t)(2 * J + 1) * BMAX], 0};
-    double ga = 0, gwa = 0;
-    for (int p = 0; p < w; ++p) {
-      double x = (double)P[(i - c0) * ldp + p];
-      double te = CHOL ? c.S[2 * J + p * ldc] : c.Tm[p + (2 * J) * BNB];
-      double tw = CHOL ? c.S[2 * J + 1 + p * ldc] : c.Tm[p + (2 * J + 1) * BNB];
-      double ta = CHOL ? c.Sa[2 * J + p * ldc] : c.Ta[p + (2 * J) * BNB];
-      double twa = CHOL ? c.Sa[2 * J + 1 + p * ldc] : c.Ta[p + (2 * J + 1) * BNB];
-      cfma(ue, -x, te);
-      cfma(uw, -x, tw);
-      ga += fabs(x) * ta;
-      gwa += fabs(x) * twa;
+  // (t = S for Cholesky: the symmetric update, t = Tm for LU)
+  for (int i = c1 + threadIdx.x; i < n; i += blockDim.x) {
+    double x[BNB];
+#pragma unroll
+    for (int p = 0; p < BNB; ++p) x[p] = p < w ? (double)P[(i - c0) * ldp + p] : 0.0;
+    const int Jend = CHOL ? i / BNB + 1 : N;
+    for (int J = k + 1; J < Jend; ++J) {
+      acc2 ue{0, 0}, uw{0, 0};
+      double ga = 0, gwa = 0;
+#pragma unroll
+      for (int p = 0; p < BNB; ++p) {
+        cfma(ue, -x[p], Sl[(2 * J) * BNB + p]);
+        cfma(uw, -x[p], Sl[(2 * J + 1) * BNB + p]);
+        ga += fabs(x[p]) * Sal[(2 * J) * BNB + p];
+        gwa += fabs(x[p]) * Sal[(2 * J + 1) * BNB + p];
+      }
+      double* re = &c.rowchk[i + (int64_t)(2 * J) * BMAX];
+      acc2 o{re[0], 0}, ow{re[BMAX], 0};
+      cmerge(o, ue);
+      cmerge(ow, uw);
+      re[0] = cval(o);
+      re[BMAX] = cval(ow);
+      c.gr[i + (int64_t)(2 * J) * BMAX] = ga;
+      c.gr[i + (int64_t)(2 * J + 1) * BMAX] = gwa;
     }
-    c.rowchk[i + (int64_t)(2 * J) * BMAX] = cval(ue);
-    c.rowchk[i + (int64_t)(2 * J + 1) * BMAX] = cval(uw);
-    c.gr[i + (int64_t)(2 * J) * BMAX] = ga;
-    c.gr[i + (int64_t)(2 * J + 1) * BMAX] = gwa;
   }
   __syncthreads();
 }
@@ -173,11 +207,22 @@ __device__ void batch_carry(const T* A, int64_t lda, int n, int k, int w, const 
 // trailing update A[c1:n, c1:n] -= X Y, X = rows of the LDS panel below the
 // diagonal block, Y = U12 (staged chunk by chunk) or X^T (Cholesky, lower
 // part only).  16 x 16 threads, each with a 4 x 4 register tile of a 64 x 64
-// output block.
+// output block; the C values of the next two blocks of a column of blocks
+// are read ahead while the current one is computed.
 template <typename T, int CHOL>
 __device__ void batch_tmu(T* A, int64_t lda, int n, int c0, int w, const T* P, int ldp, T* Uc) {
   const int c1 = c0 + w, m = n - c1;
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  auto inside = [&](int i, int jj) { return i < m && jj < m && (!CHOL || i >= jj); };
+  auto load_c = [&](int ib, int jb, T(&cv)[4][4]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = ib + tr + 16 * a, jj = jb + tc + 16 * b;
+        cv[a][b] = inside(i, jj) ? A[(c1 + i) + (int64_t)(c1 + jj) * lda] : (T)0;
+      }
+  };
   for (int jb = 0; jb < m; jb += 64) {
     const int jn = min(64, m - jb);
     if (!CHOL) {
@@ -188,7 +233,20 @@ __device__ void batch_tmu(T* A, int64_t lda, int n, int c0, int w, const T* P, i
       }
       __syncthreads();
     }
-    for (int ib = CHOL ? jb : 0; ib < m; ib += 64) {
+    const int ib0 = CHOL ? jb : 0;
+    T c_n1[4][4], c_n2[4][4];
+    load_c(ib0, jb, c_n1);
+    if (ib0 + 64 < m) load_c(ib0 + 64, jb, c_n2);
+    for (int ib = ib0; ib < m; ib += 64) {
+      T cv[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          cv[a][b] = c_n1[a][b];
+          c_n1[a][b] = c_n2[a][b];
+        }
+      if (ib + 128 < m) load_c(ib + 128, jb, c_n2);
       T acc[4][4];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
@@ -217,20 +275,108 @@ __device__ void batch_tmu(T* A, int64_t lda, int n, int c0, int w, const T* P, i
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           int i = ib + tr + 16 * a, jj = jb + tc + 16 * b;
-          if (i < m && jj < m && (!CHOL || i >= jj)) {
-            T* q = A + (c1 + i) + (int64_t)(c1 + jj) * lda;
-            *q = *q - acc[a][b];
-          }
+          if (inside(i, jj)) A[(c1 + i) + (int64_t)(c1 + jj) * lda] = cv[a][b] - acc[a][b];
         }
     }
   }
   __syncthreads();
 }
 
+// One wave checks one tile (h x w <= 32 x 32): the tile goes to a
+// wave-private LDS block (padded, conflict-free both ways), then lane j < 32
+// sums column j and lane 32 + i sums row i, both in index order with
+// compensated plain and position-weighted sums and plain magnitudes.
+// mode 0: store the sums as the tile's checksums (encode).  mode 1: compare
+// with the carried checksums (thresholds from the magnitudes and the carried
+// magnitude bounds); a clean tile's checksums are refreshed from the sums.
+// Returns the number of flagged sums; *maxr gets the largest |d|/tau of the
+// clean comparisons.
+template <typename T>
+__device__ int wave_tile32(const T* A, int64_t lda, int I, int J, int h, int w, bool sym, int mode, double* colchk,
+                           int ldc, double* rowchk, int ldr, const double* gc, const double* gr, double tsu,
+                           double* lds, double* maxr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r0 = (int64_t)I * BNB, c0 = (int64_t)J * BNB;
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = lane + 64 * q, i = e & 31, j = e >> 5;
+    double x = 0.0;
+    if (i < h && j < w) x = (sym && i < j) ? (double)A[(r0 + j) + (c0 + i) * lda] : (double)A[(r0 + i) + (c0 + j) * lda];
+    v[q] = x;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = lane + 64 * q;
+    lds[(e & 31) + 33 * (e >> 5)] = v[q];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const bool col = lane < 32;
+  const int x = lane & 31;  // column (col) or row index
+  acc2 se{0, 0}, sw{0, 0};
+  double sa = 0.0, swa = 0.0;
+  for (int t = 0; t < 32; ++t) {
+    const double val = col ? lds[t + 33 * x] : lds[x + 33 * t], wt = (double)(t + 1), av = fabs(val);
+    cadd(se, val);
+    cfma(sw, wt, val);
+    sa += av;
+    swa += wt * av;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const bool live = col ? x < w : x < h;
+  double* pe = col ? &colchk[2 * I + (c0 + x) * ldc] : &rowchk[(r0 + x) + (2 * J) * ldr];
+  double* pw = col ? pe + 1 : pe + ldr;
+  const double e = cval(se), ww = cval(sw);
+  if (mode == 0) {
+    if (live) { *pe = e; *pw = ww; }
+    return 0;
+  }
+  int nfl = 0;
+  double mr = 0.0;
+  if (live) {
+    const double ge = col ? (gc ? gc[2 * I + (c0 + x) * ldc] : 0.0) : (gr ? gr[(r0 + x) + (2 * J) * ldr] : 0.0);
+    const double gw = col ? (gc ? gc[2 * I + 1 + (c0 + x) * ldc] : 0.0) : (gr ? gr[(r0 + x) + (2 * J + 1) * ldr] : 0.0);
+    const double de = e - *pe, dw = ww - *pw;
+    const double te = tau_verify(tsu, sa, ge), tw = tau_verify(tsu, swa, gw);
+    const bool be = bad(de, te), bw = bad(dw, tw);
+    nfl = be + bw;
+    if (!be && te > 0) mr = fmax(mr, fabs(de) / te);
+    if (!bw && tw > 0) mr = fmax(mr, fabs(dw) / tw);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    nfl += __shfl_xor(nfl, o);
+    mr = fmax(mr, __shfl_xor(mr, o));
+  }
+  if (nfl == 0 && live) { *pe = e; *pw = ww; }
+  *maxr = mr;
+  return nfl;
+}
+
+#ifdef ABFT_LEAF_TIMING
+#define BT_DECL unsigned long long bt_t = __builtin_amdgcn_s_memtime(), bt_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#define BT_MARK(k)                                          \
+  do {                                                      \
+    unsigned long long bt_n = __builtin_amdgcn_s_memtime(); \
+    bt_acc[k] += bt_n - bt_t;                               \
+    bt_t = bt_n;                                            \
+  } while (0)
+#define BT_PRINT()                                                                                              \
+  if (blockIdx.x == 0 && threadIdx.x == 0)                                                                       \
+    printf("batched n=%d: init %llu panel %llu swaps %llu u12 %llu tmu %llu carry %llu verify %llu\n", n,        \
+           bt_acc[0], bt_acc[1], bt_acc[2], bt_acc[3], bt_acc[4], bt_acc[5], bt_acc[6]);
+#else
+#define BT_DECL
+#define BT_MARK(k)
+#define BT_PRINT()
+#endif
+
 template <typename T, int CHOL>
 __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, BatchChk c, int protect, double tsu,
                            const abft_fault* faults, int nfaults, int32_t* info, abft_report* rep,
                            unsigned char* smem) {
+  BT_DECL
   const int tid = threadIdx.x;
   const int N = (n + BNB - 1) / BNB;
   const int ldc = 2 * BN;
@@ -244,6 +390,8 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
   __shared__ double wv_val[4];
   __shared__ int wv_idx[4];
   __shared__ int s_fail;
+  __shared__ int s_nflag;
+  __shared__ int s_flagged[BMAXFL];
   if (tid == 0) {
     rep->flagged_tiles = rep->corrected = rep->checksum_repaired = rep->uncorrectable = rep->panel_flags = 0;
     rep->first_flag_iter = 0x7fffffff;
@@ -254,15 +402,28 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
     s_fail = 0;
   }
   __syncthreads();
+  double* wlds = reinterpret_cast<double*>(smem) + (tid >> 6) * (BNB * (BNB + 1));  // this wave's tile block
   if (protect) {
-    for (int J = 0; J < N; ++J)
-      for (int I = CHOL ? J : 0; I < N; ++I) {
-        int h = min(BNB, n - I * BNB), w = min(BNB, n - J * BNB);
-        tile_sums(A, lda, (int64_t)I * BNB, (int64_t)J * BNB, h, w, CHOL && I == J, ts);
-        store_sums(ts, I, J, BNB, h, w, c.colchk, ldc, c.rowchk, BMAX);
-        __syncthreads();
+    // encode: one tile per wave
+    const int nt = CHOL ? N * (N + 1) / 2 : N * N;
+    for (int t = tid >> 6; t < nt; t += 4) {
+      int I, J;
+      if (CHOL) {  // lower tiles, column by column
+        J = 0;
+        int r = t;
+        while (r >= N - J) { r -= N - J; ++J; }
+        I = J + r;
+      } else {
+        I = t % N;
+        J = t / N;
       }
+      double mr;
+      wave_tile32(A, lda, I, J, min(BNB, n - I * BNB), min(BNB, n - J * BNB), CHOL && I == J, 0, c.colchk, ldc,
+                  c.rowchk, BMAX, nullptr, nullptr, 0.0, wlds, &mr);
+    }
+    __syncthreads();
   }
+  BT_MARK(0);
   for (int k = 0; k < N; ++k) {
     const int c0 = k * BNB, w = min(BNB, n - c0), c1 = c0 + w, mrows = n - c0;
     // ---- panel into LDS
@@ -350,6 +511,7 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
       if (!CHOL || i >= j) A[(c0 + i) + (int64_t)(c0 + j) * lda] = P[i * ldp + j];
     }
     __syncthreads();
+    BT_MARK(1);
     if (!CHOL) {
       // interchanges outside the panel, one at a time (checksums follow the rows)
       for (int j = 0; j < w; ++j) {
@@ -380,6 +542,7 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
         __syncthreads();
       }
     }
+    BT_MARK(2);
     if (c1 >= n) break;
     if (!CHOL) {
       // panel update U12 = L11^{-1} A12, one thread per column
@@ -398,8 +561,11 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
       __syncthreads();
     }
     // ---- trailing update and checksum carry
+    BT_MARK(3);
     batch_tmu<T, CHOL>(A, lda, n, c0, w, P, ldp, Uc);
-    if (protect) batch_carry<T, CHOL>(A, lda, n, k, w, P, ldp, c);
+    BT_MARK(4);
+    if (protect) batch_carry<T, CHOL>(A, lda, n, k, w, P, ldp, c, reinterpret_cast<double*>(Uc));
+    BT_MARK(5);
     // ---- planned faults of this matrix and iteration
     if (tid == 0)
       for (int f = 0; f < nfaults; ++f) {
@@ -417,27 +583,78 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
     __syncthreads();
     // ---- verify (and correct) the trailing tiles
     if (protect) {
-      for (int J = k + 1; J < N; ++J)
-        for (int I = CHOL ? J : k + 1; I < N; ++I) {
-          int h = min(BNB, n - I * BNB), wj = min(BNB, n - J * BNB);
-          bool diag = CHOL && I == J;
-          tile_sums(A, lda, (int64_t)I * BNB, (int64_t)J * BNB, h, wj, diag, ts);
-          tile_compare(ts, tf, I, J, BNB, h, wj, c.colchk, ldc, c.rowchk, BMAX, c.gc, c.gr, tsu);
-          if (tf.nflag == 0) {
-            store_sums(ts, I, J, BNB, h, wj, c.colchk, ldc, c.rowchk, BMAX);
-            if (tid == 0 && tf.maxr > 0) rep_max_ratio(rep, tf.maxr);
-          } else {
-            if (tid == 0) {
-              rep->flagged_tiles++;
-              if (rep->first_flag_iter > k) rep->first_flag_iter = k;
-            }
-            correct_tile_dev(A, lda, I, J, BNB, h, wj, diag, c.colchk, ldc, c.rowchk, BMAX, c.gc, c.gr, tsu, rep, k,
-                             ts, tf, cs);
+      // one trailing tile per wave; flagged tiles are listed and corrected
+      // afterwards by the whole workgroup, in tile order
+      const int M = N - k - 1;
+      const int nt = CHOL ? M * (M + 1) / 2 : M * M;
+      if (tid == 0) s_nflag = 0;
+      __syncthreads();
+      double wmax = 0.0;
+      for (int t = tid >> 6; t < nt; t += 4) {
+        int I, J;
+        if (CHOL) {
+          J = 0;
+          int r = t;
+          while (r >= M - J) { r -= M - J; ++J; }
+          I = J + r;
+        } else {
+          I = t % M;
+          J = t / M;
+        }
+        I += k + 1;
+        J += k + 1;
+        double mr;
+        const int nfl = wave_tile32(A, lda, I, J, min(BNB, n - I * BNB), min(BNB, n - J * BNB), CHOL && I == J, 1,
+                                    c.colchk, ldc, c.rowchk, BMAX, c.gc, c.gr, tsu, wlds, &mr);
+        if (nfl) {
+          if ((tid & 63) == 0) {
+            const int slot = atomicAdd(&s_nflag, 1);
+            if (slot < BMAXFL) s_flagged[slot] = t;
           }
+        } else {
+          wmax = fmax(wmax, mr);
+        }
+      }
+      if ((tid & 63) == 0 && wmax > 0) rep_max_ratio(rep, wmax);
+      __syncthreads();
+      const int nf = min(s_nflag, BMAXFL);
+      if (nf > 0) {
+        // tile order (the workgroup's waves listed them in any order)
+        if (tid == 0)
+          for (int a = 1; a < nf; ++a)
+            for (int b2 = a; b2 > 0 && s_flagged[b2 - 1] > s_flagged[b2]; --b2) {
+              const int tmp = s_flagged[b2];
+              s_flagged[b2] = s_flagged[b2 - 1];
+              s_flagged[b2 - 1] = tmp;
+            }
+        __syncthreads();
+        for (int f = 0; f < nf; ++f) {
+          const int t = s_flagged[f];
+          int I, J;
+          if (CHOL) {
+            J = 0;
+            int r = t;
+            while (r >= M - J) { r -= M - J; ++J; }
+            I = J + r;
+          } else {
+            I = t % M;
+            J = t / M;
+          }
+          I += k + 1;
+          J += k + 1;
+          if (tid == 0) {
+            rep->flagged_tiles++;
+            if (rep->first_flag_iter > k) rep->first_flag_iter = k;
+          }
+          correct_tile_dev(A, lda, I, J, BNB, min(BNB, n - I * BNB), min(BNB, n - J * BNB), CHOL && I == J, c.colchk,
+                           ldc, c.rowchk, BMAX, c.gc, c.gr, tsu, rep, k, ts, tf, cs);
           __syncthreads();
         }
+      }
     }
+    BT_MARK(6);
   }
+  BT_PRINT()
   if (tid == 0) {
     if (rep->first_flag_iter == 0x7fffffff) rep->first_flag_iter = -1;
     if (rep->nev > ABFT_MAX_EVENTS) rep->nev = ABFT_MAX_EVENTS;
@@ -500,7 +717,9 @@ int batched_factor(hipStream_t s, int chol, int prec, int batch, const int32_t* 
   if (hipGetLastError() != hipSuccess) return ABFT_ERR_HIP;
   const double u = prec == ABFT_F64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
   const size_t elem = prec == ABFT_F64 ? 8 : 4;
-  size_t shm = std::max((size_t)BMAX * (BNB + 1) * elem + (size_t)BNB * 65 * elem, sizeof(TileSums) + sizeof(TileFlags));
+  // panel, then the U12 chunk / the carry's sum block, or the verify scratch
+  const size_t tail = std::max((size_t)BNB * 65 * elem, (size_t)4 * BN * BNB * sizeof(double));
+  size_t shm = std::max((size_t)BMAX * (BNB + 1) * elem + tail, sizeof(TileSums) + sizeof(TileFlags));
   shm = (shm + 255) & ~(size_t)255;
   dim3 grid(std::min(batch, wgs));  // persistent workgroups; extra ones wait for a free CU
 #define BLAUNCH(T_, C_)                                                                                            \

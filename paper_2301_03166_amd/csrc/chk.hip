@@ -81,14 +81,27 @@ struct ColAcc {
   double ca, cwa;
 };
 
+// EXACT: compensated sums (binary64 data); binary32 data is summed with
+// plain binary64 additions, whose error (about nb * 2^-53 of the magnitude
+// sum) is far below the binary32 thresholds
+template <bool EXACT>
+__device__ __forceinline__ void add_e(acc2& a, double x) {
+  if (EXACT) cadd(a, x); else a.s += x;
+}
+template <bool EXACT>
+__device__ __forceinline__ void fma_e(acc2& a, double w, double x) {
+  if (EXACT) cfma(a, w, x); else a.s = __fma_rn(w, x, a.s);
+}
+
+template <bool EXACT>
 __device__ __forceinline__ void strip_sum(const double (&v)[SCW], int s, int c, StripAcc& r, ColAcc& col,
                                           double (*blk)[65]) {
   const int lane = threadIdx.x & 63, part = lane / SCW, jj = lane % SCW;
 #pragma unroll
   for (int t = 0; t < SCW; ++t) {
     const double wj = (double)(c + t + 1), x = v[t], ax = fabs(x);
-    cadd(r.re, x);
-    cfma(r.rw, wj, x);
+    add_e<EXACT>(r.re, x);
+    fma_e<EXACT>(r.rw, wj, x);
     r.ra += ax;
     r.rwa += wj * ax;
     blk[t][lane] = x;
@@ -98,8 +111,8 @@ __device__ __forceinline__ void strip_sum(const double (&v)[SCW], int s, int c, 
   for (int q = 0; q < 64 / SRL; ++q) {
     const int il = (64 / SRL) * part + q;
     const double x = blk[jj][il], ax = fabs(x), wi = (double)(64 * s + il + 1);
-    cadd(col.ce, x);
-    cfma(col.cw, wi, x);
+    add_e<EXACT>(col.ce, x);
+    fma_e<EXACT>(col.cw, wi, x);
     col.ca += ax;
     col.cwa += wi * ax;
   }
@@ -125,11 +138,11 @@ __device__ void tile_sums_stream(const T* A, int64_t lda, int64_t r0, int64_t c0
     ColAcc col{{0, 0}, {0, 0}, 0, 0};
     const int cn = c + SCW;
     if (has0) {
-      strip_sum(v0, s0, c, r0a, col, L.blk[wv]);
+      strip_sum<sizeof(T) == 8>(v0, s0, c, r0a, col, L.blk[wv]);
       if (cn < w) strip_load(v0, A, lda, r0, c0, h, w, sym, s0, cn);
     }
     if (has1) {
-      strip_sum(v1, s1, c, r1a, col, L.blk[wv]);
+      strip_sum<sizeof(T) == 8>(v1, s1, c, r1a, col, L.blk[wv]);
       if (cn < w) strip_load(v1, A, lda, r0, c0, h, w, sym, s1, cn);
     }
     // merge the SRL row parts of each column (lanes jj, jj+SCW, ...), fixed order

@@ -256,6 +256,12 @@ constexpr uint32_t LL_NONE = 0xffffffffu;  // no candidate row in this workgroup
 // of column j it needs.
 __host__ __device__ constexpr int64_t lu_rec_words(int G, int w) { return (int64_t)G * (3 + 2 * w) + 2 * w; }
 
+// Three workgroup barriers per column: after the local argmax (every thread
+// then merges the four wave results itself), after the winner's wave
+// results (likewise), and after the pivot row has been read.  The row
+// interchange is folded into the update: the owner of row p copies the old
+// row d in before updating it, and row d (never read again in the leaf) is
+// overwritten with the pivot row by the leaf's column threads.
 template <typename T>
 __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m, int64_t c0, int w, int R,
                                                     int32_t* ipiv, int32_t* info, uint64_t* recs, uint32_t seq0,
@@ -265,11 +271,9 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
   T* Ld = reinterpret_cast<T*>(smem_raw);  // R x (w+1)
   const int ldl = w + 1;
   __shared__ double prow[CLEAF], orow[CLEAF];
-  __shared__ double wv_val[4];
-  __shared__ int64_t wv_idx[4];
-  __shared__ int wv_g[4];
-  __shared__ int64_t s_piv, s_loc;
-  __shared__ int s_pg;
+  __shared__ double am_val[4], wn_val[4];
+  __shared__ int64_t am_idx[4], wn_idx[4];
+  __shared__ int wn_g[4];
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t rbeg = c0 + (int64_t)g * R;
   const int rows = (int)max((int64_t)0, min((int64_t)R, m - rbeg));
@@ -288,36 +292,39 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
     uint64_t* rj = recs + (size_t)(j & 1) * cstride;
     uint64_t* rowd = rj + (size_t)G * rw;
     // local argmax of |a(i, j)| over owned rows i >= d
-    double bv = -1.0;
-    int64_t bi = INT64_MAX;
-    for (int i = tid; i < rows; i += 256) {
-      int64_t gi = rbeg + i;
-      if (gi < d) continue;
-      double v = fabs((double)Ld[i * ldl + j]);
-      if (better<T>(v, gi, bv, bi)) { bv = v; bi = gi; }
-    }
+    {
+      double bv = -1.0;
+      int64_t bi = INT64_MAX;
+      for (int i = tid; i < rows; i += 256) {
+        int64_t gi = rbeg + i;
+        if (gi < d) continue;
+        double v = fabs((double)Ld[i * ldl + j]);
+        if (better<T>(v, gi, bv, bi)) { bv = v; bi = gi; }
+      }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      double ov = __shfl_xor(bv, o);
-      int64_t oi = __shfl_xor(bi, o);
-      if (better<T>(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+      for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_xor(bv, o);
+        int64_t oi = __shfl_xor(bi, o);
+        if (better<T>(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+      }
+      if (lane == 0) { am_val[wv] = bv; am_idx[wv] = bi; }
     }
-    if (lane == 0) { wv_val[wv] = bv; wv_idx[wv] = bi; }
     __syncthreads();
-    uint64_t* mine = rj + (size_t)g * rw;
-    if (tid == 0) {
+    {
+      double bv = am_val[0];
+      int64_t bi = am_idx[0];
       for (int q = 1; q < 4; ++q)
-        if (better<T>(wv_val[q], wv_idx[q], bv, bi)) { bv = wv_val[q]; bi = wv_idx[q]; }
-      ll_put2(mine, bv, seq);
-      ll_put(mine + 2, bi == INT64_MAX ? LL_NONE : (uint32_t)bi, seq);
-      s_loc = bi;
-    }
-    __syncthreads();
-    // candidate row (values of the leaf columns) and, from workgroup 0, row d
-    if (tid < w) {
-      const int64_t bl = s_loc;
-      ll_put2(mine + 3 + 2 * tid, bl == INT64_MAX ? 0.0 : (double)Ld[(bl - rbeg) * ldl + tid], seq);
-      if (g == 0) ll_put2(rowd + 2 * tid, (double)Ld[(d - rbeg) * ldl + tid], seq);
+        if (better<T>(am_val[q], am_idx[q], bv, bi)) { bv = am_val[q]; bi = am_idx[q]; }
+      uint64_t* mine = rj + (size_t)g * rw;
+      if (tid == 0) {
+        ll_put2(mine, bv, seq);
+        ll_put(mine + 2, bi == INT64_MAX ? LL_NONE : (uint32_t)bi, seq);
+      }
+      // candidate row (values of the leaf columns) and, from workgroup 0, row d
+      if (tid < w) {
+        ll_put2(mine + 3 + 2 * tid, bi == INT64_MAX ? 0.0 : (double)Ld[(bi - rbeg) * ldl + tid], seq);
+        if (g == 0) ll_put2(rowd + 2 * tid, (double)Ld[(d - rbeg) * ldl + tid], seq);
+      }
     }
     LT_MARK(0);
     // every workgroup picks the same winner: one record per thread (its three
@@ -348,23 +355,16 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
         const int og = __shfl_xor(gq, o);
         if (better<T>(ov, oi, v, ii)) { v = ov; ii = oi; gq = og; }
       }
-      if (lane == 0) { wv_val[wv] = v; wv_idx[wv] = ii; wv_g[wv] = gq; }
-      __syncthreads();
-      if (tid == 0) {
-        double best = wv_val[0];
-        int64_t bidx = wv_idx[0];
-        int bg = wv_g[0];
-        for (int q = 1; q < 4; ++q)
-          if (better<T>(wv_val[q], wv_idx[q], best, bidx)) { best = wv_val[q]; bidx = wv_idx[q]; bg = wv_g[q]; }
-        if (bidx == INT64_MAX) { bidx = d; bg = 0; }
-        s_piv = bidx;
-        s_pg = bg;
-      }
-      __syncthreads();
+      if (lane == 0) { wn_val[wv] = v; wn_idx[wv] = ii; wn_g[wv] = gq; }
     }
+    __syncthreads();
+    double best = wn_val[0];
+    int64_t p = wn_idx[0];
+    int pg = wn_g[0];
+    for (int q = 1; q < 4; ++q)
+      if (better<T>(wn_val[q], wn_idx[q], best, p)) { best = wn_val[q]; p = wn_idx[q]; pg = wn_g[q]; }
+    if (p == INT64_MAX) { p = d; pg = 0; }
     LT_MARK(2);
-    const int64_t p = s_piv;
-    const int pg = s_pg;
     const bool own_p = p != d && p >= rbeg && p < rbeg + rows;
     if (tid < w) {
       prow[tid] = ll_get2b(rj + (size_t)pg * rw + 3 + 2 * tid, seq, rep);
@@ -372,28 +372,27 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
     }
     __syncthreads();
     LT_MARK(3);
-    if (p != d) {
-      if (g == 0 && tid < w) Ld[(d - rbeg) * ldl + tid] = (T)prow[tid];
-      if (own_p && tid < w) Ld[(p - rbeg) * ldl + tid] = (T)orow[tid];
-    }
-    __syncthreads();
     if (g == 0 && tid == 0) {
       ipiv[d] = (int32_t)(p + 1);
       if (prow[j] == 0.0 && info) atomicCAS(info, 0, (int32_t)(d + 1));
     }
+    if (g == 0 && p != d && tid < w) Ld[(d - rbeg) * ldl + tid] = (T)prow[tid];
     const T piv = (T)prow[j];
-    if (piv != (T)0) {
-      for (int i = tid; i < rows; i += 256) {
-        int64_t gi = rbeg + i;
-        if (gi <= d) continue;
-        T l = Ld[i * ldl + j] / piv;
-        Ld[i * ldl + j] = l;
-        row_axpy(Ld + i * ldl, prow, l, j + 1, w);  // a(i,c) - l * u(c)
+    for (int i = tid; i < rows; i += 256) {
+      const int64_t gi = rbeg + i;
+      if (gi <= d) continue;
+      T* row = Ld + i * ldl;
+      if (own_p && gi == p)
+        for (int c = 0; c < w; ++c) row[c] = (T)orow[c];  // the old row d moves to row p
+      if (piv != (T)0) {
+        const T l = row[j] / piv;
+        row[j] = l;
+        row_axpy(row, prow, l, j + 1, w);  // a(i,c) - l * u(c)
       }
     }
-    __syncthreads();
     LT_MARK(4);
   }
+  __syncthreads();
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
     A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
@@ -444,30 +443,28 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
   __syncthreads();
 
   // sum of the G records of len values (src + r * len) for entries e <
-  // len: QG threads share an entry (records r = gq, gq + QG, ...), sixteen
-  // loads in flight each; the parts are added in a fixed order.  The result
-  // goes to dst[e] (LDS).
+  // len: QG threads share an entry (records r = gq, gq + QG, ...), up to 32
+  // loads in flight each (one round trip for G <= 128); the parts are added
+  // in a fixed order.  The result goes to dst[e] (LDS).
   constexpr int QG = 256 / CLEAF;
   auto sum_slots = [&](const double* src, int len, double* dst) {
     for (int e0 = 0; e0 < len; e0 += CLEAF) {
       const int c = tid % CLEAF, gq = tid / CLEAF, e = e0 + c;
-      double pp[16];
+      double pp[32];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) pp[u] = 0.0;
+      for (int u = 0; u < 32; ++u) pp[u] = 0.0;
       if (e < len) {
-        int r = gq;
-        for (; r + 15 * QG < G; r += 16 * QG) {
-          double v[16];
+        for (int r = gq; r < G; r += 32 * QG) {
+          double v[32];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) v[u] = src[(size_t)(r + u * QG) * len + e];
+          for (int u = 0; u < 32; ++u) v[u] = r + u * QG < G ? src[(size_t)(r + u * QG) * len + e] : 0.0;
 #pragma unroll
-          for (int u = 0; u < 16; ++u) pp[u] += v[u];
+          for (int u = 0; u < 32; ++u) pp[u] += v[u];
         }
-        for (int u = 0; r < G; r += QG, ++u) pp[u] += src[(size_t)r * len + e];
       }
       double t = pp[0];
 #pragma unroll
-      for (int u = 1; u < 16; ++u) t += pp[u];
+      for (int u = 1; u < 32; ++u) t += pp[u];
       qpart[gq][c] = t;
       __syncthreads();
       if (tid < CLEAF && e0 + tid < len) {
@@ -613,8 +610,9 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
 constexpr int PB_W = 512;  // largest panel width (block size)
 __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, int64_t c0, int w, int64_t n,
                                                         int* moves) {
-  __shared__ int pv[PB_W], sidx[PB_W], ptr[PB_W];
-  __shared__ int key[2 * PB_W], mflag[2 * PB_W];
+  // (scans read four entries per LDS access)
+  __shared__ __attribute__((aligned(16))) int pv[PB_W], sidx[PB_W], ptr[PB_W];
+  __shared__ __attribute__((aligned(16))) int key[2 * PB_W], mflag[2 * PB_W];
   __shared__ int nmoved;
   const int tid = threadIdx.x;
   const int rows = (int)min<int64_t>(n - c0, 0x7fffffff);
@@ -629,9 +627,19 @@ __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, in
   if (tid < w) {
     const int p = pv[tid];
     int f = tid;
-    if (p >= w)
-      for (int t = 0; t < tid; ++t)
-        if (pv[t] == p) { f = t; break; }
+    if (p >= w) {
+      int t = 0;
+      for (; t + 4 <= tid; t += 4) {
+        const int4 q = *reinterpret_cast<const int4*>(&pv[t]);
+        if (q.x == p) { f = t; break; }
+        if (q.y == p) { f = t + 1; break; }
+        if (q.z == p) { f = t + 2; break; }
+        if (q.w == p) { f = t + 3; break; }
+      }
+      if (f == tid)
+        for (; t < tid; ++t)
+          if (pv[t] == p) { f = t; break; }
+    }
     sidx[tid] = p < w ? p : w + f;
     key[tid] = tid;
     key[w + tid] = (p >= w && f == tid) ? p : -1;
@@ -647,15 +655,25 @@ __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, in
   int ts = -1, tl = -1;
   if (tid < w) {
     const int b = sidx[tid];
-    int pr = -1;
-    for (int t2 = 0; t2 < tid; ++t2) {
+    int pr = -1, t2 = 0;
+    for (; t2 + 4 <= tid; t2 += 4) {
+      const int4 q = *reinterpret_cast<const int4*>(&sidx[t2]);
+      pr = q.w == tid ? t2 + 3 : (q.z == tid ? t2 + 2 : (q.y == tid ? t2 + 1 : (q.x == tid ? t2 : pr)));
+      ts = q.w == b ? t2 + 3 : (q.z == b ? t2 + 2 : (q.y == b ? t2 + 1 : (q.x == b ? t2 : ts)));
+    }
+    for (; t2 < tid; ++t2) {
       const int s2 = sidx[t2];
       if (s2 == tid) pr = t2;
       if (s2 == b) ts = t2;
     }
     ptr[tid] = pr >= 0 ? pr : tid;
   } else if (tid < 2 * w) {
-    for (int t = 0; t < w; ++t)
+    int t = 0;
+    for (; t + 4 <= w; t += 4) {
+      const int4 q = *reinterpret_cast<const int4*>(&sidx[t]);
+      tl = q.w == tid ? t + 3 : (q.z == tid ? t + 2 : (q.y == tid ? t + 1 : (q.x == tid ? t : tl)));
+    }
+    for (; t < w; ++t)
       if (sidx[t] == tid) tl = t;
   }
   __syncthreads();
@@ -680,12 +698,16 @@ __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, in
   // come before the outer pivot rows
   if (moved) {
     int r = 0;
-    if (tid < w) {
-      for (int q = 0; q < tid; ++q) r += mflag[q];
-    } else {
-      for (int q = 0; q < w; ++q) r += mflag[q];
+    const int lim = tid < w ? tid : w;  // moved panel rows before this one
+    int q = 0;
+    for (; q + 4 <= lim; q += 4) {
+      const int4 f4 = *reinterpret_cast<const int4*>(&mflag[q]);
+      r += f4.x + f4.y + f4.z + f4.w;
+    }
+    for (; q < lim; ++q) r += mflag[q];
+    if (tid >= w) {  // and the moved outer rows with a smaller row index
       const int kx = key[tid];
-      for (int q = w; q < 2 * w; ++q) r += (mflag[q] && key[q] < kx);
+      for (q = w; q < 2 * w; ++q) r += (mflag[q] && key[q] < kx);
     }
     moves[1 + 2 * r] = (int)(c0 + key[tid]);
     moves[2 + 2 * r] = (int)(c0 + fin);
