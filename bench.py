@@ -302,8 +302,12 @@ def energy_leg(h, torch, dev, args):
     ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     rep = h.new_report()
+    # idle level: let the board settle after the previous legs (the reported
+    # power trails the load), then take the median of two seconds of samples
+    torch.cuda.synchronize()
+    time.sleep(4.0)
     ps.start()
-    time.sleep(1.0)
+    time.sleep(2.0)
     idle = ps.stop()
     reps, t0 = 0, time.perf_counter()
     ps.start()
@@ -318,7 +322,7 @@ def energy_leg(h, torch, dev, args):
     torch.cuda.empty_cache()
     if len(busy) < 10 or not idle:
         return None
-    p_idle = sum(p for _, p in idle) / len(idle)
+    p_idle = sorted(p for _, p in idle)[len(idle) // 2]
     joules = 0.0
     for (ta, pa), (tb, pb) in zip(busy[:-1], busy[1:]):
         joules += 0.5 * (pa + pb) * (tb - ta)

@@ -47,16 +47,6 @@ template <typename T>
 __device__ __forceinline__ void strip_load(double (&v)[SCW], const T* A, int64_t lda, int64_t r0, int64_t c0, int h,
                                            int w, bool sym, int s, int c) {
   const int i = 64 * s + (threadIdx.x & 63);
-  if (sym) {  // diagonal tile of a symmetric matrix: upper part from the mirror
-#pragma unroll
-    for (int t = 0; t < SCW; ++t) {
-      const int j = c + t;
-      double x = 0.0;
-      if (i < h && j < w) x = i < j ? (double)A[(r0 + j) + (c0 + i) * lda] : (double)A[(r0 + i) + (c0 + j) * lda];
-      v[t] = x;
-    }
-    return;
-  }
   const int ic = i < h ? i : h - 1;  // clamp, then zero: no divergent loads
   const T* p = A + (r0 + ic) + (c0 + c) * lda;
   if (c + SCW <= w) {
@@ -69,6 +59,11 @@ __device__ __forceinline__ void strip_load(double (&v)[SCW], const T* A, int64_t
   if (i >= h) {
 #pragma unroll
     for (int t = 0; t < SCW; ++t) v[t] = 0.0;
+  }
+  if (sym) {  // diagonal tile of a symmetric matrix: its stored lower triangle only
+#pragma unroll
+    for (int t = 0; t < SCW; ++t)
+      if (i < c + t) v[t] = 0.0;
   }
 }
 
@@ -196,6 +191,26 @@ __device__ void tile_sums_stream(const T* A, int64_t lda, int64_t r0, int64_t c0
     ts.res[i1] = cval(r1a.re); ts.rws[i1] = cval(r1a.rw); ts.ra[i1] = r1a.ra; ts.rwa[i1] = r1a.rwa;
   }
   __syncthreads();
+  if (sym) {
+    // The symmetric tile S = X + X^T - diag(X), X its lower triangle (the
+    // sums above): both the column and the row sums of S at index j are
+    // (column j of X) + (row j of X) - x_jj, with the weight j+1 on x_jj in
+    // the weighted sums and |x_jj| in the magnitudes.
+    for (int j = threadIdx.x; j < w; j += blockDim.x) {
+      const double d = (double)A[(r0 + j) + (c0 + j) * lda], wj = (double)(j + 1);
+      acc2 e{ts.ce[j], 0.0}, ew{ts.cw[j], 0.0};
+      cadd(e, ts.res[j]);
+      cadd(e, -d);
+      cadd(ew, ts.rws[j]);
+      cadd(ew, -wj * d);
+      const double a = (ts.ca[j] + ts.ra[j]) - fabs(d), aw = (ts.cwa[j] + ts.rwa[j]) - wj * fabs(d);
+      ts.ce[j] = ts.res[j] = cval(e);
+      ts.cw[j] = ts.rws[j] = cval(ew);
+      ts.ca[j] = ts.ra[j] = a;
+      ts.cwa[j] = ts.rwa[j] = aw;
+    }
+    __syncthreads();
+  }
 }
 
 // mode 0: encode (write sums); mode 1: verify (flag, refresh clean tiles);

@@ -74,34 +74,4 @@ __device__ __forceinline__ void rep_event(abft_report* r, int iter, int kind, in
 }
 __device__ __forceinline__ void rep_flag_iter(abft_report* r, int iter) { atomicMin(&r->first_flag_iter, iter); }
 
-// ---------------------------------------------------------------------------
-// Grid-wide barrier for cooperative launches (every workgroup resident), on
-// one flag word per workgroup: workgroup g stores the barrier's sequence
-// number into flags[g] (release), then waits until every flag has reached it
-// (one flag per polling thread, so there is no contended read-modify-write).
-// Only thread 0 releases: after the workgroup barrier its agent-scope
-// release (L2 write-back) covers the whole workgroup's completed stores; the
-// acquire fence after the wait (L2 invalidate) covers the following loads.
-// Sequence numbers increase within a use of the flags (cleared before), so a
-// flag already past `seq` also counts.  The wait is bounded; on expiry the
-// workgroup records ABFT_ST_INTERNAL and carries on, so every wave always
-// reaches the end of the kernel.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void flag_barrier(unsigned* flags, unsigned seq, abft_report* rep) {
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(&flags[blockIdx.x], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  for (unsigned t = threadIdx.x; t < gridDim.x; t += blockDim.x) {
-    long spins = 0;
-    while (__hip_atomic_load(&flags[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < seq) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1L << 21)) {
-        if (rep) atomicOr(&rep->status, (int)ABFT_ST_INTERNAL);
-        break;
-      }
-    }
-  }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
 }  // namespace abft

@@ -256,12 +256,6 @@ constexpr uint32_t LL_NONE = 0xffffffffu;  // no candidate row in this workgroup
 // of column j it needs.
 __host__ __device__ constexpr int64_t lu_rec_words(int G, int w) { return (int64_t)G * (3 + 2 * w) + 2 * w; }
 
-// Three workgroup barriers per column: after the local argmax (every thread
-// then merges the four wave results itself), after the winner's wave
-// results (likewise), and after the pivot row has been read.  The row
-// interchange is folded into the update: the owner of row p copies the old
-// row d in before updating it, and row d (never read again in the leaf) is
-// overwritten with the pivot row by the leaf's column threads.
 template <typename T>
 __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m, int64_t c0, int w, int R,
                                                     int32_t* ipiv, int32_t* info, uint64_t* recs, uint32_t seq0,
@@ -271,9 +265,11 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
   T* Ld = reinterpret_cast<T*>(smem_raw);  // R x (w+1)
   const int ldl = w + 1;
   __shared__ double prow[CLEAF], orow[CLEAF];
-  __shared__ double am_val[4], wn_val[4];
-  __shared__ int64_t am_idx[4], wn_idx[4];
-  __shared__ int wn_g[4];
+  __shared__ double wv_val[4];
+  __shared__ int64_t wv_idx[4];
+  __shared__ int wv_g[4];
+  __shared__ int64_t s_piv, s_loc;
+  __shared__ int s_pg;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t rbeg = c0 + (int64_t)g * R;
   const int rows = (int)max((int64_t)0, min((int64_t)R, m - rbeg));
@@ -292,39 +288,36 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
     uint64_t* rj = recs + (size_t)(j & 1) * cstride;
     uint64_t* rowd = rj + (size_t)G * rw;
     // local argmax of |a(i, j)| over owned rows i >= d
-    {
-      double bv = -1.0;
-      int64_t bi = INT64_MAX;
-      for (int i = tid; i < rows; i += 256) {
-        int64_t gi = rbeg + i;
-        if (gi < d) continue;
-        double v = fabs((double)Ld[i * ldl + j]);
-        if (better<T>(v, gi, bv, bi)) { bv = v; bi = gi; }
-      }
+    double bv = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int i = tid; i < rows; i += 256) {
+      int64_t gi = rbeg + i;
+      if (gi < d) continue;
+      double v = fabs((double)Ld[i * ldl + j]);
+      if (better<T>(v, gi, bv, bi)) { bv = v; bi = gi; }
+    }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        double ov = __shfl_xor(bv, o);
-        int64_t oi = __shfl_xor(bi, o);
-        if (better<T>(ov, oi, bv, bi)) { bv = ov; bi = oi; }
-      }
-      if (lane == 0) { am_val[wv] = bv; am_idx[wv] = bi; }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ov = __shfl_xor(bv, o);
+      int64_t oi = __shfl_xor(bi, o);
+      if (better<T>(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { wv_val[wv] = bv; wv_idx[wv] = bi; }
+    __syncthreads();
+    uint64_t* mine = rj + (size_t)g * rw;
+    if (tid == 0) {
+      for (int q = 1; q < 4; ++q)
+        if (better<T>(wv_val[q], wv_idx[q], bv, bi)) { bv = wv_val[q]; bi = wv_idx[q]; }
+      ll_put2(mine, bv, seq);
+      ll_put(mine + 2, bi == INT64_MAX ? LL_NONE : (uint32_t)bi, seq);
+      s_loc = bi;
     }
     __syncthreads();
-    {
-      double bv = am_val[0];
-      int64_t bi = am_idx[0];
-      for (int q = 1; q < 4; ++q)
-        if (better<T>(am_val[q], am_idx[q], bv, bi)) { bv = am_val[q]; bi = am_idx[q]; }
-      uint64_t* mine = rj + (size_t)g * rw;
-      if (tid == 0) {
-        ll_put2(mine, bv, seq);
-        ll_put(mine + 2, bi == INT64_MAX ? LL_NONE : (uint32_t)bi, seq);
-      }
-      // candidate row (values of the leaf columns) and, from workgroup 0, row d
-      if (tid < w) {
-        ll_put2(mine + 3 + 2 * tid, bi == INT64_MAX ? 0.0 : (double)Ld[(bi - rbeg) * ldl + tid], seq);
-        if (g == 0) ll_put2(rowd + 2 * tid, (double)Ld[(d - rbeg) * ldl + tid], seq);
-      }
+    // candidate row (values of the leaf columns) and, from workgroup 0, row d
+    if (tid < w) {
+      const int64_t bl = s_loc;
+      ll_put2(mine + 3 + 2 * tid, bl == INT64_MAX ? 0.0 : (double)Ld[(bl - rbeg) * ldl + tid], seq);
+      if (g == 0) ll_put2(rowd + 2 * tid, (double)Ld[(d - rbeg) * ldl + tid], seq);
     }
     LT_MARK(0);
     // every workgroup picks the same winner: one record per thread (its three
@@ -355,16 +348,23 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
         const int og = __shfl_xor(gq, o);
         if (better<T>(ov, oi, v, ii)) { v = ov; ii = oi; gq = og; }
       }
-      if (lane == 0) { wn_val[wv] = v; wn_idx[wv] = ii; wn_g[wv] = gq; }
+      if (lane == 0) { wv_val[wv] = v; wv_idx[wv] = ii; wv_g[wv] = gq; }
+      __syncthreads();
+      if (tid == 0) {
+        double best = wv_val[0];
+        int64_t bidx = wv_idx[0];
+        int bg = wv_g[0];
+        for (int q = 1; q < 4; ++q)
+          if (better<T>(wv_val[q], wv_idx[q], best, bidx)) { best = wv_val[q]; bidx = wv_idx[q]; bg = wv_g[q]; }
+        if (bidx == INT64_MAX) { bidx = d; bg = 0; }
+        s_piv = bidx;
+        s_pg = bg;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    double best = wn_val[0];
-    int64_t p = wn_idx[0];
-    int pg = wn_g[0];
-    for (int q = 1; q < 4; ++q)
-      if (better<T>(wn_val[q], wn_idx[q], best, p)) { best = wn_val[q]; p = wn_idx[q]; pg = wn_g[q]; }
-    if (p == INT64_MAX) { p = d; pg = 0; }
     LT_MARK(2);
+    const int64_t p = s_piv;
+    const int pg = s_pg;
     const bool own_p = p != d && p >= rbeg && p < rbeg + rows;
     if (tid < w) {
       prow[tid] = ll_get2b(rj + (size_t)pg * rw + 3 + 2 * tid, seq, rep);
@@ -372,27 +372,28 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
     }
     __syncthreads();
     LT_MARK(3);
+    if (p != d) {
+      if (g == 0 && tid < w) Ld[(d - rbeg) * ldl + tid] = (T)prow[tid];
+      if (own_p && tid < w) Ld[(p - rbeg) * ldl + tid] = (T)orow[tid];
+    }
+    __syncthreads();
     if (g == 0 && tid == 0) {
       ipiv[d] = (int32_t)(p + 1);
       if (prow[j] == 0.0 && info) atomicCAS(info, 0, (int32_t)(d + 1));
     }
-    if (g == 0 && p != d && tid < w) Ld[(d - rbeg) * ldl + tid] = (T)prow[tid];
     const T piv = (T)prow[j];
-    for (int i = tid; i < rows; i += 256) {
-      const int64_t gi = rbeg + i;
-      if (gi <= d) continue;
-      T* row = Ld + i * ldl;
-      if (own_p && gi == p)
-        for (int c = 0; c < w; ++c) row[c] = (T)orow[c];  // the old row d moves to row p
-      if (piv != (T)0) {
-        const T l = row[j] / piv;
-        row[j] = l;
-        row_axpy(row, prow, l, j + 1, w);  // a(i,c) - l * u(c)
+    if (piv != (T)0) {
+      for (int i = tid; i < rows; i += 256) {
+        int64_t gi = rbeg + i;
+        if (gi <= d) continue;
+        T l = Ld[i * ldl + j] / piv;
+        Ld[i * ldl + j] = l;
+        row_axpy(Ld + i * ldl, prow, l, j + 1, w);  // a(i,c) - l * u(c)
       }
     }
+    __syncthreads();
     LT_MARK(4);
   }
-  __syncthreads();
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
     A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
@@ -407,31 +408,38 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
 // columnwise) written at T[toff + toff*ldt].
 //
 // Per column j every workgroup forms the partial Gram row
-// S_c = sum over its rows i > d of a(i,j) a(i,c) for every c < w, stores it
-// (workgroup 0 also row d), and after one flag barrier adds the G partial
-// rows in one fixed order (plain loads: the records are shared through each
-// XCD's L2).  Entries c >= j give the column norm and the reflector's dot
-// products with the trailing columns; entries c < j give
+// S_c = sum over its rows i > d of a(i,j) a(i,c) for every c < w.  The G
+// partial rows are added in two levels through self-validating exchange
+// records (as in the LU leaf; no barrier, no fence): the first workgroup of
+// each group of 16 adds its members' rows in member order and publishes the
+// group sum, then every workgroup adds the group sums in group order, so all
+// hold the same Gram row.  Entries c >= j give the column norm and the
+// reflector's dot products with the trailing columns; entries c < j give
 // v_c . v_j = v_c(d) + scale S_c, the inputs of T's column j, which
 // workgroup 0 stages in T's strictly upper part.  After the loop workgroup
-// 0 runs T's recurrence in LDS.  Records of two columns alternate (a
-// workgroup rewrites column j's records only after the barrier of column
-// j + 1, which every workgroup passes only after reading column j).
+// 0 runs T's recurrence in LDS.  Records of two columns alternate: a
+// workgroup rewrites column j's records only after it has read every group
+// sum of column j + 1, which no group publishes before its members have
+// finished column j.
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int64_t qr_rec_words(int G, int w) { return (int64_t)(G + 1) * w; }
+constexpr int QR_GROUP = 16;
+__host__ __device__ constexpr int64_t qr_rec_words(int G, int w) {
+  return (int64_t)(G + (G + QR_GROUP - 1) / QR_GROUP + 1) * 2 * w;
+}
 
 __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int64_t m, int64_t c0, int w, int R,
-                                                    double* tau, double* Tm, int ldt, int toff, double* recs,
-                                                    unsigned* flags, unsigned seq0, abft_report* rep) {
+                                                    double* tau, double* Tm, int ldt, int toff, uint64_t* recs,
+                                                    uint32_t seq0, abft_report* rep) {
   extern __shared__ unsigned char smem_raw[];
   LT_DECL
   double* Ld = reinterpret_cast<double*>(smem_raw);  // R x (w+1)
   const int ldl = w + 1;
   __shared__ double part[4][CLEAF];
-  __shared__ double qpart[256 / CLEAF][CLEAF];
-  __shared__ double svec[CLEAF], orow[CLEAF], fvec[CLEAF];
+  __shared__ double qpart[4][CLEAF], gpart[4][CLEAF];
+  __shared__ double orow[CLEAF], fvec[CLEAF];
   __shared__ double s_beta, s_tau, s_scale;
-  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, e = tid & 63, wq = tid >> 6;
+  const int NG = (G + QR_GROUP - 1) / QR_GROUP;
   const int64_t rbeg = c0 + (int64_t)g * R;
   const int rows = (int)max((int64_t)0, min((int64_t)R, m - rbeg));
   const int64_t cstride = qr_rec_words(G, w);
@@ -442,48 +450,45 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
   }
   __syncthreads();
 
-  // sum of the G records of len values (src + r * len) for entries e <
-  // len: QG threads share an entry (records r = gq, gq + QG, ...), up to 32
-  // loads in flight each (one round trip for G <= 128); the parts are added
-  // in a fixed order.  The result goes to dst[e] (LDS).
-  constexpr int QG = 256 / CLEAF;
-  auto sum_slots = [&](const double* src, int len, double* dst) {
-    for (int e0 = 0; e0 < len; e0 += CLEAF) {
-      const int c = tid % CLEAF, gq = tid / CLEAF, e = e0 + c;
-      double pp[32];
+  // sum of up to four records (q0, q0 + 4, ... < q1) of 2w words at base:
+  // entry e of this thread, all loads issued before any is polled
+  auto sum4 = [&](const uint64_t* base, int q0, int q1, uint32_t seq) {
+    double acc = 0.0;
+    if (e < w) {
+      uint64_t wd[8];
 #pragma unroll
-      for (int u = 0; u < 32; ++u) pp[u] = 0.0;
-      if (e < len) {
-        for (int r = gq; r < G; r += 32 * QG) {
-          double v[32];
-#pragma unroll
-          for (int u = 0; u < 32; ++u) v[u] = r + u * QG < G ? src[(size_t)(r + u * QG) * len + e] : 0.0;
-#pragma unroll
-          for (int u = 0; u < 32; ++u) pp[u] += v[u];
+      for (int k = 0; k < 4; ++k) {
+        const int q = q0 + 4 * k;
+        if (q < q1) {
+          const uint64_t* pr = base + (size_t)q * 2 * w + 2 * e;
+          wd[2 * k] = __hip_atomic_load(pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          wd[2 * k + 1] = __hip_atomic_load(pr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
-      double t = pp[0];
 #pragma unroll
-      for (int u = 1; u < 32; ++u) t += pp[u];
-      qpart[gq][c] = t;
-      __syncthreads();
-      if (tid < CLEAF && e0 + tid < len) {
-        double v = qpart[0][tid];
-        for (int u = 1; u < QG; ++u) v += qpart[u][tid];
-        dst[e0 + tid] = v;
+      for (int k = 0; k < 4; ++k) {
+        const int q = q0 + 4 * k;
+        if (q < q1) {
+          const uint64_t* pr = base + (size_t)q * 2 * w + 2 * e;
+          ll_poll(pr, wd[2 * k], seq, rep);
+          ll_poll(pr + 1, wd[2 * k + 1], seq, rep);
+          acc += ll_dbl(wd[2 * k], wd[2 * k + 1]);
+        }
       }
-      __syncthreads();
     }
+    return acc;
   };
 
   for (int j = 0; j < w; ++j) {
     const int64_t d = c0 + j;
-    double* sj = recs + (size_t)(j & 1) * cstride;
-    double* rowd = sj + (size_t)G * w;
+    const uint32_t seq = seq0 + (uint32_t)j;
+    uint64_t* r1 = recs + (size_t)(j & 1) * cstride;  // G partial rows
+    uint64_t* r2 = r1 + (size_t)G * 2 * w;           // NG group sums
+    uint64_t* rdw = r2 + (size_t)NG * 2 * w;         // row d
     // partial Gram row: thread (q, c) takes column c over the rows i = q
     // (mod 4) below d of the LDS panel, eight rows per step, loads first
     {
-      const int c = tid & 63, q = tid >> 6;
+      const int c = e, q = wq;
       double acc = 0.0;
       if (c < w) {
         const int i0 = (int)max((int64_t)0, d + 1 - rbeg);
@@ -504,18 +509,30 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
     }
     __syncthreads();
     if (tid < w) {
-      sj[(size_t)g * w + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
-      if (g == 0) rowd[tid] = Ld[(d - rbeg) * ldl + tid];
+      ll_put2(r1 + (size_t)g * 2 * w + 2 * tid, ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid], seq);
+      if (g == 0) ll_put2(rdw + 2 * tid, Ld[(d - rbeg) * ldl + tid], seq);
     }
     LT_MARK(0);
-    flag_barrier(flags, seq0 + (unsigned)j, rep);
+    // level 1: the group's first workgroup adds its members' rows
+    if (g % QR_GROUP == 0) {
+      qpart[wq][e] = sum4(r1, g + wq, min(G, g + QR_GROUP), seq);
+      __syncthreads();
+      if (tid < w)
+        ll_put2(r2 + (size_t)(g / QR_GROUP) * 2 * w + 2 * tid,
+                ((qpart[0][tid] + qpart[1][tid]) + qpart[2][tid]) + qpart[3][tid], seq);
+    }
     LT_MARK(1);
-    // every workgroup: the same Gram row (hence the same reflector), and row d
-    if (tid < w) orow[tid] = rowd[tid];
-    sum_slots(sj, w, svec);
+    // level 2: every workgroup adds the group sums (and reads row d)
+    gpart[wq][e] = sum4(r2, wq, NG, seq);
+    if (tid < w) orow[tid] = ll_get2b(rdw + 2 * tid, seq, rep);
+    __syncthreads();
+    double sv = 0.0;
+    if (tid < w) sv = ((gpart[0][tid] + gpart[1][tid]) + gpart[2][tid]) + gpart[3][tid];
+    if (tid < w) fvec[tid] = sv;  // the Gram row, for thread 0's reflector
+    __syncthreads();
     LT_MARK(2);
     if (tid == 0) {
-      const double alpha = orow[j], s2 = svec[j];
+      const double alpha = orow[j], s2 = fvec[j];
       if (s2 == 0.0) {
         s_tau = 0.0; s_scale = 0.0; s_beta = alpha;
       } else {
@@ -529,9 +546,9 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
     __syncthreads();
     const double t = s_tau, sc = s_scale;
     if (g == 0 && tid < j)  // v_c . v_j for c < j, staged in T's strictly upper part
-      Tm[(toff + tid) + (int64_t)(toff + j) * ldt] = orow[tid] + sc * svec[tid];
+      Tm[(toff + tid) + (int64_t)(toff + j) * ldt] = orow[tid] + sc * sv;
     if (t != 0.0) {
-      if (tid < w && tid > j) fvec[tid] = t * (orow[tid] + sc * svec[tid]);
+      if (tid < w && tid > j) fvec[tid] = t * (orow[tid] + sc * sv);
       __syncthreads();
       for (int i = tid; i < rows; i += 256) {
         int64_t gi = rbeg + i;
@@ -883,14 +900,16 @@ int getrf_leaf(hipStream_t s, T* A, int64_t lda, int64_t m, int64_t c0, int w, i
 
 int geqrf_leaf(hipStream_t s, double* A, int64_t lda, int64_t m, int64_t c0, int w, double* tau, double* Tm, int ldt,
                int toff, double* slots, unsigned* ctr, unsigned* ctr_base, abft_report* rep, int maxg) {
+  (void)ctr;
   int G, R;
   const int max_rows = (int)((140 * 1024) / ((w + 1) * sizeof(double)));
   coop_shape(m - c0, w, maxg, max_rows, G, R);
   if ((int64_t)G * R < m - c0) return ABFT_ERR_UNSUPPORTED;
   if (w > CLEAF || G > 256 || (size_t)(2 * qr_rec_words(G, w)) > SLOT_WORDS) return ABFT_ERR_UNSUPPORTED;
   size_t shm = (size_t)R * (w + 1) * sizeof(double);
-  unsigned seq0 = *ctr_base + 1;
-  void* args[] = {&A, &lda, &m, &c0, &w, &R, &tau, &Tm, &ldt, &toff, &slots, &ctr, &seq0, &rep};
+  uint64_t* recs = reinterpret_cast<uint64_t*>(slots);
+  uint32_t seq0 = *ctr_base + 1;
+  void* args[] = {&A, &lda, &m, &c0, &w, &R, &tau, &Tm, &ldt, &toff, &recs, &seq0, &rep};
   hipError_t e = hipLaunchCooperativeKernel((const void*)k_geqrf_leaf, dim3(G), dim3(256), args, shm, s);
   *ctr_base += (unsigned)w;
   return e == hipSuccess ? 0 : ABFT_ERR_HIP;
