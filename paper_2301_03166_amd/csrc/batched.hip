@@ -74,6 +74,12 @@ __global__ void k_batch_order(const int32_t* dn, int batch, int* order, unsigned
   if (threadIdx.x == 0) *queue = 0u;
 }
 
+// LDS writes of one wave made visible to its other lanes
+__device__ __forceinline__ void wave_sync_b() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <typename T>
 __device__ __forceinline__ T fms_b(T a, T b, T c) {
   return a - b * c;
@@ -433,33 +439,48 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
     }
     __syncthreads();
     if (CHOL) {
-      // diagonal block, right-looking
-      for (int j = 0; j < w; ++j) {
-        if (tid == 0) {
-          T d = P[j * ldp + j];
-          if (!(d > (T)0) && !s_fail) {
-            s_fail = 1;
-            *info = c0 + j + 1;
-          }
-          P[j * ldp + j] = sqrt(d);
-        }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < w; i += blockDim.x) P[i * ldp + j] = P[i * ldp + j] / P[j * ldp + j];
-        __syncthreads();
-        const int r = w - j - 1;
-        for (int e = tid; e < r * r; e += blockDim.x) {
-          int i = j + 1 + e % r, jj = j + 1 + e / r;
-          if (i >= jj) P[i * ldp + jj] = fms_b(P[i * ldp + jj], P[i * ldp + j], P[jj * ldp + j]);
-        }
-        __syncthreads();
-      }
-      // rows below: x L^T = a, one thread per row
-      for (int i = w + tid; i < mrows; i += blockDim.x)
+      // diagonal block, right-looking, by wave 0 alone (no workgroup barriers)
+      if (tid < 64) {
         for (int j = 0; j < w; ++j) {
-          T sacc = P[i * ldp + j];
-          for (int p = 0; p < j; ++p) sacc = fms_b(sacc, P[i * ldp + p], P[j * ldp + p]);
-          P[i * ldp + j] = sacc / P[j * ldp + j];
+          if (tid == 0) {
+            T d = P[j * ldp + j];
+            if (!(d > (T)0) && !s_fail) {
+              s_fail = 1;
+              *info = c0 + j + 1;
+            }
+            P[j * ldp + j] = sqrt(d);
+          }
+          wave_sync_b();
+          for (int i = j + 1 + tid; i < w; i += 64) P[i * ldp + j] = P[i * ldp + j] / P[j * ldp + j];
+          wave_sync_b();
+          const int r = w - j - 1;
+          for (int e = tid; e < r * r; e += 64) {
+            int i = j + 1 + e % r, jj = j + 1 + e / r;
+            if (i >= jj) P[i * ldp + jj] = fms_b(P[i * ldp + jj], P[i * ldp + j], P[jj * ldp + j]);
+          }
+          wave_sync_b();
         }
+      }
+      __syncthreads();
+      // rows below: x L^T = a, one thread per row, the row in registers
+      // (same operation order as the plain substitution)
+      for (int i = w + tid; i < mrows; i += blockDim.x) {
+        T x[BNB];
+#pragma unroll
+        for (int j = 0; j < BNB; ++j) x[j] = j < w ? P[i * ldp + j] : (T)0;
+#pragma unroll
+        for (int j = 0; j < BNB; ++j) {
+          if (j < w) {
+            T sacc = x[j];
+#pragma unroll
+            for (int p = 0; p < j; ++p) sacc = fms_b(sacc, x[p], P[j * ldp + p]);
+            x[j] = sacc / P[j * ldp + j];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < BNB; ++j)
+          if (j < w) P[i * ldp + j] = x[j];
+      }
       __syncthreads();
     } else {
       for (int j = 0; j < w; ++j) {
@@ -513,34 +534,45 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
     __syncthreads();
     BT_MARK(1);
     if (!CHOL) {
-      // interchanges outside the panel, one at a time (checksums follow the rows)
-      for (int j = 0; j < w; ++j) {
-        const int r = c0 + j, q = c0 + swp[j];
-        if (q != r) {
-          const int Ir = r / BNB, Iq = q / BNB;
-          const double wr = r - Ir * BNB + 1, wq = q - Iq * BNB + 1;
-          for (int col = tid; col < n; col += blockDim.x) {
-            if (col >= c0 && col < c1) continue;
-            T ar = A[r + (int64_t)col * lda], aq = A[q + (int64_t)col * lda];
-            if (protect && col >= c1) {
-              double d = (double)aq - (double)ar;
-              c.colchk[2 * Ir + (int64_t)col * ldc] += d;
-              c.colchk[2 * Ir + 1 + (int64_t)col * ldc] += wr * d;
-              c.colchk[2 * Iq + (int64_t)col * ldc] -= d;
-              c.colchk[2 * Iq + 1 + (int64_t)col * ldc] -= wq * d;
-            }
-            A[r + (int64_t)col * lda] = aq;
-            A[q + (int64_t)col * lda] = ar;
+      // interchanges outside the panel: every thread applies all of them, in
+      // order, to its own columns (checksums follow the rows), so no barrier
+      // is needed between them; the changes of tile-row k (every row r of the
+      // panel lies in it) are gathered in registers
+      for (int col = tid; col < n; col += blockDim.x) {
+        if (col >= c0 && col < c1) continue;
+        T* colp = A + (int64_t)col * lda;
+        const bool chk = protect && col >= c1;
+        double dk = 0.0, dkw = 0.0;
+        for (int j = 0; j < w; ++j) {
+          const int r = c0 + j, q = c0 + swp[j];
+          if (q == r) continue;
+          const T ar = colp[r], aq = colp[q];
+          if (chk) {
+            const int Iq = q / BNB;
+            const double d = (double)aq - (double)ar, wr = (double)(j + 1), wq = (double)(q - Iq * BNB + 1);
+            dk += d;
+            dkw += wr * d;
+            c.colchk[2 * Iq + (int64_t)col * ldc] -= d;
+            c.colchk[2 * Iq + 1 + (int64_t)col * ldc] -= wq * d;
           }
-          if (protect)
-            for (int cc = tid; cc < 2 * N; cc += blockDim.x) {
-              double t = c.rowchk[r + (int64_t)cc * BMAX];
-              c.rowchk[r + (int64_t)cc * BMAX] = c.rowchk[q + (int64_t)cc * BMAX];
-              c.rowchk[q + (int64_t)cc * BMAX] = t;
-            }
+          colp[r] = aq;
+          colp[q] = ar;
         }
-        __syncthreads();
+        if (chk) {
+          c.colchk[2 * k + (int64_t)col * ldc] += dk;
+          c.colchk[2 * k + 1 + (int64_t)col * ldc] += dkw;
+        }
       }
+      if (protect)
+        for (int cc = tid; cc < 2 * N; cc += blockDim.x)
+          for (int j = 0; j < w; ++j) {
+            const int r = c0 + j, q = c0 + swp[j];
+            if (q == r) continue;
+            const double t = c.rowchk[r + (int64_t)cc * BMAX];
+            c.rowchk[r + (int64_t)cc * BMAX] = c.rowchk[q + (int64_t)cc * BMAX];
+            c.rowchk[q + (int64_t)cc * BMAX] = t;
+          }
+      __syncthreads();
     }
     BT_MARK(2);
     if (c1 >= n) break;
