@@ -36,6 +36,12 @@ struct StreamLds {
   double blk[4][SCW][65];  // per-wave transpose buffer [column in chunk][row in strip]
   double cp[4][SCW][6];    // per-wave column partials of the chunk
 };
+// the sums of one tile as the streaming pass leaves them (32 KB of LDS, so
+// two verify workgroups fit on a CU)
+struct StreamSums {
+  double ce[MAXNB], cw[MAXNB], ca[MAXNB], cwa[MAXNB];
+  double res[MAXNB], rws[MAXNB], ra[MAXNB], rwa[MAXNB];
+};
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -118,8 +124,8 @@ __device__ __forceinline__ acc2 shfl_acc(const acc2& a, int m) {
   return acc2{__shfl_xor(a.s, m), __shfl_xor(a.c, m)};
 }
 
-template <typename T>
-__device__ void tile_sums_stream(const T* A, int64_t lda, int64_t r0, int64_t c0, int h, int w, bool sym, TileSums& ts,
+template <typename T, typename TS>
+__device__ void tile_sums_stream(const T* A, int64_t lda, int64_t r0, int64_t c0, int h, int w, bool sym, TS& ts,
                                  StreamLds& L) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, jj = lane % SCW;
   const int nstrip = (h + 63) / 64;
@@ -220,21 +226,62 @@ __global__ __launch_bounds__(256) void k_verify(const T* A, int64_t lda, int64_t
                                                 int nI, int sym, int mode, double* colchk, int64_t ldc, double* rowchk,
                                                 int64_t ldr, const double* gc, const double* gr, double tsu,
                                                 int* tflags, abft_report* rep, int iter) {
-  __shared__ TileSums ts;
-  __shared__ TileFlags tf;
+  __shared__ StreamSums ts;
   __shared__ StreamLds sl;
+  __shared__ int s_nfl;
+  __shared__ double s_maxr;
   int I, J, h, w;
   tile_geom(blockIdx.x, I0, J0, nI, nb, nr, nc, I, J, h, w);
   const int tile = I + J * (int)((nr + nb - 1) / nb);
   if (sym && I < J) return;
+  if (threadIdx.x == 0) { s_nfl = 0; s_maxr = 0.0; }
   tile_sums_stream(A, lda, (int64_t)I * nb, (int64_t)J * nb, h, w, sym && I == J, ts, sl);
+  const int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
+  auto store = [&]() {
+    for (int j = threadIdx.x; j < w; j += blockDim.x) {
+      colchk[2 * I + (c0 + j) * ldc] = ts.ce[j];
+      colchk[2 * I + 1 + (c0 + j) * ldc] = ts.cw[j];
+    }
+    for (int i = threadIdx.x; i < h; i += blockDim.x) {
+      rowchk[(r0 + i) + (2 * J) * ldr] = ts.res[i];
+      rowchk[(r0 + i) + (2 * J + 1) * ldr] = ts.rws[i];
+    }
+  };
   if (mode == 0) {
-    store_sums(ts, I, J, nb, h, w, colchk, ldc, rowchk, ldr);
+    store();
     return;
   }
-  tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu);
-  const bool flagged = tf.nflag > 0;
-  if (!flagged && mode == 1) store_sums(ts, I, J, nb, h, w, colchk, ldc, rowchk, ldr);
+  // comparison with the carried checksums (the flags themselves are
+  // recomputed by the correction pass of a flagged tile)
+  int nfl = 0;
+  double mr = 0.0;
+  auto cmp = [&](double d, double t) {
+    const bool b = bad(d, t);
+    nfl += b;
+    if (!b && t > 0) mr = fmax(mr, fabs(d) / t);
+  };
+  for (int j = threadIdx.x; j < w; j += blockDim.x) {
+    const int64_t o = 2 * I + (c0 + j) * ldc;
+    cmp(ts.ce[j] - colchk[o], tau_verify(tsu, ts.ca[j], gc ? gc[o] : 0.0));
+    cmp(ts.cw[j] - colchk[o + 1], tau_verify(tsu, ts.cwa[j], gc ? gc[o + 1] : 0.0));
+  }
+  for (int i = threadIdx.x; i < h; i += blockDim.x) {
+    const int64_t o = (r0 + i) + (2 * J) * ldr;
+    cmp(ts.res[i] - rowchk[o], tau_verify(tsu, ts.ra[i], gr ? gr[o] : 0.0));
+    cmp(ts.rws[i] - rowchk[o + ldr], tau_verify(tsu, ts.rwa[i], gr ? gr[o + ldr] : 0.0));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    nfl += __shfl_xor(nfl, o);
+    mr = fmax(mr, __shfl_xor(mr, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (nfl) atomicAdd(&s_nfl, nfl);
+    if (mr > 0) atomicMax(reinterpret_cast<unsigned long long*>(&s_maxr), (unsigned long long)__double_as_longlong(mr));
+  }
+  __syncthreads();
+  const bool flagged = s_nfl > 0;
+  if (!flagged && mode == 1) store();
   if (threadIdx.x == 0) {
     if (tflags) tflags[tile] = flagged ? 1 : 0;
     if (rep) {
@@ -242,7 +289,7 @@ __global__ __launch_bounds__(256) void k_verify(const T* A, int64_t lda, int64_t
         atomicAdd((unsigned long long*)&rep->flagged_tiles, 1ull);
         rep_flag_iter(rep, iter);
       }
-      if (tf.maxr > 0) rep_max_ratio(rep, tf.maxr);
+      if (s_maxr > 0) rep_max_ratio(rep, s_maxr);
     }
   }
 }

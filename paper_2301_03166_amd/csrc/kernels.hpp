@@ -63,6 +63,8 @@ template <typename T>
 int trsm_rlt_leaf(hipStream_t s, T* A, int64_t lda, int64_t r0, int64_t r1, int64_t c0, int w);
 template <typename T>
 int trsm_llu_leaf(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1);
+template <typename T>
+int trsm_llu_blk(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1);
 // cooperative-leaf exchange area, in 8-byte words (the LU leaf's records are
 // cleared at the start of each factorization: their sequence numbers restart)
 constexpr size_t SLOT_WORDS = (size_t)3 << 20;

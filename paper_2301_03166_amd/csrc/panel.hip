@@ -15,6 +15,8 @@
 
 namespace abft {
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 constexpr int LEAF = 32;   // width of the triangular leaf kernels (potrf / trsm)
 constexpr int CLEAF = 64;  // widest cooperative LU / QR leaf
 
@@ -176,6 +178,89 @@ __global__ __launch_bounds__(256) void k_trsm_llu_leaf(T* A, int64_t lda, int64_
   for (int idx = tid; idx < 256 * w; idx += 256) {
     int i = idx % w, c = idx / w;
     if (jb + c < j1) A[(c0 + i) + (jb + c) * lda] = B[c][i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// X = L^{-1} B in one launch, L unit lower w x w at (c0, c0) (w <= 512), B
+// rows [c0, c0+w) of columns [j0, j1).  A workgroup keeps a strip of
+// TRS_CB columns of B in LDS and walks the 32-row blocks of L: the diagonal
+// block's substitution runs in registers (one thread per column, the
+// elimination order of the 32-wide leaf), its solution is copied row-major,
+// and the rows below subtract its products with the block's 32 columns of L
+// (read straight from memory, shared by all strips through L2) on FP64 MFMA
+// tiles of 16 rows x 16 strip columns.
+// ---------------------------------------------------------------------------
+constexpr int TRS_CB = 16;
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm_llu_blk(T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1) {
+  extern __shared__ unsigned char trs_raw[];
+  const int wp = (w + LEAF - 1) / LEAF * LEAF;  // rows padded with zeros to whole blocks
+  const int ldb = wp + 1;
+  T* Bs = reinterpret_cast<T*>(trs_raw);  // Bs[c * ldb + i]
+  __shared__ T Ls[LEAF][LEAF + 1];
+  __shared__ __attribute__((aligned(16))) T Xs[LEAF][TRS_CB];  // solved block, row-major
+  const int tid = threadIdx.x;
+  const int64_t jb = j0 + (int64_t)blockIdx.x * TRS_CB;
+  const int ncol = (int)min((int64_t)TRS_CB, j1 - jb);
+  for (int idx = tid; idx < wp * TRS_CB; idx += 256) {
+    const int i = idx % wp, c = idx / wp;
+    Bs[c * ldb + i] = (c < ncol && i < w) ? A[(c0 + i) + (jb + c) * lda] : (T)0;
+  }
+  for (int r0 = 0; r0 < w; r0 += LEAF) {
+    const int bw = min(LEAF, w - r0);
+    for (int idx = tid; idx < LEAF * LEAF; idx += 256) {
+      const int i = idx % LEAF, p = idx / LEAF;
+      Ls[i][p] = (i < bw && p < i) ? A[(c0 + r0 + i) + (c0 + r0 + p) * lda] : (T)0;
+    }
+    __syncthreads();
+    if (tid < TRS_CB) {
+      // (rows past w are zero and their L rows too: no guards needed)
+      T x[LEAF];
+#pragma unroll
+      for (int i = 0; i < LEAF; ++i) x[i] = Bs[tid * ldb + r0 + i];
+#pragma unroll
+      for (int i = 1; i < LEAF; ++i) {
+        T sacc = x[i];
+#pragma unroll
+        for (int p = 0; p < i; ++p) sacc = fms(sacc, Ls[i][p], x[p]);
+        x[i] = sacc;
+      }
+#pragma unroll
+      for (int i = 0; i < LEAF; ++i) {
+        Bs[tid * ldb + r0 + i] = x[i];
+        Xs[i][tid] = x[i];
+      }
+    }
+    __syncthreads();
+    // rows below the block, 16-row tiles per wave on FP64 MFMA (16x16x4):
+    // lane (il, kl) feeds L(row il, column kl of the k-step) and X(row kl,
+    // column il), and holds rows il, columns 4r + kl of the tile in reg r
+    {
+      const int lane = tid & 63, wv = tid >> 6, il = lane & 15, kl = lane >> 4;
+      for (int rt = r0 + bw + 16 * wv; rt < w; rt += 64) {
+        const bool rin = rt + il < w;
+        f64x4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = rin ? (double)Bs[(4 * r + kl) * ldb + rt + il] : 0.0;
+#pragma unroll
+        for (int p0 = 0; p0 < LEAF; p0 += 4) {
+          const int p = p0 + kl;
+          const double a = (rin && p < bw) ? -(double)A[(c0 + rt + il) + (c0 + r0 + p) * lda] : 0.0;
+          const double b = p < bw ? (double)Xs[p][il] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, acc, 0, 0, 0);
+        }
+        if (rin) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Bs[(4 * r + kl) * ldb + rt + il] = (T)acc[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < w * TRS_CB; idx += 256) {
+    const int i = idx % w, c = idx / w;
+    if (c < ncol) A[(c0 + i) + (jb + c) * lda] = Bs[c * ldb + i];
   }
 }
 
@@ -862,6 +947,15 @@ int trsm_rlt_leaf(hipStream_t s, T* A, int64_t lda, int64_t r0, int64_t r1, int6
   CHECK_LAUNCH();
 }
 template <typename T>
+int trsm_llu_blk(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1) {
+  if (j1 <= j0 || w <= 0) return 0;
+  if (w > PB_W) return ABFT_ERR_UNSUPPORTED;
+  const size_t shm = (size_t)((w + LEAF - 1) / LEAF * LEAF + 1) * TRS_CB * sizeof(T);
+  hipLaunchKernelGGL(k_trsm_llu_blk<T>, dim3((unsigned)((j1 - j0 + TRS_CB - 1) / TRS_CB)), dim3(256), shm, s, A, lda, c0,
+                     w, j0, j1);
+  CHECK_LAUNCH();
+}
+template <typename T>
 int trsm_llu_leaf(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1) {
   if (j1 <= j0) return 0;
   hipLaunchKernelGGL(k_trsm_llu_leaf<T>, dim3((unsigned)((j1 - j0 + 255) / 256)), dim3(256), 0, s, A, lda, c0, w, j0, j1);
@@ -940,6 +1034,8 @@ template int potrf_leaf<float>(hipStream_t, float*, int64_t, int64_t, int, int32
 template int trsm_rlt_leaf<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int64_t, int);
 template int trsm_rlt_leaf<float>(hipStream_t, float*, int64_t, int64_t, int64_t, int64_t, int);
 template int trsm_llu_leaf<double>(hipStream_t, double*, int64_t, int64_t, int, int64_t, int64_t);
+template int trsm_llu_blk<double>(hipStream_t, double*, int64_t, int64_t, int, int64_t, int64_t);
+template int trsm_llu_blk<float>(hipStream_t, float*, int64_t, int64_t, int, int64_t, int64_t);
 template int trsm_llu_leaf<float>(hipStream_t, float*, int64_t, int64_t, int, int64_t, int64_t);
 template int getrf_leaf<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int, int32_t*, int32_t*, double*,
                                 unsigned*, unsigned*, abft_report*, int);
