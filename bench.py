@@ -150,11 +150,36 @@ def fp64_legs(h, torch, dev, args, legs):
         launches = sum(a["tmu_launches"] for a in prof_acc.values())
         achieved = fl / ms / 1e9 if ms > 0 else None
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": None,
+                "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": measured_traffic(),
                 "kernel": "k_dgemm (FP64 trailing-matrix update products)", "launches": launches,
                 "avg_launch_ms": ms / launches if launches else None,
                 "flops_per_launch": fl / launches if launches else None}
     return value, total_ms / args.steps, per_leg, status, roof
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dgemm_tmu_traffic_n32768_nb512.md")
+DGEMM_SRC = os.path.join(ROOT, "paper_2301_03166_amd", "csrc", "dgemm.hip")
+
+
+def measured_traffic():
+    """HBM bytes per trailing-update launch from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the product
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if "=" in line and line.strip().startswith(("source_sha256", "traffic_bytes_per_launch")):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip().strip("`")
+        with open(DGEMM_SRC, "rb") as f:
+            cur = hashlib.sha256(f.read()).hexdigest()
+        if kv.get("source_sha256") != cur:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def mp_leg(h, torch, dev, args):
