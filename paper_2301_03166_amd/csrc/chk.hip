@@ -30,7 +30,7 @@ namespace abft {
 // waves' column partials are merged in a fixed order.  The next strip's
 // loads are in flight while the current one is summed.
 // ---------------------------------------------------------------------------
-constexpr int SCW = 16;          // columns per chunk
+constexpr int SCW = 8;           // columns per chunk
 constexpr int SRL = 64 / SCW;    // lanes summing one column (each takes 64/SRL rows)
 struct StreamLds {
   double blk[4][SCW][65];  // per-wave transpose buffer [column in chunk][row in strip]
@@ -222,7 +222,7 @@ __device__ void tile_sums_stream(const T* A, int64_t lda, int64_t r0, int64_t c0
 // mode 0: encode (write sums); mode 1: verify (flag, refresh clean tiles);
 // mode 2: verify only
 template <typename T>
-__global__ __launch_bounds__(256) void k_verify(const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0,
+__global__ __launch_bounds__(256, 2) void k_verify(const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0,
                                                 int nI, int sym, int mode, double* colchk, int64_t ldc, double* rowchk,
                                                 int64_t ldr, const double* gc, const double* gr, double tsu,
                                                 int* tflags, abft_report* rep, int iter) {
