@@ -528,7 +528,8 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
 // Extra workspace of the mixed-precision solve, after the factorization's.
 struct MpWs {
   void* F;          // factor copy (float, or double for the FP64 reference)
-  int32_t *ipiv, *perm, *info, *ready;
+  int32_t *ipiv, *perm, *info;
+  uint64_t* xw;  // solution words of the triangular solves (2n)
   unsigned* counter;
   double *r, *xd, *part, *norms;
   float* d32;
@@ -549,7 +550,7 @@ MpWs carve_mp(char* base, size_t off, int64_t n, int elem) {
   m.perm = (int32_t*)take((size_t)n * 4);
   m.info = (int32_t*)take(256);
   m.counter = (unsigned*)take(256);
-  m.ready = (int32_t*)take((size_t)(n / 64 + 2) * 4);
+  m.xw = (uint64_t*)take((size_t)n * 16);
   m.r = (double*)take((size_t)n * 8);
   m.xd = (double*)take((size_t)n * 8);
   m.part = (double*)take((size_t)NSPLIT * n * 8);
@@ -567,10 +568,10 @@ int read_norms(hipStream_t s, const double* dn, double* hn, int cnt) {
 // x := M^{-1} P x for the factor of the solve (float or double data)
 template <typename T>
 int solve_factor(hipStream_t s, const T* F, int64_t n, const int* perm, int chol, T* x, const MpWs& m,
-                 abft_report* rep) {
+                 uint32_t& seq, abft_report* rep) {
   (void)perm;
-  TRY(trsv<T>(s, F, n, (int)n, chol ? 2 : 0, x, m.counter, m.ready, rep));
-  return trsv<T>(s, F, n, (int)n, chol ? 3 : 1, x, m.counter, m.ready, rep);
+  TRY(trsv<T>(s, F, n, (int)n, chol ? 2 : 0, x, m.counter, m.xw, ++seq, rep));
+  return trsv<T>(s, F, n, (int)n, chol ? 3 : 1, x, m.counter, m.xw, ++seq, rep);
 }
 
 int gesv_mp_impl(abft_handle h, int64_t n, const double* dA, int64_t lda, const double* db, double* dx, int prec,
@@ -607,6 +608,8 @@ int gesv_mp_impl(abft_handle h, int64_t n, const double* dA, int64_t lda, const 
   }
   const int ni = (int)n;
   double hn[8];
+  uint32_t seq = 0;  // sequence numbers of the triangular solves (their words start cleared)
+  TRY(fill_zero(s, m.xw, (size_t)n * 16));
   // factorization of a working copy
   if (prec == ABFT_F64) {
     if (hipMemcpy2DAsync(m.F, n * 8, dA, lda * 8, n * 8, n, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -636,7 +639,7 @@ int gesv_mp_impl(abft_handle h, int64_t n, const double* dA, int64_t lda, const 
   if (prec == ABFT_F64) {
     // direct FP64 solve (reference method)
     TRY(gather64(s, db, perm, m.xd, ni));
-    TRY(solve_factor<double>(s, (const double*)m.F, n, perm, chol, m.xd, m, drep));
+    TRY(solve_factor<double>(s, (const double*)m.F, n, perm, chol, m.xd, m, seq, drep));
     TRY(copy_f64(s, m.xd, dx, ni));
     TRY(fill_zero(s, m.norms, 32));
     TRY(residual(s, dA, lda, ni, dx, db, m.r, m.part, NSPLIT, m.norms));
@@ -648,7 +651,7 @@ int gesv_mp_impl(abft_handle h, int64_t n, const double* dA, int64_t lda, const 
   }
   // x0 from the low-precision factors
   TRY(gather_scale(s, db, perm, 1.0, m.d32, ni));
-  TRY(solve_factor<float>(s, (const float*)m.F, n, perm, chol, m.d32, m, drep));
+  TRY(solve_factor<float>(s, (const float*)m.F, n, perm, chol, m.d32, m, seq, drep));
   TRY(f32_to_f64(s, m.d32, dx, ni));
   double prev = INFINITY;
   for (int it = 1; it <= max_iter; ++it) {
@@ -662,7 +665,7 @@ int gesv_mp_impl(abft_handle h, int64_t n, const double* dA, int64_t lda, const 
     if (rn <= u * ir.a_norm * xn) { ir.converged = 1; break; }
     const double sc = rn > 0 ? rn : 1.0;
     TRY(gather_scale(s, m.r, perm, 1.0 / sc, m.d32, ni));
-    TRY(solve_factor<float>(s, (const float*)m.F, n, perm, chol, m.d32, m, drep));
+    TRY(solve_factor<float>(s, (const float*)m.F, n, perm, chol, m.d32, m, seq, drep));
     TRY(update_x(s, dx, m.d32, sc, ni, m.norms));
     TRY(read_norms(s, m.norms, hn, 4));
     const double dn = hn[2], xn2 = hn[3];

@@ -85,9 +85,11 @@ int convert_f64_f32(hipStream_t s, const double* A, int64_t lda, float* B, int64
 int perm_vector(hipStream_t s, const int32_t* ipiv, int n, int* perm);
 int gather_scale(hipStream_t s, const double* x, const int* perm, double scale, float* y, int n);
 int gather64(hipStream_t s, const double* x, const int* perm, double* y, int n);
+// solution words xw: 2n 64-bit words, zero before the first call of a
+// sequence; seq > 0 distinct per call
 template <typename T>
-int trsv(hipStream_t s, const T* F, int64_t ld, int n, int kind, T* x, unsigned* counter, int* ready,
-         abft_report* rep);
+int trsv(hipStream_t s, const T* F, int64_t ld, int n, int kind, T* x, unsigned* counter, uint64_t* xw,
+         uint32_t seq, abft_report* rep);
 int residual(hipStream_t s, const double* A, int64_t lda, int n, const double* x, const double* b, double* r,
              double* part, int nsplit, double* norms);
 int update_x(hipStream_t s, double* x, const float* d32, double scale, int n, double* norms);

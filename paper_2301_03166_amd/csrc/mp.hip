@@ -45,14 +45,17 @@ __global__ void k_gather64(const double* x, const int* perm, double* y, int n) {
 // array F): KIND 0 = unit lower (LU's L), 1 = upper (LU's U), 2 = lower
 // (Cholesky L), 3 = upper given as the transpose of the stored lower
 // Cholesky factor.  Workgroups take 64-row blocks in solve order from a
-// counter.  A block first subtracts the products of every earlier block of
-// the solution: its 64 x 64 coefficient blocks do not depend on the solution
-// and are read ahead, and each wave polls the earlier blocks' ready flags
-// itself and consumes every block it finds published in one go (one acquire
-// per group).  One wave then solves the diagonal block with its row of the
-// block in registers: substitution, one lane broadcast per step, the
-// reciprocals of the diagonal formed up front.  The accumulation order is
-// fixed, so results are reproducible.
+// counter.  A solved block is published as self-validating words in xw
+// (each 64-bit word = 32 bits of the value and the call's sequence number
+// seq; one word per binary32 value, two per binary64 value), so a later
+// block polls the very values it needs, with no flag and no fence between
+// writer and reader.  A block first subtracts the products of every earlier
+// block: its 64 x 64 coefficient blocks do not depend on the solution and
+// are read ahead, and each wave takes every earlier block whose first word
+// is already published in one go.  One wave then solves the diagonal block
+// with its row of the block in registers: substitution, one lane broadcast
+// per step, the reciprocals of the diagonal formed up front.  The
+// accumulation order is fixed, so results are reproducible.
 template <typename T>
 __device__ __forceinline__ T fmat(T a, T b, T c);
 template <>
@@ -73,10 +76,40 @@ __device__ __forceinline__ double lane_bcast<double>(double v, int j) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// words per value and the encode / poll of one value
+template <typename T>
+constexpr int xw_words() { return sizeof(T) == 4 ? 1 : 2; }
+__device__ __forceinline__ void xw_put(uint64_t* p, uint32_t payload, uint32_t seq) {
+  __hip_atomic_store(p, ((uint64_t)payload << 32) | seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void xw_store(uint64_t* xw, int64_t i, T v, uint32_t seq) {
+  if (sizeof(T) == 4) {
+    xw_put(xw + i, __float_as_uint((float)v), seq);
+  } else {
+    const uint64_t u = (uint64_t)__double_as_longlong((double)v);
+    xw_put(xw + 2 * i, (uint32_t)(u >> 32), seq);
+    xw_put(xw + 2 * i + 1, (uint32_t)u, seq);
+  }
+}
+__device__ __forceinline__ uint64_t xw_poll(const uint64_t* p, uint32_t seq, long& spins, abft_report* rep) {
+  uint64_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while ((uint32_t)v != seq) {
+    __builtin_amdgcn_s_sleep(1);
+    v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (++spins > (1L << 22)) {
+      if (rep) atomicOr(&rep->status, (int)ABFT_ST_INTERNAL);
+      break;
+    }
+  }
+  return v;
+}
+
 template <typename T, int KIND>
 __global__ __launch_bounds__(256) void k_trsv(const T* __restrict__ F, int64_t ld, int n, T* x, unsigned* counter,
-                                              int* ready, abft_report* rep) {
+                                              uint64_t* xw, uint32_t seq, abft_report* rep) {
   constexpr bool LOWER = KIND == 0 || KIND == 2, TR = KIND == 3;
+  constexpr int WPV = xw_words<T>();
   __shared__ T part[4][TB];
   __shared__ T D[TB][TB + 1];
   __shared__ int s_blk;
@@ -108,26 +141,51 @@ __global__ __launch_bounds__(256) void k_trsv(const T* __restrict__ F, int64_t l
       m[s] = (r < rows && s < cl) ? (TR ? F[col + (r0 + r) * ld] : F[(r0 + r) + col * ld]) : (T)0;
     }
   };
+  long spins = 0;
   T acc = (T)0;
   auto accum = [&](int k, const T(&m)[16]) {
     const int64_t c0 = (int64_t)pred(k) * TB;
     const int cl = (int)min((int64_t)TB, (int64_t)n - c0) - 16 * q;
+    uint64_t wd[16 * WPV];
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+#pragma unroll
+      for (int u = 0; u < WPV; ++u)
+        wd[s * WPV + u] = s < cl ? __hip_atomic_load(xw + WPV * (c0 + 16 * q + s) + u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : (uint64_t)seq;
     T xs[16];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) xs[s] = s < cl ? x[c0 + 16 * q + s] : (T)0;
+    for (int s = 0; s < 16; ++s) {
+      if (s < cl) {
+#pragma unroll
+        for (int u = 0; u < WPV; ++u)
+          if ((uint32_t)wd[s * WPV + u] != seq) wd[s * WPV + u] = xw_poll(xw + WPV * (c0 + 16 * q + s) + u, seq, spins, rep);
+        if (sizeof(T) == 4)
+          xs[s] = (T)__uint_as_float((uint32_t)(wd[s * WPV] >> 32));
+        else
+          xs[s] = (T)__longlong_as_double(
+              (long long)((wd[s * WPV] & 0xffffffff00000000ull) | (wd[s * WPV + WPV - 1] >> 32)));
+      } else {
+        xs[s] = (T)0;
+      }
+    }
 #pragma unroll
     for (int s = 0; s < 16; ++s) acc = fmat(m[s], xs[s], acc);
   };
   T mp[16];
   if (ord > 0) load_m(0, mp);
-  long spins = 0;
   for (int k = 0; k < ord;) {
-    // earlier blocks k, k+1, ... already published (lane l looks at k + l)
+    // earlier blocks k, k+1, ... whose first value is published (lane l looks at k + l)
     int nr;
     for (;;) {
       const int kl = k + r;
       int f = 1;
-      if (kl < ord) f = __hip_atomic_load(&ready[pred(kl)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (kl < ord) {
+        const uint64_t v = __hip_atomic_load(xw + WPV * ((int64_t)pred(kl) * TB), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        f = (uint32_t)v == seq;
+      }
       const unsigned long long waiting = __ballot(f == 0);
       nr = min(waiting ? (int)__builtin_ctzll(waiting) : TB, ord - k);
       if (nr > 0) break;
@@ -138,7 +196,6 @@ __global__ __launch_bounds__(256) void k_trsv(const T* __restrict__ F, int64_t l
         break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     accum(k, mp);
     int kk = k + 1;
     for (; kk + 1 < k + nr; kk += 2) {
@@ -175,9 +232,10 @@ __global__ __launch_bounds__(256) void k_trsv(const T* __restrict__ F, int64_t l
       else if (LOWER ? r > j : r < j) xv = fmat(-dr[j], xj, xv);
     }
   }
-  if (r < rows) x[r0 + r] = xv;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (r == 0) __hip_atomic_store(&ready[b], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (r < rows) {
+    xw_store(xw, r0 + r, xv, seq);
+    x[r0 + r] = xv;
+  }
 }
 
 // residual partials: part[s][i] = sum over column chunk s of A(i, j) x(j)
@@ -312,23 +370,24 @@ int gather64(hipStream_t s, const double* x, const int* perm, double* y, int n) 
   LAUNCH_OK;
 }
 template <typename T>
-int trsv(hipStream_t s, const T* F, int64_t ld, int n, int kind, T* x, unsigned* counter, int* ready,
-         abft_report* rep) {
+int trsv(hipStream_t s, const T* F, int64_t ld, int n, int kind, T* x, unsigned* counter, uint64_t* xw,
+         uint32_t seq, abft_report* rep) {
   if (n <= 0) return 0;
-  if (kind < 0 || kind > 3) return ABFT_ERR_UNSUPPORTED;
+  if (kind < 0 || kind > 3 || seq == 0) return ABFT_ERR_UNSUPPORTED;
   const int nblk = (n + TB - 1) / TB;
   if (fill_zero(s, counter, 4)) return ABFT_ERR_HIP;
-  if (fill_zero(s, ready, (size_t)nblk * sizeof(int))) return ABFT_ERR_HIP;
   switch (kind) {
-    case 0: hipLaunchKernelGGL((k_trsv<T, 0>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, ready, rep); break;
-    case 1: hipLaunchKernelGGL((k_trsv<T, 1>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, ready, rep); break;
-    case 2: hipLaunchKernelGGL((k_trsv<T, 2>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, ready, rep); break;
-    default: hipLaunchKernelGGL((k_trsv<T, 3>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, ready, rep);
+    case 0: hipLaunchKernelGGL((k_trsv<T, 0>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, xw, seq, rep); break;
+    case 1: hipLaunchKernelGGL((k_trsv<T, 1>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, xw, seq, rep); break;
+    case 2: hipLaunchKernelGGL((k_trsv<T, 2>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, xw, seq, rep); break;
+    default: hipLaunchKernelGGL((k_trsv<T, 3>), dim3(nblk), dim3(256), 0, s, F, ld, n, x, counter, xw, seq, rep);
   }
   LAUNCH_OK;
 }
-template int trsv<float>(hipStream_t, const float*, int64_t, int, int, float*, unsigned*, int*, abft_report*);
-template int trsv<double>(hipStream_t, const double*, int64_t, int, int, double*, unsigned*, int*, abft_report*);
+template int trsv<float>(hipStream_t, const float*, int64_t, int, int, float*, unsigned*, uint64_t*, uint32_t,
+                         abft_report*);
+template int trsv<double>(hipStream_t, const double*, int64_t, int, int, double*, unsigned*, uint64_t*, uint32_t,
+                          abft_report*);
 
 int residual(hipStream_t s, const double* A, int64_t lda, int n, const double* x, const double* b, double* r,
              double* part, int nsplit, double* norms) {
