@@ -21,14 +21,14 @@ namespace abft {
 
 // ---------------------------------------------------------------------------
 // Tile sums for the streaming passes (encode / verify).  Every sum is
-// accumulated serially in one lane with compensated arithmetic, so no
-// cross-lane reduction is needed: wave v owns the 64-row strips v and v + 4
-// (tiles have at most 512 rows) and walks the tile in chunks of 32 columns.
-// The lane that loads row i accumulates row i's sums; each 64 x 32 block is
-// then transposed through the wave's LDS buffer so that lane (half, jj) sums
-// rows 32*half .. 32*half + 31 of column jj.  The two halves and the four
-// waves' column partials are merged in a fixed order.  The next strip's
-// loads are in flight while the current one is summed.
+// accumulated serially (compensated for binary64 data) in a fixed order, so
+// the result does not depend on timing: wave v owns the 64-row strips v and
+// v + 4 (tiles have at most 512 rows) and walks the tile in chunks of SCW
+// columns.  The lane that loads row i accumulates row i's sums; each
+// 64 x SCW block is then transposed through the wave's LDS buffer so that
+// lane (part, jj) sums rows 8*part .. 8*part + 7 of column jj.  The parts
+// and the four waves' column partials are merged in a fixed order.  Two
+// chunks of each strip are in flight while the current one is summed.
 // ---------------------------------------------------------------------------
 constexpr int SCW = 8;           // columns per chunk
 constexpr int SRL = 64 / SCW;    // lanes summing one column (each takes 64/SRL rows)
@@ -48,28 +48,20 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// rows 64 s .. 64 s + 63 (this lane: one row), columns c .. c + SCW - 1
+// rows 64 s .. 64 s + 63 (this lane: one row), columns c .. c + SCW - 1.
+// Indices outside the tile are clamped to a valid element and the values
+// stay raw: the masks (tile edge, the symmetric tile's upper triangle) are
+// applied where the values are used, so nothing waits for the loads here.
 template <typename T>
-__device__ __forceinline__ void strip_load(double (&v)[SCW], const T* A, int64_t lda, int64_t r0, int64_t c0, int h,
-                                           int w, bool sym, int s, int c) {
+__device__ __forceinline__ void strip_load(T (&v)[SCW], const T* A, int64_t lda, int64_t r0, int64_t c0, int h,
+                                           int w, int s, int c) {
   const int i = 64 * s + (threadIdx.x & 63);
-  const int ic = i < h ? i : h - 1;  // clamp, then zero: no divergent loads
-  const T* p = A + (r0 + ic) + (c0 + c) * lda;
-  if (c + SCW <= w) {
+  const int ic = i < h ? i : h - 1;
+  const T* base = A + r0 + c0 * lda;  // the column addresses are uniform, the row a lane offset
 #pragma unroll
-    for (int t = 0; t < SCW; ++t) v[t] = (double)p[t * lda];
-  } else {
-#pragma unroll
-    for (int t = 0; t < SCW; ++t) v[t] = (c + t < w) ? (double)p[t * lda] : 0.0;
-  }
-  if (i >= h) {
-#pragma unroll
-    for (int t = 0; t < SCW; ++t) v[t] = 0.0;
-  }
-  if (sym) {  // diagonal tile of a symmetric matrix: its stored lower triangle only
-#pragma unroll
-    for (int t = 0; t < SCW; ++t)
-      if (i < c + t) v[t] = 0.0;
+  for (int t = 0; t < SCW; ++t) {
+    const int cc = c + t < w ? c + t : w - 1;
+    v[t] = base[(int64_t)cc * lda + ic];
   }
 }
 
@@ -94,13 +86,16 @@ __device__ __forceinline__ void fma_e(acc2& a, double w, double x) {
   if (EXACT) cfma(a, w, x); else a.s = __fma_rn(w, x, a.s);
 }
 
-template <bool EXACT>
-__device__ __forceinline__ void strip_sum(const double (&v)[SCW], int s, int c, StripAcc& r, ColAcc& col,
-                                          double (*blk)[65]) {
+template <bool EXACT, typename T>
+__device__ __forceinline__ void strip_sum(const T (&v)[SCW], int s, int c, int h, int w, bool sym, StripAcc& r,
+                                          ColAcc& col, double (*blk)[65]) {
   const int lane = threadIdx.x & 63, part = lane / SCW, jj = lane % SCW;
+  const int i = 64 * s + lane;
 #pragma unroll
   for (int t = 0; t < SCW; ++t) {
-    const double wj = (double)(c + t + 1), x = v[t], ax = fabs(x);
+    // outside the tile, or above the diagonal of a symmetric tile: zero
+    const bool in = i < h && c + t < w && !(sym && i < c + t);
+    const double wj = (double)(c + t + 1), x = in ? (double)v[t] : 0.0, ax = fabs(x);
     add_e<EXACT>(r.re, x);
     fma_e<EXACT>(r.rw, wj, x);
     r.ra += ax;
@@ -132,20 +127,23 @@ __device__ void tile_sums_stream(const T* A, int64_t lda, int64_t r0, int64_t c0
   const int s0 = wv, s1 = wv + 4;
   const bool has0 = s0 < nstrip, has1 = s1 < nstrip;
   StripAcc r0a{{0, 0}, {0, 0}, 0, 0}, r1a{{0, 0}, {0, 0}, 0, 0};
-  double v0[SCW], v1[SCW];
-  if (has0) strip_load(v0, A, lda, r0, c0, h, w, sym, s0, 0);
-  if (has1) strip_load(v1, A, lda, r0, c0, h, w, sym, s1, 0);
-  for (int c = 0; c < w; c += SCW) {
+  // two chunks of each strip in flight: chunk c is summed while chunk c + SCW
+  // is still arriving, and chunk c + 2 SCW is requested into c's registers.
+  // Every load is unconditional (indices clamped, values masked where used),
+  // so the loads are issued in the same order on every path and the waits
+  // before each use let the younger chunks stay in flight.
+  T v0[SCW], v1[SCW], u0[SCW], u1[SCW];
+  strip_load(v0, A, lda, r0, c0, h, w, s0, 0);
+  strip_load(v1, A, lda, r0, c0, h, w, s1, 0);
+  strip_load(u0, A, lda, r0, c0, h, w, s0, SCW);
+  strip_load(u1, A, lda, r0, c0, h, w, s1, SCW);
+  auto chunk = [&](int c, T (&x0)[SCW], T (&x1)[SCW]) {
     ColAcc col{{0, 0}, {0, 0}, 0, 0};
-    const int cn = c + SCW;
-    if (has0) {
-      strip_sum<sizeof(T) == 8>(v0, s0, c, r0a, col, L.blk[wv]);
-      if (cn < w) strip_load(v0, A, lda, r0, c0, h, w, sym, s0, cn);
-    }
-    if (has1) {
-      strip_sum<sizeof(T) == 8>(v1, s1, c, r1a, col, L.blk[wv]);
-      if (cn < w) strip_load(v1, A, lda, r0, c0, h, w, sym, s1, cn);
-    }
+    const int cn = c + 2 * SCW;
+    if (has0) strip_sum<sizeof(T) == 8>(x0, s0, c, h, w, sym, r0a, col, L.blk[wv]);
+    strip_load(x0, A, lda, r0, c0, h, w, s0, cn);
+    if (has1) strip_sum<sizeof(T) == 8>(x1, s1, c, h, w, sym, r1a, col, L.blk[wv]);
+    strip_load(x1, A, lda, r0, c0, h, w, s1, cn);
     // merge the SRL row parts of each column (lanes jj, jj+SCW, ...), fixed order
 #pragma unroll
     for (int m = SCW; m < 64; m <<= 1) {
@@ -188,6 +186,10 @@ __device__ void tile_sums_stream(const T* A, int64_t lda, int64_t r0, int64_t c0
       ts.cwa[c + t] = wa;
     }
     __syncthreads();
+  };
+  for (int c = 0; c < w; c += 2 * SCW) {
+    chunk(c, v0, v1);
+    chunk(c + SCW, u0, u1);  // (entirely masked when c + SCW >= w)
   }
   const int i0 = 64 * s0 + lane, i1 = 64 * s1 + lane;
   if (has0 && i0 < h) {
