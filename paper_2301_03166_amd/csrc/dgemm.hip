@@ -20,8 +20,9 @@
 // diagonal are enumerated, column by column, so the chunks carry equal work.
 //
 // Operand options: op(A) = A or A^T, op(B) = B or B^T, a unit-lower mask on
-// the stored A (Householder vectors with their implicit unit diagonal), and a
-// lower-triangular write mask on C.
+// the stored A (Householder vectors with their implicit unit diagonal),
+// magnitudes |op(A)| / |op(B)| (the checksum carries' threshold products),
+// and a lower-triangular write mask on C.
 #include <cstdlib>
 
 #include "common.hpp"
@@ -109,18 +110,24 @@ __device__ __forceinline__ void stage_load(Stage<BK, ALONG_R>& st, const double*
   }
 }
 
-// LDS image of a tile (layout lidx): element (p, i), p in [0, BK), i in [0, R)
-template <int BK, bool ALONG_R>
+// LDS image of a tile (layout lidx): element (p, i), p in [0, BK), i in [0, R);
+// ABS stores magnitudes (|.| products for checksum thresholds)
+template <int BK, bool ALONG_R, bool ABS>
 __device__ __forceinline__ void stage_store(const Stage<BK, ALONG_R>& st, double* S) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int s = 0; s < BK / 4; ++s) {
     const int v = tid + 256 * s;
+    f64x2 x = st.v[s];
+    if (ABS) {
+      x[0] = fabs(x[0]);
+      x[1] = fabs(x[1]);
+    }
     if (ALONG_R) {
-      *reinterpret_cast<f64x2*>(&S[lidx<BK, true>(v >> 6, 2 * (v & 63))]) = st.v[s];
+      *reinterpret_cast<f64x2*>(&S[lidx<BK, true>(v >> 6, 2 * (v & 63))]) = x;
     } else {
       const int p = 2 * (v & (BK / 2 - 1)), i = v / (BK / 2);
-      *reinterpret_cast<f64x2*>(&S[lidx<BK, false>(p, i)]) = st.v[s];
+      *reinterpret_cast<f64x2*>(&S[lidx<BK, false>(p, i)]) = x;
     }
   }
 }
@@ -140,9 +147,11 @@ __device__ __forceinline__ void lower_tile(int lin, int T, int& tm, int& tn) {
 
 }  // namespace
 
-// TRI: the grid enumerates only the lower tiles of a square T x T grid
-// (requires LOWER, M == N, doff == 0).  ROLE only separates the launches of
-// the trailing-matrix update (1) from the other products (0) in profiles.
+// FA: operand modes, bit 0 the unit-lower mask on the stored A, bit 1 |op(A)|,
+// bit 2 |op(B)| (magnitude products).  TRI: the grid enumerates only the
+// lower tiles of a square T x T grid (requires LOWER, M == N, doff == 0).
+// ROLE only separates the launches of the trailing-matrix update (1) from
+// the other products (0) in profiles.
 template <int TA, int TB, int FA, int LOWER, int TRI, int ROLE, int BK>
 __global__ __launch_bounds__(256, BK == 16 ? 2 : 1) void k_dgemm(int M, int N, int K, double alpha,
                                                                  const double* __restrict__ A, int64_t lda,
@@ -188,21 +197,21 @@ __global__ __launch_bounds__(256, BK == 16 ? 2 : 1) void k_dgemm(int M, int N, i
   auto load = [&](int k0) {
     const bool full = inner && (k0 + BK <= kend);
     const bool needmask =
-        FA == 1 && (TA == 0 ? (m0 < k0 + BK) : (k0 < m0 + BM));  // some stored row <= stored column
+        (FA & 1) && (TA == 0 ? (m0 < k0 + BK) : (k0 < m0 + BM));  // some stored row <= stored column
     if (full) {
-      if (FA == 1 && needmask)
+      if ((FA & 1) && needmask)
         stage_load<BK, TA == 0, true, true>(sa, A, lda, m0, M, k0, kend);
       else
         stage_load<BK, TA == 0, true, false>(sa, A, lda, m0, M, k0, kend);
       stage_load<BK, TB == 1, true, false>(sb, B, ldb, n0, N, k0, kend);
     } else {
-      stage_load<BK, TA == 0, false, FA == 1>(sa, A, lda, m0, M, k0, kend);
+      stage_load<BK, TA == 0, false, (FA & 1) != 0>(sa, A, lda, m0, M, k0, kend);
       stage_load<BK, TB == 1, false, false>(sb, B, ldb, n0, N, k0, kend);
     }
   };
   auto store = [&](int buf) {
-    stage_store<BK, TA == 0>(sa, As[buf]);
-    stage_store<BK, TB == 1>(sb, Bs[buf]);
+    stage_store<BK, TA == 0, (FA & 2) != 0>(sa, As[buf]);
+    stage_store<BK, TB == 1, (FA & 4) != 0>(sb, Bs[buf]);
   };
 
   f64x4 acc[4][4];
@@ -305,9 +314,12 @@ static int dgemm_bk() {
 
 // Returns 1 when the product was launched here, 0 when the caller should use
 // the general kernel (unsupported option combination or alignment), <0 on error.
-int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, int k, double alpha, const double* A,
-               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int S,
-               int kc, double* ws, int role) {
+// fa: 0 plain, 1 unit-lower A, 2 |A|, 3 |unit-lower A|; fb: 0 plain, 2 |B|.
+int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int n, int k, double alpha,
+               const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+               int64_t doff, int S, int kc, double* ws, int role) {
+  if (fa < 0 || fa > 3 || (fb != 0 && fb != 2)) return 0;
+  const int modes = fa | (fb == 2 ? 4 : 0);
   if ((reinterpret_cast<uintptr_t>(A) & 15) || (reinterpret_cast<uintptr_t>(B) & 15) || (lda & 1) || (ldb & 1))
     return 0;
   const int64_t tM = (m + DG_BM - 1) / DG_BM, tN = (n + DG_BN - 1) / DG_BN;
@@ -326,7 +338,7 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, i
                          ldb, beta, C, ldc, doff, kc, ws);                                                         \
   } while (0)
 #define DG_CASE(TA_, TB_, FA_, LO_)                                                                              \
-  if (ta == TA_ && tb == TB_ && fa == FA_ && lower == LO_) {                                                       \
+  if (ta == TA_ && tb == TB_ && modes == FA_ && lower == LO_) {                                                    \
     if (LO_ && tri) {                                                                                              \
       if (role) DG_LAUNCH(TA_, TB_, FA_, LO_, LO_, 1); else DG_LAUNCH(TA_, TB_, FA_, LO_, LO_, 0);                 \
     } else {                                                                                                       \
@@ -339,6 +351,11 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, i
   DG_CASE(0, 1, 0, 0)  // X Y^T
   DG_CASE(1, 0, 1, 0)  // W = V^T C (QR)
   DG_CASE(0, 0, 1, 0)  // C -= V W (QR)
+  DG_CASE(0, 0, 4, 0)  // magnitude products of the checksum carries: S |Y|
+  DG_CASE(0, 1, 4, 0)  //   S |Y^T| (symmetric update)
+  DG_CASE(0, 0, 2, 0)  //   |X| T
+  DG_CASE(0, 1, 2, 0)  //   |X| S^T (symmetric update)
+  DG_CASE(0, 0, 3, 0)  //   |V| T (unit-lower V)
 #undef DG_CASE
 #undef DG_LAUNCH
   return 0;

@@ -54,7 +54,9 @@ constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
   } while (0)
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
-constexpr size_t SPLITK_ELEMS = (size_t)1 << 22;  // split-K partials (32 MB)
+// split-K partials (128 MB): a split fills about 512 workgroups of 128 x 128
+// tiles, so S m n stays near 512 * 128^2 whatever the shape
+constexpr size_t SPLITK_ELEMS = (size_t)1 << 24;
 // cooperative-leaf exchange records (SLOT_WORDS 8-byte words), two columns
 // alternating: per column 4G (3 + 2w) + 2w words (LU) or G 2w + 2w (QR);
 // G <= 256, w <= 64

@@ -26,9 +26,9 @@ int splitk_reduce(hipStream_t s, const double* P, int S, int m, int n, double be
 // bf16 / fp16 MFMA with FP32 accumulation (ABFT_BF16 / ABFT_F16).
 // FP64 MFMA GEMM for the large plain products (aligned operands); returns 1
 // if launched, 0 if the option combination is not covered, <0 on error
-int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int lower, int m, int n, int k, double alpha, const double* A,
-               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t doff, int S,
-               int kc, double* ws, int role);
+int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int n, int k, double alpha,
+               const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+               int64_t doff, int S, int kc, double* ws, int role);
 int gemm32(hipStream_t s, int prec, int ta, int tb, int lower, int m, int n, int k, float alpha, const float* A,
            int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, int64_t doff);
 
