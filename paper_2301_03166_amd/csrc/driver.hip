@@ -247,12 +247,17 @@ int chol_panel(hipStream_t s, T* A, int64_t lda, int64_t n, int64_t c0, int64_t 
 
 // X = L^{-1} B: L unit lower at (c0, c0) of order w, B = rows [c0, c0+w) of
 // columns [j0, j1).  One blocked launch (strips of B in LDS) up to the
-// largest block size; recursive halves with a product in between beyond it.
+// largest block size for few columns; recursive halves with a product in
+// between beyond it, and for many columns down to TRSM_REC_W rows (each
+// strip's substitution is a chain of w/32 dependent block steps, while the
+// products in between run at MFMA rate over all columns at once).
+constexpr int TRSM_REC_W = 256;
+constexpr int64_t TRSM_REC_COLS = 4096;
 template <typename T>
 int trsm_llu(hipStream_t s, T* A, int64_t lda, int64_t c0, int w, int64_t j0, int64_t j1) {
   if (j1 <= j0) return 0;
   if (w <= LEAFW) return trsm_llu_leaf(s, A, lda, c0, w, j0, j1);
-  if (w <= 512) return trsm_llu_blk(s, A, lda, c0, w, j0, j1);
+  if (w <= 512 && (w <= TRSM_REC_W || j1 - j0 < TRSM_REC_COLS)) return trsm_llu_blk(s, A, lda, c0, w, j0, j1);
   const int h = split(w);
   TRY(trsm_llu(s, A, lda, c0, h, j0, j1));
   TRY(gemmT(s, panel_prec<T>(), 0, 0, 0, w - h, (int)(j1 - j0), h, -1.0, A + (c0 + h) + c0 * lda, lda,
