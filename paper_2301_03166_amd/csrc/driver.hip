@@ -54,9 +54,13 @@ constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
   } while (0)
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
-// split-K partials (128 MB): a split fills about 512 workgroups of 128 x 128
-// tiles, so S m n stays near 512 * 128^2 whatever the shape
-constexpr size_t SPLITK_ELEMS = (size_t)1 << 24;
+// split-K partials: at least 128 MB (a split that fills about 512
+// workgroups of 128 x 128 tiles keeps S m n near 512 * 128^2), and room for
+// four partial copies of QR's nb x n product W = V^T C (its split evens out
+// the last round of workgroups)
+inline size_t splitk_elems(int64_t n, int nb) {
+  return std::max<size_t>((size_t)1 << 24, (size_t)4 * nb * n);
+}
 // cooperative-leaf exchange records (SLOT_WORDS 8-byte words), two columns
 // alternating: per column 4G (3 + 2w) + 2w words (LU) or G 2w + 2w (QR);
 // G <= 256, w <= 64
@@ -120,6 +124,7 @@ struct Ws {
   double *colchk, *rowchk, *gc, *gr, *S, *Sa, *Tm, *Ta;
   double *Tfac, *W, *W2, *Wp, *Wp2, *Xq, *Yq, *Z, *Zabs, *E, *bt, *scr;
   double *porig, *stage, *slots, *splitk;
+  size_t splitk_n;  // elements of splitk
   int *tflags, *moves;
   unsigned* ctr;
   size_t bytes;
@@ -153,7 +158,8 @@ Ws carve(char* base, int64_t n, int nb, int op, int elem) {
     w.moves = (int*)take((size_t)(4 * nb + 4) * sizeof(int));
   }
   if (op == ABFT_OP_GEQRF) {
-    w.splitk = (double*)take((size_t)SPLITK_ELEMS * sizeof(double));
+    w.splitk_n = splitk_elems(n, nb);
+    w.splitk = (double*)take(w.splitk_n * sizeof(double));
     w.Tfac = (double*)take((size_t)nb * nb * sizeof(double));
     w.W = (double*)take((size_t)nb * n * sizeof(double));
     w.W2 = (double*)take((size_t)nb * n * sizeof(double));
@@ -332,7 +338,7 @@ int qr_panel(QrCtx& c, int64_t c0, int64_t c1) {
   double* T1 = c.w->Tfac + toff + (int64_t)toff * nb;
   // apply H1^T = I - V1 T1^T V1^T to the right half
   TRY(gemm64(c.s, 1, 0, 1, 0, 0, h, (int)(c1 - r), (int)(n - c0), 1.0, V1, lda, A + c0 + r * lda, lda, 0.0, c.w->Wp,
-             nb, 0, 0, 0, 0, c.w->splitk, SPLITK_ELEMS));
+             nb, 0, 0, 0, 0, c.w->splitk, c.w->splitk_n));
   TRY(gemm64(c.s, 1, 0, 0, 0, 0, h, (int)(c1 - r), h, 1.0, T1, nb, c.w->Wp, nb, 0.0, c.w->Wp2, nb, 0));
   TRY(gemm64(c.s, 0, 0, 1, 0, 0, (int)(n - c0), (int)(c1 - r), h, -1.0, V1, lda, c.w->Wp2, nb, 1.0, A + c0 + r * lda,
              lda, 0));
@@ -340,7 +346,7 @@ int qr_panel(QrCtx& c, int64_t c0, int64_t c1) {
   // T12 = -T1 (V1^T V2) T2 ; rows of V2 above r are zero
   double* T2 = c.w->Tfac + (toff + h) + (int64_t)(toff + h) * nb;
   TRY(gemm64(c.s, 1, 0, 0, 1, 0, h, w - h, (int)(n - r), 1.0, A + r + c0 * lda, lda, A + r + r * lda, lda, 0.0,
-             c.w->Xq, nb, 0, 0, 0, 0, c.w->splitk, SPLITK_ELEMS));
+             c.w->Xq, nb, 0, 0, 0, 0, c.w->splitk, c.w->splitk_n));
   TRY(gemm64(c.s, 0, 0, 0, 0, 0, h, w - h, h, 1.0, T1, nb, c.w->Xq, nb, 0.0, c.w->Yq, nb, 0));
   return gemm64(c.s, 0, 0, 0, 0, 0, h, w - h, w - h, -1.0, c.w->Yq, nb, T2, nb, 0.0,
                 c.w->Tfac + toff + (int64_t)(toff + h) * nb, nb, 0);
@@ -841,7 +847,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     int S = 0;
     t = pf.begin(PH_TMU);
     TRY(gemm64(s, 1, 0, 1, 0, 0, kw, (int)m, (int)(n - c0), 1.0, V, lda, C, lda, 0.0, w.W, nb, 0, 0, 0, 0, w.splitk,
-               SPLITK_ELEMS, 1, &S));
+               w.splitk_n, 1, &S));
     pf.end(t);
     if (S > 1) TRY(splitk_reduce(s, w.splitk, S, kw, (int)m, 0.0, w.W, nb));
     TRY(gemm64(s, 1, 0, 0, 0, 0, kw, (int)m, kw, 1.0, w.Tfac, nb, w.W, nb, 0.0, w.W2, nb, 0));

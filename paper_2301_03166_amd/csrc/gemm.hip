@@ -223,16 +223,29 @@ int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int 
   // (a trailing-update launch splits only when its caller reduces the
   // partials itself, so that the launch stays one kernel)
   if (split_out) *split_out = 0;
-  if (ws && !lower && (!role || split_out) && grid < 512 && k >= 1024) {
-    int64_t want = std::min<int64_t>(64, std::min<int64_t>((512 + grid - 1) / grid, k / 128));
-    want = std::min<int64_t>(want, (int64_t)(ws_elems / ((size_t)m * n)));
-    if (want >= 2) {
-      int64_t kcl = ((k + want - 1) / want + 31) / 32 * 32;
-      int64_t sp = (k + kcl - 1) / kcl;
-      if (sp >= 2 && (size_t)sp * m * n <= ws_elems) {
-        S = (unsigned)sp;
-        kc = (int)kcl;
+  const int64_t slots = 512;  // resident product workgroups: two per CU
+  int64_t want = 1;
+  if (ws && !lower && (!role || split_out) && grid < slots && k >= 1024) {
+    want = std::min<int64_t>(64, std::min<int64_t>((slots + grid - 1) / grid, k / 128));
+  } else if (ws && !lower && split_out && grid % slots != 0 && k >= 2048) {
+    // several rounds of long-K tiles with a partial last round: the split
+    // (2..4) with the least time in rounds per unit of K
+    double best = (double)((grid + slots - 1) / slots);
+    for (int64_t sp = 2; sp <= 4 && k / sp >= 512; ++sp) {
+      const double cost = (double)((grid * sp + slots - 1) / slots) / (double)sp;
+      if (cost < 0.95 * best) {
+        best = cost;
+        want = sp;
       }
+    }
+  }
+  want = std::min<int64_t>(want, (int64_t)(ws_elems / ((size_t)m * n)));
+  if (want >= 2) {
+    int64_t kcl = ((k + want - 1) / want + 31) / 32 * 32;
+    int64_t sp = (k + kcl - 1) / kcl;
+    if (sp >= 2 && (size_t)sp * m * n <= ws_elems) {
+      S = (unsigned)sp;
+      kc = (int)kcl;
     }
   }
   if (atype == 0 && btype == 0 && (fb == 0 || fb == 2) && rnd == 0) {
