@@ -148,7 +148,8 @@ __device__ __forceinline__ void lower_tile(int lin, int T, int& tm, int& tn) {
 }  // namespace
 
 // FA: operand modes, bit 0 the unit-lower mask on the stored A, bit 1 |op(A)|,
-// bit 2 |op(B)| (magnitude products).  TRI: the grid enumerates only the
+// bit 2 |op(B)| (magnitude products), bit 3 the unit-lower mask on the
+// stored B.  TRI: the grid enumerates only the
 // lower tiles of a square T x T grid (requires LOWER, M == N, doff == 0).
 // ROLE only separates the launches of the trailing-matrix update (1) from
 // the other products (0) in profiles.
@@ -198,15 +199,20 @@ __global__ __launch_bounds__(256, BK == 16 ? 2 : 1) void k_dgemm(int M, int N, i
     const bool full = inner && (k0 + BK <= kend);
     const bool needmask =
         (FA & 1) && (TA == 0 ? (m0 < k0 + BK) : (k0 < m0 + BM));  // some stored row <= stored column
+    const bool needmask_b =
+        (FA & 8) && (TB == 0 ? (k0 < n0 + BN) : (n0 < k0 + BK));  // (same test on the stored B)
     if (full) {
       if ((FA & 1) && needmask)
         stage_load<BK, TA == 0, true, true>(sa, A, lda, m0, M, k0, kend);
       else
         stage_load<BK, TA == 0, true, false>(sa, A, lda, m0, M, k0, kend);
-      stage_load<BK, TB == 1, true, false>(sb, B, ldb, n0, N, k0, kend);
+      if ((FA & 8) && needmask_b)
+        stage_load<BK, TB == 1, true, true>(sb, B, ldb, n0, N, k0, kend);
+      else
+        stage_load<BK, TB == 1, true, false>(sb, B, ldb, n0, N, k0, kend);
     } else {
       stage_load<BK, TA == 0, false, (FA & 1) != 0>(sa, A, lda, m0, M, k0, kend);
-      stage_load<BK, TB == 1, false, false>(sb, B, ldb, n0, N, k0, kend);
+      stage_load<BK, TB == 1, false, (FA & 8) != 0>(sb, B, ldb, n0, N, k0, kend);
     }
   };
   auto store = [&](int buf) {
@@ -314,12 +320,13 @@ static int dgemm_bk() {
 
 // Returns 1 when the product was launched here, 0 when the caller should use
 // the general kernel (unsupported option combination or alignment), <0 on error.
-// fa: 0 plain, 1 unit-lower A, 2 |A|, 3 |unit-lower A|; fb: 0 plain, 2 |B|.
+// fa: 0 plain, 1 unit-lower A, 2 |A|, 3 |unit-lower A|; fb: 0 plain, 1
+// unit-lower B, 2 |B|.
 int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int n, int k, double alpha,
                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                int64_t doff, int S, int kc, double* ws, int role) {
-  if (fa < 0 || fa > 3 || (fb != 0 && fb != 2)) return 0;
-  const int modes = fa | (fb == 2 ? 4 : 0);
+  if (fa < 0 || fa > 3 || fb < 0 || fb > 2) return 0;
+  const int modes = fa | (fb == 2 ? 4 : 0) | (fb == 1 ? 8 : 0);
   if ((reinterpret_cast<uintptr_t>(A) & 15) || (reinterpret_cast<uintptr_t>(B) & 15) || (lda & 1) || (ldb & 1))
     return 0;
   const int64_t tM = (m + DG_BM - 1) / DG_BM, tN = (n + DG_BN - 1) / DG_BN;
@@ -356,6 +363,8 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, 
   DG_CASE(0, 0, 2, 0)  //   |X| T
   DG_CASE(0, 1, 2, 0)  //   |X| S^T (symmetric update)
   DG_CASE(0, 0, 3, 0)  //   |V| T (unit-lower V)
+  DG_CASE(1, 0, 0, 0)  // T^T W (QR)
+  DG_CASE(1, 0, 8, 0)  // V1^T V2, V2 unit lower (QR T merge)
 #undef DG_CASE
 #undef DG_LAUNCH
   return 0;

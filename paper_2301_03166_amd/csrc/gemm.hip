@@ -248,7 +248,7 @@ int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int 
       kc = (int)kcl;
     }
   }
-  if (atype == 0 && btype == 0 && (fb == 0 || fb == 2) && rnd == 0) {
+  if (atype == 0 && btype == 0 && rnd == 0) {
     const int r = dgemm_fast(s, ta, tb, fa, fb, lower, m, n, k, alpha, (const double*)A, lda, (const double*)B, ldb,
                              beta, C, ldc, doff, (int)S, kc, ws, role);
     if (r < 0) return r;
