@@ -532,45 +532,63 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
   }
 }
 
-// QR panel check helpers: Z = T (V1^T R), Zabs = |T| (|V1|^T |R|) for the
-// w x w diagonal block at (c0, c0); E[4j..] = e/w sums of R(:,j) and their
-// magnitudes; bt[j] = sqrt(m) ||R(:, j)||.
-__global__ void k_qr_check_prep(const double* A, int64_t lda, int64_t c0, int w, int64_t m, const double* T, int ldt,
-                                double* Y, double* Ya, double* Z, double* Zabs, double* E, double* bt) {
-  const int j = blockIdx.x;
+// QR panel check inputs, w = panel width, R = the factored panel's top w x w
+// block (V below its diagonal, R on and above), T the panel's triangular
+// factor:
+//   Y = V^T R (V unit lower, R upper), Ya = |V|^T |R|, Z = T Y, Zabs = |T| Ya,
+//   E(:, j) = plain / weighted sums and magnitudes of R(0..j, j), and
+//   bt(j) = sqrt(m) ||R(0..j, j)||_2.
+// The products run on the MFMA product kernel from masked copies of the
+// three triangles; the column sums take one wave per column (each lane sums
+// rows lane, lane + 64, ... compensated, merged in a fixed order).
+__global__ void k_qr_prep_mask(const double* A, int64_t lda, int64_t c0, int w, const double* T, int ldt, double* Vm,
+                               double* Rm, double* Tm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)w * w) return;
+  const int i = (int)(e % w), j = (int)(e / w);
+  const double x = A[(c0 + i) + (c0 + j) * lda];
+  Vm[e] = i > j ? x : (i == j ? 1.0 : 0.0);
+  Rm[e] = i <= j ? x : 0.0;
+  Tm[e] = i <= j ? T[i + (int64_t)j * ldt] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_qr_prep_sums(const double* A, int64_t lda, int64_t c0, int w, int64_t m,
+                                                      double* E, double* bt) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= w) return;  // (whole waves)
   const double* R = A + c0 + c0 * lda;
-  for (int p = threadIdx.x; p < w; p += blockDim.x) {
-    double s = 0, sa = 0;
-    for (int i = p; i <= j; ++i) {
-      double v = (i == p) ? 1.0 : R[i + p * lda];
-      double r = R[i + j * lda];
-      s += v * r;
-      sa += fabs(v) * fabs(r);
-    }
-    Y[p + j * w] = s;
-    Ya[p + j * w] = sa;
+  acc2 e{0, 0}, ww{0, 0};
+  double a = 0, wa = 0, n2 = 0;
+  for (int i = lane; i <= j; i += 64) {
+    const double r = R[i + (int64_t)j * lda], wi = (double)(i + 1);
+    cadd(e, r);
+    cfma(ww, wi, r);
+    a += fabs(r);
+    wa += wi * fabs(r);
+    n2 += r * r;
   }
-  __syncthreads();
-  for (int p = threadIdx.x; p < w; p += blockDim.x) {
-    double s = 0, sa = 0;
-    for (int q = p; q < w; ++q) {
-      s += T[p + q * ldt] * Y[q + j * w];
-      sa += fabs(T[p + q * ldt]) * Ya[q + j * w];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const acc2 oe = shfl_acc(e, o), ow = shfl_acc(ww, o);
+    const double oa = __shfl_xor(a, o), owa = __shfl_xor(wa, o), on2 = __shfl_xor(n2, o);
+    if (lane & o) {  // both lanes of a pair add the lower lane's partial first
+      acc2 te = oe, tw = ow;
+      cmerge(te, e);
+      cmerge(tw, ww);
+      e = te;
+      ww = tw;
+      a = oa + a;
+      wa = owa + wa;
+      n2 = on2 + n2;
+    } else {
+      cmerge(e, oe);
+      cmerge(ww, ow);
+      a += oa;
+      wa += owa;
+      n2 += on2;
     }
-    Z[p + j * w] = s;
-    Zabs[p + j * w] = sa;
   }
-  if (threadIdx.x == 0) {
-    acc2 e{0, 0}, ww{0, 0};
-    double a = 0, wa = 0, n2 = 0;
-    for (int i = 0; i <= j; ++i) {
-      double r = R[i + j * lda];
-      cadd(e, r);
-      cfma(ww, (double)(i + 1), r);
-      a += fabs(r);
-      wa += (double)(i + 1) * fabs(r);
-      n2 += r * r;
-    }
+  if (lane == 0) {
     E[4 * j + 0] = cval(e);
     E[4 * j + 1] = cval(ww);
     E[4 * j + 2] = a;
@@ -697,10 +715,21 @@ template int panel_check<float>(hipStream_t, const double*, const double*, int, 
                                 int64_t, int, int, double, const double*, const double*, const double*, int,
                                 const double*, int64_t, int64_t, int, double, abft_report*, int, int);
 
+// scratch: 5 w^2 doubles (Y, Ya and the three masked triangles)
 int qr_check_prep(hipStream_t s, const double* A, int64_t lda, int64_t c0, int w, int64_t m, const double* T, int ldt,
                   double* scratch, double* Z, double* Zabs, double* E, double* bt) {
-  hipLaunchKernelGGL(k_qr_check_prep, dim3(w), dim3(256), 0, s, A, lda, c0, w, m, T, ldt, scratch,
-                     scratch + (size_t)w * w, Z, Zabs, E, bt);
+  if (w <= 0) return 0;
+  const size_t ww = (size_t)w * w;
+  double *Y = scratch, *Ya = scratch + ww, *Vm = scratch + 2 * ww, *Rm = scratch + 3 * ww, *Tm = scratch + 4 * ww;
+  hipLaunchKernelGGL(k_qr_prep_mask, dim3((unsigned)((ww + 255) / 256)), dim3(256), 0, s, A, lda, c0, w, T, ldt, Vm,
+                     Rm, Tm);
+  if (hipGetLastError() != hipSuccess) return ABFT_ERR_HIP;
+  int rc = gemm64(s, 1, 0, 0, 0, 0, w, w, w, 1.0, Vm, w, Rm, w, 0.0, Y, w, 0);
+  if (!rc) rc = gemm64(s, 1, 0, 2, 2, 0, w, w, w, 1.0, Vm, w, Rm, w, 0.0, Ya, w, 0);
+  if (!rc) rc = gemm64(s, 0, 0, 0, 0, 0, w, w, w, 1.0, Tm, w, Y, w, 0.0, Z, w, 0);
+  if (!rc) rc = gemm64(s, 0, 0, 2, 0, 0, w, w, w, 1.0, Tm, w, Ya, w, 0.0, Zabs, w, 0);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_qr_prep_sums, dim3((unsigned)((w + 3) / 4)), dim3(256), 0, s, A, lda, c0, w, m, E, bt);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 

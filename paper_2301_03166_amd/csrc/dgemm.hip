@@ -365,6 +365,7 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, 
   DG_CASE(0, 0, 3, 0)  //   |V| T (unit-lower V)
   DG_CASE(1, 0, 0, 0)  // T^T W (QR)
   DG_CASE(1, 0, 8, 0)  // V1^T V2, V2 unit lower (QR T merge)
+  DG_CASE(1, 0, 6, 0)  // |V|^T |R| (QR panel check)
 #undef DG_CASE
 #undef DG_LAUNCH
   return 0;

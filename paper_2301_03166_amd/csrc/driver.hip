@@ -169,7 +169,7 @@ Ws carve(char* base, int64_t n, int nb, int op, int elem) {
     w.Yq = (double*)take((size_t)nb * nb * sizeof(double));
     w.Z = (double*)take((size_t)nb * nb * sizeof(double));
     w.Zabs = (double*)take((size_t)nb * nb * sizeof(double));
-    w.scr = (double*)take((size_t)2 * nb * nb * sizeof(double));
+    w.scr = (double*)take((size_t)5 * nb * nb * sizeof(double));
     w.E = (double*)take((size_t)4 * nb * sizeof(double));
     w.bt = (double*)take((size_t)nb * sizeof(double));
   }

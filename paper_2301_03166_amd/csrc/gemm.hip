@@ -276,6 +276,7 @@ int gemm64(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, int 
     GEMM_CASE(double, double, 0, 0, 2, 0, 0, 0)  // |X| * Ta
     GEMM_CASE(double, double, 0, 1, 2, 0, 0, 0)  // |X| * Sa^T
     GEMM_CASE(double, double, 0, 0, 3, 0, 0, 0)  // |V| * Ta (unit-lower V)
+    GEMM_CASE(double, double, 1, 0, 2, 2, 0, 0)  // |V|^T |R| (QR panel check, odd widths)
   }
   if (atype == 0 && btype == 1) {  // double S times binary32 Y (mixed-precision checksum carry)
     GEMM_CASE(double, float, 0, 0, 0, 0, 0, 0)
