@@ -293,6 +293,47 @@ __device__ __forceinline__ bool better(double a, int64_t ia, double b, int64_t i
   return a > b || (a == b && ia < ib);
 }
 
+// Wave arg-max of (v, i) under `better` (larger v, then smaller i), result in
+// every lane.  Lanes exchange values with DPP moves inside each row of 16
+// (quad permutations, then the half-row and row mirrors: a few cycles each,
+// against an LDS round trip per step for a general shuffle); the four row
+// results are then read with readlane and combined.  `better` is a total
+// order, so the result does not depend on the combining order.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  return __hiloint2double(dpp_i<CTRL>(__double2hiint(x)), dpp_i<CTRL>(__double2loint(x)));
+}
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& v, int& i) {
+  const double ov = dpp_d<CTRL>(v);
+  const int oi = dpp_i<CTRL>(i);
+  if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  argmax_step<0xB1>(v, i);   // quad_perm [1, 0, 3, 2]
+  argmax_step<0x4E>(v, i);   // quad_perm [2, 3, 0, 1]
+  argmax_step<0x141>(v, i);  // row_half_mirror
+  argmax_step<0x140>(v, i);  // row_mirror
+  double bv = readlane_d(v, 0);
+  int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+  for (int r = 16; r < 64; r += 16) {
+    const double ov = readlane_d(v, r);
+    const int oi = __builtin_amdgcn_readlane(i, r);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  v = bv;
+  i = bi;
+}
+
 // Exchange records of the LU leaf.  Every 64-bit word carries 32 bits of
 // payload (high half) and the sequence number of the column that wrote it
 // (low half), so a reader polls the very word it needs: a word is valid
@@ -352,7 +393,6 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
   __shared__ double prow[CLEAF], orow[CLEAF];
   __shared__ double wv_val[4];
   __shared__ int64_t wv_idx[4];
-  __shared__ int wv_g[4];
   __shared__ int64_t s_piv, s_loc;
   __shared__ int s_pg;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -372,21 +412,18 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
     const uint32_t seq = seq0 + (uint32_t)j;
     uint64_t* rj = recs + (size_t)(j & 1) * cstride;
     uint64_t* rowd = rj + (size_t)G * rw;
-    // local argmax of |a(i, j)| over owned rows i >= d
+    // local argmax of |a(i, j)| over owned rows i >= d (row indices fit in
+    // 32 bits: the exchange records carry them so)
     double bv = -1.0;
-    int64_t bi = INT64_MAX;
+    int bi32 = INT_MAX;
     for (int i = tid; i < rows; i += 256) {
-      int64_t gi = rbeg + i;
+      const int gi = (int)(rbeg + i);
       if (gi < d) continue;
-      double v = fabs((double)Ld[i * ldl + j]);
-      if (better<T>(v, gi, bv, bi)) { bv = v; bi = gi; }
+      const double v = fabs((double)Ld[i * ldl + j]);
+      if (better<T>(v, gi, bv, bi32)) { bv = v; bi32 = gi; }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      double ov = __shfl_xor(bv, o);
-      int64_t oi = __shfl_xor(bi, o);
-      if (better<T>(ov, oi, bv, bi)) { bv = ov; bi = oi; }
-    }
+    wave_argmax(bv, bi32);
+    int64_t bi = bi32 == INT_MAX ? INT64_MAX : (int64_t)bi32;
     if (lane == 0) { wv_val[wv] = bv; wv_idx[wv] = bi; }
     __syncthreads();
     uint64_t* mine = rj + (size_t)g * rw;
@@ -411,8 +448,7 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
     // choice does not depend on the order)
     {
       double v = -1.0;
-      int64_t ii = INT64_MAX;
-      int gq = 0;
+      int ii = INT_MAX;
       for (int q = tid; q < G; q += 256) {
         const uint64_t* rq = rj + (size_t)q * rw;
         uint64_t wd[3];
@@ -422,26 +458,21 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
         for (int u = 0; u < 3; ++u) ll_poll(rq + u, wd[u], seq, rep);
         const double vq = ll_dbl(wd[0], wd[1]);
         const uint32_t iq32 = (uint32_t)(wd[2] >> 32);
-        const int64_t iq = iq32 == LL_NONE ? INT64_MAX : (int64_t)iq32;
-        if (vq >= 0 && better<T>(vq, iq, v, ii)) { v = vq; ii = iq; gq = q; }
+        const int iq = iq32 == LL_NONE ? INT_MAX : (int)iq32;
+        if (vq >= 0 && better<T>(vq, iq, v, ii)) { v = vq; ii = iq; }
       }
       LT_MARK(1);
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(v, o);
-        const int64_t oi = __shfl_xor(ii, o);
-        const int og = __shfl_xor(gq, o);
-        if (better<T>(ov, oi, v, ii)) { v = ov; ii = oi; gq = og; }
-      }
-      if (lane == 0) { wv_val[wv] = v; wv_idx[wv] = ii; wv_g[wv] = gq; }
+      wave_argmax(v, ii);
+      if (lane == 0) { wv_val[wv] = v; wv_idx[wv] = ii == INT_MAX ? INT64_MAX : (int64_t)ii; }
       __syncthreads();
       if (tid == 0) {
         double best = wv_val[0];
         int64_t bidx = wv_idx[0];
-        int bg = wv_g[0];
         for (int q = 1; q < 4; ++q)
-          if (better<T>(wv_val[q], wv_idx[q], best, bidx)) { best = wv_val[q]; bidx = wv_idx[q]; bg = wv_g[q]; }
-        if (bidx == INT64_MAX) { bidx = d; bg = 0; }
+          if (better<T>(wv_val[q], wv_idx[q], best, bidx)) { best = wv_val[q]; bidx = wv_idx[q]; }
+        // the winning row names its workgroup (rows [c0 + g R, c0 + (g+1) R))
+        int bg = bidx == INT64_MAX ? 0 : (int)((bidx - c0) / R);
+        if (bidx == INT64_MAX) bidx = d;
         s_piv = bidx;
         s_pg = bg;
       }
