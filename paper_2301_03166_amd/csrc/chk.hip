@@ -460,17 +460,45 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
   if (live) { ce = colchk[2 * I + (cj0 + j) * ldc]; cw = colchk[2 * I + 1 + (cj0 + j) * ldc]; }
   acc2 xe{ce, 0}, xw{cw, 0};
   double ge = 0, gw = 0;
+  // the next chunk's values are loaded into registers while the current one
+  // is summed (indices clamped to valid elements, masks applied when staged)
+  constexpr int PE = PC * 64 / 256;
+  MT mr[PE];
+  double mar[PE], sr[4];
+  auto mpos = [&](int e, int p0, int& pl, int& jc, int& pp, int& jj) {
+    if (msp == 1) { pl = e % PC; jc = e / PC; } else { jc = e % 64; pl = e / 64; }
+    pp = p0 + pl;
+    jj = j0 + jc;
+  };
+  auto fetch = [&](int p0) {
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      int pl, jc, pp, jj;
+      mpos(tid + 256 * u, p0, pl, jc, pp, jj);
+      const int64_t o = (int64_t)min(pp, kw - 1) * msp + (int64_t)min(jj, ncols - 1) * msj;
+      mr[u] = Mp[o];
+      mar[u] = Mabs ? Mabs[o] : 0.0;
+    }
+    if (tid < 4 * PC) {
+      const int q = tid / PC, pl = tid % PC, II = min(Ib + q, I1 - 1), pp = min(p0 + pl, kw - 1);
+      sr[0] = S[2 * II + pp * (int64_t)ldS];
+      sr[1] = S[2 * II + 1 + pp * (int64_t)ldS];
+      sr[2] = Sa[2 * II + pp * (int64_t)ldS];
+      sr[3] = Sa[2 * II + 1 + pp * (int64_t)ldS];
+    }
+  };
+  fetch(0);
   for (int p0 = 0; p0 < kw; p0 += PC) {
     __syncthreads();
-    // stage M(p0 .. p0+31, j0 .. j0+63), along whichever index is contiguous
-    for (int e = tid; e < PC * 64; e += 256) {
-      int pl, jc;
-      if (msp == 1) { pl = e % PC; jc = e / PC; } else { jc = e % 64; pl = e / 64; }
-      const int pp = p0 + pl, jj = j0 + jc;
+    // stage M(p0 .. p0+31, j0 .. j0+63) and the four tile-rows' S / Sa values
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      int pl, jc, pp, jj;
+      mpos(tid + 256 * u, p0, pl, jc, pp, jj);
       double m = 0.0, ma = 0.0;
       if (pp < kw && jj < ncols && (!tri || pp <= jj + pjoff)) {
-        m = mscale * (double)Mp[pp * msp + jj * msj];
-        ma = Mabs ? Mabs[pp * msp + jj * msj] : fabs(m);
+        m = mscale * (double)mr[u];
+        ma = Mabs ? mar[u] : fabs(m);
       }
       Mc[pl][jc] = m;
       Ma[pl][jc] = ma;
@@ -478,12 +506,11 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
     if (tid < 4 * PC) {
       const int q = tid / PC, pl = tid % PC, II = Ib + q, pp = p0 + pl;
       const bool ok = II < I1 && pp < kw;
-      Sc[q][pl][0] = ok ? S[2 * II + pp * (int64_t)ldS] : 0.0;
-      Sc[q][pl][1] = ok ? S[2 * II + 1 + pp * (int64_t)ldS] : 0.0;
-      Sc[q][pl][2] = ok ? Sa[2 * II + pp * (int64_t)ldS] : 0.0;
-      Sc[q][pl][3] = ok ? Sa[2 * II + 1 + pp * (int64_t)ldS] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) Sc[q][pl][t] = ok ? sr[t] : 0.0;
     }
     __syncthreads();
+    if (p0 + PC < kw) fetch(p0 + PC);
     if (live) {
       const int pend = min(PC, kw - p0);
       const int plim = tri ? min(pend, j + pjoff + 1 - p0) : pend;  // masked products are skipped
