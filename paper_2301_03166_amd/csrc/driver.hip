@@ -35,6 +35,8 @@ struct abft_handle_s {
   hipEvent_t* ev;  // event pool for profiled calls
   int nev;
   hipStream_t cap;  // side stream used only for graph capture (created on first use)
+  hipStream_t side;  // checksum carries beside the trailing update (created on first use)
+  hipEvent_t fork_ev, join_ev;
   BatchGraph graphs[MAX_GRAPHS];
   int ngraphs, next_graph;
 };
@@ -117,6 +119,46 @@ struct Prof {
     p.iters = iters;
     h->prof = p;
   }
+};
+
+// The checksum carry of an iteration reads the panel operands (L21, U12 or
+// V, W2) and the checksum rows and writes only the checksum arrays, which
+// the trailing-matrix update never touches: it runs on a side stream,
+// concurrently with the update's product, and the main stream waits for it
+// before the verification.  Profiled calls keep one stream so that each
+// phase's events time that phase alone.
+struct Side {
+  hipStream_t main, s;
+  bool on;
+  Side(abft_handle h, bool want) : main(h->stream), s(h->stream), on(false) {
+    if (!want) return;
+    if (!h->side) {
+      if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) { h->side = nullptr; return; }
+      if (hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(h->side);
+        h->side = nullptr;
+        return;
+      }
+    }
+    s = h->side;
+    on = true;
+    fe = h->fork_ev;
+    je = h->join_ev;
+  }
+  // side stream starts after everything enqueued on the main stream so far
+  int fork() {
+    if (!on) return 0;
+    if (hipEventRecord(fe, main) != hipSuccess || hipStreamWaitEvent(s, fe, 0) != hipSuccess) return ABFT_ERR_HIP;
+    return 0;
+  }
+  // main stream continues after everything enqueued on the side stream
+  int join() {
+    if (!on) return 0;
+    if (hipEventRecord(je, s) != hipSuccess || hipStreamWaitEvent(main, je, 0) != hipSuccess) return ABFT_ERR_HIP;
+    return 0;
+  }
+  hipEvent_t fe = nullptr, je = nullptr;
 };
 
 // Workspace carve-up shared by the three factorizations.
@@ -400,6 +442,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
   const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
   const int rnd = op_rnd(prec);
   Prof pf(h, opts);
+  Side side(h, protect && !pf.on);
   int t = pf.begin(PH_VERIFY);
   if (protect)
     TRY(verify_tiles<T>(s, dA, lda, n, n, nb, 0, 0, 1, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
@@ -422,15 +465,24 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     if (c1 >= n) break;
     const int64_t m = n - c1;
     T* L21 = dA + c1 + c0 * lda;
+    auto carry_k = [&](hipStream_t cs) -> int {
+      if (rnd) TRY(xsums<T>(cs, dA, lda, n, nb, k + 1, c0, kw, k, 1, w.S, w.Sa, ldc, rnd));
+      return carry<T>(cs, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, L21, lda, 1, c1, 1, rnd);
+    };
+    if (side.on) {
+      TRY(side.fork());
+      TRY(carry_k(side.s));
+    }
     t = pf.begin(PH_TMU);
     TRY(gemmT(s, prec, 0, 1, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
     pf.end(t);
     pf.tmu_flops += (double)m * (double)(m + 1) * kw;
     pf.tmu_launches++;
-    if (protect) {
+    if (side.on) {
+      TRY(side.join());
+    } else if (protect) {
       t = pf.begin(PH_CARRY);
-      if (rnd) TRY(xsums<T>(s, dA, lda, n, nb, k + 1, c0, kw, k, 1, w.S, w.Sa, ldc, rnd));
-      TRY(carry<T>(s, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, L21, lda, 1, c1, 1, rnd));
+      TRY(carry_k(s));
       pf.end(t);
     }
     if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N));
@@ -465,6 +517,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
   const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
   const int rnd = op_rnd(prec);
   Prof pf(h, opts);
+  Side side(h, protect && !pf.on);
   int t = pf.begin(PH_VERIFY);
   if (protect)
     TRY(verify_tiles<T>(s, dA, lda, n, n, nb, 0, 0, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
@@ -508,16 +561,25 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
     const int64_t m = n - c1;
     T* L21 = dA + c1 + c0 * lda;
     T* U12 = dA + c0 + c1 * lda;
+    auto carry_k = [&](hipStream_t cs) -> int {
+      if (rnd) TRY(xsums<T>(cs, dA, lda, n, nb, k + 1, c0, kw, k, 2, w.S, w.Sa, ldc, rnd));
+      TRY(ysums<T>(cs, dA + c0, lda, n, nb, k + 1, kw, w.Tm, w.Ta, nb, rnd));
+      return carry<T>(cs, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, U12, lda, 0, c1, 0, rnd);
+    };
+    if (side.on) {
+      TRY(side.fork());
+      TRY(carry_k(side.s));
+    }
     t = pf.begin(PH_TMU);
     TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
     pf.end(t);
     pf.tmu_flops += 2.0 * (double)m * (double)m * kw;
     pf.tmu_launches++;
-    if (protect) {
+    if (side.on) {
+      TRY(side.join());
+    } else if (protect) {
       t = pf.begin(PH_CARRY);
-      if (rnd) TRY(xsums<T>(s, dA, lda, n, nb, k + 1, c0, kw, k, 2, w.S, w.Sa, ldc, rnd));
-      TRY(ysums<T>(s, dA + c0, lda, n, nb, k + 1, kw, w.Tm, w.Ta, nb, rnd));
-      TRY(carry<T>(s, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, U12, lda, 0, c1, 0, rnd));
+      TRY(carry_k(s));
       pf.end(t);
     }
     if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N));
@@ -720,6 +782,11 @@ int abft_destroy(abft_handle h) {
   if (h) {
     for (int i = 0; i < h->ngraphs; ++i) (void)hipGraphExecDestroy(h->graphs[i].exec);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->side) {
+      (void)hipStreamDestroy(h->side);
+      (void)hipEventDestroy(h->fork_ev);
+      (void)hipEventDestroy(h->join_ev);
+    }
   }
   free(h);
   return 0;
@@ -820,6 +887,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
                              nullptr, nullptr, -1));
   QrCtx c{s, dA, lda, n, dtau, &w, nb, 0, 0u, drep, std::min(h->cus, 256)};
   Prof pf(h, opts);
+  Side side(h, protect && !pf.on);
   int t;
   for (int k = 0; k < N; ++k) {
     const int64_t c0 = (int64_t)k * nb;
@@ -851,16 +919,25 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     pf.end(t);
     if (S > 1) TRY(splitk_reduce(s, w.splitk, S, kw, (int)m, 0.0, w.W, nb));
     TRY(gemm64(s, 1, 0, 0, 0, 0, kw, (int)m, kw, 1.0, w.Tfac, nb, w.W, nb, 0.0, w.W2, nb, 0));
+    auto carry_k = [&](hipStream_t cs) -> int {
+      TRY(ysums<double>(cs, w.W2 - c1 * nb, nb, n, nb, k + 1, kw, w.Tm, w.Ta, nb, 0));
+      return carry(cs, w, n, nb, k, k + 1, kw, V, lda, c0, 1, w.W2, nb, 0, c1, 0);
+    };
+    if (side.on) {  // (W2 is final here; the second product only reads it)
+      TRY(side.fork());
+      TRY(carry_k(side.s));
+    }
     t = pf.begin(PH_TMU);
     TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)m, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0, 0, 0, 0, nullptr,
                0, 1));
     pf.end(t);
     pf.tmu_flops += 4.0 * (double)(n - c0) * (double)m * kw;
     pf.tmu_launches += 2;
-    if (protect) {
+    if (side.on) {
+      TRY(side.join());
+    } else if (protect) {
       t = pf.begin(PH_CARRY);
-      TRY(ysums<double>(s, w.W2 - c1 * nb, nb, n, nb, k + 1, kw, w.Tm, w.Ta, nb, 0));
-      TRY(carry(s, w, n, nb, k, k + 1, kw, V, lda, c0, 1, w.W2, nb, 0, c1, 0));
+      TRY(carry_k(s));
       pf.end(t);
     }
     if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N));
