@@ -517,7 +517,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
   const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
   const int rnd = op_rnd(prec);
   Prof pf(h, opts);
-  Side side(h, protect && !pf.on);
+  Side side(h, !pf.on);
   int t = pf.begin(PH_VERIFY);
   if (protect)
     TRY(verify_tiles<T>(s, dA, lda, n, n, nb, 0, 0, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
@@ -538,12 +538,16 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
         return ABFT_ERR_HIP;
     TRY(lu_panel(c, c0, c1));
     TRY(perm_build(s, dipiv, c0, kw, n, w.moves));
-    TRY(laswp(s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
+    // the interchanges of the factored columns to the left and of the row
+    // checksums go to the side stream with the carry (nothing before the
+    // carry reads them), except after the last panel
+    const bool defer = side.on && c1 < n;
+    if (!defer) TRY(laswp(s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
     TRY(laswp(s, dA, lda, c1, n, w.moves, stage, protect ? w.colchk : (double*)nullptr, ldc, nb));
     if (protect) {
       // column checksums of the panel follow the interchanges of the original panel values
       TRY(laswp(s, porig - c0, n, 0, kw, w.moves, stage, w.colchk + c0 * ldc, ldc, nb));
-      TRY(laswp(s, w.rowchk, n, 0, 2 * N, w.moves, (double*)w.stage, (double*)nullptr, 0, nb));
+      if (!defer) TRY(laswp(s, w.rowchk, n, 0, 2 * N, w.moves, (double*)w.stage, (double*)nullptr, 0, nb));
       TRY(xsums<T>(s, dA, lda, n, nb, k, c0, kw, k, 2, w.S, w.Sa, ldc, 0));
       // e^T (P A)_I = (e^T L_I) U_kk
       TRY(panel_check<T>(s, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, 1, lda, 1, 0, 1.0, nullptr, nullptr, nullptr,
@@ -566,9 +570,13 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       TRY(ysums<T>(cs, dA + c0, lda, n, nb, k + 1, kw, w.Tm, w.Ta, nb, rnd));
       return carry<T>(cs, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, U12, lda, 0, c1, 0, rnd);
     };
-    if (side.on) {
+    if (side.on) {  // (w.moves stays unchanged until the join)
       TRY(side.fork());
-      TRY(carry_k(side.s));
+      TRY(laswp(side.s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
+      if (protect) {
+        TRY(laswp(side.s, w.rowchk, n, 0, 2 * N, w.moves, (double*)w.stage, (double*)nullptr, 0, nb));
+        TRY(carry_k(side.s));
+      }
     }
     t = pf.begin(PH_TMU);
     TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
