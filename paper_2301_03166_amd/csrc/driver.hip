@@ -442,7 +442,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
   const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
   const int rnd = op_rnd(prec);
   Prof pf(h, opts);
-  Side side(h, protect && !pf.on);
+  Side side(h, protect && !pf.on);  // (nothing to overlap without checksums)
   int t = pf.begin(PH_VERIFY);
   if (protect)
     TRY(verify_tiles<T>(s, dA, lda, n, n, nb, 0, 0, 1, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
@@ -455,11 +455,17 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     pf.iters++;
     t = pf.begin(PH_PANEL);
     TRY(chol_panel(s, dA, lda, n, c0, c1, dinfo));
+    // the panel check only reads (the panel, its checksum rows, colchk of the
+    // panel's columns): it goes to the side stream with the carry
+    const bool defer = side.on && c1 < n;
+    auto check_k = [&](hipStream_t cs) -> int {
+      // e^T A_Ik = (e^T L_I) L_kk^T:  M(p, j) = L(c0 + j, c0 + p), p <= j
+      return panel_check<T>(cs, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, lda, 1, 1, 0, 1.0, nullptr, nullptr,
+                            nullptr, -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb);
+    };
     if (protect) {
       TRY(xsums<T>(s, dA, lda, n, nb, k, c0, kw, k, 1, w.S, w.Sa, ldc, 0));
-      // e^T A_Ik = (e^T L_I) L_kk^T:  M(p, j) = L(c0 + j, c0 + p), p <= j
-      TRY(panel_check<T>(s, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, lda, 1, 1, 0, 1.0, nullptr, nullptr, nullptr,
-                         -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb));
+      if (!defer) TRY(check_k(s));
     }
     pf.end(t);
     if (c1 >= n) break;
@@ -471,7 +477,10 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     };
     if (side.on) {
       TRY(side.fork());
-      TRY(carry_k(side.s));
+      if (protect) {
+        TRY(check_k(side.s));
+        TRY(carry_k(side.s));
+      }
     }
     t = pf.begin(PH_TMU);
     TRY(gemmT(s, prec, 0, 1, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
@@ -542,6 +551,16 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
     // checksums go to the side stream with the carry (nothing before the
     // carry reads them), except after the last panel
     const bool defer = side.on && c1 < n;
+    // the panel checks only read (panel, U12, checksum rows, colchk of
+    // tile-row k and of the panel's columns): deferred likewise
+    auto check_pd = [&](hipStream_t cs) -> int {  // e^T (P A)_I = (e^T L_I) U_kk
+      return panel_check<T>(cs, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, 1, lda, 1, 0, 1.0, nullptr, nullptr,
+                            nullptr, -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb);
+    };
+    auto check_pu = [&](hipStream_t cs) -> int {  // (e^T L_kk) U12 = e^T A12 on tile-row k
+      return panel_check<T>(cs, w.S, w.Sa, ldc, k, k + 1, kw, dA + c0 + c1 * lda, 1, lda, 0, 0, 1.0, nullptr, nullptr,
+                            nullptr, -1, w.colchk, ldc, c1, (int)(n - c1), tsu_p, drep, k, nb);
+    };
     if (!defer) TRY(laswp(s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
     TRY(laswp(s, dA, lda, c1, n, w.moves, stage, protect ? w.colchk : (double*)nullptr, ldc, nb));
     if (protect) {
@@ -549,18 +568,14 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       TRY(laswp(s, porig - c0, n, 0, kw, w.moves, stage, w.colchk + c0 * ldc, ldc, nb));
       if (!defer) TRY(laswp(s, w.rowchk, n, 0, 2 * N, w.moves, (double*)w.stage, (double*)nullptr, 0, nb));
       TRY(xsums<T>(s, dA, lda, n, nb, k, c0, kw, k, 2, w.S, w.Sa, ldc, 0));
-      // e^T (P A)_I = (e^T L_I) U_kk
-      TRY(panel_check<T>(s, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, 1, lda, 1, 0, 1.0, nullptr, nullptr, nullptr,
-                         -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb));
+      if (!defer) TRY(check_pd(s));
     }
     if (c1 >= n) {
       pf.end(t);
       break;
     }
     TRY(trsm_llu(s, dA, lda, c0, kw, c1, n));
-    if (protect)  // (e^T L_kk) U12 = e^T A12 on tile-row k
-      TRY(panel_check<T>(s, w.S, w.Sa, ldc, k, k + 1, kw, dA + c0 + c1 * lda, 1, lda, 0, 0, 1.0, nullptr, nullptr,
-                         nullptr, -1, w.colchk, ldc, c1, (int)(n - c1), tsu_p, drep, k, nb));
+    if (protect && !defer) TRY(check_pu(s));
     pf.end(t);
     const int64_t m = n - c1;
     T* L21 = dA + c1 + c0 * lda;
@@ -574,6 +589,8 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       TRY(side.fork());
       TRY(laswp(side.s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
       if (protect) {
+        TRY(check_pd(side.s));
+        TRY(check_pu(side.s));
         TRY(laswp(side.s, w.rowchk, n, 0, 2 * N, w.moves, (double*)w.stage, (double*)nullptr, 0, nb));
         TRY(carry_k(side.s));
       }
@@ -906,12 +923,22 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     t = pf.begin(PH_PANEL);
     TRY(fill_zero(s, w.Tfac, (size_t)nb * nb * sizeof(double)));
     TRY(qr_panel(c, c0, c1));
+    // the panel check reads the panel, T and colchk of the panel's columns
+    // only: on the side stream it runs beside the trailing update
+    auto check_k = [&](hipStream_t cs) -> int {
+      TRY(qr_check_prep(cs, dA, lda, c0, kw, n - c0, w.Tfac, nb, w.scr, w.Z, w.Zabs, w.E, w.bt));
+      // e^T A_I = [I==k] e^T R - (e^T V_I) T V1^T R
+      return panel_check(cs, w.S, w.Sa, ldc, k, N, kw, w.Z, 1, kw, 0, 0, -1.0, w.Zabs, w.E, w.bt, k, w.colchk, ldc,
+                         c0, kw, tsu_p, drep, k, nb);
+    };
     if (protect) {
       TRY(xsums<double>(s, dA, lda, n, nb, k, c0, kw, k, 2, w.S, w.Sa, ldc, 0));
-      TRY(qr_check_prep(s, dA, lda, c0, kw, n - c0, w.Tfac, nb, w.scr, w.Z, w.Zabs, w.E, w.bt));
-      // e^T A_I = [I==k] e^T R - (e^T V_I) T V1^T R
-      TRY(panel_check(s, w.S, w.Sa, ldc, k, N, kw, w.Z, 1, kw, 0, 0, -1.0, w.Zabs, w.E, w.bt, k, w.colchk, ldc, c0, kw,
-                      tsu_p, drep, k, nb));
+      if (side.on && c1 < n) {
+        TRY(side.fork());
+        TRY(check_k(side.s));
+      } else {
+        TRY(check_k(s));
+      }
     }
     pf.end(t);
     if (c1 >= n) break;
