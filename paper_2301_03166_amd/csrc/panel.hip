@@ -527,9 +527,9 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
 // S_c = sum over its rows i > d of a(i,j) a(i,c) for every c < w.  The G
 // partial rows are added in two levels through self-validating exchange
 // records (as in the LU leaf; no barrier, no fence): the first workgroup of
-// each group of 16 adds its members' rows in member order and publishes the
-// group sum, then every workgroup adds the group sums in group order, so all
-// hold the same Gram row.  Entries c >= j give the column norm and the
+// each group of 8 (16 beyond 128 workgroups) adds its members' rows in
+// member order and publishes the group sum, then every workgroup adds the
+// group sums in group order, so all hold the same Gram row.  Entries c >= j give the column norm and the
 // reflector's dot products with the trailing columns; entries c < j give
 // v_c . v_j = v_c(d) + scale S_c, the inputs of T's column j, which
 // workgroup 0 stages in T's strictly upper part.  After the loop workgroup
@@ -538,9 +538,11 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
 // sum of column j + 1, which no group publishes before its members have
 // finished column j.
 // ---------------------------------------------------------------------------
-constexpr int QR_GROUP = 16;
+// groups of 8 workgroups up to 128 workgroups, of 16 beyond: at most 16
+// group sums, four per thread of the second level
+__host__ __device__ constexpr int qr_group(int G) { return G <= 128 ? 8 : 16; }
 __host__ __device__ constexpr int64_t qr_rec_words(int G, int w) {
-  return (int64_t)(G + (G + QR_GROUP - 1) / QR_GROUP + 1) * 2 * w;
+  return (int64_t)(G + (G + qr_group(G) - 1) / qr_group(G) + 1) * 2 * w;
 }
 
 __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int64_t m, int64_t c0, int w, int R,
@@ -555,7 +557,7 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
   __shared__ double orow[CLEAF], fvec[CLEAF];
   __shared__ double s_beta, s_tau, s_scale;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, e = tid & 63, wq = tid >> 6;
-  const int NG = (G + QR_GROUP - 1) / QR_GROUP;
+  const int grp = qr_group(G), NG = (G + grp - 1) / grp;
   const int64_t rbeg = c0 + (int64_t)g * R;
   const int rows = (int)max((int64_t)0, min((int64_t)R, m - rbeg));
   const int64_t cstride = qr_rec_words(G, w);
@@ -630,11 +632,11 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
     }
     LT_MARK(0);
     // level 1: the group's first workgroup adds its members' rows
-    if (g % QR_GROUP == 0) {
-      qpart[wq][e] = sum4(r1, g + wq, min(G, g + QR_GROUP), seq);
+    if (g % grp == 0) {
+      qpart[wq][e] = sum4(r1, g + wq, min(G, g + grp), seq);
       __syncthreads();
       if (tid < w)
-        ll_put2(r2 + (size_t)(g / QR_GROUP) * 2 * w + 2 * tid,
+        ll_put2(r2 + (size_t)(g / grp) * 2 * w + 2 * tid,
                 ((qpart[0][tid] + qpart[1][tid]) + qpart[2][tid]) + qpart[3][tid], seq);
     }
     LT_MARK(1);
