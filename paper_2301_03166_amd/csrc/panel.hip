@@ -861,7 +861,7 @@ __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, in
 // tile-row adds the run's plain and position-weighted differences
 // (compensated, in the moves' order: increasing destination row) to that
 // tile-row's column checksums.
-constexpr int LASWP_PAIRS = 16;                      // (move, column) pairs per thread
+constexpr int LASWP_PAIRS = 8;                       // (move, column) pairs per thread
 constexpr int LASWP_CPW = 256 * LASWP_PAIRS / 1024;  // columns per workgroup (up to 1024 moves)
 constexpr int LASWP_NBK = 1024 / 16;                 // blocks of 16 moves per column
 template <typename T>
