@@ -149,15 +149,23 @@ struct Side {
   // side stream starts after everything enqueued on the main stream so far
   int fork() {
     if (!on) return 0;
+    pending = true;
     if (hipEventRecord(fe, main) != hipSuccess || hipStreamWaitEvent(s, fe, 0) != hipSuccess) return ABFT_ERR_HIP;
     return 0;
   }
   // main stream continues after everything enqueued on the side stream
   int join() {
     if (!on) return 0;
+    pending = false;
     if (hipEventRecord(je, s) != hipSuccess || hipStreamWaitEvent(main, je, 0) != hipSuccess) return ABFT_ERR_HIP;
     return 0;
   }
+  // a call that returns early (an error between fork and join) still leaves
+  // the caller's stream ordered after the side stream's work
+  ~Side() {
+    if (pending) (void)join();
+  }
+  bool pending = false;
   hipEvent_t fe = nullptr, je = nullptr;
 };
 
