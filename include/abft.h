@@ -21,6 +21,10 @@
  *     memory and are read before the call returns.
  *   - Calls are asynchronous on the handle's HIP stream.  Results, `dinfo`
  *     and the report become valid once the stream has been synchronized.
+ *     The blocked factorizations also use an internal side stream of the
+ *     handle (created on first use, default priority) for work that only
+ *     reads the panel; it is ordered after the caller's stream by an event
+ *     and joined back before the call's last operation on that stream.
  *   - Return value: 0 on success; -i when argument i (1-based) is invalid;
  *     ABFT_ERR_HIP when a HIP call failed (launch or cooperative-launch
  *     error); ABFT_ERR_WORKSPACE when `work_bytes` is too small;
@@ -117,8 +121,8 @@ typedef struct {
 } abft_opts;
 
 /* opts.flags: ABFT_FLAG_PROFILE times the phases of the call with HIP
-   events on the handle's stream (the call then waits for its own completion
-   before returning); ABFT_FLAG_GRAPH lets the batched calls capture and
+   events on the handle's stream, all work on that one stream (the call then
+   waits for its own completion before returning); ABFT_FLAG_GRAPH lets the batched calls capture and
    replay HIP graphs (see abft_potrf_batched). */
 enum { ABFT_FLAG_PROFILE = 1, ABFT_FLAG_GRAPH = 2 };
 
