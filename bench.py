@@ -464,6 +464,7 @@ def main():
     campaign = campaign_leg(h, torch, dev, args) if args.campaign > 0 else None
     energy = None if args.no_energy else energy_leg(h, torch, dev, args)
     wall = time.perf_counter() - t0
+    h.close()
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -29,8 +29,16 @@
  * round-to-nearest-even to that format.
  *
  * Storage: column-major, element (i,j) at A[i + j*lda].
+ *
+ * Threads: the loops over independent output elements (tiles, columns,
+ * rows of a block of rows) are spread over OpenMP threads.  Every element
+ * is still computed by one thread with the same operations in the same
+ * order as a plain serial loop, so the results are bitwise independent of
+ * the thread count (a test runs the same factorization with 1 and with
+ * several threads).  Report events are emitted in the serial order.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -96,6 +104,11 @@ static inline double rop(int prec, double x) {
   }
 }
 static inline double unit_round(int prec) { return prec == PR64 ? ldexp(1.0, -53) : ldexp(1.0, -24); }
+
+void orc_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
+static inline int imin(int a, int b) { return a < b ? a : b; }
+static inline int imax(int a, int b) { return a > b ? a : b; }
 
 /* Compensated accumulator (value s + c): Knuth's two-sum for additions and
    an FMA-based two-product for products, so checksum sums and checksum
@@ -207,6 +220,7 @@ static void geqr2_cols(int m, double* A, int lda, double* tau, int c0, int c1) {
     if (t == 0.0) continue;
     for (int i = j + 1; i < m; ++i) AT(A, i, j, lda) *= sc;
     AT(A, j, j, lda) = beta;
+#pragma omp parallel for schedule(static) if ((size_t)(c1 - j) * (size_t)(m - j) > ((size_t)1 << 16))
     for (int c = j + 1; c < c1; ++c) {
       double w = AT(A, j, c, lda);
       for (int i = j + 1; i < m; ++i) w += AT(A, i, j, lda) * AT(A, i, c, lda);
@@ -258,15 +272,17 @@ static void note_flag(ctx_t* c) {
   if (c->rep->first_flag_iter < 0) c->rep->first_flag_iter = c->iter;
 }
 
-/* all sums of one tile (symmetric view when c->sym and I == J) */
+/* all sums of one tile (symmetric view when c->sym and I == J), with the
+   compensated accumulators they are formed in */
 typedef struct {
   double ce[1024], cw[1024], ca[1024], cwa[1024];
   double re[1024], rw[1024], ra[1024], rwa[1024];
+  acc_t ace[1024], acw[1024], are[1024], arw[1024];
 } tsums_t;
 
 static void tile_sums(const ctx_t* c, const double* A, int lda, int I, int J, tsums_t* t) {
   int r0 = I * c->nb, h = tlen(c, I), c0 = J * c->nb, w = tlen(c, J);
-  static acc_t ce[1024], cw[1024], re[1024], rw[1024];
+  acc_t *ce = t->ace, *cw = t->acw, *re = t->are, *rw = t->arw;
   for (int j = 0; j < w; ++j) { ce[j].s = ce[j].c = cw[j].s = cw[j].c = 0.0; t->ca[j] = t->cwa[j] = 0.0; }
   for (int i = 0; i < h; ++i) { re[i].s = re[i].c = rw[i].s = rw[i].c = 0.0; t->ra[i] = t->rwa[i] = 0.0; }
   for (int j = 0; j < w; ++j)
@@ -393,11 +409,13 @@ static int ratio_index(double dw, double de, int len) {
 static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
   int r0 = I * c->nb, h = tlen(c, I), c0 = J * c->nb, w = tlen(c, J);
   int diag = c->sym && I == J;
-  static tsums_t t;
-  static tflags_t f;
+  tsums_t* tp = malloc(sizeof(tsums_t));
+  tflags_t* fp = malloc(sizeof(tflags_t));
+#define t (*tp)
+#define f (*fp)
   tile_sums(c, A, lda, I, J, &t);
   int nf = tile_flags(c, I, J, &t, &f, NULL, NULL);
-  if (nf == 0) return;
+  if (nf == 0) { free(tp); free(fp); return; }
   int nFe = 0, nGe = 0, nFw = 0, nGw = 0, jf[2] = {-1, -1}, ig = -1;
   for (int j = 0; j < w; ++j) {
     if (f.fe[j]) { if (nFe < 2) jf[nFe] = j; nFe++; }
@@ -460,38 +478,78 @@ static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
   /* refresh the tile's checksums from the (corrected) data */
   tile_sums(c, A, lda, I, J, &t);
   store_sums(c, I, J, &t);
+#undef t
+#undef f
+  free(tp);
+  free(fp);
 }
 
-/* verify tiles I >= Ia, J >= Ja (lower tiles only when sym); flagged tiles go
-   to correction, clean ones get their checksums refreshed from the data */
-static void verify_region(ctx_t* c, double* A, int lda, int Ia, int Ja) {
-  static tsums_t t;
-  static tflags_t f;
+/* the tiles I >= Ia, J >= Ja (lower tiles only when sym), in the serial
+   visiting order: tile-columns left to right, tile-rows top to bottom */
+static int tile_list(const ctx_t* c, int Ia, int Ja, int* IJ) {
+  int nt = 0;
   for (int J = Ja; J < c->N; ++J)
     for (int I = Ia; I < c->N; ++I) {
       if (c->sym && I < J) continue;
-      tile_sums(c, A, lda, I, J, &t);
-      double mr = c->rep->max_ratio;
-      int nf = tile_flags(c, I, J, &t, &f, &mr, NULL);
-      if (nf) {
-        c->rep->flagged_tiles++;
-        note_flag(c);
-        correct_tile(c, A, lda, I, J);
-      } else {
-        c->rep->max_ratio = mr;
-        store_sums(c, I, J, &t);
-      }
+      IJ[2 * nt] = I;
+      IJ[2 * nt + 1] = J;
+      nt++;
     }
+  return nt;
+}
+
+/* verify tiles I >= Ia, J >= Ja (lower tiles only when sym); flagged tiles go
+   to correction, clean ones get their checksums refreshed from the data.
+   Tiles are independent: their sums and comparisons run in parallel, the
+   flagged ones are then corrected one by one in the visiting order. */
+static void verify_region(ctx_t* c, double* A, int lda, int Ia, int Ja) {
+  int* IJ = malloc(sizeof(int) * 2 * (size_t)c->N * c->N + 2);
+  int nt = tile_list(c, Ia, Ja, IJ);
+  int* flagged = calloc((size_t)nt + 1, sizeof(int));
+  double* mr = calloc((size_t)nt + 1, sizeof(double));
+#pragma omp parallel
+  {
+    tsums_t* t = malloc(sizeof(tsums_t));
+    tflags_t* f = malloc(sizeof(tflags_t));
+#pragma omp for schedule(dynamic, 1)
+    for (int q = 0; q < nt; ++q) {
+      int I = IJ[2 * q], J = IJ[2 * q + 1];
+      tile_sums(c, A, lda, I, J, t);
+      double m = 0.0;
+      if (tile_flags(c, I, J, t, f, &m, NULL)) flagged[q] = 1;
+      else { mr[q] = m; store_sums(c, I, J, t); }
+    }
+    free(t);
+    free(f);
+  }
+  for (int q = 0; q < nt; ++q) {
+    if (flagged[q]) {
+      c->rep->flagged_tiles++;
+      note_flag(c);
+      correct_tile(c, A, lda, IJ[2 * q], IJ[2 * q + 1]);
+    } else if (mr[q] > c->rep->max_ratio) {
+      c->rep->max_ratio = mr[q];
+    }
+  }
+  free(IJ);
+  free(flagged);
+  free(mr);
 }
 
 static void encode_all(ctx_t* c, const double* A, int lda) {
-  static tsums_t t;
-  for (int J = 0; J < c->N; ++J)
-    for (int I = 0; I < c->N; ++I) {
-      if (c->sym && I < J) continue;
-      tile_sums(c, A, lda, I, J, &t);
-      store_sums(c, I, J, &t);
+  int* IJ = malloc(sizeof(int) * 2 * (size_t)c->N * c->N + 2);
+  int nt = tile_list(c, 0, 0, IJ);
+#pragma omp parallel
+  {
+    tsums_t* t = malloc(sizeof(tsums_t));
+#pragma omp for schedule(dynamic, 1)
+    for (int q = 0; q < nt; ++q) {
+      tile_sums(c, A, lda, IJ[2 * q], IJ[2 * q + 1], t);
+      store_sums(c, IJ[2 * q], IJ[2 * q + 1], t);
     }
+    free(t);
+  }
+  free(IJ);
 }
 
 /* ------------------------------------------------------------------ */
@@ -514,6 +572,7 @@ static inline double xval(const double* A, int lda, int i, int p, int xc0, int d
 typedef struct { double *e, *w, *a, *wa; } vec4_t; /* each N x nb, index [I*nb + p] */
 
 static void x_colsums(ctx_t* c, const double* A, int lda, int I0, int xc0, int kw, int dI, int mode, vec4_t* s) {
+#pragma omp parallel for schedule(dynamic, 1)
   for (int I = I0; I < c->N; ++I) {
     int r0 = I * c->nb, h = tlen(c, I);
     for (int p = 0; p < kw; ++p) {
@@ -545,6 +604,7 @@ static void carry(ctx_t* c, const double* A, int lda, int I0, int J0, int xc0, i
   t.a = calloc((size_t)N * nb, sizeof(double)); t.wa = calloc((size_t)N * nb, sizeof(double));
   x_colsums(c, A, lda, I0, xc0, kw, dI, mode, &s);
   /* row sums of Y over each tile-column J */
+#pragma omp parallel for schedule(dynamic, 1)
   for (int J = J0; J < N; ++J) {
     int c0 = J * nb, w = tlen(c, J);
     for (int p = 0; p < kw; ++p) {
@@ -558,6 +618,7 @@ static void carry(ctx_t* c, const double* A, int lda, int I0, int J0, int xc0, i
     }
   }
   /* column side */
+#pragma omp parallel for schedule(dynamic, 16)
   for (int j = J0 * nb; j < n; ++j) {
     int Jj = j / nb;
     for (int I = I0; I < N; ++I) {
@@ -577,6 +638,7 @@ static void carry(ctx_t* c, const double* A, int lda, int I0, int J0, int xc0, i
   }
   /* row side */
   int dr0 = dI * nb, dr1 = dI * nb + tlen(c, dI);
+#pragma omp parallel for schedule(dynamic, 16)
   for (int i = I0 * nb; i < n; ++i) {
     int Ii = i / nb;
     for (int J = J0; J < N; ++J) {
@@ -611,8 +673,10 @@ static void panel_check(ctx_t* c, const double* A, int lda, int I0, int I1, int 
   s.e = calloc((size_t)N * nb, sizeof(double)); s.w = calloc((size_t)N * nb, sizeof(double));
   s.a = calloc((size_t)N * nb, sizeof(double)); s.wa = calloc((size_t)N * nb, sizeof(double));
   x_colsums(c, A, lda, I0, xc0, kw, dI, mode, &s);
+  int* flagged = calloc((size_t)N + 1, sizeof(int));
+  double* mr = calloc((size_t)N + 1, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
   for (int I = I0; I < I1; ++I) {
-    int flagged = 0;
     for (int j = j0; j < j1; ++j) {
       double ce = AT(c->cc, 2 * I, j, c->ldc), cw = AT(c->cc, 2 * I + 1, j, c->ldc);
       acc_t xe = {ce, 0}, xw = {cw, 0};
@@ -630,19 +694,24 @@ static void panel_check(ctx_t* c, const double* A, int lda, int I0, int I1, int 
       }
       double de = acc_val(xe), dw = acc_val(xw);
       double te = tau_panel(c, fabs(ce) + ge), tw = tau_panel(c, fabs(cw) + gw);
-      if (bad(de, te) || bad(dw, tw)) flagged = 1;
+      if (bad(de, te) || bad(dw, tw)) flagged[I] = 1;
       else {
-        if (te > 0 && fabs(de) / te > c->rep->max_ratio) c->rep->max_ratio = fabs(de) / te;
-        if (tw > 0 && fabs(dw) / tw > c->rep->max_ratio) c->rep->max_ratio = fabs(dw) / tw;
+        if (te > 0 && fabs(de) / te > mr[I]) mr[I] = fabs(de) / te;
+        if (tw > 0 && fabs(dw) / tw > mr[I]) mr[I] = fabs(dw) / tw;
       }
     }
-    if (flagged) {
+  }
+  for (int I = I0; I < I1; ++I) {
+    if (mr[I] > c->rep->max_ratio) c->rep->max_ratio = mr[I];
+    if (flagged[I]) {
       c->rep->panel_flags++;
       c->rep->status |= 8;
       note_flag(c);
       add_event(c->rep, c->iter, 4, (int64_t)I * nb, j0);
     }
   }
+  free(flagged);
+  free(mr);
   free(s.e); free(s.w); free(s.a); free(s.wa);
 }
 
@@ -689,6 +758,99 @@ static void zero_g(ctx_t* c) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Update loops shared by the decompositions.  Rows are split into     */
+/* blocks of RB handled by one thread each; inside a block every       */
+/* element still sees its operations in the plain serial order.        */
+/* ------------------------------------------------------------------ */
+#define RB 256
+typedef double v4d __attribute__((vector_size(32)));  /* four independent lanes */
+
+/* C(i, j) -= sum_p X(i, p) Y(p, j) for rows i in [0, mr) and columns j in
+   [0, nc) (only i >= j when lower): element (i, j) accumulates its products
+   over p = 0, 1, ..., kw-1 (rounded to prec after every step), then C(i, j)
+   becomes rs(C(i, j) - acc).  X is column-major with leading dimension
+   ldx, Y(p, j) = Y[p + j*ldy]. */
+static void update_rows(int prec, int mr, int nc, int kw, const double* X, int ldx, const double* Y, int ldy,
+                        double* C, int ldc, int lower) {
+#pragma omp parallel
+  {
+    double* acc = malloc(sizeof(double) * 4 * RB);
+#pragma omp for schedule(dynamic, 1)
+    for (int ib = 0; ib < mr; ib += RB) {
+      int ie = imin(ib + RB, mr);
+      int jend = lower ? imin(nc, ie) : nc;
+      /* four columns at a time; rows [i0, ie) of the block, where rows above
+         a column's diagonal (lower) are computed but not stored */
+      for (int j0 = 0; j0 < jend; j0 += 4) {
+        int nj = imin(4, jend - j0);
+        int i0 = lower ? imax(ib, j0) : ib;
+        int i = i0;
+        if (prec == PR64 && nj == 4) {
+          /* 8 rows x 4 columns of accumulators held in registers: each lane
+             of a v4d is one element's own running sum */
+          const double* y0 = Y + (size_t)j0 * ldy;
+          for (; i + 8 <= ie; i += 8) {
+            v4d a[4][2];
+            for (int jj = 0; jj < 4; ++jj) a[jj][0] = a[jj][1] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int p = 0; p < kw; ++p) {
+              v4d x0, x1;
+              memcpy(&x0, X + (size_t)p * ldx + i, sizeof x0);
+              memcpy(&x1, X + (size_t)p * ldx + i + 4, sizeof x1);
+              for (int jj = 0; jj < 4; ++jj) {
+                double y = y0[p + (size_t)jj * ldy];
+                a[jj][0] = a[jj][0] + x0 * y;
+                a[jj][1] = a[jj][1] + x1 * y;
+              }
+            }
+            for (int jj = 0; jj < 4; ++jj) {
+              memcpy(acc + jj * RB + (i - ib), &a[jj][0], sizeof(v4d));
+              memcpy(acc + jj * RB + (i - ib) + 4, &a[jj][1], sizeof(v4d));
+            }
+          }
+        }
+        /* the remaining rows, one accumulator per element */
+        for (int jj = 0; jj < nj; ++jj)
+          for (int r = i; r < ie; ++r) acc[jj * RB + (r - ib)] = 0.0;
+        for (int p = 0; p < kw; ++p) {
+          const double* x = X + (size_t)p * ldx;
+          for (int jj = 0; jj < nj; ++jj) {
+            double y = Y[p + (size_t)(j0 + jj) * ldy];
+            double* aj = acc + jj * RB - ib;
+            for (int r = i; r < ie; ++r) aj[r] = rs(prec, aj[r] + x[r] * y);
+          }
+        }
+        for (int jj = 0; jj < nj; ++jj) {
+          int j = j0 + jj;
+          double* cj = C + (size_t)j * ldc;
+          const double* aj = acc + jj * RB - ib;
+          for (int r = lower ? imax(i0, j) : i0; r < ie; ++r) cj[r] = rs(prec, cj[r] - aj[r]);
+        }
+      }
+    }
+    free(acc);
+  }
+}
+
+/* operand copies of an update, rounded as the update's inputs are:
+   X[i + p*m] = rop(A(r0 + i, c0 + p)) and Y[p + j*kw] = rop(A(yr0 + p, yc0 + j))
+   (ty = 0) or rop(A(yc0 + j, yr0 + p)) (ty = 1, a transposed operand) */
+static double* copy_x(int prec, const double* A, int lda, int r0, int m, int c0, int kw) {
+  double* X = malloc(sizeof(double) * ((size_t)m * kw + 1));
+#pragma omp parallel for schedule(static)
+  for (int p = 0; p < kw; ++p)
+    for (int i = 0; i < m; ++i) X[i + (size_t)p * m] = rop(prec, AT(A, r0 + i, c0 + p, lda));
+  return X;
+}
+static double* copy_y(int prec, const double* A, int lda, int yr0, int kw, int yc0, int nc, int ty) {
+  double* Y = malloc(sizeof(double) * ((size_t)nc * kw + 1));
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < nc; ++j)
+    for (int p = 0; p < kw; ++p)
+      Y[p + (size_t)j * kw] = rop(prec, ty ? AT(A, yc0 + j, yr0 + p, lda) : AT(A, yr0 + p, yc0 + j, lda));
+  return Y;
+}
+
+/* ------------------------------------------------------------------ */
 /* Blocked right-looking Cholesky (lower) with ABFT.                  */
 /* ------------------------------------------------------------------ */
 typedef struct { const double* A; int lda; int c0; } lctx_t;
@@ -726,13 +888,23 @@ int orc_abft_potrf(int n, int nb, double* A, int lda, int prec, int protect, dou
           AT(A, i, jj, lda) = rs(prec, AT(A, i, jj, lda) - AT(A, i, j, lda) * AT(A, jj, j, lda));
     }
     if (info) break;
-    /* PU: L21 = A21 * L_kk^{-T}, row by row forward substitution */
-    for (int i = c1; i < n; ++i)
+    /* PU: L21 = A21 * L_kk^{-T}, forward substitution along each row:
+       element (i, j) subtracts L(i, p) L(j, p) for p = c0 .. j-1 in order,
+       then is divided by L(j, j) */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int ib = c1; ib < n; ib += RB) {
+      int ie = imin(ib + RB, n);
       for (int j = c0; j < c1; ++j) {
-        double s = AT(A, i, j, lda);
-        for (int p = c0; p < j; ++p) s = rs(prec, s - AT(A, i, p, lda) * AT(A, j, p, lda));
-        AT(A, i, j, lda) = rs(prec, s / AT(A, j, j, lda));
+        double* aj = &AT(A, 0, j, lda);
+        for (int p = c0; p < j; ++p) {
+          const double* ap = &AT(A, 0, p, lda);
+          double ljp = AT(A, j, p, lda);
+          for (int i = ib; i < ie; ++i) aj[i] = rs(prec, aj[i] - ap[i] * ljp);
+        }
+        double d = AT(A, j, j, lda);
+        for (int i = ib; i < ie; ++i) aj[i] = rs(prec, aj[i] / d);
       }
+    }
     lctx_t l = {A, lda, c0};
     if (protect) {
       /* panel check: e^T A_Ik = (e^T L_I) L_kk^T for every tile-row I >= k */
@@ -740,12 +912,14 @@ int orc_abft_potrf(int n, int nb, double* A, int lda, int prec, int protect, dou
     }
     if (c1 >= n) break;
     /* TMU: A22 -= L21 L21^T (lower part), operands rounded for MP forms */
-    for (int j = c1; j < n; ++j)
-      for (int i = j; i < n; ++i) {
-        double acc = 0.0;
-        for (int p = c0; p < c1; ++p) acc = rs(prec, acc + rop(prec, AT(A, i, p, lda)) * rop(prec, AT(A, j, p, lda)));
-        AT(A, i, j, lda) = rs(prec, AT(A, i, j, lda) - acc);
-      }
+    {
+      int m = n - c1;
+      double* X = copy_x(prec, A, lda, c1, m, c0, w);
+      double* Y = copy_y(prec, A, lda, c0, w, c1, m, 1);
+      update_rows(prec, m, m, w, X, m, Y, w, &AT(A, c1, c1, lda), lda, 1);
+      free(X);
+      free(Y);
+    }
     if (protect) {
       zero_g(&c);
       carry(&c, A, lda, k + 1, k + 1, c0, w, k, XM_LOWER, y_lt, &l);
@@ -792,21 +966,21 @@ int orc_abft_getrf(int n, int nb, double* A, int lda, int32_t* ipiv, int prec, i
     int mp = n - c0;
     if (protect)
       for (int j = 0; j < w; ++j) for (int i = 0; i < mp; ++i) porig[i + (size_t)j * mp] = AT(A, c0 + i, c0 + j, lda);
-    /* PD: getf2 on the panel; each swap is applied to the whole row */
+    /* PD: getf2 on the panel.  Each interchange is applied to the panel
+       columns at once and to the other columns after the panel (column by
+       column, in the panel's order): nothing else reads those columns in
+       between, so every value is the same as with whole-row swaps. */
     for (int j = c0; j < c1; ++j) {
       int p = pick_pivot(A, lda, j, j, n);
       ipiv[j] = p + 1;
       if (p != j) {
         if (protect) {
-          /* checksum fix-up for the swap: panel columns use the original
-             panel values, the trailing columns the current ones; row
-             checksums move with their rows */
+          /* checksum fix-up of the panel columns, from the original panel
+             values; row checksums move with their rows */
           int Ir = j / nb, Ip = p / nb;
           double wr = (double)(j - Ir * nb + 1), wp = (double)(p - Ip * nb + 1);
-          for (int jj = c0; jj < n; ++jj) {
-            double ar, ap;
-            if (jj < c1) { ar = porig[(j - c0) + (size_t)(jj - c0) * mp]; ap = porig[(p - c0) + (size_t)(jj - c0) * mp]; }
-            else { ar = AT(A, j, jj, lda); ap = AT(A, p, jj, lda); }
+          for (int jj = c0; jj < c1; ++jj) {
+            double ar = porig[(j - c0) + (size_t)(jj - c0) * mp], ap = porig[(p - c0) + (size_t)(jj - c0) * mp];
             AT(c.cc, 2 * Ir, jj, c.ldc) += ap - ar;
             AT(c.cc, 2 * Ir + 1, jj, c.ldc) += wr * (ap - ar);
             AT(c.cc, 2 * Ip, jj, c.ldc) += ar - ap;
@@ -819,35 +993,61 @@ int orc_abft_getrf(int n, int nb, double* A, int lda, int32_t* ipiv, int prec, i
           }
           swap_rows(c.rc, c.ldr, j, p, 0, 2 * c.N);
         }
-        swap_rows(A, lda, j, p, 0, n);
+        swap_rows(A, lda, j, p, c0, c1);
       }
       double piv = AT(A, j, j, lda);
       if (piv == 0.0) { if (!info) info = j + 1; continue; }
       for (int i = j + 1; i < n; ++i) AT(A, i, j, lda) = rs(prec, AT(A, i, j, lda) / piv);
+#pragma omp parallel for schedule(static) if ((size_t)(c1 - j) * (size_t)(n - j) > ((size_t)1 << 16))
       for (int cc = j + 1; cc < c1; ++cc) {
         double u = AT(A, j, cc, lda);
         for (int i = j + 1; i < n; ++i) AT(A, i, cc, lda) = rs(prec, AT(A, i, cc, lda) - AT(A, i, j, lda) * u);
       }
     }
+    /* the panel's interchanges on the columns left and right of it; each
+       trailing column's checksum fix-up uses the column's current values at
+       each interchange */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int jj = 0; jj < n; ++jj) {
+      if (jj >= c0 && jj < c1) continue;
+      for (int j = c0; j < c1; ++j) {
+        int p = ipiv[j] - 1;
+        if (p == j) continue;
+        double ar = AT(A, j, jj, lda), ap = AT(A, p, jj, lda);
+        if (protect && jj >= c1) {
+          int Ir = j / nb, Ip = p / nb;
+          double wr = (double)(j - Ir * nb + 1), wp = (double)(p - Ip * nb + 1);
+          AT(c.cc, 2 * Ir, jj, c.ldc) += ap - ar;
+          AT(c.cc, 2 * Ir + 1, jj, c.ldc) += wr * (ap - ar);
+          AT(c.cc, 2 * Ip, jj, c.ldc) += ar - ap;
+          AT(c.cc, 2 * Ip + 1, jj, c.ldc) += wp * (ar - ap);
+        }
+        AT(A, j, jj, lda) = ap;
+        AT(A, p, jj, lda) = ar;
+      }
+    }
     uctx_t u = {A, lda, c0, c1};
     if (protect) panel_check(&c, A, lda, k, c.N, c0, w, k, XM_UNIT, c0, c1, m_ukk, NULL, &u);
     if (c1 >= n) break;
-    /* PU: U12 = L11^{-1} A12 (unit lower forward substitution per column) */
+    /* PU: U12 = L11^{-1} A12, unit lower forward substitution per column:
+       element (i, j) subtracts L(i, p) U(p, j) for p = c0 .. i-1 in order */
+#pragma omp parallel for schedule(dynamic, 16)
     for (int j = c1; j < n; ++j)
-      for (int i = c0; i < c1; ++i) {
-        double s = AT(A, i, j, lda);
-        for (int p = c0; p < i; ++p) s = rs(prec, s - AT(A, i, p, lda) * AT(A, p, j, lda));
-        AT(A, i, j, lda) = s;
+      for (int p = c0; p < c1; ++p) {
+        double u = AT(A, p, j, lda);
+        for (int i = p + 1; i < c1; ++i) AT(A, i, j, lda) = rs(prec, AT(A, i, j, lda) - AT(A, i, p, lda) * u);
       }
     /* PU check: (e^T L11) U12 = e^T A12 on tile-row k */
     if (protect) panel_check(&c, A, lda, k, k + 1, c0, w, k, XM_UNIT, c1, n, m_u12, NULL, &u);
     /* TMU: A22 -= L21 U12 */
-    for (int j = c1; j < n; ++j)
-      for (int i = c1; i < n; ++i) {
-        double acc = 0.0;
-        for (int p = c0; p < c1; ++p) acc = rs(prec, acc + rop(prec, AT(A, i, p, lda)) * rop(prec, AT(A, p, j, lda)));
-        AT(A, i, j, lda) = rs(prec, AT(A, i, j, lda) - acc);
-      }
+    {
+      int m = n - c1;
+      double* X = copy_x(prec, A, lda, c1, m, c0, w);
+      double* Y = copy_y(prec, A, lda, c0, w, c1, m, 0);
+      update_rows(prec, m, m, w, X, m, Y, w, &AT(A, c1, c1, lda), lda, 0);
+      free(X);
+      free(Y);
+    }
     if (protect) {
       zero_g(&c);
       carry(&c, A, lda, k + 1, k + 1, c0, w, k, XM_FULL, y_u12, &u);
@@ -870,6 +1070,7 @@ static void larft(int n, const double* A, int lda, const double* tau, int c0, in
     for (int i = 0; i < w; ++i) T[i + j * w] = 0.0;
     T[j + j * w] = tau[c0 + j];
     double* g = malloc(sizeof(double) * (j + 1));
+#pragma omp parallel for schedule(static) if ((size_t)j * (size_t)(n - c0) > ((size_t)1 << 16))
     for (int q = 0; q < j; ++q) {
       /* V(:,q)^T V(:,j), V(c0+j, j) = 1, rows above c0+j of column j are 0 */
       double s = AT(A, c0 + j, c0 + q, lda); /* V(c0+j, q) * 1 */
@@ -882,6 +1083,64 @@ static void larft(int n, const double* A, int lda, const double* tau, int c0, in
       T[i + j * w] = -tau[c0 + j] * s;
     }
     free(g);
+  }
+}
+
+/* W = V^T C and W2 = T^T W for C = columns [c1, n) of rows [c0, n):
+   W(p, j) = C(c0+p, j) + sum over i > c0+p of V(i, p) C(i, j), each a plain
+   running sum over i in ascending order, then
+   W2(p, j) = sum over q <= p of T(q, p) W(q, j) in ascending q.
+   Blocks of 8 values of p and 4 columns advance their 32 independent sums
+   together (lanes of a v4d are the 4 columns of one p), which changes no
+   sum's order. */
+static void qr_w(int n, const double* A, int lda, int c0, int w, int c1, const double* T, double* W2) {
+  int ncol = n - c1;
+#pragma omp parallel
+  {
+    double* wv = malloc(sizeof(double) * 4 * (size_t)w);
+    double* ct = malloc(sizeof(double) * 4 * (size_t)(n - c0) + 32);
+#pragma omp for schedule(dynamic, 1)
+    for (int jb = 0; jb < ncol; jb += 4) {
+      int nj = imin(4, ncol - jb);
+      /* rows of the 4-column block side by side: ct[4 (i - c0) + jj] = C(i, j) */
+      for (int i = c0; i < n; ++i)
+        for (int jj = 0; jj < 4; ++jj) ct[4 * (size_t)(i - c0) + jj] = jj < nj ? AT(A, i, c1 + jb + jj, lda) : 0.0;
+      for (int p0 = 0; p0 < w; p0 += 8) {
+        int np = imin(8, w - p0);
+        double sacc[8][4];
+        for (int q = 0; q < np; ++q)
+          for (int jj = 0; jj < 4; ++jj) sacc[q][jj] = ct[4 * (size_t)(p0 + q) + jj];
+        /* rows inside the block of p: only the sums that have started */
+        for (int i = c0 + p0 + 1; i < c0 + p0 + np && i < n; ++i)
+          for (int q = 0; q < np; ++q)
+            if (c0 + p0 + q < i)
+              for (int jj = 0; jj < 4; ++jj) sacc[q][jj] += AT(A, i, c0 + p0 + q, lda) * ct[4 * (size_t)(i - c0) + jj];
+        if (np == 8) {
+          v4d a[8];
+          for (int q = 0; q < 8; ++q) memcpy(&a[q], sacc[q], sizeof(v4d));
+          for (int i = c0 + p0 + 8; i < n; ++i) {
+            v4d cv;
+            memcpy(&cv, ct + 4 * (size_t)(i - c0), sizeof cv);
+            for (int q = 0; q < 8; ++q) a[q] = a[q] + AT(A, i, c0 + p0 + q, lda) * cv;
+          }
+          for (int q = 0; q < 8; ++q) memcpy(sacc[q], &a[q], sizeof(v4d));
+        } else {
+          for (int i = c0 + p0 + np; i < n; ++i)
+            for (int q = 0; q < np; ++q)
+              for (int jj = 0; jj < 4; ++jj) sacc[q][jj] += AT(A, i, c0 + p0 + q, lda) * ct[4 * (size_t)(i - c0) + jj];
+        }
+        for (int q = 0; q < np; ++q)
+          for (int jj = 0; jj < 4; ++jj) wv[(p0 + q) + (size_t)jj * w] = sacc[q][jj];
+      }
+      for (int jj = 0; jj < nj; ++jj)
+        for (int p = 0; p < w; ++p) {
+          double s = 0.0;
+          for (int q = 0; q <= p; ++q) s += T[q + p * w] * wv[q + (size_t)jj * w];
+          W2[p + (size_t)(c1 + jb + jj) * w] = s;
+        }
+    }
+    free(wv);
+    free(ct);
   }
 }
 
@@ -953,30 +1212,29 @@ int orc_abft_geqrf(int n, int nb, double* A, int lda, double* tau, int protect, 
     }
     if (c1 >= n) break;
     /* TMU (larfb): W = V^T C, W2 = T^T W, C -= V W2 over rows [c0,n), cols [c1,n) */
-    for (int j = c1; j < n; ++j) {
-      double* wv = malloc(sizeof(double) * w);
-      for (int p = 0; p < w; ++p) {
-        double s = AT(A, c0 + p, j, lda);
-        for (int i = c0 + p + 1; i < n; ++i) s += AT(A, i, c0 + p, lda) * AT(A, i, j, lda);
-        wv[p] = s;
-      }
-      for (int p = 0; p < w; ++p) {
-        double s = 0.0;
-        for (int q2 = 0; q2 <= p; ++q2) s += T[q2 + p * w] * wv[q2];
-        W2[p + (size_t)j * w] = s;
-      }
-      free(wv);
-    }
-    for (int j = c1; j < n; ++j)
-      for (int i = c0; i < n; ++i) {
-        double acc = 0.0;
-        int pmax = (i - c0 < w - 1) ? i - c0 : w - 1;
-        for (int p = 0; p <= pmax; ++p) {
-          double v = (i - c0 == p) ? 1.0 : AT(A, i, c0 + p, lda);
-          acc += v * W2[p + (size_t)j * w];
+    qr_w(n, A, lda, c0, w, c1, T, W2);
+    /* C(i, j) -= sum over p <= min(i - c0, w - 1) of V(i, p) W2(p, j), with
+       V(c0 + p, p) = 1, accumulated in ascending p: the rows of V's unit
+       triangle term by term, the rows below it (all w terms, no unit
+       entry) with the update loop above */
+    {
+      int mt = imin(w, n - c0);
+#pragma omp parallel for schedule(dynamic, 16)
+      for (int j = c1; j < n; ++j) {
+        const double* y = W2 + (size_t)j * w;
+        for (int i = c0; i < c0 + mt; ++i) {
+          double acc = 0.0;
+          for (int p = 0; p <= i - c0; ++p) acc += (i - c0 == p ? 1.0 : AT(A, i, c0 + p, lda)) * y[p];
+          AT(A, i, j, lda) -= acc;
         }
-        AT(A, i, j, lda) -= acc;
       }
+      if (n - c0 > w) {
+        double* X = copy_x(PR64, A, lda, c0 + w, n - c0 - w, c0, w);
+        update_rows(PR64, n - c0 - w, n - c1, w, X, n - c0 - w, W2 + (size_t)c1 * w, w, &AT(A, c0 + w, c1, lda), lda,
+                    0);
+        free(X);
+      }
+    }
     if (protect) {
       zero_g(&c);
       carry(&c, A, lda, k, k + 1, c0, w, k, XM_UNIT, y_w2, &q);
@@ -1138,6 +1396,7 @@ int orc_gesv_mp(int n, int nb, const double* A, int lda, const double* b, double
   double prev = INFINITY;
   int it;
   for (it = 1; it <= max_iter; ++it) {
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
       double s = b[i];
       for (int j = 0; j < n; ++j) s -= AT(A, i, j, lda) * x[j];
@@ -1183,6 +1442,7 @@ void orc_solve_ref(int n, const double* A, int lda, const double* b, double* x, 
   lu_solve(n, F, n, ipiv, x, PR64);
   double* r = malloc(sizeof(double) * n);
   for (int it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
       double hi = b[i], lo = 0.0;
       for (int j = 0; j < n; ++j) {

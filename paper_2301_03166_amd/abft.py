@@ -151,10 +151,26 @@ class Handle:
                    "abft_create")
         self._ws = {}
 
+    def close(self):
+        """Finish the handle's work and destroy it (abft_destroy synchronizes
+        its streams first).  Call it before the process exits: a handle left to
+        the interpreter's teardown may be destroyed after the HIP runtime."""
+        h, self._h = self._h, None
+        if h:
+            self.torch.cuda.synchronize(self.device)
+            self._ws.clear()
+            _check(lib().abft_destroy(h), "abft_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
         try:
-            if self._h:
-                lib().abft_destroy(self._h)
+            self.close()
         except Exception:
             pass
 

@@ -180,6 +180,7 @@ def main(argv=None):
                 table.setdefault("batched", {})[f"{op}:{prec}"] = r
                 print(f"[autotune] batched {op} {prec}: best wgs_per_cu={r['best']}  {r['ms']}", flush=True)
                 save(table, args.out)
+    h.close()
     print(f"[autotune] done in {time.time() - t0:.1f} s -> {args.out}", flush=True)
 
 

@@ -360,29 +360,11 @@ __device__ int wave_tile32(const T* A, int64_t lda, int I, int J, int h, int w, 
   return nfl;
 }
 
-#ifdef ABFT_LEAF_TIMING
-#define BT_DECL unsigned long long bt_t = __builtin_amdgcn_s_memtime(), bt_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#define BT_MARK(k)                                          \
-  do {                                                      \
-    unsigned long long bt_n = __builtin_amdgcn_s_memtime(); \
-    bt_acc[k] += bt_n - bt_t;                               \
-    bt_t = bt_n;                                            \
-  } while (0)
-#define BT_PRINT()                                                                                              \
-  if (blockIdx.x == 0 && threadIdx.x == 0)                                                                       \
-    printf("batched n=%d: init %llu panel %llu swaps %llu u12 %llu tmu %llu carry %llu verify %llu\n", n,        \
-           bt_acc[0], bt_acc[1], bt_acc[2], bt_acc[3], bt_acc[4], bt_acc[5], bt_acc[6]);
-#else
-#define BT_DECL
-#define BT_MARK(k)
-#define BT_PRINT()
-#endif
 
 template <typename T, int CHOL>
 __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, BatchChk c, int protect, double tsu,
                            const abft_fault* faults, int nfaults, int32_t* info, abft_report* rep,
                            unsigned char* smem) {
-  BT_DECL
   const int tid = threadIdx.x;
   const int N = (n + BNB - 1) / BNB;
   const int ldc = 2 * BN;
@@ -429,7 +411,6 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
     }
     __syncthreads();
   }
-  BT_MARK(0);
   for (int k = 0; k < N; ++k) {
     const int c0 = k * BNB, w = min(BNB, n - c0), c1 = c0 + w, mrows = n - c0;
     // ---- panel into LDS
@@ -532,7 +513,6 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
       if (!CHOL || i >= j) A[(c0 + i) + (int64_t)(c0 + j) * lda] = P[i * ldp + j];
     }
     __syncthreads();
-    BT_MARK(1);
     if (!CHOL) {
       // interchanges outside the panel: every thread applies all of them, in
       // order, to its own columns (checksums follow the rows), so no barrier
@@ -574,7 +554,6 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
           }
       __syncthreads();
     }
-    BT_MARK(2);
     if (c1 >= n) break;
     if (!CHOL) {
       // panel update U12 = L11^{-1} A12, one thread per column
@@ -593,11 +572,8 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
       __syncthreads();
     }
     // ---- trailing update and checksum carry
-    BT_MARK(3);
     batch_tmu<T, CHOL>(A, lda, n, c0, w, P, ldp, Uc);
-    BT_MARK(4);
     if (protect) batch_carry<T, CHOL>(A, lda, n, k, w, P, ldp, c, reinterpret_cast<double*>(Uc));
-    BT_MARK(5);
     // ---- planned faults of this matrix and iteration
     if (tid == 0)
       for (int f = 0; f < nfaults; ++f) {
@@ -684,9 +660,7 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
         }
       }
     }
-    BT_MARK(6);
   }
-  BT_PRINT()
   if (tid == 0) {
     if (rep->first_flag_iter == 0x7fffffff) rep->first_flag_iter = -1;
     if (rep->nev > ABFT_MAX_EVENTS) rep->nev = ABFT_MAX_EVENTS;

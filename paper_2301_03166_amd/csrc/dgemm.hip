@@ -308,16 +308,6 @@ __global__ __launch_bounds__(256, BK == 16 ? 2 : 1) void k_dgemm(int M, int N, i
   }
 }
 
-// K step of the product kernel: 16 unless ABFT_DGEMM_BK=32 in the environment
-// (read once; a tuning override)
-static int dgemm_bk() {
-  static const int bk = [] {
-    const char* e = getenv("ABFT_DGEMM_BK");
-    return (e && atoi(e) == 32) ? 32 : 16;
-  }();
-  return bk;
-}
-
 // Returns 1 when the product was launched here, 0 when the caller should use
 // the general kernel (unsupported option combination or alignment), <0 on error.
 // fa: 0 plain, 1 unit-lower A, 2 |A|, 3 |unit-lower A|; fb: 0 plain, 1
@@ -334,16 +324,9 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, 
   const int64_t nt = tri ? tM * (tM + 1) / 2 : tM * tN;
   if (nt > 0x7fffffff) return 0;
   const dim3 grid((unsigned)nt, (unsigned)S), block(256);
-  const bool bk16 = dgemm_bk() == 16;
-#define DG_LAUNCH(TA_, TB_, FA_, LO_, TRI_, RO_)                                                                    \
-  do {                                                                                                             \
-    if (bk16)                                                                                                      \
-      hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, TRI_, RO_, 16>), grid, block, 0, s, m, n, k, alpha, A, lda, B,  \
-                         ldb, beta, C, ldc, doff, kc, ws);                                                         \
-    else                                                                                                           \
-      hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, TRI_, RO_, 32>), grid, block, 0, s, m, n, k, alpha, A, lda, B,  \
-                         ldb, beta, C, ldc, doff, kc, ws);                                                         \
-  } while (0)
+#define DG_LAUNCH(TA_, TB_, FA_, LO_, TRI_, RO_)                                                                  \
+  hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, TRI_, RO_, 16>), grid, block, 0, s, m, n, k, alpha, A, lda, B, ldb, \
+                     beta, C, ldc, doff, kc, ws)
 #define DG_CASE(TA_, TB_, FA_, LO_)                                                                              \
   if (ta == TA_ && tb == TB_ && modes == FA_ && lower == LO_) {                                                    \
     if (LO_ && tri) {                                                                                              \

@@ -808,21 +808,26 @@ int abft_create(abft_handle* h, void* stream) {
 }
 
 int abft_destroy(abft_handle h) {
-  if (h && h->ev) {
+  if (!h) return 0;
+  // finish every call still in flight on the handle's streams before their
+  // streams, events and graphs go away
+  int rc = 0;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) rc = ABFT_ERR_HIP;
+  if (h->side && hipStreamSynchronize(h->side) != hipSuccess) rc = ABFT_ERR_HIP;
+  if (h->cap && hipStreamSynchronize(h->cap) != hipSuccess) rc = ABFT_ERR_HIP;
+  if (h->ev) {
     for (int i = 0; i < h->nev; ++i) (void)hipEventDestroy(h->ev[i]);
     free(h->ev);
   }
-  if (h) {
-    for (int i = 0; i < h->ngraphs; ++i) (void)hipGraphExecDestroy(h->graphs[i].exec);
-    if (h->cap) (void)hipStreamDestroy(h->cap);
-    if (h->side) {
-      (void)hipStreamDestroy(h->side);
-      (void)hipEventDestroy(h->fork_ev);
-      (void)hipEventDestroy(h->join_ev);
-    }
+  for (int i = 0; i < h->ngraphs; ++i) (void)hipGraphExecDestroy(h->graphs[i].exec);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  if (h->side) {
+    (void)hipStreamDestroy(h->side);
+    (void)hipEventDestroy(h->fork_ev);
+    (void)hipEventDestroy(h->join_ev);
   }
   free(h);
-  return 0;
+  return rc;
 }
 
 int abft_set_stream(abft_handle h, void* stream) {

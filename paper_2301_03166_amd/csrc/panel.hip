@@ -270,23 +270,6 @@ __global__ __launch_bounds__(256) void k_trsm_llu_blk(T* A, int64_t lda, int64_t
 // index on ties; row interchanges inside the leaf columns only (the caller
 // applies them to the other columns).
 // ---------------------------------------------------------------------------
-#ifdef ABFT_LEAF_TIMING
-#define LT_DECL unsigned long long lt_t = __builtin_amdgcn_s_memtime(), lt_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#define LT_MARK(k)                                        \
-  do {                                                    \
-    unsigned long long lt_n = __builtin_amdgcn_s_memtime(); \
-    lt_acc[k] += lt_n - lt_t;                             \
-    lt_t = lt_n;                                          \
-  } while (0)
-#define LT_PRINT(name)                                                                                          \
-  if (blockIdx.x == 0 && threadIdx.x == 0 && c0 < 64)                                                          \
-    printf("%s c0=%ld G=%d R=%d w=%d: %llu %llu %llu %llu %llu %llu %llu %llu\n", name, (long)c0, (int)gridDim.x, R, w, \
-           lt_acc[0], lt_acc[1], lt_acc[2], lt_acc[3], lt_acc[4], lt_acc[5], lt_acc[6], lt_acc[7]);
-#else
-#define LT_DECL
-#define LT_MARK(k)
-#define LT_PRINT(name)
-#endif
 
 template <typename T>
 __device__ __forceinline__ bool better(double a, int64_t ia, double b, int64_t ib) {
@@ -387,7 +370,6 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
                                                     int32_t* ipiv, int32_t* info, uint64_t* recs, uint32_t seq0,
                                                     abft_report* rep) {
   extern __shared__ unsigned char smem_raw[];
-  LT_DECL
   T* Ld = reinterpret_cast<T*>(smem_raw);  // R x (w+1)
   const int ldl = w + 1;
   __shared__ double prow[CLEAF], orow[CLEAF];
@@ -441,7 +423,6 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
       ll_put2(mine + 3 + 2 * tid, bl == INT64_MAX ? 0.0 : (double)Ld[(bl - rbeg) * ldl + tid], seq);
       if (g == 0) ll_put2(rowd + 2 * tid, (double)Ld[(d - rbeg) * ldl + tid], seq);
     }
-    LT_MARK(0);
     // every workgroup picks the same winner: one record per thread (its three
     // words loaded together), then a block argmax (largest |value|, first
     // row index on ties; the row index identifies its workgroup, so the
@@ -458,10 +439,11 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
         for (int u = 0; u < 3; ++u) ll_poll(rq + u, wd[u], seq, rep);
         const double vq = ll_dbl(wd[0], wd[1]);
         const uint32_t iq32 = (uint32_t)(wd[2] >> 32);
-        const int iq = iq32 == LL_NONE ? INT_MAX : (int)iq32;
+        // a record that expired unwritten (ABFT_ST_INTERNAL already set) may
+        // decode to any index: only rows [d, m) count as candidates
+        const int iq = (iq32 == LL_NONE || (int64_t)iq32 < d || (int64_t)iq32 >= m) ? INT_MAX : (int)iq32;
         if (vq >= 0 && better<T>(vq, iq, v, ii)) { v = vq; ii = iq; }
       }
-      LT_MARK(1);
       wave_argmax(v, ii);
       if (lane == 0) { wv_val[wv] = v; wv_idx[wv] = ii == INT_MAX ? INT64_MAX : (int64_t)ii; }
       __syncthreads();
@@ -472,13 +454,15 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
           if (better<T>(wv_val[q], wv_idx[q], best, bidx)) { best = wv_val[q]; bidx = wv_idx[q]; }
         // the winning row names its workgroup (rows [c0 + g R, c0 + (g+1) R))
         int bg = bidx == INT64_MAX ? 0 : (int)((bidx - c0) / R);
-        if (bidx == INT64_MAX) bidx = d;
+        if (bidx == INT64_MAX || bg < 0 || bg >= G) {  // (bounds kept on the degraded path too)
+          bidx = d;
+          bg = 0;
+        }
         s_piv = bidx;
         s_pg = bg;
       }
       __syncthreads();
     }
-    LT_MARK(2);
     const int64_t p = s_piv;
     const int pg = s_pg;
     const bool own_p = p != d && p >= rbeg && p < rbeg + rows;
@@ -487,7 +471,6 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
       if (own_p) orow[tid] = ll_get2b(rowd + 2 * tid, seq, rep);
     }
     __syncthreads();
-    LT_MARK(3);
     if (p != d) {
       if (g == 0 && tid < w) Ld[(d - rbeg) * ldl + tid] = (T)prow[tid];
       if (own_p && tid < w) Ld[(p - rbeg) * ldl + tid] = (T)orow[tid];
@@ -508,14 +491,11 @@ __global__ __launch_bounds__(256) void k_getrf_leaf(T* A, int64_t lda, int64_t m
       }
     }
     __syncthreads();
-    LT_MARK(4);
   }
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
     A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
   }
-  LT_MARK(5);
-  LT_PRINT("lu_leaf")
 }
 
 // ---------------------------------------------------------------------------
@@ -549,7 +529,6 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
                                                     double* tau, double* Tm, int ldt, int toff, uint64_t* recs,
                                                     uint32_t seq0, abft_report* rep) {
   extern __shared__ unsigned char smem_raw[];
-  LT_DECL
   double* Ld = reinterpret_cast<double*>(smem_raw);  // R x (w+1)
   const int ldl = w + 1;
   __shared__ double part[4][CLEAF];
@@ -630,7 +609,6 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
       ll_put2(r1 + (size_t)g * 2 * w + 2 * tid, ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid], seq);
       if (g == 0) ll_put2(rdw + 2 * tid, Ld[(d - rbeg) * ldl + tid], seq);
     }
-    LT_MARK(0);
     // level 1: the group's first workgroup adds its members' rows
     if (g % grp == 0) {
       qpart[wq][e] = sum4(r1, g + wq, min(G, g + grp), seq);
@@ -639,7 +617,6 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
         ll_put2(r2 + (size_t)(g / grp) * 2 * w + 2 * tid,
                 ((qpart[0][tid] + qpart[1][tid]) + qpart[2][tid]) + qpart[3][tid], seq);
     }
-    LT_MARK(1);
     // level 2: every workgroup adds the group sums (and reads row d)
     gpart[wq][e] = sum4(r2, wq, NG, seq);
     if (tid < w) orow[tid] = ll_get2b(rdw + 2 * tid, seq, rep);
@@ -648,7 +625,6 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
     if (tid < w) sv = ((gpart[0][tid] + gpart[1][tid]) + gpart[2][tid]) + gpart[3][tid];
     if (tid < w) fvec[tid] = sv;  // the Gram row, for thread 0's reflector
     __syncthreads();
-    LT_MARK(2);
     if (tid == 0) {
       const double alpha = orow[j], s2 = fvec[j];
       if (s2 == 0.0) {
@@ -682,13 +658,11 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
       }
     }
     __syncthreads();
-    LT_MARK(3);
   }
   for (int idx = tid; idx < rows * w; idx += 256) {
     int i = idx % rows, j = idx / rows;
     A[(rbeg + i) + (c0 + j) * lda] = Ld[i * ldl + j];
   }
-  LT_MARK(4);
   if (g == 0) {
     // T from the staged dot products: T(0:j, j) = -tau_j T(0:j, 0:j) z_j
     __syncthreads();
@@ -724,8 +698,6 @@ __global__ __launch_bounds__(256) void k_geqrf_leaf(double* A, int64_t lda, int6
     for (int e = tid; e < w * w; e += 256)
       Tm[(toff + e % w) + (int64_t)(toff + e / w) * ldt] = Tl[(e % w) * ldl + e / w];
   }
-  LT_MARK(5);
-  LT_PRINT("qr_leaf")
 }
 
 // ---------------------------------------------------------------------------

@@ -260,12 +260,6 @@ __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h,
     cs.ci = ci;
     cs.cj = cj;
     cs.kind = (repair == -1) ? 0 : (ci >= 0 ? 1 : (repair ? 2 : 3));
-#ifdef ABFT_DEBUG_CORRECT
-    printf("correct I=%d J=%d diag=%d nflag=%d nFe=%d nGe=%d nFw=%d nGw=%d jf0=%d jf1=%d ig=%d -> ci=%d cj=%d kind=%d\n",
-           I, J, (int)diag, tf.nflag, nFe, nGe, nFw, nGw, jf0, jf1, ig, ci, cj, cs.kind);
-    for (int j = 0; j < w; ++j)
-      if (tf.fe[j] || tf.fw[j]) printf("  col %d de=%g dw=%g fe=%d fw=%d\n", j, tf.de[j], tf.dw[j], tf.fe[j], tf.fw[j]);
-#endif
   }
   __syncthreads();
   if (cs.kind == 1) {
@@ -289,15 +283,6 @@ __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h,
     tile_sums(A, lda, r0, c0, h, w, diag, ts);
     tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu, ci, cj, diag);
     if (tf.nflag != 0) {
-#ifdef ABFT_DEBUG_CORRECT
-      if (threadIdx.x == 0) {
-        printf("recheck failed: nflag=%d\n", tf.nflag);
-        for (int j = 0; j < w; ++j)
-          if (tf.fe[j] || tf.fw[j]) printf("  col %d de=%g dw=%g\n", j, tf.de[j], tf.dw[j]);
-        for (int i = 0; i < h; ++i)
-          if (tf.ge[i] || tf.gw[i]) printf("  row %d de=%g dw=%g\n", i, tf.he[i], tf.hw[i]);
-      }
-#endif
       if (threadIdx.x == 0) {
         A[(r0 + ci) + (c0 + cj) * lda] = (T)cs.old;
         cs.kind = 3;

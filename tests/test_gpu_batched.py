@@ -12,7 +12,8 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def h():
     from paper_2301_03166_amd import abft
-    return abft.Handle()
+    with abft.Handle() as hh:
+        yield hh
 
 
 def dev(a, dtype=None):

@@ -16,7 +16,8 @@ U64 = 2.0 ** -53
 @pytest.fixture(scope="module")
 def h():
     from paper_2301_03166_amd import abft
-    return abft.Handle()
+    with abft.Handle() as hh:
+        yield hh
 
 
 def dev(a):

@@ -17,7 +17,8 @@ def h():
     import torch
     from paper_2301_03166_amd import abft
     assert torch.cuda.is_available()
-    return abft.Handle()
+    with abft.Handle() as hh:
+        yield hh
 
 
 def dev(a):

@@ -421,3 +421,33 @@ def test_gemm_definition_brute_force(ta, tb, unit, lower):
                 b = B[j, p] if tb else B[p, j]
                 s += a * b
             assert out[i, j] == beta * C[i, j] + alpha * s
+
+
+# ------------------------------------------------------------- threading
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
+def test_threads_do_not_change_results(kind):
+    """The oracle's parallel loops give every element to one thread with the
+    serial order of operations: one thread and several threads must agree bit
+    for bit, on the factors, the reports and with a planned flip."""
+    n, nb = 700, 128
+    A = gen.spd(n, 7) if kind == "chol" else gen.general(n, 7)
+    f = gen.fault_plan(kind, n, nb, seed=3)
+    f["bit"] = 60
+    outs = []
+    saved = oracle.get_threads()
+    try:
+        for t in (1, 5):
+            oracle.set_threads(t)
+            B = A.copy(order="F")
+            if kind == "chol":
+                aux, rep = oracle.potrf(B, nb, faults=[f])
+            elif kind == "lu":
+                aux, _, rep = oracle.getrf(B, nb, faults=[f])
+            else:
+                aux, rep = oracle.geqrf(B, nb, faults=[f])
+            outs.append((B, np.asarray(aux), rep.status, rep.corrected, rep.max_ratio, rep.events()))
+    finally:
+        oracle.set_threads(saved)
+    (B1, a1, *r1), (B2, a2, *r2) = outs
+    assert np.array_equal(B1, B2) and np.array_equal(a1, a2) and r1 == r2
+    assert r1[1] == 1  # the flip was found and corrected
