@@ -78,6 +78,7 @@ def lib():
         _lib.orc_abft_geqrf.argtypes = [i, i, P, i, P, i, d, P, i, P]
         _lib.orc_encode.argtypes = [i, i, P, i, i, P, i, P, i]
         _lib.orc_verify.argtypes = [i, i, P, i, i, P, i, P, i, d, P, P]
+        _lib.orc_verify_correct.argtypes = [i, i, P, i, P, P, d, P]
         _lib.orc_getrs.argtypes = [i, P, i, P, P]
         _lib.orc_potrs.argtypes = [i, P, i, P]
         _lib.orc_gesv_mp.argtypes = [i, i, P, i, P, P, i, i, i, P]
@@ -182,6 +183,17 @@ def verify(A, nb, colchk, rowchk, tau_scale=4.0):
     nfl = lib().orc_verify(m, n, _f64(A), m, nb, _f64(colchk), colchk.shape[0], _f64(rowchk), rowchk.shape[0],
                            tau_scale, flags.ctypes.data, C.byref(mr))
     return nfl, flags, mr.value
+
+
+def verify_correct(A, nb, colchk, rowchk, tau_scale=4.0):
+    """Verify square A (in place) against its checksums with the
+    factorizations' locate / correct rules; returns the Report.  colchk and
+    rowchk (from encode) are refreshed in place."""
+    n = A.shape[0]
+    assert A.shape == (n, n) and colchk.shape == (2 * -(-n // nb), n) and rowchk.shape == (n, 2 * -(-n // nb))
+    rep = Report()
+    lib().orc_verify_correct(n, nb, _f64(A), n, _f64(colchk), _f64(rowchk), tau_scale, C.byref(rep))
+    return rep
 
 
 def getrs(LU, ipiv, b):

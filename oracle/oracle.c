@@ -1310,6 +1310,25 @@ int orc_verify(int m, int n, const double* A, int lda, int nb, const double* col
   return nfl;
 }
 
+/* Verify a square matrix against its per-tile checksums and send flagged
+   tiles through the locate / correct rules of the factorizations (the
+   detection interval here is the single call).  colchk is (2N) x n with
+   ld 2N, rowchk n x (2N) with ld n; both are refreshed in place: clean and
+   corrected tiles get sums recomputed from the data. */
+int orc_verify_correct(int n, int nb, double* A, int lda, double* colchk, double* rowchk, double tau_scale,
+                       orc_report* rep) {
+  ctx_t c;
+  if (ctx_init(&c, n, nb, 0, PR64, 1, tau_scale, rep)) return -2;
+  memcpy(c.cc, colchk, sizeof(double) * (size_t)c.ldc * n);
+  memcpy(c.rc, rowchk, sizeof(double) * (size_t)c.ldr * 2 * c.N);
+  c.iter = 0;
+  verify_region(&c, A, lda, 0, 0);
+  memcpy(colchk, c.cc, sizeof(double) * (size_t)c.ldc * n);
+  memcpy(rowchk, c.rc, sizeof(double) * (size_t)c.ldr * 2 * c.N);
+  ctx_free(&c);
+  return (int)rep->flagged_tiles;
+}
+
 /* ------------------------------------------------------------------ */
 /* Solves and iterative refinement.                                   */
 /* ------------------------------------------------------------------ */

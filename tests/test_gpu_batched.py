@@ -154,3 +154,37 @@ def test_batched_graph_replay_matches_eager(h, chol):
             if not chol:
                 assert torch.equal(ipivs[q], ipivs0[q])
         assert np.array_equal(infos, infos0)
+
+
+@pytest.mark.parametrize("chol", [True, False])
+def test_batched_fp32_matches_oracle(h, chol):
+    """Binary32 batched factors against the oracle's binary32 emulation
+    (every operation rounded to binary32) on the same binary32 inputs:
+    the same pivots, factors within binary32 rounding of each other, and a
+    backward error within 2x of the oracle's."""
+    import torch
+    sizes = [1, 31, 33, 100, 200, 333, 512]
+    mats0 = [(gen.spd(n, 200 + n) if chol else gen.general(n, 200 + n)).astype(np.float32).astype(np.float64)
+             for n in sizes]
+    mats = [dev(a, torch.float32) for a in mats0]
+    infos, ipivs, reps = h.batched(mats, chol)
+    u32 = 2.0 ** -24
+    for q, (n, a0) in enumerate(zip(sizes, mats0)):
+        g = mats[q].cpu().numpy().astype(np.float64)
+        o = a0.copy(order="F")
+        if chol:
+            oinfo, orep = oracle.potrf(o, 32, prec=oracle.PR32)
+            g, o = np.tril(g), np.tril(o)
+            berr = lambda F: np.linalg.norm(a0 - F @ F.T) / np.linalg.norm(a0)
+        else:
+            opiv, oinfo, orep = oracle.getrf(o, 32, prec=oracle.PR32)
+            gp = ipivs[q].cpu().numpy()[:n]
+            assert np.array_equal(gp, opiv), n
+            P = np.arange(n)
+            for j, p in enumerate(gp):
+                P[j], P[p - 1] = P[p - 1], P[j]
+            berr = lambda F: np.linalg.norm(a0[P] - (np.tril(F, -1) + np.eye(n)) @ np.triu(F)) / np.linalg.norm(a0)
+        assert infos[q] == oinfo == 0, n
+        assert np.linalg.norm(g - o) <= 8 * n * u32 * np.linalg.norm(o), n
+        assert berr(g) <= 2.0 * berr(o) + u32, (n, berr(g), berr(o))
+        assert reps[q].status == 0 and orep.status == 0, n

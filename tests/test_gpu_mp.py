@@ -29,7 +29,8 @@ PRECS = {"f32": 1, "bf16": 2, "f16": 3}
 
 
 @pytest.mark.parametrize("chol", [False, True])
-@pytest.mark.parametrize("prec,kappa", [("f32", 1e2), ("f32", 1e6), ("bf16", 1e2), ("f16", 1e2), ("bf16", 1e10)])
+@pytest.mark.parametrize("kappa", [1e2, 1e6, 1e10])
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f16"])
 def test_mp_solve_matches_oracle(h, chol, prec, kappa):
     n, nb = 384, 64
     A, s, V = gen.mp_matrix(n, kappa, seed=21)
@@ -47,8 +48,12 @@ def test_mp_solve_matches_oracle(h, chol, prec, kappa):
         # flags; the report describes faults only for a completed factorization
         assert not rep.status & 4 and rep.flagged_tiles == 0
     if ir.converged:
+        # forward error within 2x of the oracle emulation's (plus a rounding
+        # floor of the order of kappa u: both end at the FP64 solution's error)
         xr = oracle.solve_ref(A, b)
         err = np.linalg.norm(x.cpu().numpy() - xr, np.inf) / np.linalg.norm(xr, np.inf)
+        oerr = np.linalg.norm(xo - xr, np.inf) / np.linalg.norm(xr, np.inf)
+        assert err <= 2.0 * oerr + 10 * kappa * U64, (err, oerr)
         assert err < max(1e-12, 20 * kappa * U64)
 
 

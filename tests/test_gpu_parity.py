@@ -260,3 +260,42 @@ def test_chol_diagonal_tile_flip(h, pos):
     assert rep.status == orep.status == 1
     assert rep.events() == orep.events() == [(1, 1, pos[0], pos[1])]
     assert np.max(np.abs(G - clean)) <= 1e-11 * np.max(np.abs(clean))
+
+
+@pytest.mark.parametrize("flag_side", ["col", "row"])
+def test_single_line_flag_matches_oracle(h, flag_side):
+    """Only one side of an off-diagonal tile flags (a large line makes the
+    other side's threshold exceed the perturbation): the element is located
+    by the ratio of the flagged line's weighted and plain differences, as in
+    the oracle."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_oracle import _one_line_case
+    A, i0, j0 = _one_line_case(flag_side)
+    orig = A[i0, j0]
+    dA = dev(A)
+    cc, rc = h.encode(dA, 32)
+    dA[i0, j0] += 1e-10
+    flags, rep = h.verify(dA, 32, cc, rc, correct=True)
+    Ao = A.copy(order="F")
+    occ, orc = oracle.encode(Ao, 32)
+    Ao[i0, j0] += 1e-10
+    orep = oracle.verify_correct(Ao, 32, occ, orc)
+    assert rep.status == orep.status == 1
+    assert rep.events() == orep.events() == [(0, 1, i0, j0)]
+    tol = 16 * U64 * np.abs(A[32:64, j0]).sum()
+    assert abs(host(dA)[i0, j0] - orig) <= tol
+    assert abs(host(dA)[i0, j0] - Ao[i0, j0]) <= tol
+
+
+def test_chol_diagonal_checksum_repair_matches_oracle(h):
+    n, nb = 96, 32
+    A = gen.spd(n, 12)
+    f = {"iter": 0, "target": 2, "row": 45, "col": 2, "bit": 56}
+    clean, _ = _gpu(h, "chol", A, nb)
+    G, rep = _gpu(h, "chol", A, nb, faults=[f])
+    O, orep = _orc("chol", A, nb, faults=[f])
+    assert rep.status == orep.status == 2 and rep.checksum_repaired == 1
+    assert rep.events() == orep.events() == [(0, 2, 32, 32)]
+    assert np.array_equal(G, clean)

@@ -348,6 +348,66 @@ def test_checksum_flip_repaired(target):
     assert np.array_equal(A, clean)
 
 
+def _one_line_case(flag_side):
+    """A 64 x 64 matrix whose tile (1, 0) (nb = 32) has one line of large
+    entries: row i0 = 40 (flag_side "col": a perturbation of element (40, 5)
+    only exceeds the column's threshold) or column j0 = 5 (flag_side "row":
+    only the row's).  Returns (A, i0, j0)."""
+    A = np.asfortranarray(gen.rng(31).uniform(-1, 1, (64, 64)))
+    i0, j0 = 40, 5
+    if flag_side == "col":
+        A[i0, 0:32] = 1e6
+        A[i0, j0] = 0.375
+    else:
+        A[32:64, j0] = 1e6
+        A[i0, j0] = 0.375
+    return A, i0, j0
+
+
+@pytest.mark.parametrize("flag_side", ["col", "row"])
+def test_single_line_flag_located_by_ratio(flag_side):
+    """Off-diagonal tile where only one side flags: the weighted / plain
+    difference ratio of the flagged line is the element's position (1-based)
+    inside the tile, so the located element is the perturbed one, and it is
+    rebuilt from its column checksum to within that checksum's tolerance."""
+    A, i0, j0 = _one_line_case(flag_side)
+    colchk, rowchk = oracle.encode(A, 32)
+    orig = A[i0, j0]
+    A[i0, j0] += 1e-10
+    _, flags, _ = oracle.verify(A, 32, colchk, rowchk)
+    assert flags[1, 0] == 1 and flags.sum() == 1
+    rep = oracle.verify_correct(A, 32, colchk, rowchk)
+    assert rep.flagged_tiles == 1 and rep.corrected == 1 and rep.status == oracle.ST_CORRECTED
+    assert rep.events() == [(0, 1, i0, j0)]
+    # the rebuilt value: the column sum minus the other entries, exact up to
+    # the rounding of that column's sums (tolerance 16 u sum |column|)
+    tol = 16 * U64 * np.abs(A[32:64, j0]).sum()
+    assert abs(A[i0, j0] - orig) <= tol
+    if flag_side == "col":
+        assert abs(A[i0, j0] - orig) < 1e-13  # the column is O(1): far below the perturbation
+    # and the refreshed checksums now pass
+    _, flags, _ = oracle.verify(A, 32, colchk, rowchk)
+    assert flags.sum() == 0
+
+
+def test_chol_diagonal_tile_checksum_repair():
+    """A flipped row-checksum entry of a diagonal tile in the symmetric view:
+    no column of the tile flags, so no data element is suspect; the tile's
+    checksums are re-encoded from its data, and the factor is bitwise the
+    clean one (the data never changed)."""
+    n, nb = 96, 32
+    A0 = gen.spd(n, seed=12)
+    clean = A0.copy(order="F")
+    oracle.potrf(clean, nb)
+    A = A0.copy(order="F")
+    f = {"iter": 0, "target": 2, "row": 45, "col": 2 * 1, "bit": 56}
+    info, rep = oracle.potrf(A, nb, faults=[f])
+    assert info == 0
+    assert rep.status == oracle.ST_REPAIRED and rep.checksum_repaired == 1 and rep.corrected == 0
+    assert rep.events() == [(0, 2, 32, 32)]
+    assert np.array_equal(np.tril(A), np.tril(clean))
+
+
 # ------------------------------------------------------------ MP + refinement
 def test_bf16_fp16_rounding_vs_libraries():
     import torch
