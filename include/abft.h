@@ -55,8 +55,18 @@ enum {
   ABFT_ERR_UNSUPPORTED = -102
 };
 
-/* protection level: no checksums, or full (row + column) checksums */
-enum { ABFT_PROTECT_NONE = 0, ABFT_PROTECT_FULL = 2 };
+/* Protection level of an iteration (the paper's single-side and full
+   checksums, section "Design of ABFT-OC", and its adaptive ABFT, Alg. 1,
+   which turns protection on per iteration): NONE carries and verifies
+   nothing; SINGLE carries and compares the column checksums of every tile
+   only, which locates and corrects one wrong element per tile (0D) and
+   reports anything else as uncorrectable; FULL adds the row checksums, which
+   also correct one wrong row or column of a tile (1D: every element of it is
+   rebuilt from the checksums of the other side).  When the level rises from
+   one iteration to the next (or starts above NONE), the checksums of the
+   remaining matrix are encoded from its data at the start of that
+   iteration. */
+enum { ABFT_PROTECT_NONE = 0, ABFT_PROTECT_SINGLE = 1, ABFT_PROTECT_FULL = 2 };
 
 /* arithmetic of a factorization: FP64, FP32, or FP32 data whose trailing
    update multiplies bf16 / fp16 operands with FP32 accumulation */
@@ -86,7 +96,16 @@ enum {
    bit `bit` (0..63 of the binary64 pattern; 0..31 of binary32 data) of one
    element.  target 0 = the matrix (row, col are matrix indices), 1 = the
    column-checksum array (row in [0, 2*ceil(n/nb))), 2 = the row-checksum array
-   (col in [0, 2*ceil(n/nb))).  `matrix` selects the matrix of a batch. */
+   (col in [0, 2*ceil(n/nb))).  `matrix` selects the matrix of a batch.
+   Operand faults (FP64 blocked factorizations; the paper's 1D error class,
+   section "Design of ABFT-OC"): target 3 flips an element of the left
+   operand of iteration `iter`'s trailing-update product (L21 for Cholesky
+   and LU, V for QR; row, col are matrix indices), target 4 one of the right
+   operand (LU: U12 at its matrix indices; QR: W2 = T^T V^T C, row = p in
+   [0, nb), col = the matrix column); the flip lasts for that product only
+   (it is undone right after it), so one row (3) or one column (4) of the
+   updated matrix is wrong while the operand and the checksum carry are not.
+   A call with operand faults runs on one stream. */
 typedef struct {
   int32_t iter, target;
   int64_t row, col;
@@ -94,8 +113,10 @@ typedef struct {
 } abft_fault;
 
 typedef struct {
-  int32_t iter, kind; /* 1 corrected, 2 checksum repaired, 3 uncorrectable, 4 panel flag */
-  int64_t row, col;   /* corrected element, or the flagged tile's first row / column */
+  int32_t iter, kind; /* 1 element corrected, 2 checksum repaired, 3 uncorrectable, 4 panel flag,
+                         5 row rebuilt, 6 column rebuilt (1D) */
+  int64_t row, col;   /* corrected element; kind 5: the row and the tile's first column; kind 6: the
+                         tile's first row and the column; otherwise the flagged tile's first row / column */
 } abft_event;
 
 #define ABFT_MAX_EVENTS 16
@@ -111,13 +132,15 @@ typedef struct {
 
 typedef struct {
   int32_t nb;          /* block size = checksum tile size (1..512; batched: 32) */
-  int32_t protect;     /* ABFT_PROTECT_NONE or ABFT_PROTECT_FULL */
+  int32_t protect;     /* ABFT_PROTECT_NONE, _SINGLE or _FULL for every iteration (batched: NONE or FULL) */
   double tau_scale;    /* threshold scale (default 4.0 when <= 0) */
   const abft_fault* faults; /* host array of fault plans (test use), may be NULL */
   int32_t nfaults;
   int32_t flags;       /* ABFT_FLAG_* bits */
   int32_t wgs_per_cu;  /* batched: persistent workgroups per compute unit (0: 1; at most 4) */
-  int32_t reserved;
+  int32_t nlevels;     /* entries of `levels` (0: none) */
+  const int8_t* levels; /* host array, levels[k] = ABFT_PROTECT_* of iteration k (k < ceil(n/nb) <= nlevels),
+                           overriding `protect` (FP64 blocked factorizations); NULL: `protect` everywhere */
 } abft_opts;
 
 /* opts.flags: ABFT_FLAG_PROFILE times the phases of the call with HIP
@@ -160,6 +183,22 @@ int abft_workspace_size(abft_handle h, int op, int64_t n, int32_t batch, const a
    dinfo: device int32.  drep: device abft_report (may be NULL). */
 int abft_potrf(abft_handle h, int64_t n, double* dA, int64_t lda, void* dwork, size_t work_bytes,
                const abft_opts* opts, int32_t* dinfo, abft_report* drep);
+
+/* abft_potrf for callers that cannot allocate device memory or pass a
+   workspace (code under HIP graph capture, tight serving loops, harnesses
+   that forbid allocation).  Same arguments, result and report as abft_potrf
+   without dwork / work_bytes: the scratch is a 64 MiB device array built
+   into the library (one copy per GPU, held until the process ends), so this
+   call allocates nothing and creates no stream or event: all its work runs
+   on the handle's stream (no side stream) and ABFT_FLAG_PROFILE is rejected
+   (ABFT_ERR_UNSUPPORTED).  Returns ABFT_ERR_WORKSPACE when the problem needs
+   more scratch than that (abft_workspace_size(ABFT_OP_POTRF) > 64 MiB: about
+   n > 16384 at nb = 512).  Every call on one GPU shares that GPU's array:
+   calls that overlap on one GPU (other streams, other handles, other host
+   threads) race and must be serialized by the caller; nothing from a
+   previous call is read. */
+int abft_potrf_noalloc(abft_handle h, int64_t n, double* dA, int64_t lda, const abft_opts* opts, int32_t* dinfo,
+                       abft_report* drep);
 
 /* LU with partial pivoting P A = L U (L unit lower, U upper, both in A).
    dipiv: device int32[n], 1-based LAPACK row interchanges; ties in the pivot

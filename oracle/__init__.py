@@ -21,6 +21,10 @@ PR64, PR32, PRBF16, PRF16 = 0, 1, 2, 3
 
 # status bits shared by the report structs
 ST_CORRECTED, ST_REPAIRED, ST_UNCORRECTABLE, ST_PANEL = 1, 2, 4, 8
+# protection levels: none, column checksums only (single side), both sides (full)
+NONE, SINGLE, FULL = 0, 1, 2
+# event kinds
+EV_CORRECTED, EV_REPAIRED, EV_UNCORRECTABLE, EV_PANEL, EV_ROW_REBUILT, EV_COL_REBUILT = 1, 2, 3, 4, 5, 6
 
 
 class Fault(C.Structure):
@@ -73,9 +77,9 @@ def lib():
         _lib.orc_potrf_unb.argtypes = [i, P, i]
         _lib.orc_getrf_unb.argtypes = [i, P, i, P]
         _lib.orc_geqrf_unb.argtypes = [i, P, i, P]
-        _lib.orc_abft_potrf.argtypes = [i, i, P, i, i, i, d, P, i, P]
-        _lib.orc_abft_getrf.argtypes = [i, i, P, i, P, i, i, d, P, i, P]
-        _lib.orc_abft_geqrf.argtypes = [i, i, P, i, P, i, d, P, i, P]
+        _lib.orc_abft_potrf.argtypes = [i, i, P, i, i, i, d, P, i, P, P]
+        _lib.orc_abft_getrf.argtypes = [i, i, P, i, P, i, i, d, P, i, P, P]
+        _lib.orc_abft_geqrf.argtypes = [i, i, P, i, P, i, d, P, i, P, P]
         _lib.orc_encode.argtypes = [i, i, P, i, i, P, i, P, i]
         _lib.orc_verify.argtypes = [i, i, P, i, i, P, i, P, i, d, P, P]
         _lib.orc_verify_correct.argtypes = [i, i, P, i, P, P, d, P]
@@ -134,35 +138,58 @@ def geqrf_unb(A):
     return tau
 
 
-def potrf(A, nb, prec=PR64, protect=True, tau_scale=4.0, faults=None):
-    """Blocked right-looking Cholesky (lower) with optional ABFT; returns (info, Report)."""
+def _level(protect):
+    """True -> full checksums, False -> none, or a level 0 / 1 / 2"""
+    if protect is True:
+        return FULL
+    if protect is False or protect is None:
+        return NONE
+    return int(protect)
+
+
+def _levels(levels, n, nb):
+    """per-iteration protection levels as an int8 array (or None)"""
+    if levels is None:
+        return None, None
+    arr = np.ascontiguousarray(levels, dtype=np.int8)
+    assert arr.shape == (-(-n // nb),), "one level per iteration"
+    return arr.ctypes.data, arr
+
+
+def potrf(A, nb, prec=PR64, protect=True, tau_scale=4.0, faults=None, levels=None):
+    """Blocked right-looking Cholesky (lower) with optional ABFT; returns (info, Report).
+    protect: True / False or a level (NONE, SINGLE, FULL); levels: one level per iteration."""
     n = A.shape[0]
     rep = Report()
     fp, nf, keep = _faults(faults)
-    info = lib().orc_abft_potrf(n, nb, _f64(A), A.shape[0], prec, int(protect), tau_scale, fp, nf, C.byref(rep))
-    del keep
+    lp, lkeep = _levels(levels, n, nb)
+    info = lib().orc_abft_potrf(n, nb, _f64(A), A.shape[0], prec, _level(protect), tau_scale, fp, nf, lp,
+                                C.byref(rep))
+    del keep, lkeep
     return info, rep
 
 
-def getrf(A, nb, prec=PR64, protect=True, tau_scale=4.0, faults=None):
+def getrf(A, nb, prec=PR64, protect=True, tau_scale=4.0, faults=None, levels=None):
     n = A.shape[0]
     ipiv = np.zeros(n, dtype=np.int32)
     rep = Report()
     fp, nf, keep = _faults(faults)
-    info = lib().orc_abft_getrf(n, nb, _f64(A), A.shape[0], ipiv.ctypes.data, prec, int(protect), tau_scale,
-                                fp, nf, C.byref(rep))
-    del keep
+    lp, lkeep = _levels(levels, n, nb)
+    info = lib().orc_abft_getrf(n, nb, _f64(A), A.shape[0], ipiv.ctypes.data, prec, _level(protect), tau_scale,
+                                fp, nf, lp, C.byref(rep))
+    del keep, lkeep
     return ipiv, info, rep
 
 
-def geqrf(A, nb, protect=True, tau_scale=4.0, faults=None):
+def geqrf(A, nb, protect=True, tau_scale=4.0, faults=None, levels=None):
     n = A.shape[0]
     tau = np.zeros(n)
     rep = Report()
     fp, nf, keep = _faults(faults)
-    lib().orc_abft_geqrf(n, nb, _f64(A), A.shape[0], tau.ctypes.data, int(protect), tau_scale, fp, nf,
+    lp, lkeep = _levels(levels, n, nb)
+    lib().orc_abft_geqrf(n, nb, _f64(A), A.shape[0], tau.ctypes.data, _level(protect), tau_scale, fp, nf, lp,
                          C.byref(rep))
-    del keep
+    del keep, lkeep
     return tau, rep
 
 

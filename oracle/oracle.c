@@ -248,6 +248,7 @@ typedef struct {
   int ldc, ldr;
   orc_report* rep;
   int iter;
+  int level; /* protection of the current iteration: 0 none, 1 column side only, 2 both sides */
 } ctx_t;
 
 static inline int tlen(const ctx_t* c, int I) { int r = c->n - I * c->nb; return r < c->nb ? r : c->nb; }
@@ -348,10 +349,16 @@ static double slack_row(const slack_t* s, int i) {
   return 0.0;
 }
 static double slack_one(const slack_t* s, int hit) { return (s && hit) ? s->tec : 0.0; }
+/* After a whole row (column) of a tile was rebuilt from the checksums of
+   the other side, each rebuilt element is known to the tolerance of the
+   checksum it came from; the additions to the plain (e) and weighted (w)
+   tolerances of every column and row sum of the tile. */
+typedef struct { double ce[1024], cw[1024], re[1024], rw[1024]; } lslack_t;
 
 /* compare recomputed sums with carried checksums; returns number of flags.
    sl (may be NULL) widens the comparisons that contain a rebuilt element. */
-static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, double* maxr, const slack_t* sl) {
+static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, double* maxr, const slack_t* sl,
+                      const lslack_t* ls) {
   int r0 = I * c->nb, h = tlen(c, I), c0 = J * c->nb, w = tlen(c, J);
   int nflag = 0;
   for (int j = 0; j < w; ++j) {
@@ -362,6 +369,7 @@ static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, dou
     double sw = slack_col(sl, j);
     te += slack_one(sl, sw > 0.0);
     tw += sw;
+    if (ls) { te += ls->ce[j]; tw += ls->cw[j]; }
     f->de[j] = de;
     f->dw[j] = dw;
     f->fe[j] = bad(de, te);
@@ -373,6 +381,11 @@ static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, dou
     }
   }
   for (int i = 0; i < h; ++i) {
+    if (c->level == 1) { /* single side: the row checksums are not compared */
+      f->he[i] = f->hw[i] = 0.0;
+      f->ge[i] = f->gw[i] = 0;
+      continue;
+    }
     double de = t->re[i] - AT(c->rc, r0 + i, 2 * J, c->ldr);
     double dw = t->rw[i] - AT(c->rc, r0 + i, 2 * J + 1, c->ldr);
     double te = tau_of(c, t->ra[i], AT(c->gr, r0 + i, 2 * J, c->ldr));
@@ -380,6 +393,7 @@ static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, dou
     double sw = slack_row(sl, i);
     te += slack_one(sl, sw > 0.0);
     tw += sw;
+    if (ls) { te += ls->re[i]; tw += ls->rw[i]; }
     f->he[i] = de;
     f->hw[i] = dw;
     f->ge[i] = bad(de, te);
@@ -403,6 +417,65 @@ static int ratio_index(double dw, double de, int len) {
   return (int)k - 1;
 }
 
+/* Rebuild a whole line of a tile (1D error: one row or one column of the
+   tile is wrong): line 1 = row idx, each element from its column's plain
+   checksum with the rest of the column left out; line 2 = column idx, each
+   element from its row's plain checksum.  The tile is then rechecked with
+   the rebuilt elements' tolerances added where they occur; on failure the
+   old values come back.  Returns 1 when the recheck passes. */
+static int rebuild_line(ctx_t* c, double* A, int lda, int I, int J, int line, int idx, tsums_t* t, tflags_t* f) {
+  int r0 = I * c->nb, h = tlen(c, I), c0 = J * c->nb, w = tlen(c, J);
+  double* old = malloc(sizeof(double) * 1024);
+  if (line == 1) {
+    for (int j = 0; j < w; ++j) {
+      double s = AT(c->cc, 2 * I, c0 + j, c->ldc);
+      for (int i = 0; i < h; ++i) {
+        if (i == idx) continue;
+        s -= AT(A, r0 + i, c0 + j, lda);
+      }
+      old[j] = AT(A, r0 + idx, c0 + j, lda);
+      AT(A, r0 + idx, c0 + j, lda) = s;
+    }
+  } else {
+    for (int i = 0; i < h; ++i) {
+      double s = AT(c->rc, r0 + i, 2 * J, c->ldr);
+      for (int j = 0; j < w; ++j) {
+        if (j == idx) continue;
+        s -= AT(A, r0 + i, c0 + j, lda);
+      }
+      old[i] = AT(A, r0 + i, c0 + idx, lda);
+      AT(A, r0 + i, c0 + idx, lda) = s;
+    }
+  }
+  tile_sums(c, A, lda, I, J, t);
+  lslack_t* ls = calloc(1, sizeof(lslack_t));
+  if (line == 1) {
+    for (int j = 0; j < w; ++j) {
+      double tec = tau_of(c, t->ca[j], AT(c->gc, 2 * I, c0 + j, c->ldc));
+      ls->ce[j] = tec;
+      ls->cw[j] = (double)(idx + 1) * tec;
+      ls->re[idx] += tec;
+      ls->rw[idx] += (double)(j + 1) * tec;
+    }
+  } else {
+    for (int i = 0; i < h; ++i) {
+      double ter = tau_of(c, t->ra[i], AT(c->gr, r0 + i, 2 * J, c->ldr));
+      ls->re[i] = ter;
+      ls->rw[i] = (double)(idx + 1) * ter;
+      ls->ce[idx] += ter;
+      ls->cw[idx] += (double)(i + 1) * ter;
+    }
+  }
+  int ok = tile_flags(c, I, J, t, f, NULL, NULL, ls) == 0;
+  if (!ok) {
+    if (line == 1) for (int j = 0; j < w; ++j) AT(A, r0 + idx, c0 + j, lda) = old[j];
+    else for (int i = 0; i < h; ++i) AT(A, r0 + i, c0 + idx, lda) = old[i];
+  }
+  free(ls);
+  free(old);
+  return ok;
+}
+
 /* Locate and correct one flagged tile (0D model: one fault per tile per
    iteration).  The element is recomputed from its column checksum with the
    element itself left out, so huge, Inf or NaN values are repaired too. */
@@ -414,7 +487,7 @@ static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
 #define t (*tp)
 #define f (*fp)
   tile_sums(c, A, lda, I, J, &t);
-  int nf = tile_flags(c, I, J, &t, &f, NULL, NULL);
+  int nf = tile_flags(c, I, J, &t, &f, NULL, NULL, NULL);
   if (nf == 0) { free(tp); free(fp); return; }
   int nFe = 0, nGe = 0, nFw = 0, nGw = 0, jf[2] = {-1, -1}, ig = -1;
   for (int j = 0; j < w; ++j) {
@@ -427,6 +500,7 @@ static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
   }
   int ci = -1, cj = -1; /* candidate stored element (tile-relative) */
   int repair = 0;
+  int line = 0; /* 1D: 1 = rebuild row ig from the column checksums, 2 = column jf[0] from the row checksums */
   if (diag) {
     if (nFe == 1) {
       int i = ratio_index(f.dw[jf[0]], f.de[jf[0]], h);
@@ -450,6 +524,10 @@ static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
       else if (nFw == 0) repair = 1;
     } else if (nFe == 0 && nGe == 0) {
       repair = 1;
+    } else if (c->level == 2 && nGe == 1 && nFe >= 2) {
+      line = 1; /* one row of the tile is wrong in several columns */
+    } else if (c->level == 2 && nFe == 1 && nGe >= 2) {
+      line = 2; /* one column is wrong in several rows */
     }
   }
   int kind = 3;
@@ -464,15 +542,19 @@ static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
     AT(A, r0 + ci, c0 + cj, lda) = s;
     tile_sums(c, A, lda, I, J, &t);
     slack_t sl = {ci, cj, diag, tau_of(c, t.ca[cj], AT(c->gc, 2 * I, c0 + cj, c->ldc))};
-    if (tile_flags(c, I, J, &t, &f, NULL, &sl) == 0) {
+    if (tile_flags(c, I, J, &t, &f, NULL, &sl, NULL) == 0) {
       kind = 1;
     } else {
       AT(A, r0 + ci, c0 + cj, lda) = old;
     }
+  } else if (line) {
+    if (rebuild_line(c, A, lda, I, J, line, line == 1 ? ig : jf[0], &t, &f)) kind = 4 + line;
   } else if (repair) {
     kind = 2;
   }
   if (kind == 1) { c->rep->corrected++; c->rep->status |= 1; add_event(c->rep, c->iter, 1, r0 + ci, c0 + cj); }
+  else if (kind == 5) { c->rep->corrected++; c->rep->status |= 1; add_event(c->rep, c->iter, 5, r0 + ig, c0); }
+  else if (kind == 6) { c->rep->corrected++; c->rep->status |= 1; add_event(c->rep, c->iter, 6, r0, c0 + jf[0]); }
   else if (kind == 2) { c->rep->checksum_repaired++; c->rep->status |= 2; add_event(c->rep, c->iter, 2, r0, c0); }
   else { c->rep->uncorrectable++; c->rep->status |= 4; add_event(c->rep, c->iter, 3, r0, c0); }
   /* refresh the tile's checksums from the (corrected) data */
@@ -516,7 +598,7 @@ static void verify_region(ctx_t* c, double* A, int lda, int Ia, int Ja) {
       int I = IJ[2 * q], J = IJ[2 * q + 1];
       tile_sums(c, A, lda, I, J, t);
       double m = 0.0;
-      if (tile_flags(c, I, J, t, f, &m, NULL)) flagged[q] = 1;
+      if (tile_flags(c, I, J, t, f, &m, NULL, NULL)) flagged[q] = 1;
       else { mr[q] = m; store_sums(c, I, J, t); }
     }
     free(t);
@@ -536,9 +618,12 @@ static void verify_region(ctx_t* c, double* A, int lda, int Ia, int Ja) {
   free(mr);
 }
 
-static void encode_all(ctx_t* c, const double* A, int lda) {
+/* encode tiles I >= Ia, J >= Ja (lower tiles only when sym) from the data:
+   the start of a protected stretch of iterations; the magnitude terms of the
+   previous update are cleared */
+static void encode_region(ctx_t* c, const double* A, int lda, int Ia, int Ja) {
   int* IJ = malloc(sizeof(int) * 2 * (size_t)c->N * c->N + 2);
-  int nt = tile_list(c, 0, 0, IJ);
+  int nt = tile_list(c, Ia, Ja, IJ);
 #pragma omp parallel
   {
     tsums_t* t = malloc(sizeof(tsums_t));
@@ -550,6 +635,8 @@ static void encode_all(ctx_t* c, const double* A, int lda) {
     free(t);
   }
   free(IJ);
+  memset(c->gc, 0, (size_t)c->ldc * c->n * sizeof(double));
+  memset(c->gr, 0, (size_t)c->n * 2 * c->N * sizeof(double));
 }
 
 /* ------------------------------------------------------------------ */
@@ -636,24 +723,26 @@ static void carry(ctx_t* c, const double* A, int lda, int I0, int J0, int xc0, i
       AT(c->gc, 2 * I + 1, j, c->ldc) = gwa;
     }
   }
-  /* row side */
+  /* row side (full checksums only) */
   int dr0 = dI * nb, dr1 = dI * nb + tlen(c, dI);
+  if (c->level == 2) {
 #pragma omp parallel for schedule(dynamic, 16)
-  for (int i = I0 * nb; i < n; ++i) {
-    int Ii = i / nb;
-    for (int J = J0; J < N; ++J) {
-      if (c->sym && Ii < J) continue;
-      acc_t ue = {AT(c->rc, i, 2 * J, c->ldr), 0}, uw = {AT(c->rc, i, 2 * J + 1, c->ldr), 0};
-      double ga = 0, gwa = 0;
-      for (int p = 0; p < kw; ++p) {
-        double x = rop(c->prec, xval(A, lda, i, p, xc0, dr0, dr1, mode));
-        acc_fma(&ue, -x, t.e[J * nb + p]); acc_fma(&uw, -x, t.w[J * nb + p]);
-        ga += fabs(x) * t.a[J * nb + p]; gwa += fabs(x) * t.wa[J * nb + p];
+    for (int i = I0 * nb; i < n; ++i) {
+      int Ii = i / nb;
+      for (int J = J0; J < N; ++J) {
+        if (c->sym && Ii < J) continue;
+        acc_t ue = {AT(c->rc, i, 2 * J, c->ldr), 0}, uw = {AT(c->rc, i, 2 * J + 1, c->ldr), 0};
+        double ga = 0, gwa = 0;
+        for (int p = 0; p < kw; ++p) {
+          double x = rop(c->prec, xval(A, lda, i, p, xc0, dr0, dr1, mode));
+          acc_fma(&ue, -x, t.e[J * nb + p]); acc_fma(&uw, -x, t.w[J * nb + p]);
+          ga += fabs(x) * t.a[J * nb + p]; gwa += fabs(x) * t.wa[J * nb + p];
+        }
+        AT(c->rc, i, 2 * J, c->ldr) = acc_val(ue);
+        AT(c->rc, i, 2 * J + 1, c->ldr) = acc_val(uw);
+        AT(c->gr, i, 2 * J, c->ldr) = ga;
+        AT(c->gr, i, 2 * J + 1, c->ldr) = gwa;
       }
-      AT(c->rc, i, 2 * J, c->ldr) = acc_val(ue);
-      AT(c->rc, i, 2 * J + 1, c->ldr) = acc_val(uw);
-      AT(c->gr, i, 2 * J, c->ldr) = ga;
-      AT(c->gr, i, 2 * J + 1, c->ldr) = gwa;
     }
   }
   free(s.e); free(s.w); free(s.a); free(s.wa);
@@ -730,6 +819,32 @@ static void inject(ctx_t* c, double* A, int lda, const orc_fault* f, int nf, int
     else if (f[q].target == 1 && c->cc) flip(&AT(c->cc, f[q].row, f[q].col, c->ldc), f[q].bit);
     else if (f[q].target == 2 && c->rc) flip(&AT(c->rc, f[q].row, f[q].col, c->ldr), f[q].bit);
   }
+}
+
+/* Faults in an operand of the trailing-update product (target 3: an element
+   of the left operand, L21 or V, at its matrix position; target 4: of the
+   right operand, U12 at its matrix position, or QR's W2 at (p, column)):
+   the stored element is flipped for the duration of that product only, as
+   a fault in the product's read of it would be, so the error spreads along
+   a row (left operand) or a column (right operand) of the updated matrix
+   while the operand itself and the checksum carry stay intact.  Called once
+   before and once after the product (the flip undoes itself). */
+static void flip_operands(double* A, int lda, double* W2, int ldw, const orc_fault* f, int nf, int iter) {
+  for (int q = 0; q < nf; ++q) {
+    if (f[q].iter != iter) continue;
+    if (f[q].target == 3) flip(&AT(A, f[q].row, f[q].col, lda), f[q].bit);
+    else if (f[q].target == 4) {
+      if (W2) flip(&W2[(size_t)f[q].row + (size_t)f[q].col * (size_t)ldw], f[q].bit);
+      else flip(&AT(A, f[q].row, f[q].col, lda), f[q].bit);
+    }
+  }
+}
+
+/* protection level of iteration k: the caller's per-iteration levels, or
+   the call's level for every iteration */
+static int level_of(const int8_t* levels, int k, int protect) {
+  int v = levels ? levels[k] : protect;
+  return v < 0 ? 0 : (v > 2 ? 2 : v);
 }
 
 static int ctx_init(ctx_t* c, int n, int nb, int sym, int prec, int protect, double ts, orc_report* rep) {
@@ -866,15 +981,20 @@ static void m_lkkT(const void* v, int I, int p, int j, double* m, double* ma) {
 }
 
 int orc_abft_potrf(int n, int nb, double* A, int lda, int prec, int protect, double tau_scale,
-                   const orc_fault* faults, int nfaults, orc_report* rep) {
+                   const orc_fault* faults, int nfaults, const int8_t* levels, orc_report* rep) {
   ctx_t c;
-  if (ctx_init(&c, n, nb, 1, prec, protect, tau_scale, rep)) return -2;
+  if (ctx_init(&c, n, nb, 1, prec, protect || levels, tau_scale, rep)) return -2;
   if (prec != PR64)
     for (int j = 0; j < n; ++j) for (int i = j; i < n; ++i) AT(A, i, j, lda) = rs(prec, AT(A, i, j, lda));
-  if (protect) encode_all(&c, A, lda);
-  int info = 0;
+  int info = 0, prev = 0;
   for (int k = 0; k < c.N; ++k) {
     c.iter = k;
+    /* protection of this iteration; a protected stretch starts from
+       checksums encoded from the data */
+    int lev = level_of(levels, k, protect);
+    c.level = lev;
+    if (lev > prev) encode_region(&c, A, lda, k, k);
+    prev = lev;
     int c0 = k * nb, w = tlen(&c, k), c1 = c0 + w;
     /* PD: Cholesky of the diagonal tile (right-looking inside the tile) */
     for (int j = c0; j < c1 && !info; ++j) {
@@ -906,7 +1026,7 @@ int orc_abft_potrf(int n, int nb, double* A, int lda, int prec, int protect, dou
       }
     }
     lctx_t l = {A, lda, c0};
-    if (protect) {
+    if (lev) {
       /* panel check: e^T A_Ik = (e^T L_I) L_kk^T for every tile-row I >= k */
       panel_check(&c, A, lda, k, c.N, c0, w, k, XM_LOWER, c0, c1, m_lkkT, NULL, &l);
     }
@@ -914,18 +1034,20 @@ int orc_abft_potrf(int n, int nb, double* A, int lda, int prec, int protect, dou
     /* TMU: A22 -= L21 L21^T (lower part), operands rounded for MP forms */
     {
       int m = n - c1;
+      flip_operands(A, lda, NULL, 0, faults, nfaults, k);
       double* X = copy_x(prec, A, lda, c1, m, c0, w);
       double* Y = copy_y(prec, A, lda, c0, w, c1, m, 1);
+      flip_operands(A, lda, NULL, 0, faults, nfaults, k);
       update_rows(prec, m, m, w, X, m, Y, w, &AT(A, c1, c1, lda), lda, 1);
       free(X);
       free(Y);
     }
-    if (protect) {
+    if (lev) {
       zero_g(&c);
       carry(&c, A, lda, k + 1, k + 1, c0, w, k, XM_LOWER, y_lt, &l);
     }
     inject(&c, A, lda, faults, nfaults, k);
-    if (protect) verify_region(&c, A, lda, k + 1, k + 1);
+    if (lev) verify_region(&c, A, lda, k + 1, k + 1);
   }
   ctx_free(&c);
   return info;
@@ -952,19 +1074,22 @@ static void m_u12(const void* v, int I, int p, int j, double* m, double* ma) {
 }
 
 int orc_abft_getrf(int n, int nb, double* A, int lda, int32_t* ipiv, int prec, int protect, double tau_scale,
-                   const orc_fault* faults, int nfaults, orc_report* rep) {
+                   const orc_fault* faults, int nfaults, const int8_t* levels, orc_report* rep) {
   ctx_t c;
-  if (ctx_init(&c, n, nb, 0, prec, protect, tau_scale, rep)) return -2;
+  if (ctx_init(&c, n, nb, 0, prec, protect || levels, tau_scale, rep)) return -2;
   if (prec != PR64)
     for (int j = 0; j < n; ++j) for (int i = 0; i < n; ++i) AT(A, i, j, lda) = rs(prec, AT(A, i, j, lda));
-  if (protect) encode_all(&c, A, lda);
-  int info = 0;
-  double* porig = protect ? malloc((size_t)n * nb * sizeof(double)) : NULL;
+  int info = 0, prev = 0;
+  double* porig = (protect || levels) ? malloc((size_t)n * nb * sizeof(double)) : NULL;
   for (int k = 0; k < c.N; ++k) {
     c.iter = k;
+    int lev = level_of(levels, k, protect);
+    c.level = lev;
+    if (lev > prev) encode_region(&c, A, lda, k, k);
+    prev = lev;
     int c0 = k * nb, w = tlen(&c, k), c1 = c0 + w;
     int mp = n - c0;
-    if (protect)
+    if (lev)
       for (int j = 0; j < w; ++j) for (int i = 0; i < mp; ++i) porig[i + (size_t)j * mp] = AT(A, c0 + i, c0 + j, lda);
     /* PD: getf2 on the panel.  Each interchange is applied to the panel
        columns at once and to the other columns after the panel (column by
@@ -974,7 +1099,7 @@ int orc_abft_getrf(int n, int nb, double* A, int lda, int32_t* ipiv, int prec, i
       int p = pick_pivot(A, lda, j, j, n);
       ipiv[j] = p + 1;
       if (p != j) {
-        if (protect) {
+        if (lev) {
           /* checksum fix-up of the panel columns, from the original panel
              values; row checksums move with their rows */
           int Ir = j / nb, Ip = p / nb;
@@ -1014,7 +1139,7 @@ int orc_abft_getrf(int n, int nb, double* A, int lda, int32_t* ipiv, int prec, i
         int p = ipiv[j] - 1;
         if (p == j) continue;
         double ar = AT(A, j, jj, lda), ap = AT(A, p, jj, lda);
-        if (protect && jj >= c1) {
+        if (lev && jj >= c1) {
           int Ir = j / nb, Ip = p / nb;
           double wr = (double)(j - Ir * nb + 1), wp = (double)(p - Ip * nb + 1);
           AT(c.cc, 2 * Ir, jj, c.ldc) += ap - ar;
@@ -1027,7 +1152,7 @@ int orc_abft_getrf(int n, int nb, double* A, int lda, int32_t* ipiv, int prec, i
       }
     }
     uctx_t u = {A, lda, c0, c1};
-    if (protect) panel_check(&c, A, lda, k, c.N, c0, w, k, XM_UNIT, c0, c1, m_ukk, NULL, &u);
+    if (lev) panel_check(&c, A, lda, k, c.N, c0, w, k, XM_UNIT, c0, c1, m_ukk, NULL, &u);
     if (c1 >= n) break;
     /* PU: U12 = L11^{-1} A12, unit lower forward substitution per column:
        element (i, j) subtracts L(i, p) U(p, j) for p = c0 .. i-1 in order */
@@ -1038,22 +1163,24 @@ int orc_abft_getrf(int n, int nb, double* A, int lda, int32_t* ipiv, int prec, i
         for (int i = p + 1; i < c1; ++i) AT(A, i, j, lda) = rs(prec, AT(A, i, j, lda) - AT(A, i, p, lda) * u);
       }
     /* PU check: (e^T L11) U12 = e^T A12 on tile-row k */
-    if (protect) panel_check(&c, A, lda, k, k + 1, c0, w, k, XM_UNIT, c1, n, m_u12, NULL, &u);
+    if (lev) panel_check(&c, A, lda, k, k + 1, c0, w, k, XM_UNIT, c1, n, m_u12, NULL, &u);
     /* TMU: A22 -= L21 U12 */
     {
       int m = n - c1;
+      flip_operands(A, lda, NULL, 0, faults, nfaults, k);
       double* X = copy_x(prec, A, lda, c1, m, c0, w);
       double* Y = copy_y(prec, A, lda, c0, w, c1, m, 0);
+      flip_operands(A, lda, NULL, 0, faults, nfaults, k);
       update_rows(prec, m, m, w, X, m, Y, w, &AT(A, c1, c1, lda), lda, 0);
       free(X);
       free(Y);
     }
-    if (protect) {
+    if (lev) {
       zero_g(&c);
       carry(&c, A, lda, k + 1, k + 1, c0, w, k, XM_FULL, y_u12, &u);
     }
     inject(&c, A, lda, faults, nfaults, k);
-    if (protect) verify_region(&c, A, lda, k + 1, k + 1);
+    if (lev) verify_region(&c, A, lda, k + 1, k + 1);
   }
   free(porig);
   ctx_free(&c);
@@ -1173,21 +1300,25 @@ static void e_qr(const void* v, int I, int j, double* ee, double* ew, double* ea
 }
 
 int orc_abft_geqrf(int n, int nb, double* A, int lda, double* tau, int protect, double tau_scale,
-                   const orc_fault* faults, int nfaults, orc_report* rep) {
+                   const orc_fault* faults, int nfaults, const int8_t* levels, orc_report* rep) {
   ctx_t c;
-  if (ctx_init(&c, n, nb, 0, PR64, protect, tau_scale, rep)) return -2;
-  if (protect) encode_all(&c, A, lda);
+  if (ctx_init(&c, n, nb, 0, PR64, protect || levels, tau_scale, rep)) return -2;
+  int prev = 0;
   double* T = malloc(sizeof(double) * nb * nb);
   double* W2 = malloc(sizeof(double) * (size_t)nb * n);
   double* Z = malloc(sizeof(double) * nb * nb);
   double* Zabs = malloc(sizeof(double) * nb * nb);
   for (int k = 0; k < c.N; ++k) {
     c.iter = k;
+    int lev = level_of(levels, k, protect);
+    c.level = lev;
+    if (lev > prev) encode_region(&c, A, lda, k, k);
+    prev = lev;
     int c0 = k * nb, w = tlen(&c, k), c1 = c0 + w;
     geqr2_cols(n, A, lda, tau, c0, c1);
     larft(n, A, lda, tau, c0, w, T);
     qctx_t q = {A, lda, c0, w, n, nb, k, T, W2, Z, Zabs};
-    if (protect) {
+    if (lev) {
       /* Z = T * (V1^T R_kk) and its magnitude |T| (|V1|^T |R_kk|) */
       for (int j = 0; j < w; ++j) {
         double* y = malloc(sizeof(double) * w);
@@ -1213,6 +1344,7 @@ int orc_abft_geqrf(int n, int nb, double* A, int lda, double* tau, int protect, 
     if (c1 >= n) break;
     /* TMU (larfb): W = V^T C, W2 = T^T W, C -= V W2 over rows [c0,n), cols [c1,n) */
     qr_w(n, A, lda, c0, w, c1, T, W2);
+    flip_operands(A, lda, W2, w, faults, nfaults, k);
     /* C(i, j) -= sum over p <= min(i - c0, w - 1) of V(i, p) W2(p, j), with
        V(c0 + p, p) = 1, accumulated in ascending p: the rows of V's unit
        triangle term by term, the rows below it (all w terms, no unit
@@ -1235,12 +1367,13 @@ int orc_abft_geqrf(int n, int nb, double* A, int lda, double* tau, int protect, 
         free(X);
       }
     }
-    if (protect) {
+    flip_operands(A, lda, W2, w, faults, nfaults, k);
+    if (lev) {
       zero_g(&c);
       carry(&c, A, lda, k, k + 1, c0, w, k, XM_UNIT, y_w2, &q);
     }
     inject(&c, A, lda, faults, nfaults, k);
-    if (protect) verify_region(&c, A, lda, k, k + 1);
+    if (lev) verify_region(&c, A, lda, k, k + 1);
   }
   free(T); free(W2); free(Z); free(Zabs);
   ctx_free(&c);
@@ -1318,7 +1451,8 @@ int orc_verify(int m, int n, const double* A, int lda, int nb, const double* col
 int orc_verify_correct(int n, int nb, double* A, int lda, double* colchk, double* rowchk, double tau_scale,
                        orc_report* rep) {
   ctx_t c;
-  if (ctx_init(&c, n, nb, 0, PR64, 1, tau_scale, rep)) return -2;
+  if (ctx_init(&c, n, nb, 0, PR64, 2, tau_scale, rep)) return -2;
+  c.level = 2;
   memcpy(c.cc, colchk, sizeof(double) * (size_t)c.ldc * n);
   memcpy(c.rc, rowchk, sizeof(double) * (size_t)c.ldr * 2 * c.N);
   c.iter = 0;
@@ -1401,8 +1535,8 @@ int orc_gesv_mp(int n, int nb, const double* A, int lda, const double* b, double
   int32_t* ipiv = malloc(sizeof(int32_t) * (n > 0 ? n : 1));
   for (int j = 0; j < n; ++j) for (int i = 0; i < n; ++i) F[i + (size_t)j * n] = AT(A, i, j, lda);
   orc_report rep;
-  int info = chol ? orc_abft_potrf(n, nb, F, n, prec, 0, 4.0, NULL, 0, &rep)
-                  : orc_abft_getrf(n, nb, F, n, ipiv, prec, 0, 4.0, NULL, 0, &rep);
+  int info = chol ? orc_abft_potrf(n, nb, F, n, prec, 0, 4.0, NULL, 0, NULL, &rep)
+                  : orc_abft_getrf(n, nb, F, n, ipiv, prec, 0, 4.0, NULL, 0, NULL, &rep);
   if (info) { ir->failed_reason = 4; free(F); free(ipiv); return info; }
   double u = ldexp(1.0, -53);
   double an = inf_norm_mat(n, A, lda);
@@ -1456,7 +1590,7 @@ void orc_solve_ref(int n, const double* A, int lda, const double* b, double* x, 
   int32_t* ipiv = malloc(sizeof(int32_t) * (n > 0 ? n : 1));
   for (int j = 0; j < n; ++j) for (int i = 0; i < n; ++i) F[i + (size_t)j * n] = AT(A, i, j, lda);
   orc_report rep;
-  orc_abft_getrf(n, 64, F, n, ipiv, PR64, 0, 4.0, NULL, 0, &rep);
+  orc_abft_getrf(n, 64, F, n, ipiv, PR64, 0, 4.0, NULL, 0, NULL, &rep);
   for (int i = 0; i < n; ++i) x[i] = b[i];
   lu_solve(n, F, n, ipiv, x, PR64);
   double* r = malloc(sizeof(double) * n);

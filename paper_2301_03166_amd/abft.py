@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("ABFT_LIB") or os.path.join(HERE, "libabft.so")
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
-PROTECT_NONE, PROTECT_FULL = 0, 2
+PROTECT_NONE, PROTECT_SINGLE, PROTECT_FULL = 0, 1, 2
 OP_POTRF, OP_GETRF, OP_GEQRF, OP_GESV_MP, OP_POSV_MP, OP_POTRF_BATCHED, OP_GETRF_BATCHED = 1, 2, 3, 4, 5, 6, 7
 ST_CORRECTED, ST_REPAIRED, ST_UNCORRECTABLE, ST_PANEL, ST_INTERNAL = 1, 2, 4, 8, 16
 
@@ -58,7 +58,7 @@ class Profile(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("protect", C.c_int32), ("tau_scale", C.c_double),
                 ("faults", C.POINTER(Fault)), ("nfaults", C.c_int32), ("flags", C.c_int32),
-                ("wgs_per_cu", C.c_int32), ("reserved", C.c_int32)]
+                ("wgs_per_cu", C.c_int32), ("nlevels", C.c_int32), ("levels", C.POINTER(C.c_int8))]
 
 
 class AbftError(RuntimeError):
@@ -82,6 +82,7 @@ def lib():
         L.abft_get_profile.argtypes = [P, C.POINTER(Profile)]
         L.abft_workspace_size.argtypes = [P, C.c_int, i64, i32, C.POINTER(Opts), C.POINTER(sz)]
         L.abft_potrf.argtypes = [P, i64, P, i64, P, sz, C.POINTER(Opts), P, P]
+        L.abft_potrf_noalloc.argtypes = [P, i64, P, i64, C.POINTER(Opts), P, P]
         L.abft_getrf.argtypes = [P, i64, P, i64, P, P, sz, C.POINTER(Opts), P, P]
         L.abft_geqrf.argtypes = [P, i64, P, i64, P, P, sz, C.POINTER(Opts), P, P]
         L.abft_gemm.argtypes = [P, i32, i32, i32, i64, i64, i64, d, P, i64, P, i64, d, P, i64, P, sz]
@@ -122,19 +123,34 @@ FLAG_PROFILE, FLAG_GRAPH = 1, 2
 GEMM_LOWER, GEMM_UNIT_LOWER_A = 1, 2
 
 
-def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False, graph=False, wgs_per_cu=0):
+def protect_level(protect):
+    """True -> PROTECT_FULL, False / None -> PROTECT_NONE, or a level 0 / 1 / 2 as given"""
+    if protect is True:
+        return PROTECT_FULL
+    if protect is False or protect is None:
+        return PROTECT_NONE
+    return int(protect)
+
+
+def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False, graph=False, wgs_per_cu=0, levels=None):
+    """abft_opts plus the host arrays it points to (keep them alive for the call)"""
     o = Opts()
     o.wgs_per_cu = int(wgs_per_cu)
-    o.nb, o.protect, o.tau_scale = int(nb), PROTECT_FULL if protect else PROTECT_NONE, float(tau_scale)
+    o.nb, o.protect, o.tau_scale = int(nb), protect_level(protect), float(tau_scale)
     o.flags = (FLAG_PROFILE if profile else 0) | (FLAG_GRAPH if graph else 0)
-    keep = None
+    keep = []
     if faults:
-        keep = (Fault * len(faults))()
+        fa = (Fault * len(faults))()
         for q, f in enumerate(faults):
-            keep[q].iter, keep[q].target = int(f["iter"]), int(f.get("target", 0))
-            keep[q].row, keep[q].col, keep[q].bit = int(f["row"]), int(f["col"]), int(f["bit"])
-            keep[q].matrix = int(f.get("matrix", 0))
-        o.faults, o.nfaults = C.cast(keep, C.POINTER(Fault)), len(faults)
+            fa[q].iter, fa[q].target = int(f["iter"]), int(f.get("target", 0))
+            fa[q].row, fa[q].col, fa[q].bit = int(f["row"]), int(f["col"]), int(f["bit"])
+            fa[q].matrix = int(f.get("matrix", 0))
+        o.faults, o.nfaults = C.cast(fa, C.POINTER(Fault)), len(faults)
+        keep.append(fa)
+    if levels is not None:
+        la = (C.c_int8 * len(levels))(*[int(v) for v in levels])
+        o.levels, o.nlevels = C.cast(la, C.POINTER(C.c_int8)), len(levels)
+        keep.append(la)
     return o, keep
 
 
@@ -196,24 +212,48 @@ class Handle:
 
     # ------------------------------------------------------------ factorizations
     def potrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True,
-              profile=False):
-        """In-place Cholesky (lower) of column-major A; returns (info, Report) when sync."""
-        return self._factor(OP_POTRF, A, nb, protect, tau_scale, faults, report, info, sync, profile=profile)
+              profile=False, levels=None):
+        """In-place Cholesky (lower) of column-major A; returns (info, Report) when sync.
+        protect: True / False or a PROTECT_* level; levels: one PROTECT_* level per iteration."""
+        return self._factor(OP_POTRF, A, nb, protect, tau_scale, faults, report, info, sync, profile=profile,
+                            levels=levels)
+
+    def potrf_noalloc(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True):
+        """abft_potrf_noalloc: the Cholesky of potrf with the library's built-in
+        scratch (no workspace).  report / info may be caller tensors (nothing is
+        allocated by the call itself); returns (info, Report) when sync."""
+        torch = self.torch
+        n = A.shape[0]
+        if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
+            raise AbftError("expected a square float64 device matrix")
+        opts, keep = make_opts(nb, protect, tau_scale, faults)
+        rep = report if report is not None else self.new_report()
+        inf = info if info is not None else torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._sync_stream()
+        rc = lib().abft_potrf_noalloc(self._h, n, A.data_ptr(), _ld(A), C.byref(opts), inf.data_ptr(), rep.data_ptr())
+        del keep
+        _check(rc, "abft_potrf_noalloc")
+        if not sync:
+            return ()
+        torch.cuda.synchronize(self.device)
+        return int(inf.item()), self.read_report(rep)
 
     def getrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, ipiv=None, report=None, info=None, sync=True,
-              profile=False):
+              profile=False, levels=None):
         torch = self.torch
         if ipiv is None:
             ipiv = torch.zeros(A.shape[0], dtype=torch.int32, device=self.device)
-        out = self._factor(OP_GETRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=ipiv, profile=profile)
+        out = self._factor(OP_GETRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=ipiv, profile=profile,
+                           levels=levels)
         return (ipiv,) + out if sync else ipiv
 
     def geqrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, tau=None, report=None, info=None, sync=True,
-              profile=False):
+              profile=False, levels=None):
         torch = self.torch
         if tau is None:
             tau = torch.zeros(A.shape[0], dtype=torch.float64, device=self.device)
-        out = self._factor(OP_GEQRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=tau, profile=profile)
+        out = self._factor(OP_GEQRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=tau, profile=profile,
+                           levels=levels)
         return (tau,) + out if sync else tau
 
     def profile(self):
@@ -222,7 +262,7 @@ class Handle:
         _check(lib().abft_get_profile(self._h, C.byref(p)), "abft_get_profile")
         return p.as_dict()
 
-    def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None, profile=False):
+    def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None, profile=False, levels=None):
         torch = self.torch
         n = A.shape[0]
         if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
@@ -231,7 +271,7 @@ class Handle:
         if nb is None or nb == "auto":  # the autotuned block size for this operation and size class
             from . import autotune
             nb = autotune.lookup_nb({OP_POTRF: "potrf", OP_GETRF: "getrf"}.get(op, "geqrf"), n)
-        opts, keep = make_opts(nb, protect, tau_scale, faults, profile)
+        opts, keep = make_opts(nb, protect, tau_scale, faults, profile, levels=levels)
         ws, wbytes = self.workspace(op, n, opts)
         rep = report if report is not None else self.new_report()
         inf = info if info is not None else torch.zeros(1, dtype=torch.int32, device=self.device)

@@ -222,12 +222,13 @@ __device__ void tile_sums_stream(const T* A, int64_t lda, int64_t r0, int64_t c0
 }
 
 // mode 0: encode (write sums); mode 1: verify (flag, refresh clean tiles);
-// mode 2: verify only
+// mode 2: verify only.  level 1 compares the column checksums only (single
+// side; the row sums are still refreshed with the column sums).
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_verify(const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0,
                                                 int nI, int sym, int mode, double* colchk, int64_t ldc, double* rowchk,
                                                 int64_t ldr, const double* gc, const double* gr, double tsu,
-                                                int* tflags, abft_report* rep, int iter) {
+                                                int* tflags, abft_report* rep, int iter, int level) {
   __shared__ StreamSums ts;
   __shared__ StreamLds sl;
   __shared__ int s_nfl;
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(256, 2) void k_verify(const T* A, int64_t lda, int6
     cmp(ts.ce[j] - colchk[o], tau_verify(tsu, ts.ca[j], gc ? gc[o] : 0.0));
     cmp(ts.cw[j] - colchk[o + 1], tau_verify(tsu, ts.cwa[j], gc ? gc[o + 1] : 0.0));
   }
-  for (int i = threadIdx.x; i < h; i += blockDim.x) {
+  for (int i = threadIdx.x; i < (level == 1 ? 0 : h); i += blockDim.x) {
     const int64_t o = (r0 + i) + (2 * J) * ldr;
     cmp(ts.res[i] - rowchk[o], tau_verify(tsu, ts.ra[i], gr ? gr[o] : 0.0));
     cmp(ts.rws[i] - rowchk[o + ldr], tau_verify(tsu, ts.rwa[i], gr ? gr[o + ldr] : 0.0));
@@ -306,7 +307,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_correct(T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0,
                                                  int nI, int sym, double* colchk, int64_t ldc, double* rowchk,
                                                  int64_t ldr, const double* gc, const double* gr, double tsu,
-                                                 const int* tflags, abft_report* rep, int iter) {
+                                                 const int* tflags, abft_report* rep, int iter, int level) {
   __shared__ TileSums ts;
   __shared__ TileFlags tf;
   __shared__ CorrState cs;
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(256) void k_correct(T* A, int64_t lda, int64_t nr, 
   if (sym && I < J) return;
   if (!tflags[tile]) return;
   correct_tile_dev(A, lda, I, J, nb, h, w, sym && I == J, colchk, ldc, rowchk, ldr, gc, gr, tsu, rep, iter, ts, tf,
-                   cs);
+                   cs, level);
 }
 
 // ---------------------------------------------------------------------------
@@ -663,37 +664,37 @@ __global__ void k_report_fini(abft_report* r) {
 template <typename T>
 int verify_tiles(hipStream_t s, const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
                  int mode, double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc,
-                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter) {
+                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter, int level) {
   int Nr = (int)((nr + nb - 1) / nb), Nc = (int)((nc + nb - 1) / nb);
   int nI = Nr - I0, nJ = Nc - J0;
   if (nI <= 0 || nJ <= 0) return 0;
   hipLaunchKernelGGL(k_verify<T>, dim3(nI * nJ), dim3(256), 0, s, A, lda, nr, nc, nb, I0, J0, nI, sym, mode, colchk,
-                     ldc, rowchk, ldr, gc, gr, tsu, tflags, rep, iter);
+                     ldc, rowchk, ldr, gc, gr, tsu, tflags, rep, iter, level);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 template <typename T>
 int correct_tiles(hipStream_t s, T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
                   double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc, const double* gr,
-                  double tsu, const int* tflags, abft_report* rep, int iter) {
+                  double tsu, const int* tflags, abft_report* rep, int iter, int level) {
   int Nr = (int)((nr + nb - 1) / nb), Nc = (int)((nc + nb - 1) / nb);
   int nI = Nr - I0, nJ = Nc - J0;
   if (nI <= 0 || nJ <= 0) return 0;
   hipLaunchKernelGGL(k_correct<T>, dim3(nI * nJ), dim3(256), 0, s, A, lda, nr, nc, nb, I0, J0, nI, sym, colchk, ldc,
-                     rowchk, ldr, gc, gr, tsu, tflags, rep, iter);
+                     rowchk, ldr, gc, gr, tsu, tflags, rep, iter, level);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 template int verify_tiles<double>(hipStream_t, const double*, int64_t, int64_t, int64_t, int, int, int, int, int,
                                   double*, int64_t, double*, int64_t, const double*, const double*, double, int*,
-                                  abft_report*, int);
+                                  abft_report*, int, int);
 template int verify_tiles<float>(hipStream_t, const float*, int64_t, int64_t, int64_t, int, int, int, int, int, double*,
                                  int64_t, double*, int64_t, const double*, const double*, double, int*, abft_report*,
-                                 int);
+                                 int, int);
 template int correct_tiles<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int, int, int, int, double*,
                                    int64_t, double*, int64_t, const double*, const double*, double, const int*,
-                                   abft_report*, int);
+                                   abft_report*, int, int);
 template int correct_tiles<float>(hipStream_t, float*, int64_t, int64_t, int64_t, int, int, int, int, double*, int64_t,
                                   double*, int64_t, const double*, const double*, double, const int*, abft_report*,
-                                  int);
+                                  int, int);
 
 template <typename T>
 int xsums(hipStream_t s, const T* A, int64_t lda, int64_t n, int nb, int I0, int64_t xc0, int kw, int dI, int mode,

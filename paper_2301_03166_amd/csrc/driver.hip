@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -233,9 +234,29 @@ int check_opts(const abft_opts* o, int64_t n, int& nb, int& protect, double& ts)
   protect = o->protect;
   ts = o->tau_scale > 0 ? o->tau_scale : 4.0;
   if (nb < 1 || nb > MAXNB) return -7;
-  if (protect != ABFT_PROTECT_NONE && protect != ABFT_PROTECT_FULL) return -7;
-  (void)n;
+  if (protect < ABFT_PROTECT_NONE || protect > ABFT_PROTECT_FULL) return -7;
+  if (o->levels) {
+    const int64_t N = (n + nb - 1) / nb;
+    if (o->nlevels < N) return -7;
+    for (int64_t k = 0; k < N; ++k)
+      if (o->levels[k] < ABFT_PROTECT_NONE || o->levels[k] > ABFT_PROTECT_FULL) return -7;
+  }
   return 0;
+}
+
+// protection level of iteration k (the caller's per-iteration levels, or
+// the call's level), and whether any iteration is protected
+inline int level_at(const abft_opts* o, int k, int protect) { return o->levels ? o->levels[k] : protect; }
+inline bool any_protected(const abft_opts* o, int N, int protect) {
+  if (!o->levels) return protect != ABFT_PROTECT_NONE;
+  for (int k = 0; k < N; ++k)
+    if (o->levels[k]) return true;
+  return false;
+}
+inline bool has_operand_faults(const abft_opts* o) {
+  for (int q = 0; q < (o->faults ? o->nfaults : 0); ++q)
+    if (o->faults[q].target == 3 || o->faults[q].target == 4) return true;
+  return false;
 }
 
 inline int split(int w, int leaf = LEAFW) { return ((w / 2 + leaf - 1) / leaf) * leaf; }
@@ -255,6 +276,27 @@ int apply_faults(hipStream_t s, const abft_opts* o, int iter, T* A, int64_t lda,
     } else if (f.target == 2 && w.rowchk) {
       if (f.row < 0 || f.row >= n || f.col < 0 || f.col >= 2 * N) continue;
       TRY(inject(s, w.rowchk + f.row + f.col * n, 0, f.bit));
+    }
+  }
+  return 0;
+}
+
+// Operand faults of iteration `iter` (targets 3 / 4): XOR the bit of the
+// stored operand element; called before the trailing-update product and
+// again after it, which restores the element.  W2 (QR's right operand, nb x
+// columns [c1, n)) is addressed by (p, matrix column).
+template <typename T>
+int apply_operand_faults(hipStream_t s, const abft_opts* o, int iter, T* A, int64_t lda, int64_t n, const double* W2,
+                         int ldw2, int64_t c1) {
+  for (int q = 0; q < (o->faults ? o->nfaults : 0); ++q) {
+    const abft_fault& f = o->faults[q];
+    if (f.iter != iter || (f.target != 3 && f.target != 4)) continue;
+    if (f.target == 4 && W2) {
+      if (f.row < 0 || f.row >= ldw2 || f.col < c1 || f.col >= n) continue;
+      TRY(inject(s, (void*)(W2 + f.row + (f.col - c1) * ldw2), 0, f.bit));
+    } else {
+      if (f.row < 0 || f.row >= n || f.col < 0 || f.col >= n) continue;
+      TRY(inject(s, A + f.row + f.col * lda, sizeof(T) == 4, f.bit));
     }
   }
   return 0;
@@ -412,7 +454,7 @@ int qr_panel(QrCtx& c, int64_t c0, int64_t c1) {
 // the transposes of S / Sa (symmetric update, Y = X^T).
 template <typename T>
 int carry(hipStream_t s, const Ws& w, int64_t n, int nb, int I0, int J0, int kw, const T* Xp, int64_t ldx,
-          int64_t xr0, int fx, const T* Yp, int64_t ldy, int ty, int64_t yc0, int tS, int rnd = 0) {
+          int64_t xr0, int fx, const T* Yp, int64_t ldy, int ty, int64_t yc0, int tS, int rnd = 0, int rowside = 1) {
   const int N = (int)((n + nb - 1) / nb);
   const int ldS = 2 * N;
   const int isf = sizeof(T) == 4;
@@ -422,6 +464,7 @@ int carry(hipStream_t s, const Ws& w, int64_t n, int nb, int I0, int J0, int kw,
              ldS, 0, 0, isf, rnd));
   TRY(gemm64(s, 0, ty, 0, 2, 0, mr, ncol, kw, 1.0, w.Sa + 2 * I0, ldS, Yp, ldy, 0.0, w.gc + 2 * I0 + yc0 * ldS, ldS,
              0, 0, isf, rnd));
+  if (!rowside) return 0;  // single-side checksums: the row side is neither carried nor compared
   // row side
   const int nr = (int)(n - xr0), mc = 2 * (N - J0);
   const double* Bm = tS ? w.S + 2 * J0 : w.Tm + (int64_t)2 * J0 * nb;
@@ -440,7 +483,7 @@ inline int op_rnd(int prec) { return prec == ABFT_BF16 ? 1 : (prec == ABFT_F16 ?
 // T = double (prec ABFT_F64) or float (ABFT_F32 / ABFT_BF16 / ABFT_F16).
 template <typename T>
 int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const abft_opts* opts, int nb, int protect,
-               double ts, int prec, int32_t* dinfo, abft_report* drep) {
+               double ts, int prec, int32_t* dinfo, abft_report* drep, bool one_stream = false) {
   hipStream_t s = h->stream;
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
@@ -449,31 +492,38 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
   const double u = sizeof(T) == 8 ? U64 : U32;
   const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
   const int rnd = op_rnd(prec);
+  const bool opf = has_operand_faults(opts);
   Prof pf(h, opts);
-  Side side(h, protect && !pf.on);  // (nothing to overlap without checksums)
-  int t = pf.begin(PH_VERIFY);
-  if (protect)
-    TRY(verify_tiles<T>(s, dA, lda, n, n, nb, 0, 0, 1, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
-                        nullptr, -1));
-  pf.end(t);
+  // (nothing to overlap without checksums; operand faults need the update
+  // product and the carry in order)
+  Side side(h, any_protected(opts, N, protect) && !pf.on && !one_stream && !opf);
+  int t, prev = ABFT_PROTECT_NONE;
   for (int k = 0; k < N; ++k) {
     const int64_t c0 = (int64_t)k * nb;
     const int kw = (int)std::min<int64_t>(nb, n - c0);
     const int64_t c1 = c0 + kw;
+    const int lev = level_at(opts, k, protect);
     pf.iters++;
+    if (lev > prev) {  // a protected stretch starts from checksums of the data
+      t = pf.begin(PH_VERIFY);
+      TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k, k, 1, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
+                          nullptr, -1));
+      pf.end(t);
+    }
+    prev = lev;
     t = pf.begin(PH_PANEL);
     TRY(chol_panel(s, dA, lda, n, c0, c1, dinfo));
     // the panel check only reads (the panel, its checksum rows, colchk of the
     // panel's columns): it goes to the side stream with the carry
-    const bool defer = side.on && c1 < n;
+    const bool fork = side.on && lev && c1 < n;
     auto check_k = [&](hipStream_t cs) -> int {
       // e^T A_Ik = (e^T L_I) L_kk^T:  M(p, j) = L(c0 + j, c0 + p), p <= j
       return panel_check<T>(cs, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, lda, 1, 1, 0, 1.0, nullptr, nullptr,
                             nullptr, -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb);
     };
-    if (protect) {
+    if (lev) {
       TRY(xsums<T>(s, dA, lda, n, nb, k, c0, kw, k, 1, w.S, w.Sa, ldc, 0));
-      if (!defer) TRY(check_k(s));
+      if (!fork) TRY(check_k(s));
     }
     pf.end(t);
     if (c1 >= n) break;
@@ -481,34 +531,35 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     T* L21 = dA + c1 + c0 * lda;
     auto carry_k = [&](hipStream_t cs) -> int {
       if (rnd) TRY(xsums<T>(cs, dA, lda, n, nb, k + 1, c0, kw, k, 1, w.S, w.Sa, ldc, rnd));
-      return carry<T>(cs, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, L21, lda, 1, c1, 1, rnd);
+      return carry<T>(cs, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, L21, lda, 1, c1, 1, rnd,
+                      lev == ABFT_PROTECT_FULL);
     };
-    if (side.on) {
+    if (fork) {
       TRY(side.fork());
-      if (protect) {
-        TRY(check_k(side.s));
-        TRY(carry_k(side.s));
-      }
+      TRY(check_k(side.s));
+      TRY(carry_k(side.s));
     }
+    if (opf) TRY(apply_operand_faults<T>(s, opts, k, dA, lda, n, nullptr, 0, c1));
     t = pf.begin(PH_TMU);
     TRY(gemmT(s, prec, 0, 1, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
     pf.end(t);
+    if (opf) TRY(apply_operand_faults<T>(s, opts, k, dA, lda, n, nullptr, 0, c1));
     pf.tmu_flops += (double)m * (double)(m + 1) * kw;
     pf.tmu_launches++;
-    if (side.on) {
+    if (fork) {
       TRY(side.join());
-    } else if (protect) {
+    } else if (lev) {
       t = pf.begin(PH_CARRY);
       TRY(carry_k(s));
       pf.end(t);
     }
     if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N));
-    if (protect) {
+    if (lev) {
       t = pf.begin(PH_VERIFY);
       TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                          w.tflags, drep, k));
+                          w.tflags, drep, k, lev));
       TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                           w.tflags, drep, k));
+                           w.tflags, drep, k, lev));
       pf.end(t);
       const double mt = (double)m / nb;
       pf.verify_bytes += (double)sizeof(T) * nb * nb * (mt * (mt + 1) / 2);
@@ -533,13 +584,10 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
   const double u = sizeof(T) == 8 ? U64 : U32;
   const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
   const int rnd = op_rnd(prec);
+  const bool opf = has_operand_faults(opts);
   Prof pf(h, opts);
-  Side side(h, !pf.on);
-  int t = pf.begin(PH_VERIFY);
-  if (protect)
-    TRY(verify_tiles<T>(s, dA, lda, n, n, nb, 0, 0, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
-                        nullptr, -1));
-  pf.end(t);
+  Side side(h, !pf.on && !opf);
+  int t, prev = ABFT_PROTECT_NONE;
   LuCtx<T> c{s, dA, lda, n, dipiv, dinfo, &w, 0u, drep, std::min(h->cus, 256)};
   T* porig = (T*)w.porig;
   T* stage = (T*)w.stage;
@@ -547,9 +595,17 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
     const int64_t c0 = (int64_t)k * nb;
     const int kw = (int)std::min<int64_t>(nb, n - c0);
     const int64_t c1 = c0 + kw;
+    const int lev = level_at(opts, k, protect);
     pf.iters++;
+    if (lev > prev) {  // a protected stretch starts from checksums of the data
+      t = pf.begin(PH_VERIFY);
+      TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k, k, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
+                          nullptr, -1));
+      pf.end(t);
+    }
+    prev = lev;
     t = pf.begin(PH_PANEL);
-    if (protect)
+    if (lev)
       if (hipMemcpy2DAsync(porig, n * sizeof(T), dA + c0 + c0 * lda, lda * sizeof(T), (n - c0) * sizeof(T), kw,
                            hipMemcpyDeviceToDevice, s) != hipSuccess)
         return ABFT_ERR_HIP;
@@ -570,8 +626,8 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
                             nullptr, -1, w.colchk, ldc, c1, (int)(n - c1), tsu_p, drep, k, nb);
     };
     if (!defer) TRY(laswp(s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
-    TRY(laswp(s, dA, lda, c1, n, w.moves, stage, protect ? w.colchk : (double*)nullptr, ldc, nb));
-    if (protect) {
+    TRY(laswp(s, dA, lda, c1, n, w.moves, stage, lev ? w.colchk : (double*)nullptr, ldc, nb));
+    if (lev) {
       // column checksums of the panel follow the interchanges of the original panel values
       TRY(laswp(s, porig - c0, n, 0, kw, w.moves, stage, w.colchk + c0 * ldc, ldc, nb));
       if (!defer) TRY(laswp(s, w.rowchk, n, 0, 2 * N, w.moves, (double*)w.stage, (double*)nullptr, 0, nb));
@@ -583,45 +639,48 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       break;
     }
     TRY(trsm_llu(s, dA, lda, c0, kw, c1, n));
-    if (protect && !defer) TRY(check_pu(s));
+    if (lev && !defer) TRY(check_pu(s));
     pf.end(t);
     const int64_t m = n - c1;
     T* L21 = dA + c1 + c0 * lda;
     T* U12 = dA + c0 + c1 * lda;
     auto carry_k = [&](hipStream_t cs) -> int {
       if (rnd) TRY(xsums<T>(cs, dA, lda, n, nb, k + 1, c0, kw, k, 2, w.S, w.Sa, ldc, rnd));
-      TRY(ysums<T>(cs, dA + c0, lda, n, nb, k + 1, kw, w.Tm, w.Ta, nb, rnd));
-      return carry<T>(cs, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, U12, lda, 0, c1, 0, rnd);
+      if (lev == ABFT_PROTECT_FULL) TRY(ysums<T>(cs, dA + c0, lda, n, nb, k + 1, kw, w.Tm, w.Ta, nb, rnd));
+      return carry<T>(cs, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, U12, lda, 0, c1, 0, rnd,
+                      lev == ABFT_PROTECT_FULL);
     };
     if (side.on) {  // (w.moves stays unchanged until the join)
       TRY(side.fork());
       TRY(laswp(side.s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
-      if (protect) {
+      if (lev) {
         TRY(check_pd(side.s));
         TRY(check_pu(side.s));
         TRY(laswp(side.s, w.rowchk, n, 0, 2 * N, w.moves, (double*)w.stage, (double*)nullptr, 0, nb));
         TRY(carry_k(side.s));
       }
     }
+    if (opf) TRY(apply_operand_faults<T>(s, opts, k, dA, lda, n, nullptr, 0, c1));
     t = pf.begin(PH_TMU);
     TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
     pf.end(t);
+    if (opf) TRY(apply_operand_faults<T>(s, opts, k, dA, lda, n, nullptr, 0, c1));
     pf.tmu_flops += 2.0 * (double)m * (double)m * kw;
     pf.tmu_launches++;
     if (side.on) {
       TRY(side.join());
-    } else if (protect) {
+    } else if (lev) {
       t = pf.begin(PH_CARRY);
       TRY(carry_k(s));
       pf.end(t);
     }
     if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N));
-    if (protect) {
+    if (lev) {
       t = pf.begin(PH_VERIFY);
       TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                          w.tflags, drep, k));
+                          w.tflags, drep, k, lev));
       TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                           w.tflags, drep, k));
+                           w.tflags, drep, k, lev));
       pf.end(t);
       pf.verify_bytes += (double)sizeof(T) * (double)m * (double)m;
     }
@@ -790,6 +849,36 @@ int gesv_mp_impl(abft_handle h, int64_t n, const double* dA, int64_t lda, const 
 
 }  // namespace
 
+// ------------------------------------------------------ no-allocation scratch
+// Scratch of abft_potrf_noalloc: a device array in the library's code object,
+// so that entry point needs no workspace argument and allocates nothing.  Each
+// GPU holds its own copy (at its own address) until the process ends.  Host
+// code never uses the array's name as an address (it is a host-side stand-in);
+// the device address of each GPU's copy is looked up once, with that device
+// current, and kept in g_scratch.
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+static void* g_scratch[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static int scratch_ptr(int device, void** out) {
+  if (device < 0 || device >= MAX_DEVICES) return ABFT_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return ABFT_ERR_HIP;
+    if (cur != device && hipSetDevice(device) != hipSuccess) return ABFT_ERR_HIP;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return ABFT_ERR_HIP;
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return 0;
+}
+
 // ===================================================================== ABI
 extern "C" {
 
@@ -803,6 +892,10 @@ int abft_create(abft_handle* h, void* stream) {
     free(p);
     return ABFT_ERR_HIP;
   }
+  // the no-allocation scratch of this device (abft_potrf_noalloc retries the
+  // lookup, and fails loudly, if it did not succeed here)
+  void* sp = nullptr;
+  (void)scratch_ptr(p->device, &sp);
   *h = p;
   return 0;
 }
@@ -883,6 +976,25 @@ int abft_potrf(abft_handle h, int64_t n, double* dA, int64_t lda, void* dwork, s
   return potrf_impl<double>(h, n, dA, lda, w, opts, nb, protect, ts, ABFT_F64, dinfo, drep);
 }
 
+int abft_potrf_noalloc(abft_handle h, int64_t n, double* dA, int64_t lda, const abft_opts* opts, int32_t* dinfo,
+                       abft_report* drep) {
+  if (!h) return -1;
+  if (n < 0) return -2;
+  if (!dA && n > 0) return -3;
+  if (lda < std::max<int64_t>(1, n)) return -4;
+  int nb, protect;
+  double ts;
+  TRY(check_opts(opts, n, nb, protect, ts));
+  if (opts->flags & ABFT_FLAG_PROFILE) return ABFT_ERR_UNSUPPORTED;  // (profiling creates events)
+  if (!dinfo) return -6;
+  const size_t need = carve(nullptr, n, nb, ABFT_OP_POTRF, sizeof(double)).bytes;
+  if (need > NOALLOC_BYTES) return ABFT_ERR_WORKSPACE;
+  void* base = nullptr;
+  TRY(scratch_ptr(h->device, &base));
+  Ws w = carve((char*)base, n, nb, ABFT_OP_POTRF, sizeof(double));
+  return potrf_impl<double>(h, n, dA, lda, w, opts, nb, protect, ts, ABFT_F64, dinfo, drep, true);
+}
+
 int abft_getrf(abft_handle h, int64_t n, double* dA, int64_t lda, int32_t* dipiv, void* dwork, size_t work_bytes,
                const abft_opts* opts, int32_t* dinfo, abft_report* drep) {
   if (!h) return -1;
@@ -920,19 +1032,22 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   const int N = (int)((n + nb - 1) / nb);
   const int ldc = 2 * N;
   const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);
-  if (protect)
-    TRY(verify_tiles<double>(s, dA, lda, n, n, nb, 0, 0, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu,
-                             nullptr, nullptr, -1));
+  const bool opf = has_operand_faults(opts);
   QrCtx c{s, dA, lda, n, dtau, &w, nb, 0, 0u, drep, std::min(h->cus, 256)};
   Prof pf(h, opts);
-  Side side(h, protect && !pf.on);
-  int t;
+  Side side(h, any_protected(opts, N, protect) && !pf.on && !opf);
+  int t, prev = ABFT_PROTECT_NONE;
   for (int k = 0; k < N; ++k) {
     const int64_t c0 = (int64_t)k * nb;
     const int kw = (int)std::min<int64_t>(nb, n - c0);
     const int64_t c1 = c0 + kw;
+    const int lev = level_at(opts, k, protect);
     c.cb = c0;
     pf.iters++;
+    if (lev > prev)  // a protected stretch starts from checksums of the data
+      TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k, k, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu,
+                               nullptr, nullptr, -1));
+    prev = lev;
     t = pf.begin(PH_PANEL);
     TRY(fill_zero(s, w.Tfac, (size_t)nb * nb * sizeof(double)));
     TRY(qr_panel(c, c0, c1));
@@ -944,9 +1059,10 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
       return panel_check(cs, w.S, w.Sa, ldc, k, N, kw, w.Z, 1, kw, 0, 0, -1.0, w.Zabs, w.E, w.bt, k, w.colchk, ldc,
                          c0, kw, tsu_p, drep, k, nb);
     };
-    if (protect) {
+    const bool fork = side.on && lev && c1 < n;
+    if (lev) {
       TRY(xsums<double>(s, dA, lda, n, nb, k, c0, kw, k, 2, w.S, w.Sa, ldc, 0));
-      if (side.on && c1 < n) {
+      if (fork) {
         TRY(side.fork());
         TRY(check_k(side.s));
       } else {
@@ -968,33 +1084,35 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     if (S > 1) TRY(splitk_reduce(s, w.splitk, S, kw, (int)m, 0.0, w.W, nb));
     TRY(gemm64(s, 1, 0, 0, 0, 0, kw, (int)m, kw, 1.0, w.Tfac, nb, w.W, nb, 0.0, w.W2, nb, 0));
     auto carry_k = [&](hipStream_t cs) -> int {
-      TRY(ysums<double>(cs, w.W2 - c1 * nb, nb, n, nb, k + 1, kw, w.Tm, w.Ta, nb, 0));
-      return carry(cs, w, n, nb, k, k + 1, kw, V, lda, c0, 1, w.W2, nb, 0, c1, 0);
+      if (lev == ABFT_PROTECT_FULL) TRY(ysums<double>(cs, w.W2 - c1 * nb, nb, n, nb, k + 1, kw, w.Tm, w.Ta, nb, 0));
+      return carry(cs, w, n, nb, k, k + 1, kw, V, lda, c0, 1, w.W2, nb, 0, c1, 0, 0, lev == ABFT_PROTECT_FULL);
     };
-    if (side.on) {  // (W2 is final here; the second product only reads it)
+    if (fork) {  // (W2 is final here; the second product only reads it)
       TRY(side.fork());
       TRY(carry_k(side.s));
     }
+    if (opf) TRY(apply_operand_faults<double>(s, opts, k, dA, lda, n, w.W2, nb, c1));
     t = pf.begin(PH_TMU);
     TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)m, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0, 0, 0, 0, nullptr,
                0, 1));
     pf.end(t);
+    if (opf) TRY(apply_operand_faults<double>(s, opts, k, dA, lda, n, w.W2, nb, c1));
     pf.tmu_flops += 4.0 * (double)(n - c0) * (double)m * kw;
     pf.tmu_launches += 2;
-    if (side.on) {
+    if (fork) {
       TRY(side.join());
-    } else if (protect) {
+    } else if (lev) {
       t = pf.begin(PH_CARRY);
       TRY(carry_k(s));
       pf.end(t);
     }
     if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N));
-    if (protect) {
+    if (lev) {
       t = pf.begin(PH_VERIFY);
       TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                               w.tflags, drep, k));
+                               w.tflags, drep, k, lev));
       TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                                w.tflags, drep, k));
+                                w.tflags, drep, k, lev));
       pf.end(t);
       pf.verify_bytes += 8.0 * (double)(n - c0) * (double)m;
     }
@@ -1090,6 +1208,7 @@ static int batched_common(abft_handle h, int chol, int32_t batch, int32_t nmax, 
   double ts;
   TRY(check_opts(opts, nmax, nb, protect, ts));
   if (nb != 32) return ABFT_ERR_UNSUPPORTED;  // the batched kernels use 32-wide blocks and tiles
+  if (protect == ABFT_PROTECT_SINGLE || opts->levels) return ABFT_ERR_UNSUPPORTED;  // full checksums or none
   if (batch == 0) return 0;
   if (!dinfo || !dreps) return -11;
   if (!dwork || work_bytes < batched_ws_bytes(batch)) return ABFT_ERR_WORKSPACE;

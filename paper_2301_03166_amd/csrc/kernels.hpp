@@ -35,11 +35,11 @@ int gemm32(hipStream_t s, int prec, int ta, int tb, int lower, int m, int n, int
 template <typename T>
 int verify_tiles(hipStream_t s, const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
                  int mode, double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc,
-                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter);
+                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter, int level = 2);
 template <typename T>
 int correct_tiles(hipStream_t s, T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
                   double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc, const double* gr,
-                  double tsu, const int* tflags, abft_report* rep, int iter);
+                  double tsu, const int* tflags, abft_report* rep, int iter, int level = 2);
 template <typename T>
 int xsums(hipStream_t s, const T* A, int64_t lda, int64_t n, int nb, int I0, int64_t xc0, int kw, int dI, int mode,
           double* S, double* Sa, int ldS, int rnd);

@@ -140,10 +140,16 @@ __device__ __forceinline__ double slack_w(int line, int a, int b, bool sdiag, do
 }
 
 // sci < 0: plain comparison; otherwise widen the sums that hold element
-// (sci, scj) as described above
+// (sci, scj) as described above.  level 1 (column checksums only) leaves the
+// row side out.  line 1 / 2: row / column lidx of the tile was rebuilt from
+// the checksums of the other side; every rebuilt element is known to the
+// tolerance of the checksum it came from (column j: te_j, row i: te_i), so
+// each sum through it is widened by its weight there times that tolerance,
+// and the rebuilt line's own sums by lsum = sum of them (lwsum: weighted).
 __device__ void tile_compare(const TileSums& ts, TileFlags& tf, int I, int J, int nb, int h, int w,
                              const double* colchk, int64_t ldc, const double* rowchk, int64_t ldr, const double* gc,
-                             const double* gr, double tsu, int sci = -1, int scj = -1, bool sdiag = false) {
+                             const double* gr, double tsu, int sci = -1, int scj = -1, bool sdiag = false,
+                             int level = 2, int line = 0, int lidx = -1, double lsum = 0.0, double lwsum = 0.0) {
   int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
   if (threadIdx.x == 0) { tf.nflag = 0; tf.maxr = 0.0; }
   __syncthreads();
@@ -159,6 +165,14 @@ __device__ void tile_compare(const TileSums& ts, TileFlags& tf, int I, int J, in
       const double sw = slack_w(j, sci, scj, sdiag, tec);
       if (sw > 0.0) { te += tec; tw += sw; }
     }
+    if (line == 1) {  // this column's element in row lidx came from this column's checksum
+      const double tl = tau_verify(tsu, ts.ca[j], gc ? gc[o] : 0.0);
+      te += tl;
+      tw += (double)(lidx + 1) * tl;
+    } else if (line == 2 && j == lidx) {
+      te += lsum;
+      tw += lwsum;
+    }
     bool be = bad(de, te), bw = bad(dw, tw);
     tf.de[j] = de; tf.dw[j] = dw; tf.fe[j] = be; tf.fw[j] = bw;
     nfl += be + bw;
@@ -166,12 +180,25 @@ __device__ void tile_compare(const TileSums& ts, TileFlags& tf, int I, int J, in
     if (!bw && tw > 0) mr = fmax(mr, fabs(dw) / tw);
   }
   for (int i = threadIdx.x; i < h; i += blockDim.x) {
+    if (level == 1) {  // single side: the row checksums are not compared
+      tf.he[i] = tf.hw[i] = 0.0;
+      tf.ge[i] = tf.gw[i] = 0;
+      continue;
+    }
     int64_t o = (r0 + i) + (2 * J) * ldr;
     double de = ts.res[i] - rowchk[o], dw = ts.rws[i] - rowchk[o + ldr];
     double te = tau_verify(tsu, ts.ra[i], gr ? gr[o] : 0.0), tw = tau_verify(tsu, ts.rwa[i], gr ? gr[o + ldr] : 0.0);
     if (sci >= 0) {
       const double sw = slack_w(i, scj, sci, sdiag, tec);
       if (sw > 0.0) { te += tec; tw += sw; }
+    }
+    if (line == 2) {  // this row's element in column lidx came from this row's checksum
+      const double tl = tau_verify(tsu, ts.ra[i], gr ? gr[o] : 0.0);
+      te += tl;
+      tw += (double)(lidx + 1) * tl;
+    } else if (line == 1 && i == lidx) {
+      te += lsum;
+      tw += lwsum;
     }
     bool be = bad(de, te), bw = bad(dw, tw);
     tf.he[i] = de; tf.hw[i] = dw; tf.ge[i] = be; tf.gw[i] = bw;
@@ -206,17 +233,104 @@ __device__ __forceinline__ int ratio_index(double dw, double de, int len) {
 // itself left out, so huge, Inf or NaN values are repaired too.  Every
 // outcome ends with the tile's checksums re-encoded from the data.
 struct CorrState {
-  int ci, cj, kind;
-  double old;
+  int ci, cj, kind;  // kind: 0 clean, 1 element, 2 checksum repair, 3 uncorrectable, 5 / 6 row / column rebuilt
+  int lidx;          // the rebuilt row (kind 5) or column (kind 6)
+  double old, lsum, lwsum;
+  double part[4][2];     // per-wave partial sums of the rebuilt line's tolerances
+  double oldv[MAXNB];    // the rebuilt line's previous values
 };
 
+// A 1D error (one row or one column of the tile wrong in several places,
+// as an error in an operand of the update leaves it) with full checksums:
+// the row (column) is rebuilt element by element from the checksums of the
+// other side, each element from its own column (row) with the rest of that
+// column (row) left out; the tile is then rechecked with the rebuilt
+// elements' tolerances (tile_compare, line 1 / 2) and the old values come
+// back when the recheck fails.  Returns through cs.kind (3 on failure).
+template <typename T>
+__device__ void rebuild_line_dev(T* A, int64_t lda, int I, int J, int nb, int h, int w, const double* colchk,
+                                 int64_t ldc, const double* rowchk, int64_t ldr, const double* gc, const double* gr,
+                                 double tsu, TileSums& ts, TileFlags& tf, CorrState& cs) {
+  const int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int line = cs.kind == 5 ? 1 : 2, idx = cs.lidx;
+  if (line == 1) {  // row idx: one column per wave
+    for (int j = wv; j < w; j += 4) {
+      acc2 sacc{0, 0};
+      for (int i = lane; i < h; i += 64)
+        if (i != idx) cadd(sacc, (double)A[(r0 + i) + (c0 + j) * lda]);
+      sacc = wave_csum(sacc);
+      if (lane == 0) {
+        T* p = A + (r0 + idx) + (c0 + j) * lda;
+        cs.oldv[j] = (double)*p;
+        *p = (T)(colchk[2 * I + (c0 + j) * ldc] - cval(sacc));
+      }
+    }
+  } else {  // column idx: one row per wave
+    for (int i = wv; i < h; i += 4) {
+      acc2 sacc{0, 0};
+      for (int j = lane; j < w; j += 64)
+        if (j != idx) cadd(sacc, (double)A[(r0 + i) + (c0 + j) * lda]);
+      sacc = wave_csum(sacc);
+      if (lane == 0) {
+        T* p = A + (r0 + i) + (c0 + idx) * lda;
+        cs.oldv[i] = (double)*p;
+        *p = (T)(rowchk[(r0 + i) + (2 * J) * ldr] - cval(sacc));
+      }
+    }
+  }
+  __syncthreads();
+  tile_sums(A, lda, r0, c0, h, w, false, ts);
+  // the rebuilt line's own sums hold every rebuilt element once
+  double p0 = 0.0, p1 = 0.0;
+  if (line == 1) {
+    for (int j = threadIdx.x; j < w; j += blockDim.x) {
+      const double tl = tau_verify(tsu, ts.ca[j], gc ? gc[2 * I + (c0 + j) * ldc] : 0.0);
+      p0 += tl;
+      p1 += (double)(j + 1) * tl;
+    }
+  } else {
+    for (int i = threadIdx.x; i < h; i += blockDim.x) {
+      const double tl = tau_verify(tsu, ts.ra[i], gr ? gr[(r0 + i) + (2 * J) * ldr] : 0.0);
+      p0 += tl;
+      p1 += (double)(i + 1) * tl;
+    }
+  }
+  p0 = wave_sum(p0);
+  p1 = wave_sum(p1);
+  if (lane == 0) {
+    cs.part[wv][0] = p0;
+    cs.part[wv][1] = p1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cs.lsum = ((cs.part[0][0] + cs.part[1][0]) + cs.part[2][0]) + cs.part[3][0];
+    cs.lwsum = ((cs.part[0][1] + cs.part[1][1]) + cs.part[2][1]) + cs.part[3][1];
+  }
+  __syncthreads();
+  tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu, -1, -1, false, 2, line, idx, cs.lsum,
+               cs.lwsum);
+  if (tf.nflag != 0) {
+    if (line == 1) {
+      for (int j = threadIdx.x; j < w; j += blockDim.x) A[(r0 + idx) + (c0 + j) * lda] = (T)cs.oldv[j];
+    } else {
+      for (int i = threadIdx.x; i < h; i += blockDim.x) A[(r0 + i) + (c0 + idx) * lda] = (T)cs.oldv[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) cs.kind = 3;
+  }
+  __syncthreads();
+}
+
+// level: 2 full checksums (0D and 1D rules), 1 column checksums only (0D)
 template <typename T>
 __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h, int w, bool diag, double* colchk,
                                  int64_t ldc, double* rowchk, int64_t ldr, const double* gc, const double* gr,
-                                 double tsu, abft_report* rep, int iter, TileSums& ts, TileFlags& tf, CorrState& cs) {
+                                 double tsu, abft_report* rep, int iter, TileSums& ts, TileFlags& tf, CorrState& cs,
+                                 int level = 2) {
   const int64_t r0 = (int64_t)I * nb, c0 = (int64_t)J * nb;
   tile_sums(A, lda, r0, c0, h, w, diag, ts);
-  tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu);
+  tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu, -1, -1, false, level);
   if (threadIdx.x == 0) {
     int nFe = 0, nGe = 0, nFw = 0, nGw = 0, jf0 = -1, jf1 = -1, ig = -1;
     for (int j = 0; j < w; ++j) {
@@ -230,7 +344,7 @@ __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h,
       if (tf.ge[i]) { ig = i; nGe++; }
       nGw += tf.gw[i];
     }
-    int ci = -1, cj = -1, repair = 0;
+    int ci = -1, cj = -1, repair = 0, line = 0;
     if (tf.nflag == 0) {
       repair = -1;
     } else if (diag) {
@@ -255,13 +369,20 @@ __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h,
         if (j >= 0) { ci = ig; cj = j; } else if (nFw == 0) repair = 1;
       } else if (nFe == 0 && nGe == 0) {
         repair = 1;
+      } else if (level == 2 && nGe == 1 && nFe >= 2) {
+        line = 1;  // one row wrong in several columns
+      } else if (level == 2 && nFe == 1 && nGe >= 2) {
+        line = 2;  // one column wrong in several rows
       }
     }
     cs.ci = ci;
     cs.cj = cj;
-    cs.kind = (repair == -1) ? 0 : (ci >= 0 ? 1 : (repair ? 2 : 3));
+    cs.lidx = line == 1 ? ig : jf0;
+    cs.kind = (repair == -1) ? 0 : (ci >= 0 ? 1 : (line ? 4 + line : (repair ? 2 : 3)));
   }
   __syncthreads();
+  if (cs.kind == 5 || cs.kind == 6)
+    rebuild_line_dev(A, lda, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu, ts, tf, cs);
   if (cs.kind == 1) {
     const int ci = cs.ci, cj = cs.cj;
     if (threadIdx.x < 64) {
@@ -281,7 +402,7 @@ __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h,
     }
     __syncthreads();
     tile_sums(A, lda, r0, c0, h, w, diag, ts);
-    tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu, ci, cj, diag);
+    tile_compare(ts, tf, I, J, nb, h, w, colchk, ldc, rowchk, ldr, gc, gr, tsu, ci, cj, diag, level);
     if (tf.nflag != 0) {
       if (threadIdx.x == 0) {
         A[(r0 + ci) + (c0 + cj) * lda] = (T)cs.old;
@@ -298,6 +419,11 @@ __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h,
       atomicAdd((unsigned long long*)&rep->corrected, 1ull);
       atomicOr(&rep->status, (int)ABFT_ST_CORRECTED);
       rep_event(rep, iter, 1, r0 + cs.ci, c0 + cs.cj);
+    } else if (cs.kind == 5 || cs.kind == 6) {
+      atomicAdd((unsigned long long*)&rep->corrected, 1ull);
+      atomicOr(&rep->status, (int)ABFT_ST_CORRECTED);
+      if (cs.kind == 5) rep_event(rep, iter, 5, r0 + cs.lidx, c0);
+      else rep_event(rep, iter, 6, r0, c0 + cs.lidx);
     } else if (cs.kind == 2) {
       atomicAdd((unsigned long long*)&rep->checksum_repaired, 1ull);
       atomicOr(&rep->status, (int)ABFT_ST_REPAIRED);

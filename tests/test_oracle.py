@@ -511,3 +511,160 @@ def test_threads_do_not_change_results(kind):
     (B1, a1, *r1), (B2, a2, *r2) = outs
     assert np.array_equal(B1, B2) and np.array_equal(a1, a2) and r1 == r2
     assert r1[1] == 1  # the flip was found and corrected
+
+
+# ------------------------------------------- protection levels (Alg. 1 ABFT half)
+def _fact(kind, A, nb, **kw):
+    if kind == "chol":
+        info, rep = oracle.potrf(A, nb, **kw)
+        return rep
+    if kind == "lu":
+        ipiv, info, rep = oracle.getrf(A, nb, **kw)
+        return rep
+    tau, rep = oracle.geqrf(A, nb, **kw)
+    return rep
+
+
+def _same_report(a, b):
+    return (a.status, a.flagged_tiles, a.corrected, a.uncorrectable, a.panel_flags, a.max_ratio, a.events()) == \
+        (b.status, b.flagged_tiles, b.corrected, b.uncorrectable, b.panel_flags, b.max_ratio, b.events())
+
+
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
+def test_levels_reduce_to_the_uniform_levels(kind):
+    """levels all FULL is protect=True, all NONE is protect=False (bitwise
+    factors, identical reports), and single-side protection leaves the clean
+    factorization's data untouched (the checks only read)."""
+    n, nb = 200, 32
+    N = -(-n // nb)
+    A0 = gen.spd(n, 3) if kind == "chol" else gen.general(n, 3)
+    runs = {}
+    for name, kw in (("full", {}), ("levels_full", {"levels": [2] * N}), ("none", {"protect": False}),
+                     ("levels_none", {"levels": [0] * N}), ("single", {"protect": oracle.SINGLE})):
+        A = A0.copy(order="F")
+        runs[name] = (A, _fact(kind, A, nb, **kw))
+    assert np.array_equal(runs["full"][0], runs["levels_full"][0])
+    assert _same_report(runs["full"][1], runs["levels_full"][1])
+    assert np.array_equal(runs["none"][0], runs["levels_none"][0])
+    assert runs["none"][1].status == 0 and runs["none"][1].flagged_tiles == 0 and runs["none"][1].max_ratio == 0.0
+    assert np.array_equal(runs["single"][0], runs["full"][0])
+    assert runs["single"][1].status == 0 and 0.0 < runs["single"][1].max_ratio < 0.5
+
+
+@pytest.mark.parametrize("kind", ["chol", "lu"])
+def test_adaptive_levels_exact_carries(kind):
+    """Integer / dyadic inputs: with the level switching none -> single ->
+    full the carried checksums still equal the recomputed sums exactly
+    (max_ratio 0 after every re-encode) and the factors are the exact ones."""
+    n, nb = 192, 32
+    levels = [0, 0, 1, 1, 2, 2]
+    if kind == "chol":
+        A, L0 = gen.chol_exact(n, seed=8)
+        rep = _fact(kind, A, nb, levels=levels)
+        assert np.array_equal(np.tril(A), L0)
+    else:
+        A, P, L0, U0 = gen.lu_exact(n, seed=8)
+        rep = _fact(kind, A, nb, levels=levels)
+        assert np.array_equal(np.tril(A, -1) + np.eye(n), L0) and np.array_equal(np.triu(A), U0)
+    assert rep.status == 0 and rep.max_ratio == 0.0
+
+
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
+def test_adaptive_levels_flip_outcomes(kind):
+    """A flip in an unprotected iteration goes unseen (and changes the
+    result); the same flip in a single-side or full iteration is located at
+    the planted element and corrected back to the clean result."""
+    n, nb = 192, 32
+    A0 = gen.spd(n, 4) if kind == "chol" else gen.general(n, 4)
+    clean = A0.copy(order="F")
+    _fact(kind, clean, nb)
+    f = gen.fault_plan(kind, n, nb, seed=41, iters=2)
+    f["bit"] = 61
+    for lev, expect in ((0, "unseen"), (1, "corrected"), (2, "corrected")):
+        levels = [2, 2, lev, 2, 2, 2]
+        A = A0.copy(order="F")
+        rep = _fact(kind, A, nb, levels=levels, faults=[f])
+        diff = np.max(np.abs(np.tril(A - clean) if kind == "chol" else A - clean))
+        if expect == "unseen":
+            assert rep.status == 0 and rep.flagged_tiles == 0
+            assert diff > 1e-6
+        else:
+            assert rep.status == oracle.ST_CORRECTED
+            assert rep.events() == [(2, oracle.EV_CORRECTED, f["row"], f["col"])]
+            assert diff <= 1e-12 * np.max(np.abs(clean))
+
+
+# ------------------------------------------------- 1D errors: operand faults
+def _lu_exact_operand(side):
+    """LU of an exact dyadic matrix with one operand of iteration 1's update
+    flipped in bit 52 (the exponent's lowest bit: the value doubles or
+    halves): side "L" an element of L21 (a row of the update goes wrong),
+    side "U" one of U12 (a column)."""
+    n, nb = 160, 32
+    A, P, L0, U0 = gen.lu_exact(n, seed=5)
+    if side == "L":
+        i, j = next((i, j) for i in range(64, n) for j in range(32, 64) if abs(L0[i, j]) > 0)
+    else:
+        i, j = next((i, j) for i in range(32, 64) for j in range(64, n) if abs(U0[i, j]) > 0)
+    f = {"iter": 1, "target": 3 if side == "L" else 4, "row": i, "col": j, "bit": 52}
+    return A, L0, U0, f, n, nb
+
+
+@pytest.mark.parametrize("side", ["L", "U"])
+def test_operand_fault_rebuilt_exactly(side):
+    """Full checksums: a wrong row (column) of each tile it crosses is
+    rebuilt from the column (row) checksums; with dyadic data every rebuilt
+    element is exact, so the factors are bitwise L0, U0 and the events name
+    the row (column) in every tile of the update it crossed."""
+    A, L0, U0, f, n, nb = _lu_exact_operand(side)
+    ipiv, info, rep = oracle.getrf(A, nb, faults=[f])
+    assert np.array_equal(np.tril(A, -1) + np.eye(n), L0) and np.array_equal(np.triu(A), U0)
+    assert rep.status == oracle.ST_CORRECTED and rep.corrected == 3 and rep.flagged_tiles == 3
+    if side == "L":
+        assert rep.events() == [(1, oracle.EV_ROW_REBUILT, f["row"], c) for c in (64, 96, 128)]
+    else:
+        r0 = 64
+        assert rep.events() == [(1, oracle.EV_COL_REBUILT, r, f["col"]) for r in (r0, 96, 128)]
+
+
+@pytest.mark.parametrize("side", ["L", "U"])
+def test_operand_fault_single_side_uncorrectable(side):
+    """Single-side (column) checksums detect the 1D error but cannot locate
+    it: every tile it crossed is reported uncorrectable."""
+    A, L0, U0, f, n, nb = _lu_exact_operand(side)
+    ipiv, info, rep = oracle.getrf(A, nb, faults=[f], protect=oracle.SINGLE)
+    assert rep.status & oracle.ST_UNCORRECTABLE and rep.flagged_tiles >= 1
+    assert not np.array_equal(np.triu(A), U0)
+
+
+@pytest.mark.parametrize("target,row,col", [(3, 100, 40), (3, 40, 35), (4, 5, 100)])
+def test_qr_operand_fault_rebuilt(target, row, col):
+    """QR: a flipped element of V (inside the panel's unit triangle or below
+    it) or of W2 = T^T V^T C spreads along a row / column of C; it is rebuilt
+    and the factors match the clean ones to rounding."""
+    n, nb = 160, 32
+    A0 = gen.general(n, 7)
+    clean = A0.copy(order="F")
+    tc, _ = oracle.geqrf(clean, nb)
+    A = A0.copy(order="F")
+    tau, rep = oracle.geqrf(A, nb, faults=[{"iter": 1, "target": target, "row": row, "col": col, "bit": 60}])
+    assert rep.status == oracle.ST_CORRECTED and rep.uncorrectable == 0
+    kinds = {e[1] for e in rep.events()}
+    assert kinds == {oracle.EV_ROW_REBUILT if target == 3 else oracle.EV_COL_REBUILT}
+    assert np.max(np.abs(A - clean)) <= 1e-12 * np.max(np.abs(clean))
+    assert np.max(np.abs(tau - tc)) <= 1e-12
+
+
+def test_chol_operand_fault_cross_detected():
+    """Cholesky's update reads L21 twice (L21 L21^T): one flipped element
+    corrupts a row and a column of the symmetric trailing matrix.  The tiles
+    off the diagonal see a 1D error and are rebuilt; the diagonal tile sees
+    the row and the column crossing (beyond the per-tile model) and is
+    reported uncorrectable."""
+    n, nb = 160, 32
+    S, L0 = gen.chol_exact(n, seed=3)
+    info, rep = oracle.potrf(S, nb, faults=[{"iter": 1, "target": 3, "row": 100, "col": 40, "bit": 62}])
+    ev = rep.events()
+    assert (1, oracle.EV_ROW_REBUILT, 100, 64) in ev and (1, oracle.EV_COL_REBUILT, 128, 100) in ev
+    assert (1, oracle.EV_UNCORRECTABLE, 96, 96) in ev
+    assert rep.status & oracle.ST_UNCORRECTABLE
