@@ -407,6 +407,10 @@ static int tile_flags(ctx_t* c, int I, int J, const tsums_t* t, tflags_t* f, dou
   return nflag;
 }
 
+/* whether the weighted / plain difference ratio exists (it does not when a
+   difference is not finite or the weighted one overflowed) */
+static int ratio_finite(double dw, double de) { return de != 0.0 && isfinite(dw / de); }
+
 /* locate a row (column) from the weighted / plain difference ratio */
 static int ratio_index(double dw, double de, int len) {
   if (!(de != 0.0) || !isfinite(dw / de)) return -1;
@@ -502,26 +506,36 @@ static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
   int repair = 0;
   int line = 0; /* 1D: 1 = rebuild row ig from the column checksums, 2 = column jf[0] from the row checksums */
   if (diag) {
+    /* In the symmetric view an off-diagonal element shows in two columns
+       (itself and its mirror), a diagonal one in one.  The ratio names the
+       row; where it does not exist (a non-finite value, or a weighted sum
+       that overflowed) the pattern alone names the element. */
     if (nFe == 1) {
-      int i = ratio_index(f.dw[jf[0]], f.de[jf[0]], h);
-      if (i == jf[0]) { ci = i; cj = i; }
+      int a = jf[0], i = ratio_index(f.dw[a], f.de[a], h);
+      if (i >= 0) { ci = i > a ? i : a; cj = i > a ? a : i; }
+      else if (!ratio_finite(f.dw[a], f.de[a])) { ci = a; cj = a; }
+      else if (nGe == 0 && !f.fw[a]) repair = 1; /* a flipped e entry of the column checksums */
     } else if (nFe == 2) {
       int a = jf[0], b = jf[1];
-      if (ratio_index(f.dw[a], f.de[a], h) == b && ratio_index(f.dw[b], f.de[b], h) == a) { ci = b; cj = a; }
+      if ((ratio_index(f.dw[a], f.de[a], h) == b && ratio_index(f.dw[b], f.de[b], h) == a) ||
+          !ratio_finite(f.dw[a], f.de[a]) || !ratio_finite(f.dw[b], f.de[b])) { ci = b; cj = a; }
     } else if (nFe == 0) {
       repair = 1;
     }
   } else {
+    /* a checksum entry is taken for wrong only when its data side is
+       consistent: a plain column (row) difference with an unflagged weighted
+       one (a flipped e entry), or weighted differences alone */
     if (nFe == 1 && nGe == 1) {
       ci = ig; cj = jf[0];
     } else if (nFe == 1 && nGe == 0) {
       int i = ratio_index(f.dw[jf[0]], f.de[jf[0]], h);
       if (i >= 0) { ci = i; cj = jf[0]; }
-      else if (nGw == 0) repair = 1;
+      else if (nGw == 0 && !f.fw[jf[0]]) repair = 1;
     } else if (nFe == 0 && nGe == 1) {
       int j = ratio_index(f.hw[ig], f.he[ig], w);
       if (j >= 0) { ci = ig; cj = j; }
-      else if (nFw == 0) repair = 1;
+      else if (nFw == 0 && !f.gw[ig]) repair = 1;
     } else if (nFe == 0 && nGe == 0) {
       repair = 1;
     } else if (c->level == 2 && nGe == 1 && nFe >= 2) {

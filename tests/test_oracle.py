@@ -270,13 +270,16 @@ def test_single_flip_detected_and_corrected(kind, bit):
 
 
 @pytest.mark.parametrize("pos", [(87, 64), (95, 64), (70, 70), (95, 95), (80, 79)])
-@pytest.mark.parametrize("bit", [57, 55])
+@pytest.mark.parametrize("bit", [57, 55, 62])
 def test_chol_diagonal_tile_flip_corrected(pos, bit):
     """Cholesky keeps one triangle of a diagonal tile; a flip anywhere in it
     shows in two columns (the element and its mirror) and is corrected.  The
     rebuilt element carries the column checksum's rounding, which the
     recheck sees multiplied by the element's row weight (up to nb): the far
-    corner (nb-1, 0) of the tile is the case that exercises that allowance."""
+    corner (nb-1, 0) of the tile is the case that exercises that allowance.
+    Bit 62 turns an off-diagonal entry (|a| ~ 0.1) into ~1e307, whose
+    weighted column sum overflows: the pattern of two flagged columns alone
+    names the element and its mirror."""
     n, nb = 128, 32
     A0 = gen.spd(n, 0)
     clean = A0.copy(order="F")
@@ -406,6 +409,62 @@ def test_chol_diagonal_tile_checksum_repair():
     assert rep.status == oracle.ST_REPAIRED and rep.checksum_repaired == 1 and rep.corrected == 0
     assert rep.events() == [(0, 2, 32, 32)]
     assert np.array_equal(np.tril(A), np.tril(clean))
+
+
+def test_chol_diagonal_tile_column_checksum_entry_repaired():
+    """A flipped plain (e) entry of a diagonal tile's column checksums: one
+    column's plain difference flags, its weighted one and every row agree, so
+    no data element is suspect; the checksums are re-encoded and the factor
+    is bitwise the clean one."""
+    n, nb = 96, 32
+    A0 = gen.spd(n, seed=12)
+    clean = A0.copy(order="F")
+    oracle.potrf(clean, nb)
+    A = A0.copy(order="F")
+    f = {"iter": 0, "target": 1, "row": 2 * 1, "col": 45, "bit": 56}
+    info, rep = oracle.potrf(A, nb, faults=[f])
+    assert info == 0
+    assert rep.status == oracle.ST_REPAIRED and rep.checksum_repaired == 1 and rep.corrected == 0
+    assert rep.events() == [(0, 2, 32, 32)]
+    assert np.array_equal(np.tril(A), np.tril(clean))
+
+
+def _huge_offdiag_plan(n, nb, k, seed):
+    """An element of an off-diagonal tile of the Cholesky trailing matrix after
+    iteration k whose bit-62 flip gives a finite value near 1e307 (|a| in
+    [1/16, 1/2)) placed at least 20 rows into its tile, so that its weighted
+    column sum (row weight >= 21) overflows; the trailing matrix is the
+    Schur complement formed from the clean factor."""
+    A0 = gen.spd(n, seed)
+    L = A0.copy(order="F")
+    oracle.potrf(L, nb)
+    L = np.tril(L)
+    c1 = (k + 1) * nb
+    S = L[c1:, c1:] @ L[c1:, c1:].T
+    for i in range(c1 + nb, n):
+        for j in range(c1, i - nb + 1):
+            if (i // nb) != (j // nb) and (i % nb) >= 20 and 1 / 16 <= abs(S[i - c1, j - c1]) < 0.5:
+                return A0, np.tril(L), {"iter": k, "row": i, "col": j, "bit": 62}
+    raise AssertionError("no candidate")
+
+
+def test_huge_flip_full_corrected_single_side_not_repaired():
+    """A flip to ~1e307 in an off-diagonal tile: with full checksums the
+    flagged row and column intersect at the element, which is rebuilt; with
+    the column side alone the weighted / plain ratio overflows and the row
+    cannot be named, and the tile is reported uncorrectable (a data error is
+    never taken for a checksum error: its weighted sum is flagged too)."""
+    n, nb = 128, 32
+    A0, Lc, f = _huge_offdiag_plan(n, nb, 0, seed=4)
+    A = A0.copy(order="F")
+    info, rep = oracle.potrf(A, nb, faults=[f])
+    assert info == 0 and rep.status == oracle.ST_CORRECTED
+    assert rep.events() == [(0, 1, f["row"], f["col"])]
+    assert np.max(np.abs(np.tril(A) - Lc)) <= 1e-12 * np.max(np.abs(Lc))
+    A = A0.copy(order="F")
+    info, rep = oracle.potrf(A, nb, faults=[f], protect=oracle.SINGLE)
+    assert rep.status & oracle.ST_UNCORRECTABLE and not rep.status & oracle.ST_REPAIRED
+    assert rep.checksum_repaired == 0
 
 
 # ------------------------------------------------------------ MP + refinement
