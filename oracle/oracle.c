@@ -507,18 +507,21 @@ static void correct_tile(ctx_t* c, double* A, int lda, int I, int J) {
   int line = 0; /* 1D: 1 = rebuild row ig from the column checksums, 2 = column jf[0] from the row checksums */
   if (diag) {
     /* In the symmetric view an off-diagonal element shows in two columns
-       (itself and its mirror), a diagonal one in one.  The ratio names the
-       row; where it does not exist (a non-finite value, or a weighted sum
-       that overflowed) the pattern alone names the element. */
+       (itself and its mirror), a diagonal one in one.  Two flagged columns
+       therefore name the element by the pattern alone (the ratios would only
+       confirm it, and near the threshold they carry the weighted sums'
+       rounding noise); the recheck after the rebuild rejects any other
+       cause.  One flagged column: the ratio names the row (the element, or
+       its mirror when the other column stayed below its threshold); where
+       the ratio does not exist (a non-finite value, or a weighted sum that
+       overflowed) it is the diagonal element. */
     if (nFe == 1) {
       int a = jf[0], i = ratio_index(f.dw[a], f.de[a], h);
       if (i >= 0) { ci = i > a ? i : a; cj = i > a ? a : i; }
       else if (!ratio_finite(f.dw[a], f.de[a])) { ci = a; cj = a; }
       else if (nGe == 0 && !f.fw[a]) repair = 1; /* a flipped e entry of the column checksums */
     } else if (nFe == 2) {
-      int a = jf[0], b = jf[1];
-      if ((ratio_index(f.dw[a], f.de[a], h) == b && ratio_index(f.dw[b], f.de[b], h) == a) ||
-          !ratio_finite(f.dw[a], f.de[a]) || !ratio_finite(f.dw[b], f.de[b])) { ci = b; cj = a; }
+      ci = jf[1]; cj = jf[0];
     } else if (nFe == 0) {
       repair = 1;
     }

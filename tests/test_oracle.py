@@ -411,6 +411,27 @@ def test_chol_diagonal_tile_checksum_repair():
     assert np.array_equal(np.tril(A), np.tril(clean))
 
 
+@pytest.mark.parametrize("k,i,j,bit", [(2, 246, 219, 18), (0, 79, 78, 17), (0, 252, 241, 21), (2, 224, 205, 18),
+                                        (2, 213, 205, 20), (1, 172, 133, 19), (2, 254, 192, 20)])
+def test_chol_diagonal_tile_near_threshold_flip_located_by_pattern(k, i, j, bit):
+    """Mid-mantissa flips (a few thresholds in size) inside diagonal tiles:
+    both columns of the element and its mirror flag, while the weighted /
+    plain ratios carry rounding noise of the weighted sums that can move them
+    off an integer by more than the 0.25 acceptance.  Under the one fault per
+    tile model the two flagged columns alone name the element; it is rebuilt,
+    and the factor is the clean one to rounding."""
+    n, nb = 256, 64
+    A0 = gen.spd(n, 21)
+    clean = A0.copy(order="F")
+    oracle.potrf(clean, nb)
+    f = {"iter": k, "row": i, "col": j, "bit": bit}
+    A = A0.copy(order="F")
+    info, rep = oracle.potrf(A, nb, faults=[f])
+    assert info == 0 and rep.status == oracle.ST_CORRECTED
+    assert rep.events() == [(k, 1, i, j)]
+    assert np.max(np.abs(np.tril(A) - np.tril(clean))) <= 1e-14 * np.max(np.abs(clean))
+
+
 def test_chol_diagonal_tile_column_checksum_entry_repaired():
     """A flipped plain (e) entry of a diagonal tile's column checksums: one
     column's plain difference flags, its weighted one and every row agree, so
