@@ -528,13 +528,21 @@ def campaign_leg(h, torch, dev, args):
     r = 0 .. R/2 - 1 of runs on their own seeded matrix: a clean run (false
     alarms are counted over these distinct matrices) and a run with one flip
     (uniform iteration, stored trailing element and bit 0..63, seeded per
-    pair) whose factors are compared with that clean run.  Outcomes are split
-    by bit class: a flip of the sign or exponent bits changes the value by
-    far more than any threshold and must always be detected; low mantissa
-    bits change it by less than the rounding-level threshold and can go
-    unnoticed, which is harmless exactly when the result stays within
-    rounding of the clean one (counted separately).  The campaign stops at
-    the first call that reports a cooperative-kernel wait expiry."""
+    pair).
+
+    Each flip is classified by the size of the change it made, |delta| (the
+    library records it when it plants the flip), against tau, the threshold
+    of the column checksum that covers the element at the verification right
+    after the flip (also recorded).  A flip with |delta| > tau must be
+    detected; below tau it is at the level of the checksums' rounding and may
+    pass, which is harmless when the result stays as accurate as the clean
+    one.  A faulted run's result is correct when its factors equal the clean
+    run's to 1e-12 (relative, max norm) or, failing that (a rebuilt element
+    is only known to its column's rounding, and partial pivoting can then
+    pick a different one of two near-equal pivots), when its backward error
+    is within 2x of the clean run's.  The campaign stops at the first call
+    that reports a cooperative-kernel wait expiry."""
+    import math
     from paper_2301_03166_amd import gen
     n, nb, R = args.campaign_n, args.campaign_nb, args.campaign
     classes = (("sign_exponent_52_63", 52, 64), ("mantissa_40_51", 40, 52), ("mantissa_20_39", 20, 40),
@@ -543,9 +551,10 @@ def campaign_leg(h, torch, dev, args):
     for d, kind in enumerate(("chol", "lu", "qr")):
         ref = torch.empty((n, n), dtype=torch.float64, device=dev)
         W = torch.empty_like(ref)
-        aux = torch.zeros(n, dtype=torch.float64 if kind == "qr" else torch.int32, device=dev)
+        adt = torch.float64 if kind == "qr" else torch.int32
+        aux_ref, aux_f = torch.zeros(n, dtype=adt, device=dev), torch.zeros(n, dtype=adt, device=dev)
 
-        def run(A0, dst, faults):
+        def run(A0, dst, faults, aux):
             dst.copy_(A0)
             A = dst.t()
             if kind == "chol":
@@ -557,62 +566,93 @@ def campaign_leg(h, torch, dev, args):
             return rep
 
         tally = {"clean_runs": 0, "false_alarms": 0, "faulted_runs": 0, "corrected": 0, "checksum_repaired": 0,
-                 "uncorrectable": 0, "undetected_harmless": 0, "undetected_corrupting": 0,
-                 "corrected_but_wrong": 0, "internal_errors": 0}
-        by_class = {c[0]: {"flips": 0, "detected": 0, "undetected_harmless": 0} for c in classes}
-        undetected_bits = []
+                 "uncorrectable": 0, "undetected": 0, "results_equal_clean": 0, "results_within_backward_error": 0,
+                 "results_wrong": 0, "internal_errors": 0, "significant_flips": 0, "significant_detected": 0,
+                 "subthreshold_flips": 0, "subthreshold_detected": 0, "unverified_flips": 0}
+        by_class = {c[0]: {"flips": 0, "detected": 0, "significant": 0, "significant_detected": 0}
+                    for c in classes}
+        undetected, uncorrectable = [], []
+        min_detected_ratio, max_undetected_ratio = math.inf, 0.0
         for r in range(max(1, R // 2)):
             seed = 100000 * (d + 1) + r
             A0 = gen.spd_torch(n, seed, dev) if kind == "chol" else gen.general_torch(n, seed, dev)
-            rep = run(A0, ref, None)
+            rep = run(A0, ref, None, aux_ref)
             tally["clean_runs"] += 1
             tally["false_alarms"] += int(rep.status != 0)
             if rep.status & 16:
                 tally["internal_errors"] += 1
                 break
             f = gen.fault_plan(kind, n, nb, seed=10 ** 6 * (d + 1) + r)
-            rep = run(A0, W, [f])
+            rep = run(A0, W, [f], aux_f)
             if rep.status & 16:
                 tally["internal_errors"] += 1
                 break
             ref_t, Wt = ref.t(), W.t()
             scale = float(ref_t.abs().max())
             diff = float((torch.tril(Wt - ref_t) if kind == "chol" else (Wt - ref_t)).abs().max())
-            same = diff <= 1e-12 * scale
             tally["faulted_runs"] += 1
+            if diff <= 1e-12 * scale:
+                tally["results_equal_clean"] += 1
+            else:
+                bf, _ = backward_error(kind, A0.t(), Wt, None if kind == "chol" else aux_f)
+                bc, _ = backward_error(kind, A0.t(), ref_t, None if kind == "chol" else aux_ref)
+                tally["results_within_backward_error" if bf <= 2.0 * bc else "results_wrong"] += 1
             detected = bool(rep.status & 7)
             if rep.status & 4:
                 tally["uncorrectable"] += 1
             elif rep.status & 1:
                 tally["corrected"] += 1
-                tally["corrected_but_wrong"] += int(not same)
             elif rep.status & 2:
                 tally["checksum_repaired"] += 1
             else:
-                tally["undetected_harmless" if same else "undetected_corrupting"] += 1
-                undetected_bits.append(int(f["bit"]))
+                tally["undetected"] += 1
+            # |delta| / tau of this flip (tau < 0: the flip was not verified)
+            ratio = rep.fault_delta / rep.fault_tau if rep.fault_tau > 0 else (math.inf if rep.fault_tau == 0 else None)
+            if ratio is None:
+                tally["unverified_flips"] += 1
+            else:
+                sig = ratio > 1.0
+                tally["significant_flips" if sig else "subthreshold_flips"] += 1
+                tally["significant_detected" if sig else "subthreshold_detected"] += int(detected)
+                if detected:
+                    min_detected_ratio = min(min_detected_ratio, ratio)
+                else:
+                    max_undetected_ratio = max(max_undetected_ratio, ratio)
+            if not detected:
+                undetected.append({"bit": int(f["bit"]), "delta_over_tau": ratio})
+            if rep.status & 4:
+                uncorrectable.append({"pair": r, "plan": {k: int(v) for k, v in f.items()}, "delta_over_tau": ratio})
             for name, lo, hi in classes:
                 if lo <= f["bit"] < hi:
                     c = by_class[name]
                     c["flips"] += 1
                     c["detected"] += int(detected)
-                    c["undetected_harmless"] += int(not detected and same)
+                    if ratio is not None and ratio > 1.0:
+                        c["significant"] += 1
+                        c["significant_detected"] += int(detected)
             del A0
         fr = max(1, tally["faulted_runs"])
-        tally["detected_pct"] = 100.0 * (fr - tally["undetected_harmless"] - tally["undetected_corrupting"]) / fr
-        tally["correct_result_pct"] = 100.0 * (tally["corrected"] - tally["corrected_but_wrong"] +
-                                               tally["undetected_harmless"] + tally["checksum_repaired"]) / fr
+        tally["detected_pct"] = 100.0 * (fr - tally["undetected"]) / fr
+        tally["significant_detected_pct"] = (100.0 * tally["significant_detected"] / tally["significant_flips"]
+                                             if tally["significant_flips"] else None)
+        tally["correct_result_pct"] = 100.0 * (tally["results_equal_clean"] +
+                                               tally["results_within_backward_error"]) / fr
+        tally["min_detected_delta_over_tau"] = min_detected_ratio if min_detected_ratio < math.inf else None
+        tally["max_undetected_delta_over_tau"] = max_undetected_ratio
         for c in by_class.values():
             c["detected_pct"] = 100.0 * c["detected"] / c["flips"] if c["flips"] else None
         tally["by_bit_class"] = by_class
-        tally["undetected_bits"] = sorted(undetected_bits)
+        tally["undetected_flips"] = sorted(undetected, key=lambda e: e["bit"])
+        tally["uncorrectable_flips"] = uncorrectable
         out[kind] = tally
-        log(f"campaign {kind}: " + json.dumps({k: v for k, v in tally.items() if k != "by_bit_class"}))
+        log(f"campaign {kind}: " + json.dumps({k: v for k, v in tally.items()
+                                               if k not in ("by_bit_class", "undetected_flips", "uncorrectable_flips")}))
         del ref, W
         torch.cuda.empty_cache()
     return {"n": n, "nb": nb, "runs_per_decomposition": 2 * max(1, R // 2),
             "plan": "pairs of runs on one seeded matrix each: clean, then one flip (iteration, stored trailing "
                     "element and bit 0..63 uniform, seeded per pair) compared with the clean factors",
+            "significant": "|delta| > tau of the element's column checksum at the verification after the flip",
             "outcomes": out}
 
 
@@ -628,7 +668,7 @@ def main():
     ap.add_argument("--mp-nb", type=int, default=512)
     ap.add_argument("--mp-kappas", default="1e2,1e6,1e10")
     ap.add_argument("--batch", type=int, default=4096)
-    ap.add_argument("--campaign", type=int, default=160, help="fault-campaign runs per decomposition (0: skip)")
+    ap.add_argument("--campaign", type=int, default=400, help="fault-campaign runs per decomposition (0: skip)")
     ap.add_argument("--campaign-n", type=int, default=8192)
     ap.add_argument("--campaign-nb", type=int, default=256)
     ap.add_argument("--energy-n", type=int, default=16384)

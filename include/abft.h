@@ -128,6 +128,11 @@ typedef struct {
   double max_ratio;                /* largest |d| / tau over the unflagged comparisons */
   int32_t nev, pad;
   abft_event ev[ABFT_MAX_EVENTS];
+  /* test use: the last single-bit fault planted in the matrix (target 0):
+     |value after - value before| (+Inf when either is not finite), and the
+     |d| and tau of the plain column checksum that covers it at the
+     verification right after the flip (-1 when it was not verified) */
+  double fault_delta, fault_d, fault_tau;
 } abft_report;
 
 typedef struct {

@@ -34,7 +34,8 @@ class Report(C.Structure):
     _fields_ = [("flagged_tiles", C.c_int64), ("corrected", C.c_int64), ("checksum_repaired", C.c_int64),
                 ("uncorrectable", C.c_int64), ("panel_flags", C.c_int64), ("first_flag_iter", C.c_int32),
                 ("status", C.c_int32), ("max_ratio", C.c_double), ("nev", C.c_int32), ("pad", C.c_int32),
-                ("ev", Event * 16)]
+                ("ev", Event * 16), ("fault_delta", C.c_double), ("fault_d", C.c_double),
+                ("fault_tau", C.c_double)]
 
     def events(self):
         return sorted((self.ev[i].iter, self.ev[i].kind, self.ev[i].row, self.ev[i].col)

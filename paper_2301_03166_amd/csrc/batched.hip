@@ -386,6 +386,8 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
     rep->status = 0;
     rep->max_ratio = 0.0;
     rep->nev = 0;
+    rep->fault_delta = 0.0;
+    rep->fault_d = rep->fault_tau = -1.0;
     *info = 0;
     s_fail = 0;
   }
@@ -689,6 +691,8 @@ __global__ __launch_bounds__(256) void k_batched(int batch, const int32_t* dn, v
         dreps[mi].status = 0;
         dreps[mi].nev = 0;
         dreps[mi].first_flag_iter = -1;
+        dreps[mi].fault_delta = 0.0;
+        dreps[mi].fault_d = dreps[mi].fault_tau = -1.0;
       }
       continue;
     }

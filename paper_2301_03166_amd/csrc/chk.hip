@@ -228,7 +228,8 @@ template <typename T>
 __global__ __launch_bounds__(256, 2) void k_verify(const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0,
                                                 int nI, int sym, int mode, double* colchk, int64_t ldc, double* rowchk,
                                                 int64_t ldr, const double* gc, const double* gr, double tsu,
-                                                int* tflags, abft_report* rep, int iter, int level) {
+                                                int* tflags, abft_report* rep, int iter, int level, int64_t frow,
+                                                int64_t fcol) {
   __shared__ StreamSums ts;
   __shared__ StreamLds sl;
   __shared__ int s_nfl;
@@ -265,8 +266,13 @@ __global__ __launch_bounds__(256, 2) void k_verify(const T* A, int64_t lda, int6
   };
   for (int j = threadIdx.x; j < w; j += blockDim.x) {
     const int64_t o = 2 * I + (c0 + j) * ldc;
-    cmp(ts.ce[j] - colchk[o], tau_verify(tsu, ts.ca[j], gc ? gc[o] : 0.0));
+    const double de = ts.ce[j] - colchk[o], te = tau_verify(tsu, ts.ca[j], gc ? gc[o] : 0.0);
+    cmp(de, te);
     cmp(ts.cw[j] - colchk[o + 1], tau_verify(tsu, ts.cwa[j], gc ? gc[o + 1] : 0.0));
+    if (rep && c0 + j == fcol && frow >= r0 && frow < r0 + h) {  // the planted element's column checksum
+      rep->fault_d = fabs(de);
+      rep->fault_tau = te;
+    }
   }
   for (int i = threadIdx.x; i < (level == 1 ? 0 : h); i += blockDim.x) {
     const int64_t o = (r0 + i) + (2 * J) * ldr;
@@ -445,16 +451,16 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
                                                      double mscale, const double* Mabs, const double* E,
                                                      const double* bt, int Ik, const double* colchk, int64_t ldc,
                                                      int64_t cj0, int ncols, double tsu_p, abft_report* rep,
-                                                     int iter, int nb) {
+                                                     int iter, int nb, int* pflags) {
   constexpr int PC = 32;
   __shared__ double Mc[PC][65], Ma[PC][65];
   __shared__ double Sc[4][PC][4];
-  __shared__ int flag[4], fcol[4];
+  __shared__ int flag[4];
   __shared__ unsigned long long smax;
   const int tid = threadIdx.x, jl = tid & 63, il = tid >> 6;
   const int j0 = blockIdx.x * 64, j = j0 + jl;
   const int Ib = I0 + blockIdx.y * 4, I = Ib + il;
-  if (tid < 4) { flag[tid] = 0; fcol[tid] = 0x7fffffff; }
+  if (tid < 4) flag[tid] = 0;
   if (tid == 0) smax = 0;
   const bool live = j < ncols && I < I1;
   double ce = 0, cw = 0;
@@ -539,7 +545,6 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
     double te = tsu_p * (fabs(ce) + ge), tw = tsu_p * (fabs(cw) + gw);
     if (bad(de, te) || bad(dw, tw)) {
       atomicOr(&flag[il], 1);
-      atomicMin(&fcol[il], j);
     } else {
       double r = 0;
       if (te > 0) r = fabs(de) / te;
@@ -552,11 +557,28 @@ __global__ __launch_bounds__(256) void k_panel_check(const double* S, const doub
     if (smax) rep_max_ratio(rep, __longlong_as_double((long long)smax));
     for (int q = 0; q < 4; ++q)
       if (flag[q]) {
-        atomicAdd((unsigned long long*)&rep->panel_flags, 1ull);
-        atomicOr(&rep->status, (int)ABFT_ST_PANEL);
-        rep_flag_iter(rep, iter);
-        rep_event(rep, iter, 4, (int64_t)(Ib + q) * nb, cj0 + fcol[q]);
+        if (pflags) {
+          atomicOr(&pflags[Ib + q], 1);  // one event per tile-row, however many column blocks flag it
+        } else {
+          atomicAdd((unsigned long long*)&rep->panel_flags, 1ull);
+          atomicOr(&rep->status, (int)ABFT_ST_PANEL);
+          rep_flag_iter(rep, iter);
+          rep_event(rep, iter, 4, (int64_t)(Ib + q) * nb, cj0);
+        }
       }
+  }
+}
+
+// One report entry per flagged tile-row of a panel check, in tile-row
+// order; the flags are cleared for the next check.
+__global__ void k_panel_events(int* pflags, int I0, int I1, abft_report* rep, int iter, int64_t nb, int64_t cj0) {
+  for (int I = I0; I < I1; ++I) {
+    if (!pflags[I]) continue;
+    pflags[I] = 0;
+    atomicAdd((unsigned long long*)&rep->panel_flags, 1ull);
+    atomicOr(&rep->status, (int)ABFT_ST_PANEL);
+    rep_flag_iter(rep, iter);
+    rep_event(rep, iter, 4, (int64_t)I * nb, cj0);
   }
 }
 
@@ -625,16 +647,28 @@ __global__ __launch_bounds__(256) void k_qr_prep_sums(const double* A, int64_t l
   }
 }
 
-// fault injection (test use): XOR one bit of one element
-__global__ void k_inject64(double* p, int bit) {
-  unsigned long long u = (unsigned long long)__double_as_longlong(*p);
+// fault injection (test use): XOR one bit of one element; with a report,
+// record the size of the change and clear the record of its verification
+__device__ void rep_fault(abft_report* r, double before, double after) {
+  if (!r) return;
+  const double d = fabs(after - before);
+  r->fault_delta = (d <= 1.79e308) ? d : __builtin_inf();
+  r->fault_d = -1.0;
+  r->fault_tau = -1.0;
+}
+__global__ void k_inject64(double* p, int bit, abft_report* r) {
+  const double before = *p;
+  unsigned long long u = (unsigned long long)__double_as_longlong(before);
   u ^= 1ull << bit;
   *p = __longlong_as_double((long long)u);
+  rep_fault(r, before, *p);
 }
-__global__ void k_inject32(float* p, int bit) {
-  unsigned u = __float_as_uint(*p);
+__global__ void k_inject32(float* p, int bit, abft_report* r) {
+  const float before = *p;
+  unsigned u = __float_as_uint(before);
   u ^= 1u << (bit & 31);
   *p = __uint_as_float(u);
+  rep_fault(r, (double)before, (double)*p);
 }
 
 __global__ void k_fill_zero(uint32_t* p, size_t n) {
@@ -650,6 +684,8 @@ __global__ void k_report_init(abft_report* r, int32_t* info) {
     r->max_ratio = 0.0;
     r->nev = 0;
     r->pad = 0;
+    r->fault_delta = 0.0;
+    r->fault_d = r->fault_tau = -1.0;
   }
   if (info) *info = 0;
 }
@@ -664,12 +700,13 @@ __global__ void k_report_fini(abft_report* r) {
 template <typename T>
 int verify_tiles(hipStream_t s, const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
                  int mode, double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc,
-                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter, int level) {
+                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter, int level, int64_t frow,
+                 int64_t fcol) {
   int Nr = (int)((nr + nb - 1) / nb), Nc = (int)((nc + nb - 1) / nb);
   int nI = Nr - I0, nJ = Nc - J0;
   if (nI <= 0 || nJ <= 0) return 0;
   hipLaunchKernelGGL(k_verify<T>, dim3(nI * nJ), dim3(256), 0, s, A, lda, nr, nc, nb, I0, J0, nI, sym, mode, colchk,
-                     ldc, rowchk, ldr, gc, gr, tsu, tflags, rep, iter, level);
+                     ldc, rowchk, ldr, gc, gr, tsu, tflags, rep, iter, level, frow, fcol);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 template <typename T>
@@ -685,10 +722,10 @@ int correct_tiles(hipStream_t s, T* A, int64_t lda, int64_t nr, int64_t nc, int 
 }
 template int verify_tiles<double>(hipStream_t, const double*, int64_t, int64_t, int64_t, int, int, int, int, int,
                                   double*, int64_t, double*, int64_t, const double*, const double*, double, int*,
-                                  abft_report*, int, int);
+                                  abft_report*, int, int, int64_t, int64_t);
 template int verify_tiles<float>(hipStream_t, const float*, int64_t, int64_t, int64_t, int, int, int, int, int, double*,
                                  int64_t, double*, int64_t, const double*, const double*, double, int*, abft_report*,
-                                 int, int);
+                                 int, int, int64_t, int64_t);
 template int correct_tiles<double>(hipStream_t, double*, int64_t, int64_t, int64_t, int, int, int, int, double*,
                                    int64_t, double*, int64_t, const double*, const double*, double, const int*,
                                    abft_report*, int, int);
@@ -729,19 +766,20 @@ template <typename MT>
 int panel_check(hipStream_t s, const double* S, const double* Sa, int ldS, int I0, int I1, int kw, const MT* Mp,
                 int64_t msp, int64_t msj, int tri, int pjoff, double mscale, const double* Mabs, const double* E,
                 const double* bt, int Ik, const double* colchk, int64_t ldc, int64_t cj0, int ncols, double tsu_p,
-                abft_report* rep, int iter, int nb) {
+                abft_report* rep, int iter, int nb, int* pflags) {
   if (I1 <= I0 || ncols <= 0) return 0;
   dim3 grid((ncols + 63) / 64, (I1 - I0 + 3) / 4);
   hipLaunchKernelGGL(k_panel_check<MT>, grid, dim3(256), 0, s, S, Sa, ldS, I0, I1, kw, Mp, msp, msj, tri, pjoff,
-                     mscale, Mabs, E, bt, Ik, colchk, ldc, cj0, ncols, tsu_p, rep, iter, nb);
+                     mscale, Mabs, E, bt, Ik, colchk, ldc, cj0, ncols, tsu_p, rep, iter, nb, rep ? pflags : nullptr);
+  if (rep && pflags) hipLaunchKernelGGL(k_panel_events, dim3(1), dim3(1), 0, s, pflags, I0, I1, rep, iter, nb, cj0);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 template int panel_check<double>(hipStream_t, const double*, const double*, int, int, int, int, const double*, int64_t,
                                  int64_t, int, int, double, const double*, const double*, const double*, int,
-                                 const double*, int64_t, int64_t, int, double, abft_report*, int, int);
+                                 const double*, int64_t, int64_t, int, double, abft_report*, int, int, int*);
 template int panel_check<float>(hipStream_t, const double*, const double*, int, int, int, int, const float*, int64_t,
                                 int64_t, int, int, double, const double*, const double*, const double*, int,
-                                const double*, int64_t, int64_t, int, double, abft_report*, int, int);
+                                const double*, int64_t, int64_t, int, double, abft_report*, int, int, int*);
 
 // scratch: 5 w^2 doubles (Y, Ya and the three masked triangles)
 int qr_check_prep(hipStream_t s, const double* A, int64_t lda, int64_t c0, int w, int64_t m, const double* T, int ldt,
@@ -761,9 +799,9 @@ int qr_check_prep(hipStream_t s, const double* A, int64_t lda, int64_t c0, int w
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 
-int inject(hipStream_t s, void* p, int is_float, int bit) {
-  if (is_float) hipLaunchKernelGGL(k_inject32, dim3(1), dim3(1), 0, s, (float*)p, bit);
-  else hipLaunchKernelGGL(k_inject64, dim3(1), dim3(1), 0, s, (double*)p, bit);
+int inject(hipStream_t s, void* p, int is_float, int bit, abft_report* rep) {
+  if (is_float) hipLaunchKernelGGL(k_inject32, dim3(1), dim3(1), 0, s, (float*)p, bit, rep);
+  else hipLaunchKernelGGL(k_inject64, dim3(1), dim3(1), 0, s, (double*)p, bit, rep);
   return hipGetLastError() == hipSuccess ? 0 : ABFT_ERR_HIP;
 }
 

@@ -176,7 +176,7 @@ struct Ws {
   double *Tfac, *W, *W2, *Wp, *Wp2, *Xq, *Yq, *Z, *Zabs, *E, *bt, *scr;
   double *porig, *stage, *slots, *splitk;
   size_t splitk_n;  // elements of splitk
-  int *tflags, *moves;
+  int *tflags, *moves, *pflags;
   unsigned* ctr;
   size_t bytes;
 };
@@ -201,6 +201,7 @@ Ws carve(char* base, int64_t n, int nb, int op, int elem) {
   w.Tm = (double*)take((size_t)2 * N * nb * sizeof(double));
   w.Ta = (double*)take((size_t)2 * N * nb * sizeof(double));
   w.tflags = (int*)take((size_t)N * N * sizeof(int));
+  w.pflags = (int*)take((size_t)N * sizeof(int));
   w.ctr = (unsigned*)take(CTR_BYTES);
   w.slots = (double*)take(SLOT_WORDS * sizeof(double));
   if (op == ABFT_OP_GETRF || op == ABFT_OP_GESV_MP) {
@@ -262,14 +263,21 @@ inline bool has_operand_faults(const abft_opts* o) {
 inline int split(int w, int leaf = LEAFW) { return ((w / 2 + leaf - 1) / leaf) * leaf; }
 
 // ----------------------------------------------------------------- faults
+// A flip of a matrix element records its size in the report, and its position
+// (frow, fcol; -1 when none) lets that iteration's verification record the
+// difference and threshold of the column checksum that covers it.
 template <typename T>
-int apply_faults(hipStream_t s, const abft_opts* o, int iter, T* A, int64_t lda, const Ws& w, int64_t n, int N) {
+int apply_faults(hipStream_t s, const abft_opts* o, int iter, T* A, int64_t lda, const Ws& w, int64_t n, int N,
+                 abft_report* rep, int64_t& frow, int64_t& fcol) {
+  frow = fcol = -1;
   for (int q = 0; q < o->nfaults; ++q) {
     const abft_fault& f = o->faults[q];
     if (f.iter != iter) continue;
     if (f.target == 0) {
       if (f.row < 0 || f.row >= n || f.col < 0 || f.col >= n) continue;
-      TRY(inject(s, A + f.row + f.col * lda, sizeof(T) == 4, f.bit));
+      TRY(inject(s, A + f.row + f.col * lda, sizeof(T) == 4, f.bit, rep));
+      frow = f.row;
+      fcol = f.col;
     } else if (f.target == 1 && w.colchk) {
       if (f.row < 0 || f.row >= 2 * N || f.col < 0 || f.col >= n) continue;
       TRY(inject(s, w.colchk + f.row + f.col * 2 * N, 0, f.bit));
@@ -487,6 +495,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
   hipStream_t s = h->stream;
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
+  TRY(fill_zero(s, w.pflags, (size_t)((n + nb - 1) / nb) * sizeof(int)));
   const int N = (int)((n + nb - 1) / nb);
   const int ldc = 2 * N;
   const double u = sizeof(T) == 8 ? U64 : U32;
@@ -519,7 +528,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     auto check_k = [&](hipStream_t cs) -> int {
       // e^T A_Ik = (e^T L_I) L_kk^T:  M(p, j) = L(c0 + j, c0 + p), p <= j
       return panel_check<T>(cs, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, lda, 1, 1, 0, 1.0, nullptr, nullptr,
-                            nullptr, -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb);
+                            nullptr, -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb, w.pflags);
     };
     if (lev) {
       TRY(xsums<T>(s, dA, lda, n, nb, k, c0, kw, k, 1, w.S, w.Sa, ldc, 0));
@@ -553,11 +562,12 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
       TRY(carry_k(s));
       pf.end(t);
     }
-    if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N));
+    int64_t frow = -1, fcol = -1;
+    if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N, drep, frow, fcol));
     if (lev) {
       t = pf.begin(PH_VERIFY);
       TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                          w.tflags, drep, k, lev));
+                          w.tflags, drep, k, lev, frow, fcol));
       TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                            w.tflags, drep, k, lev));
       pf.end(t);
@@ -577,6 +587,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
   hipStream_t s = h->stream;
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
+  TRY(fill_zero(s, w.pflags, (size_t)((n + nb - 1) / nb) * sizeof(int)));
   TRY(fill_zero(s, w.ctr, CTR_BYTES));
   TRY(fill_zero(s, w.slots, SLOT_WORDS * sizeof(double)));  // leaf records: sequence numbers restart
   const int N = (int)((n + nb - 1) / nb);
@@ -619,11 +630,11 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
     // tile-row k and of the panel's columns): deferred likewise
     auto check_pd = [&](hipStream_t cs) -> int {  // e^T (P A)_I = (e^T L_I) U_kk
       return panel_check<T>(cs, w.S, w.Sa, ldc, k, N, kw, dA + c0 + c0 * lda, 1, lda, 1, 0, 1.0, nullptr, nullptr,
-                            nullptr, -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb);
+                            nullptr, -1, w.colchk, ldc, c0, kw, tsu_p, drep, k, nb, w.pflags);
     };
     auto check_pu = [&](hipStream_t cs) -> int {  // (e^T L_kk) U12 = e^T A12 on tile-row k
       return panel_check<T>(cs, w.S, w.Sa, ldc, k, k + 1, kw, dA + c0 + c1 * lda, 1, lda, 0, 0, 1.0, nullptr, nullptr,
-                            nullptr, -1, w.colchk, ldc, c1, (int)(n - c1), tsu_p, drep, k, nb);
+                            nullptr, -1, w.colchk, ldc, c1, (int)(n - c1), tsu_p, drep, k, nb, w.pflags);
     };
     if (!defer) TRY(laswp(s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
     TRY(laswp(s, dA, lda, c1, n, w.moves, stage, lev ? w.colchk : (double*)nullptr, ldc, nb));
@@ -674,11 +685,12 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       TRY(carry_k(s));
       pf.end(t);
     }
-    if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N));
+    int64_t frow = -1, fcol = -1;
+    if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N, drep, frow, fcol));
     if (lev) {
       t = pf.begin(PH_VERIFY);
       TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                          w.tflags, drep, k, lev));
+                          w.tflags, drep, k, lev, frow, fcol));
       TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                            w.tflags, drep, k, lev));
       pf.end(t);
@@ -1027,6 +1039,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
+  TRY(fill_zero(s, w.pflags, (size_t)((n + nb - 1) / nb) * sizeof(int)));
   TRY(fill_zero(s, w.ctr, CTR_BYTES));
   TRY(fill_zero(s, w.slots, SLOT_WORDS * sizeof(double)));  // leaf records: sequence numbers restart
   const int N = (int)((n + nb - 1) / nb);
@@ -1057,7 +1070,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
       TRY(qr_check_prep(cs, dA, lda, c0, kw, n - c0, w.Tfac, nb, w.scr, w.Z, w.Zabs, w.E, w.bt));
       // e^T A_I = [I==k] e^T R - (e^T V_I) T V1^T R
       return panel_check(cs, w.S, w.Sa, ldc, k, N, kw, w.Z, 1, kw, 0, 0, -1.0, w.Zabs, w.E, w.bt, k, w.colchk, ldc,
-                         c0, kw, tsu_p, drep, k, nb);
+                         c0, kw, tsu_p, drep, k, nb, w.pflags);
     };
     const bool fork = side.on && lev && c1 < n;
     if (lev) {
@@ -1106,11 +1119,12 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
       TRY(carry_k(s));
       pf.end(t);
     }
-    if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N));
+    int64_t frow = -1, fcol = -1;
+    if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N, drep, frow, fcol));
     if (lev) {
       t = pf.begin(PH_VERIFY);
       TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
-                               w.tflags, drep, k, lev));
+                               w.tflags, drep, k, lev, frow, fcol));
       TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                                 w.tflags, drep, k, lev));
       pf.end(t);

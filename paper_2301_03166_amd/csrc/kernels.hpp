@@ -35,7 +35,8 @@ int gemm32(hipStream_t s, int prec, int ta, int tb, int lower, int m, int n, int
 template <typename T>
 int verify_tiles(hipStream_t s, const T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
                  int mode, double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc,
-                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter, int level = 2);
+                 const double* gr, double tsu, int* tflags, abft_report* rep, int iter, int level = 2,
+                 int64_t frow = -1, int64_t fcol = -1);
 template <typename T>
 int correct_tiles(hipStream_t s, T* A, int64_t lda, int64_t nr, int64_t nc, int nb, int I0, int J0, int sym,
                   double* colchk, int64_t ldc, double* rowchk, int64_t ldr, const double* gc, const double* gr,
@@ -50,10 +51,10 @@ template <typename MT>
 int panel_check(hipStream_t s, const double* S, const double* Sa, int ldS, int I0, int I1, int kw, const MT* Mp,
                 int64_t msp, int64_t msj, int tri, int pjoff, double mscale, const double* Mabs, const double* E,
                 const double* bt, int Ik, const double* colchk, int64_t ldc, int64_t cj0, int ncols, double tsu_p,
-                abft_report* rep, int iter, int nb);
+                abft_report* rep, int iter, int nb, int* pflags = nullptr);
 int qr_check_prep(hipStream_t s, const double* A, int64_t lda, int64_t c0, int w, int64_t m, const double* T, int ldt,
                   double* scratch, double* Z, double* Zabs, double* E, double* bt);
-int inject(hipStream_t s, void* p, int is_float, int bit);
+int inject(hipStream_t s, void* p, int is_float, int bit, abft_report* rep = nullptr);
 int report_init(hipStream_t s, abft_report* r, int32_t* info);
 int report_fini(hipStream_t s, abft_report* r);
 

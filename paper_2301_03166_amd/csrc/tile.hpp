@@ -215,6 +215,11 @@ __device__ void tile_compare(const TileSums& ts, TileFlags& tf, int I, int J, in
   __syncthreads();
 }
 
+// whether the weighted / plain difference ratio exists (it does not when a
+// difference is not finite or the weighted one overflowed)
+__device__ __forceinline__ bool ratio_finite(double dw, double de) {
+  return de != 0.0 && fabs(dw / de) <= 1.79e308;
+}
 __device__ __forceinline__ int ratio_index(double dw, double de, int len) {
   if (!(de != 0.0)) return -1;
   double r = dw / de;
@@ -348,25 +353,40 @@ __device__ void correct_tile_dev(T* A, int64_t lda, int I, int J, int nb, int h,
     if (tf.nflag == 0) {
       repair = -1;
     } else if (diag) {
+      // symmetric view: an off-diagonal element shows in two columns (itself
+      // and its mirror), a diagonal one in one.  Two flagged columns name the
+      // element by the pattern (the recheck rejects any other cause); one
+      // flagged column: the ratio names the row (the element or its mirror),
+      // and where it does not exist (non-finite value, overflowed weighted
+      // sum) it is the diagonal element
       if (nFe == 1) {
-        int i = ratio_index(tf.dw[jf0], tf.de[jf0], h);
-        if (i == jf0) { ci = i; cj = i; }
-      } else if (nFe == 2) {
-        if (ratio_index(tf.dw[jf0], tf.de[jf0], h) == jf1 && ratio_index(tf.dw[jf1], tf.de[jf1], h) == jf0) {
-          ci = jf1; cj = jf0;
+        const int i = ratio_index(tf.dw[jf0], tf.de[jf0], h);
+        if (i >= 0) {
+          ci = i > jf0 ? i : jf0;
+          cj = i > jf0 ? jf0 : i;
+        } else if (!ratio_finite(tf.dw[jf0], tf.de[jf0])) {
+          ci = cj = jf0;
+        } else if (nGe == 0 && !tf.fw[jf0]) {
+          repair = 1;  // a flipped e entry of the column checksums
         }
+      } else if (nFe == 2) {
+        ci = jf1;
+        cj = jf0;
       } else if (nFe == 0) {
         repair = 1;
       }
     } else {
+      // a checksum entry is taken for wrong only when its data side is
+      // consistent: a plain difference with an unflagged weighted one (a
+      // flipped e entry), or weighted differences alone
       if (nFe == 1 && nGe == 1) {
         ci = ig; cj = jf0;
       } else if (nFe == 1 && nGe == 0) {
         int i = ratio_index(tf.dw[jf0], tf.de[jf0], h);
-        if (i >= 0) { ci = i; cj = jf0; } else if (nGw == 0) repair = 1;
+        if (i >= 0) { ci = i; cj = jf0; } else if (nGw == 0 && !tf.fw[jf0]) repair = 1;
       } else if (nFe == 0 && nGe == 1) {
         int j = ratio_index(tf.hw[ig], tf.he[ig], w);
-        if (j >= 0) { ci = ig; cj = j; } else if (nFw == 0) repair = 1;
+        if (j >= 0) { ci = ig; cj = j; } else if (nFw == 0 && !tf.gw[ig]) repair = 1;
       } else if (nFe == 0 && nGe == 0) {
         repair = 1;
       } else if (level == 2 && nGe == 1 && nFe >= 2) {

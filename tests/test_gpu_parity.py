@@ -247,13 +247,16 @@ def test_two_flips_one_tile_uncorrectable(h):
     assert rep.status & 4 and orep.status & 4
 
 
+@pytest.mark.parametrize("bit", [57, 62])
 @pytest.mark.parametrize("pos", [(95, 64), (87, 64), (70, 70), (80, 79)])
-def test_chol_diagonal_tile_flip(h, pos):
+def test_chol_diagonal_tile_flip(h, pos, bit):
     """Flips inside a Cholesky diagonal tile, including its far corner, where
-    the rebuilt element's rounding is weighted by nb-1 in the recheck."""
+    the rebuilt element's rounding is weighted by nb-1 in the recheck; bit 62
+    makes an off-diagonal entry ~1e307, whose weighted sums overflow (located
+    by the two flagged columns alone)."""
     n, nb = 128, 32
     A = gen.spd(n, 0)
-    f = {"iter": 1, "row": pos[0], "col": pos[1], "bit": 57}
+    f = {"iter": 1, "row": pos[0], "col": pos[1], "bit": bit}
     clean, _ = _gpu(h, "chol", A, nb)
     G, rep = _gpu(h, "chol", A, nb, faults=[f])
     O, orep = _orc("chol", A, nb, faults=[f])
@@ -299,3 +302,66 @@ def test_chol_diagonal_checksum_repair_matches_oracle(h):
     assert rep.status == orep.status == 2 and rep.checksum_repaired == 1
     assert rep.events() == orep.events() == [(0, 2, 32, 32)]
     assert np.array_equal(G, clean)
+
+
+def test_chol_diagonal_column_checksum_entry_repaired(h):
+    n, nb = 96, 32
+    A = gen.spd(n, 12)
+    f = {"iter": 0, "target": 1, "row": 2, "col": 45, "bit": 56}
+    clean, _ = _gpu(h, "chol", A, nb)
+    G, rep = _gpu(h, "chol", A, nb, faults=[f])
+    O, orep = _orc("chol", A, nb, faults=[f])
+    assert rep.status == orep.status == 2 and rep.checksum_repaired == 1
+    assert rep.events() == orep.events() == [(0, 2, 32, 32)]
+    assert np.array_equal(G, clean)
+
+
+@pytest.mark.parametrize("protect", [2, 1])
+def test_huge_offdiagonal_flip_matches_oracle(h, protect):
+    """A flip to ~1e307 in an off-diagonal tile: corrected by the row and
+    column intersection with full checksums, uncorrectable (never taken for a
+    checksum error) with the column side alone, as in the oracle."""
+    n, nb = 128, 32
+    A = gen.spd(n, 4)
+    L = A.copy(order="F")
+    oracle.potrf(L, nb)
+    S = np.tril(L)[nb:, nb:] @ np.tril(L)[nb:, nb:].T
+    f = None
+    for i in range(2 * nb, n):
+        for j in range(nb, i - nb + 1):
+            if i // nb != j // nb and i % nb >= 20 and 1 / 16 <= abs(S[i - nb, j - nb]) < 0.5:
+                f = {"iter": 0, "row": i, "col": j, "bit": 62}
+                break
+        if f:
+            break
+    dA = dev(A)
+    info, rep = h.potrf(dA, nb, faults=[f], protect=protect)
+    Ao = A.copy(order="F")
+    oinfo, orep = oracle.potrf(Ao, nb, faults=[f], protect=protect)
+    assert info == oinfo and rep.status == orep.status
+    if protect == 2:
+        assert info == 0 and rep.status == 1 and rep.events() == sorted(orep.events())
+        G = np.tril(host(dA))
+        assert np.max(np.abs(G - np.tril(Ao))) <= 1e-12 * np.max(np.abs(np.tril(Ao)))
+    else:
+        # the huge value stays and the factorization breaks down later: the
+        # oracle stops there, the GPU completes on NaN data, so the events are
+        # compared up to the iteration of the breakdown
+        assert rep.status & 4 and not rep.status & 2 and info > 0
+        last = (info - 1) // nb
+        assert [e for e in rep.events() if e[0] < last] == sorted(e for e in orep.events() if e[0] < last)
+
+
+@pytest.mark.parametrize("k,i,j,bit", [(2, 246, 219, 18), (0, 79, 78, 17), (0, 252, 241, 21), (1, 172, 133, 19)])
+def test_chol_diagonal_near_threshold_flip_matches_oracle(h, k, i, j, bit):
+    """Flips a few thresholds in size inside diagonal tiles: located by the
+    pattern of the two flagged columns, as in the oracle."""
+    n, nb = 256, 64
+    A = gen.spd(n, 21)
+    f = {"iter": k, "row": i, "col": j, "bit": bit}
+    clean, _ = _gpu(h, "chol", A, nb)
+    G, rep = _gpu(h, "chol", A, nb, faults=[f])
+    O, orep = _orc("chol", A, nb, faults=[f])
+    assert rep.status == orep.status == 1
+    assert rep.events() == orep.events() == [(k, 1, i, j)]
+    assert np.max(np.abs(G - clean)) <= 1e-13 * np.max(np.abs(clean))
