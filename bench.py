@@ -209,6 +209,8 @@ def fp64_legs(h, torch, dev, args, legs):
             p = h.profile()
             prof_acc[k] = {f: p[f] for f in ("ms_total", "ms_panel", "ms_tmu", "ms_carry", "ms_verify", "tmu_flops",
                                              "tmu_launches", "verify_bytes")}
+            from paper_2301_03166_amd import timemodel
+            prof_acc[k]["time_model"] = timemodel.validate(h.iter_profile(), k, n, nb)
     unprot = {}
     if not args.no_overhead:
         for k in legs:
@@ -228,7 +230,8 @@ def fp64_legs(h, torch, dev, args, legs):
             d.update({"ms_panel": a["ms_panel"], "ms_tmu": a["ms_tmu"], "ms_carry": a["ms_carry"],
                       "ms_verify": a["ms_verify"],
                       "tmu_tflops": a["tmu_flops"] / a["ms_tmu"] / 1e9 if a["ms_tmu"] > 0 else None,
-                      "verify_gbs": a["verify_bytes"] / a["ms_verify"] / 1e6 if a["ms_verify"] > 0 else None})
+                      "verify_gbs": a["verify_bytes"] / a["ms_verify"] / 1e6 if a["ms_verify"] > 0 else None,
+                      "time_model_prediction_error": a["time_model"]})
         per_leg[k] = d
     total_ms = sum(sum(leg_ms[k]) for k in legs)
     value = sum(flops[k] for k in legs) * args.steps / total_ms / 1e9
@@ -386,12 +389,15 @@ def batched_faults(h, torch, gen, kind, dname, sizes, flat, pristine, views, sta
     """One untimed batched call with one seeded single-bit flip in each of
     len(sizes) / 64 matrices (chosen without replacement among those with a
     trailing matrix, n > 32): outcomes against the clean factors of the
-    timed calls, and every other matrix must come out bitwise unchanged."""
+    timed calls (equal to the precision's rounding, or, where pivots moved,
+    a backward error within 2x of the clean factors'), and every other
+    matrix must come out bitwise unchanged."""
     import numpy as np
     from paper_2301_03166_amd.abft import Report
     import ctypes
     chol = kind == "chol"
     clean = flat.clone()
+    clean_piv = None if chol else [p.clone() for p in state[3]]
     r = gen.rng(64 + (0 if chol else 1) + (0 if dname == "f64" else 2))
     cand = np.flatnonzero(np.asarray(sizes) > 32)
     pick = np.sort(r.choice(cand, size=len(sizes) // 64, replace=False))
@@ -409,7 +415,7 @@ def batched_faults(h, torch, gen, kind, dname, sizes, flat, pristine, views, sta
     tol = 1e-12 if dname == "f64" else 1e-5
     tally = {"flips": len(faults), "corrected": 0, "checksum_repaired": 0, "uncorrectable": 0,
              "undetected_harmless": 0, "undetected_corrupting": 0, "corrected_but_wrong": 0,
-             "other_matrices_changed": 0}
+             "other_matrices_changed": 0, "results_within_backward_error": 0}
     fset = {f["matrix"]: f for f in faults}
     for q, v in enumerate(views):
         rep = Report.from_buffer_copy(raw[q * rsz:(q + 1) * rsz])
@@ -419,6 +425,15 @@ def batched_faults(h, torch, gen, kind, dname, sizes, flat, pristine, views, sta
             tally["other_matrices_changed"] += int(rep.status != 0 or not torch.equal(g, c))
             continue
         same = float((g - c).abs().max()) <= tol * float(c.abs().max())
+        if not same:
+            # partial pivoting may pick the other of two near-equal pivots after
+            # a flip or a rebuild known to rounding: then the factors differ but
+            # are as good, judged by the backward error against the clean run's
+            A0 = torch.as_strided(pristine, v.shape, v.stride(), v.storage_offset()).double()
+            bf, _ = backward_error(kind, A0, v.double(), None if chol else state[3][q])
+            bc, _ = backward_error(kind, A0, cv.double(), None if chol else clean_piv[q])
+            same = bf <= 2.0 * bc
+            tally["results_within_backward_error"] += int(same)
         if rep.status & 4:
             tally["uncorrectable"] += 1
         elif rep.status & 1:

@@ -169,23 +169,56 @@ typedef struct {
 } abft_ir_report;
 
 /* Handle: holds the stream and device properties.  `stream` is a hipStream_t
-   (NULL = the default stream).  Returns 0 or ABFT_ERR_HIP. */
+   (NULL = the default stream).  Returns 0 or ABFT_ERR_HIP.  abft_destroy
+   synchronizes the handle's streams before releasing them.  (Library
+   plumbing; the paper's system keeps the equivalent state in its runtime,
+   section "State-of-the-art matrix decompositions".) */
 int abft_create(abft_handle* h, void* stream);
 int abft_destroy(abft_handle h);
 int abft_set_stream(abft_handle h, void* stream);
 
-/* Copy the phase profile of the handle's last ABFT_FLAG_PROFILE call. */
+/* Copy the phase profile of the handle's last ABFT_FLAG_PROFILE call (the
+   per-phase split PD / PU / TMU / checksum work of the paper's Tab. 2). */
 int abft_get_profile(abft_handle h, abft_profile* out);
 
+/* Per-iteration phase times (ms) of the handle's last ABFT_FLAG_PROFILE
+   call: ms is a host array of 5 * cap doubles, phase-major, ms[p * cap + k]
+   for iteration k < min(cap, *iters) and phase p = 0 panel decomposition
+   (PD; Cholesky's and QR's panel updates included), 1 panel update (LU's
+   U12 solve), 2 trailing-matrix update products, 3 checksum carries,
+   4 checksum verification and correction.  *iters receives the number of
+   iterations recorded.  These are the per-iteration task times that the
+   paper's algorithmic time prediction works from (section "Bi-directional
+   slack reclamation", Tab. 2 and the weighted-neighbour predictor). */
+int abft_get_iter_profile(abft_handle h, int32_t cap, double* ms, int32_t* iters);
+
 /* Bytes of device workspace needed by operation `op` on an n x n problem
-   (for the batched ops: n = the largest matrix order, `batch` matrices). */
+   (for the batched ops: n = the largest matrix order, `batch` matrices):
+   the checksum arrays of section "Design of ABFT-OC" (ABFT checksum: one
+   pair of column and row checksums per b x b block) plus panel scratch. */
 int abft_workspace_size(abft_handle h, int op, int64_t n, int32_t batch, const abft_opts* opts, size_t* bytes);
+
+/* Register a device workspace with the handle: every later call that passes
+   dwork == NULL uses it (with its size), so a caller can size and hand over
+   one buffer once.  dwork stays owned by the caller and must outlive its use
+   by enqueued calls; NULL (with bytes 0) unregisters.  Returns -2 for a NULL
+   buffer of nonzero size. */
+int abft_set_workspace(abft_handle h, void* dwork, size_t bytes);
+
+/* Copy a device report to host memory: enqueued on the handle's stream
+   after the calls before it, then the stream is synchronized, so `out`
+   holds the call's final outcome (section "Design of ABFT-OC": detected,
+   corrected or uncorrectable errors of the protected factorization). */
+int abft_report_fetch(abft_handle h, const abft_report* drep, abft_report* out);
 
 /* Cholesky A = L L^T of the lower triangle (the strict upper triangle is
    neither read nor written).  Blocked right-looking with block size opts->nb;
    the trailing update carries per-tile row and column checksums of the
    symmetric trailing matrix, verified and corrected every iteration.
-   dinfo: device int32.  drep: device abft_report (may be NULL). */
+   dinfo: device int32.  drep: device abft_report (may be NULL).
+   Paper: section "State-of-the-art matrix decompositions" (Cholesky's PD,
+   PU and TMU per iteration) and section "Design of ABFT-OC" (ABFT
+   checksum: encode, apply the same operation, verify each iteration). */
 int abft_potrf(abft_handle h, int64_t n, double* dA, int64_t lda, void* dwork, size_t work_bytes,
                const abft_opts* opts, int32_t* dinfo, abft_report* drep);
 
@@ -207,13 +240,19 @@ int abft_potrf_noalloc(abft_handle h, int64_t n, double* dA, int64_t lda, const 
 
 /* LU with partial pivoting P A = L U (L unit lower, U upper, both in A).
    dipiv: device int32[n], 1-based LAPACK row interchanges; ties in the pivot
-   search take the first (smallest) row index. */
+   search take the first (smallest) row index.  Paper: section
+   "State-of-the-art matrix decompositions" (the LU iteration: panel
+   decomposition with pivoting, U12 panel update, trailing GEMM) and section
+   "Design of ABFT-OC" (full checksums per block). */
 int abft_getrf(abft_handle h, int64_t n, double* dA, int64_t lda, int32_t* dipiv, void* dwork, size_t work_bytes,
                const abft_opts* opts, int32_t* dinfo, abft_report* drep);
 
 /* Householder QR A = Q R, LAPACK geqrf storage: R in the upper triangle, the
    reflector vectors v (v(j) = 1 implicit) below the diagonal, dtau[n] the
-   scalar factors (H_j = I - tau_j v_j v_j^T). */
+   scalar factors (H_j = I - tau_j v_j v_j^T).  Paper: section
+   "State-of-the-art matrix decompositions" (QR's panel of Householder
+   reflectors and its blocked trailing update) and section "Design of
+   ABFT-OC" (full checksums per block). */
 int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, void* dwork, size_t work_bytes,
                const abft_opts* opts, int32_t* dinfo, abft_report* drep);
 
@@ -228,7 +267,8 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
    dwork (may be NULL) lets a product with few output tiles and a long K
    split K over more workgroups (partials reduced in a fixed order), using
    up to work_bytes.  Supported: NN, NT, TN; UNIT_LOWER_A with NN or TN;
-   LOWER with NT.  m, n, k < 2^31. */
+   LOWER with NT.  m, n, k < 2^31.  Paper: section "State-of-the-art matrix
+   decompositions" (TMU, the GEMM that dominates each iteration). */
 enum { ABFT_GEMM_LOWER = 1, ABFT_GEMM_UNIT_LOWER_A = 2 };
 int abft_gemm(abft_handle h, int32_t transa, int32_t transb, int32_t flags, int64_t m, int64_t n, int64_t k,
               double alpha, const double* dA, int64_t lda, const double* dB, int64_t ldb, double beta, double* dC,
@@ -239,7 +279,9 @@ int abft_gemm(abft_handle h, int32_t transa, int32_t transb, int32_t flags, int6
    row 2I holds the column sums of tile-row I, row 2I+1 the sums weighted by
    the row's position in the tile (1..nb).  drowchk is m x (2*ceil(n/nb)) with
    ldr >= m: column 2J holds the row sums over tile-column J, column 2J+1 the
-   sums weighted by the column's position in the tile. */
+   sums weighted by the column's position in the tile.  Paper: section
+   "Design of ABFT-OC", ABFT checksum (each block encoded on its own, row
+   and column checksums for full protection). */
 int abft_encode(abft_handle h, int64_t m, int64_t n, const double* dA, int64_t lda, int32_t nb, double* dcolchk,
                 int64_t ldc, double* drowchk, int64_t ldr);
 
@@ -247,7 +289,10 @@ int abft_encode(abft_handle h, int64_t m, int64_t n, const double* dA, int64_t l
    ceil(m/nb) x ceil(n/nb), column-major, may be NULL) receives 1 for a
    flagged tile.  With correct != 0, flagged tiles go through the same
    locate / correct step as the factorizations (A and the checksums are then
-   modified in place).  drep receives counters and max_ratio. */
+   modified in place).  drep receives counters and max_ratio.  Paper:
+   section "Design of ABFT-OC", ABFT checksum (verification after the
+   operation; an error located at the intersection of the inconsistent
+   checksums is corrected, 0D / 1D / 2D error classes). */
 int abft_verify(abft_handle h, int64_t m, int64_t n, double* dA, int64_t lda, int32_t nb, double* dcolchk,
                 int64_t ldc, double* drowchk, int64_t ldr, double tau_scale, int32_t correct, int32_t* dflags,
                 abft_report* drep);
@@ -260,7 +305,10 @@ int abft_verify(abft_handle h, int64_t m, int64_t n, double* dA, int64_t lda, in
    failure on non-finite values, on ||d_i|| > ||d_(i-1)||/2 while far from
    convergence, or after max_iter corrections.  prec == ABFT_F64 factors in
    FP64 and solves directly (the reference method).  dir: device
-   abft_ir_report. */
+   abft_ir_report.  Paper: the LU / Cholesky iterations of section
+   "State-of-the-art matrix decompositions" run in lower precision, with the
+   single- vs double-precision throughput gap of the introduction as the
+   motivation (the refinement itself is this library's addition). */
 int abft_gesv_mp(abft_handle h, int64_t n, const double* dA, int64_t lda, const double* db, double* dx, int32_t prec,
                  int32_t max_iter, void* dwork, size_t work_bytes, const abft_opts* opts, abft_ir_report* dir,
                  abft_report* drep);
@@ -278,7 +326,10 @@ int abft_posv_mp(abft_handle h, int64_t n, const double* dA, int64_t lda, const 
    captured into a HIP graph the first time a given argument set is seen and
    the graph is replayed on the handle's stream by later calls with the same
    pointers and sizes (up to 8 argument sets are kept per handle); the
-   contents of the arrays may change between replays, their addresses not. */
+   contents of the arrays may change between replays, their addresses not.
+   Paper: the Cholesky / LU iteration of section "State-of-the-art matrix
+   decompositions" with the block checksums of section "Design of ABFT-OC",
+   applied to each matrix of the batch. */
 int abft_potrf_batched(abft_handle h, int32_t batch, int32_t nmax, const int32_t* dn, void* const* dA,
                        const int32_t* dlda, int32_t prec, void* dwork, size_t work_bytes, const abft_opts* opts,
                        int32_t* dinfo, abft_report* dreps);

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("ABFT_LIB") or os.path.join(HERE, "libabft.so")
 F64, F32, BF16, F16 = 0, 1, 2, 3
 PROTECT_NONE, PROTECT_SINGLE, PROTECT_FULL = 0, 1, 2
 OP_POTRF, OP_GETRF, OP_GEQRF, OP_GESV_MP, OP_POSV_MP, OP_POTRF_BATCHED, OP_GETRF_BATCHED = 1, 2, 3, 4, 5, 6, 7
+ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED = -100, -101, -102
 ST_CORRECTED, ST_REPAIRED, ST_UNCORRECTABLE, ST_PANEL, ST_INTERNAL = 1, 2, 4, 8, 16
 
 
@@ -82,6 +83,9 @@ def lib():
         L.abft_set_stream.argtypes = [P, P]
         L.abft_get_profile.argtypes = [P, C.POINTER(Profile)]
         L.abft_workspace_size.argtypes = [P, C.c_int, i64, i32, C.POINTER(Opts), C.POINTER(sz)]
+        L.abft_set_workspace.argtypes = [P, P, sz]
+        L.abft_get_iter_profile.argtypes = [P, i32, P, C.POINTER(i32)]
+        L.abft_report_fetch.argtypes = [P, P, C.POINTER(Report)]
         L.abft_potrf.argtypes = [P, i64, P, i64, P, sz, C.POINTER(Opts), P, P]
         L.abft_potrf_noalloc.argtypes = [P, i64, P, i64, C.POINTER(Opts), P, P]
         L.abft_getrf.argtypes = [P, i64, P, i64, P, P, sz, C.POINTER(Opts), P, P]
@@ -211,6 +215,24 @@ class Handle:
         raw = bytes(buf.cpu().numpy().tobytes())
         return Report.from_buffer_copy(raw)
 
+    def report_fetch(self, buf):
+        """abft_report_fetch: the report in device buffer `buf` after the work
+        enqueued on the current stream (synchronizes that stream)."""
+        out = Report()
+        self._sync_stream()
+        _check(lib().abft_report_fetch(self._h, buf.data_ptr(), C.byref(out)), "abft_report_fetch")
+        return out
+
+    def set_workspace(self, buf):
+        """abft_set_workspace: register a uint8 device tensor as the handle's
+        workspace (None unregisters); calls made with dwork == NULL use it."""
+        if buf is None:
+            _check(lib().abft_set_workspace(self._h, None, 0), "abft_set_workspace")
+        else:
+            _check(lib().abft_set_workspace(self._h, buf.data_ptr(), buf.numel() * buf.element_size()),
+                   "abft_set_workspace")
+        self._registered_ws = buf
+
     # ------------------------------------------------------------ factorizations
     def potrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True,
               profile=False, levels=None):
@@ -262,6 +284,18 @@ class Handle:
         p = Profile()
         _check(lib().abft_get_profile(self._h, C.byref(p)), "abft_get_profile")
         return p.as_dict()
+
+    ITER_PHASES = ("pd", "pu", "tmu", "carry", "verify")
+
+    def iter_profile(self):
+        """Per-iteration phase times (ms) of the last call made with
+        profile=True: a dict phase -> list over iterations."""
+        n = C.c_int32()
+        _check(lib().abft_get_iter_profile(self._h, 0, None, C.byref(n)), "abft_get_iter_profile")
+        cap = n.value
+        buf = (C.c_double * max(1, 5 * cap))()
+        _check(lib().abft_get_iter_profile(self._h, cap, buf, C.byref(n)), "abft_get_iter_profile")
+        return {ph: [buf[q * cap + k] for k in range(cap)] for q, ph in enumerate(self.ITER_PHASES)}
 
     def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None, profile=False, levels=None):
         torch = self.torch

@@ -40,7 +40,19 @@ struct abft_handle_s {
   hipEvent_t fork_ev, join_ev;
   BatchGraph graphs[MAX_GRAPHS];
   int ngraphs, next_graph;
+  void* ws;  // workspace registered with abft_set_workspace (used by calls passing dwork == NULL)
+  size_t ws_bytes;
+  double* iter_ms;  // per-iteration phase times of the last profiled call (host, phase-major)
+  int iter_n;
 };
+
+// a call's workspace: its own, else the one registered with the handle
+static inline void use_ws(abft_handle h, void*& dwork, size_t& bytes) {
+  if (!dwork) {
+    dwork = h->ws;
+    bytes = h->ws_bytes;
+  }
+}
 
 namespace {
 
@@ -71,12 +83,14 @@ constexpr size_t CTR_BYTES = 4096;  // grid-barrier counters: top + 16 groups, 1
 
 // Phase timer of profiled calls: event pairs recorded on the stream, summed
 // per phase after one synchronisation at the end of the call.
-enum { PH_PANEL = 0, PH_TMU = 1, PH_CARRY = 2, PH_VERIFY = 3, PH_N = 4 };
+// phases of a profiled call; the per-iteration record keeps them apart in this order
+enum { PH_PANEL = 0, PH_PU = 1, PH_TMU = 2, PH_CARRY = 3, PH_VERIFY = 4, PH_N = 5 };
 struct Prof {
   abft_handle h;
   bool on;
   int used;
   int tags[8192];
+  int iter_of[8192];
   double tmu_flops = 0, verify_bytes = 0;
   int tmu_launches = 0, iters = 0;
   explicit Prof(abft_handle hh, const abft_opts* o) : h(hh), on(o && (o->flags & ABFT_FLAG_PROFILE)), used(0) {
@@ -92,6 +106,7 @@ struct Prof {
     int i = used;
     used += 2;
     tags[i / 2] = tag;
+    iter_of[i / 2] = iters > 0 ? iters - 1 : 0;
     (void)hipEventRecord(h->ev[i], h->stream);
     return i;
   }
@@ -102,14 +117,26 @@ struct Prof {
     if (!on) return;
     abft_profile p;
     memset(&p, 0, sizeof(p));
+    const int ni = iters > 0 ? iters : 1;
+    double* im = (double*)realloc(h->iter_ms, sizeof(double) * PH_N * ni);
+    if (im) {
+      h->iter_ms = im;
+      h->iter_n = ni;
+      memset(im, 0, sizeof(double) * PH_N * ni);
+    } else {
+      h->iter_n = 0;
+    }
     if (used) {
       (void)hipEventSynchronize(h->ev[used - 1]);
       float ms;
-      double ph[PH_N] = {0, 0, 0, 0};
+      double ph[PH_N] = {0, 0, 0, 0, 0};
       for (int i = 0; i < used; i += 2)
-        if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) ph[tags[i / 2]] += ms;
+        if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) {
+          ph[tags[i / 2]] += ms;
+          if (h->iter_n) h->iter_ms[tags[i / 2] * h->iter_n + std::min(iter_of[i / 2], h->iter_n - 1)] += ms;
+        }
       if (hipEventElapsedTime(&ms, h->ev[0], h->ev[used - 1]) == hipSuccess) p.ms_total = ms;
-      p.ms_panel = ph[PH_PANEL];
+      p.ms_panel = ph[PH_PANEL] + ph[PH_PU];
       p.ms_tmu = ph[PH_TMU];
       p.ms_carry = ph[PH_CARRY];
       p.ms_verify = ph[PH_VERIFY];
@@ -649,6 +676,8 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       pf.end(t);
       break;
     }
+    pf.end(t);
+    t = pf.begin(PH_PU);
     TRY(trsm_llu(s, dA, lda, c0, kw, c1, n));
     if (lev && !defer) TRY(check_pu(s));
     pf.end(t);
@@ -770,6 +799,7 @@ int gesv_mp_impl(abft_handle h, int64_t n, const double* dA, int64_t lda, const 
   if (n > 40000) return ABFT_ERR_UNSUPPORTED;
   hipStream_t s = h->stream;
   const int elem = prec == ABFT_F64 ? 8 : 4;
+  use_ws(h, dwork, work_bytes);
   Ws w = carve((char*)dwork, n, nb, chol ? ABFT_OP_POTRF : ABFT_OP_GETRF, elem);
   MpWs m = carve_mp((char*)dwork, w.bytes, n, elem);
   if (!dwork || work_bytes < m.bytes) return ABFT_ERR_WORKSPACE;
@@ -931,6 +961,7 @@ int abft_destroy(abft_handle h) {
     (void)hipEventDestroy(h->fork_ev);
     (void)hipEventDestroy(h->join_ev);
   }
+  free(h->iter_ms);
   free(h);
   return rc;
 }
@@ -941,10 +972,39 @@ int abft_set_stream(abft_handle h, void* stream) {
   return 0;
 }
 
+int abft_set_workspace(abft_handle h, void* dwork, size_t bytes) {
+  if (!h) return -1;
+  if (!dwork && bytes) return -2;
+  h->ws = dwork;
+  h->ws_bytes = dwork ? bytes : 0;
+  return 0;
+}
+
+int abft_report_fetch(abft_handle h, const abft_report* drep, abft_report* out) {
+  if (!h) return -1;
+  if (!drep) return -2;
+  if (!out) return -3;
+  if (hipMemcpyAsync(out, drep, sizeof(abft_report), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+    return ABFT_ERR_HIP;
+  return hipStreamSynchronize(h->stream) == hipSuccess ? 0 : ABFT_ERR_HIP;
+}
+
 int abft_get_profile(abft_handle h, abft_profile* out) {
   if (!h) return -1;
   if (!out) return -2;
   *out = h->prof;
+  return 0;
+}
+
+int abft_get_iter_profile(abft_handle h, int32_t cap, double* ms, int32_t* iters) {
+  if (!h) return -1;
+  if (cap < 0) return -2;
+  if (!ms && cap > 0) return -3;
+  if (!iters) return -4;
+  const int n = std::min<int>(cap, h->iter_n);
+  for (int ph = 0; ph < PH_N; ++ph)
+    for (int k = 0; k < n; ++k) ms[ph * cap + k] = h->iter_ms[ph * h->iter_n + k];
+  *iters = h->iter_n;
   return 0;
 }
 
@@ -983,6 +1043,7 @@ int abft_potrf(abft_handle h, int64_t n, double* dA, int64_t lda, void* dwork, s
   double ts;
   TRY(check_opts(opts, n, nb, protect, ts));
   if (!dinfo) return -8;
+  use_ws(h, dwork, work_bytes);
   Ws w = carve((char*)dwork, n, nb, ABFT_OP_POTRF, sizeof(double));
   if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
   return potrf_impl<double>(h, n, dA, lda, w, opts, nb, protect, ts, ABFT_F64, dinfo, drep);
@@ -1018,6 +1079,7 @@ int abft_getrf(abft_handle h, int64_t n, double* dA, int64_t lda, int32_t* dipiv
   double ts;
   TRY(check_opts(opts, n, nb, protect, ts));
   if (!dinfo) return -9;
+  use_ws(h, dwork, work_bytes);
   Ws w = carve((char*)dwork, n, nb, ABFT_OP_GETRF, sizeof(double));
   if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
   return getrf_impl<double>(h, n, dA, lda, dipiv, w, opts, nb, protect, ts, ABFT_F64, dinfo, drep);
@@ -1035,6 +1097,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   TRY(check_opts(opts, n, nb, protect, ts));
   if (!dinfo) return -9;
   hipStream_t s = h->stream;
+  use_ws(h, dwork, work_bytes);
   Ws w = carve((char*)dwork, n, nb, ABFT_OP_GEQRF, sizeof(double));
   if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
   TRY(report_init(s, drep, dinfo));
@@ -1225,6 +1288,7 @@ static int batched_common(abft_handle h, int chol, int32_t batch, int32_t nmax, 
   if (protect == ABFT_PROTECT_SINGLE || opts->levels) return ABFT_ERR_UNSUPPORTED;  // full checksums or none
   if (batch == 0) return 0;
   if (!dinfo || !dreps) return -11;
+  use_ws(h, dwork, work_bytes);
   if (!dwork || work_bytes < batched_ws_bytes(batch)) return ABFT_ERR_WORKSPACE;
   const int nf = opts->faults ? opts->nfaults : 0;
   if (opts->wgs_per_cu < 0 || opts->wgs_per_cu > 4) return -10;

@@ -73,3 +73,12 @@ def test_autotune_table_lookup(tmp_path):
     p = tmp_path / "t.json"
     autotune.save(t, str(p))
     assert autotune.load(str(p)) == t
+
+
+def test_handle_calls_reject_null_handle():
+    """Argument checks that need no device: a NULL handle is argument 1."""
+    from paper_2301_03166_amd import abft
+    L = abft.lib()
+    assert L.abft_set_workspace(None, None, 0) == -1
+    assert L.abft_report_fetch(None, None, None) == -1
+    assert L.abft_set_stream(None, None) == -1
