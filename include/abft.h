@@ -146,7 +146,32 @@ typedef struct {
   int32_t nlevels;     /* entries of `levels` (0: none) */
   const int8_t* levels; /* host array, levels[k] = ABFT_PROTECT_* of iteration k (k < ceil(n/nb) <= nlevels),
                            overriding `protect` (FP64 blocked factorizations); NULL: `protect` everywhere */
+  int32_t lookahead;   /* LU and QR: compute units given to the look-ahead panel stream (<= 0: the
+                          one-stream schedule, the default; see below) */
+  int32_t pad_;
 } abft_opts;
+
+/* Look-ahead (the paper's section "State-of-the-art matrix decompositions":
+   the part of the update that the next panel needs is done first, then the
+   next panel decomposition runs concurrently with the rest of the update).
+   With opts->lookahead > 0, an LU or QR factorization with uniform
+   protection and no fault plan runs its work on two streams of the handle
+   restricted to disjoint sets of compute units (created on first use with
+   hipExtStreamCreateWithCUMask, default priority): the panel stream gets
+   opts->lookahead units (raised to what the first panel's cooperative
+   leaves need to hold its rows in LDS, at most half the device), the
+   update stream the rest.  Each iteration updates and verifies the next
+   panel's block column first, factors that panel on the panel stream while
+   the rest of the trailing matrix is updated and verified, and joins before
+   the next iteration.  Both streams are ordered after the caller's stream
+   on entry and the caller's stream after both on exit.  Profiled calls and
+   calls with fault plans or per-iteration levels use the one-stream
+   schedule.  The factors equal the one-stream schedule's bitwise when the
+   cooperative leaves get the same shape on both (small panels), and to
+   rounding otherwise.  It is off by default: on one MI355X the panel needs
+   about a quarter of the device's LDS at n = 32768, and the update loses
+   more on the remaining units than the overlap saves (LU 879 -> 1032 ms,
+   QR 1358 -> 1647 ms with 64 panel units). */
 
 /* opts.flags: ABFT_FLAG_PROFILE times the phases of the call with HIP
    events on the handle's stream, all work on that one stream (the call then

@@ -60,7 +60,8 @@ class Profile(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("protect", C.c_int32), ("tau_scale", C.c_double),
                 ("faults", C.POINTER(Fault)), ("nfaults", C.c_int32), ("flags", C.c_int32),
-                ("wgs_per_cu", C.c_int32), ("nlevels", C.c_int32), ("levels", C.POINTER(C.c_int8))]
+                ("wgs_per_cu", C.c_int32), ("nlevels", C.c_int32), ("levels", C.POINTER(C.c_int8)),
+                ("lookahead", C.c_int32), ("pad_", C.c_int32)]
 
 
 class AbftError(RuntimeError):
@@ -137,10 +138,13 @@ def protect_level(protect):
     return int(protect)
 
 
-def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False, graph=False, wgs_per_cu=0, levels=None):
-    """abft_opts plus the host arrays it points to (keep them alive for the call)"""
+def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False, graph=False, wgs_per_cu=0, levels=None,
+              lookahead=0):
+    """abft_opts plus the host arrays it points to (keep them alive for the call);
+    lookahead: CUs of the look-ahead panel stream (0 default, < 0 off)"""
     o = Opts()
     o.wgs_per_cu = int(wgs_per_cu)
+    o.lookahead = int(lookahead)
     o.nb, o.protect, o.tau_scale = int(nb), protect_level(protect), float(tau_scale)
     o.flags = (FLAG_PROFILE if profile else 0) | (FLAG_GRAPH if graph else 0)
     keep = []
@@ -235,11 +239,12 @@ class Handle:
 
     # ------------------------------------------------------------ factorizations
     def potrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True,
-              profile=False, levels=None):
+              profile=False, levels=None, lookahead=0):
         """In-place Cholesky (lower) of column-major A; returns (info, Report) when sync.
-        protect: True / False or a PROTECT_* level; levels: one PROTECT_* level per iteration."""
+        protect: True / False or a PROTECT_* level; levels: one PROTECT_* level per iteration;
+        lookahead: compute units of the look-ahead panel stream (0 default, < 0 one stream)."""
         return self._factor(OP_POTRF, A, nb, protect, tau_scale, faults, report, info, sync, profile=profile,
-                            levels=levels)
+                            levels=levels, lookahead=lookahead)
 
     def potrf_noalloc(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True):
         """abft_potrf_noalloc: the Cholesky of potrf with the library's built-in
@@ -262,21 +267,21 @@ class Handle:
         return int(inf.item()), self.read_report(rep)
 
     def getrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, ipiv=None, report=None, info=None, sync=True,
-              profile=False, levels=None):
+              profile=False, levels=None, lookahead=0):
         torch = self.torch
         if ipiv is None:
             ipiv = torch.zeros(A.shape[0], dtype=torch.int32, device=self.device)
         out = self._factor(OP_GETRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=ipiv, profile=profile,
-                           levels=levels)
+                           levels=levels, lookahead=lookahead)
         return (ipiv,) + out if sync else ipiv
 
     def geqrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, tau=None, report=None, info=None, sync=True,
-              profile=False, levels=None):
+              profile=False, levels=None, lookahead=0):
         torch = self.torch
         if tau is None:
             tau = torch.zeros(A.shape[0], dtype=torch.float64, device=self.device)
         out = self._factor(OP_GEQRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=tau, profile=profile,
-                           levels=levels)
+                           levels=levels, lookahead=lookahead)
         return (tau,) + out if sync else tau
 
     def profile(self):
@@ -297,7 +302,8 @@ class Handle:
         _check(lib().abft_get_iter_profile(self._h, cap, buf, C.byref(n)), "abft_get_iter_profile")
         return {ph: [buf[q * cap + k] for k in range(cap)] for q, ph in enumerate(self.ITER_PHASES)}
 
-    def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None, profile=False, levels=None):
+    def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None, profile=False, levels=None,
+                lookahead=0):
         torch = self.torch
         n = A.shape[0]
         if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
@@ -306,7 +312,7 @@ class Handle:
         if nb is None or nb == "auto":  # the autotuned block size for this operation and size class
             from . import autotune
             nb = autotune.lookup_nb({OP_POTRF: "potrf", OP_GETRF: "getrf"}.get(op, "geqrf"), n)
-        opts, keep = make_opts(nb, protect, tau_scale, faults, profile, levels=levels)
+        opts, keep = make_opts(nb, protect, tau_scale, faults, profile, levels=levels, lookahead=lookahead)
         ws, wbytes = self.workspace(op, n, opts)
         rep = report if report is not None else self.new_report()
         inf = info if info is not None else torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -330,7 +336,7 @@ class Handle:
 
     # ------------------------------------------------------------ mixed precision
     def gesv_mp(self, A, b, prec, nb=256, max_iter=30, chol=False, protect=True, tau_scale=4.0, faults=None,
-                x=None, report=None, ir=None, sync=True, profile=False):
+                x=None, report=None, ir=None, sync=True, profile=False, lookahead=0):
         """Solve A x = b: binary32 factorization (trailing update in `prec`) + FP64 refinement,
         or the FP64 factorization and direct solve when prec == F64.  Returns (x, IRReport, Report)."""
         torch = self.torch
@@ -342,7 +348,7 @@ class Handle:
         if x is None:
             x = torch.zeros(n, dtype=torch.float64, device=self.device)
         op = OP_POSV_MP if chol else OP_GESV_MP
-        opts, keep = make_opts(nb, protect, tau_scale, faults, profile)
+        opts, keep = make_opts(nb, protect, tau_scale, faults, profile, lookahead=lookahead)
         ws, wbytes = self.workspace(op, n, opts)
         rep = report if report is not None else self.new_report()
         irb = ir if ir is not None else torch.zeros(C.sizeof(IRReport), dtype=torch.uint8, device=self.device)

@@ -44,6 +44,11 @@ struct abft_handle_s {
   size_t ws_bytes;
   double* iter_ms;  // per-iteration phase times of the last profiled call (host, phase-major)
   int iter_n;
+  // look-ahead schedule: an update stream and a panel stream on disjoint
+  // sets of compute units (created on first use; la_pcus units for the panel)
+  hipStream_t la_main, la_panel;
+  int la_pcus;
+  hipEvent_t la_ev[4];
 };
 
 // a call's workspace: its own, else the one registered with the handle
@@ -195,6 +200,93 @@ struct Side {
   }
   bool pending = false;
   hipEvent_t fe = nullptr, je = nullptr;
+};
+
+// Look-ahead schedule of a blocked factorization.  The call's work moves
+// from the caller's stream to the handle's update stream (compute units
+// [0, cus - P)); the next panel is factored on the panel stream (units
+// [cus - P, cus)) while the update stream finishes the current iteration,
+// and the update stream waits for it before the next iteration.  The
+// caller's stream is ordered before (entry) and after (exit) both.  Off for
+// profiled calls (one stream), fault plans and per-iteration levels.
+int la_streams(abft_handle h, int pcus) {
+  if (h->la_pcus == pcus && h->la_main) return 0;
+  if (h->la_main) {
+    if (hipStreamSynchronize(h->la_main) != hipSuccess || hipStreamSynchronize(h->la_panel) != hipSuccess)
+      return ABFT_ERR_HIP;
+    (void)hipStreamDestroy(h->la_main);
+    (void)hipStreamDestroy(h->la_panel);
+    h->la_main = h->la_panel = nullptr;
+    h->la_pcus = 0;
+  }
+  if (!h->la_ev[0])
+    for (int i = 0; i < 4; ++i)
+      if (hipEventCreateWithFlags(&h->la_ev[i], hipEventDisableTiming) != hipSuccess) return ABFT_ERR_HIP;
+  const int words = (h->cus + 31) / 32;
+  uint32_t mm[16] = {0}, pm[16] = {0};
+  if (words > 16) return ABFT_ERR_UNSUPPORTED;
+  for (int c = 0; c < h->cus; ++c) (c < h->cus - pcus ? mm : pm)[c / 32] |= 1u << (c % 32);
+  if (hipExtStreamCreateWithCUMask(&h->la_main, words, mm) != hipSuccess) {
+    h->la_main = nullptr;
+    return ABFT_ERR_HIP;
+  }
+  if (hipExtStreamCreateWithCUMask(&h->la_panel, words, pm) != hipSuccess) {
+    (void)hipStreamDestroy(h->la_main);
+    h->la_main = h->la_panel = nullptr;
+    return ABFT_ERR_HIP;
+  }
+  h->la_pcus = pcus;
+  return 0;
+}
+
+struct Look {
+  abft_handle h;
+  bool on = false;
+  hipStream_t caller = nullptr, ms = nullptr, ps = nullptr;
+  int pmaxg = 0, mmaxg = 0;  // workgroup bounds of the cooperative panel leaves on each stream
+  // rows_per_cu: panel rows one compute unit's LDS holds in the narrowest
+  // cooperative leaf; the panel share is raised to cover the first panel
+  Look(abft_handle hh, const abft_opts* o, bool allowed, int64_t n, int nb, int rows_per_cu) : h(hh) {
+    if (!allowed || o->lookahead <= 0 || (o->flags & ABFT_FLAG_PROFILE) || (o->faults && o->nfaults > 0) ||
+        o->levels || n <= nb)
+      return;
+    // the panel stream must hold the first panel's leaf rows in its units' LDS
+    const int need = (int)std::min<int64_t>(h->cus, (n + rows_per_cu - 1) / rows_per_cu);
+    const int pc = std::max(need, std::min(o->lookahead, h->cus / 2));
+    if (pc >= h->cus) return;
+    if (la_streams(h, pc)) return;  // (no masked streams: the one-stream schedule)
+    caller = h->stream;
+    if (hipEventRecord(h->la_ev[0], caller) != hipSuccess || hipStreamWaitEvent(h->la_main, h->la_ev[0], 0) != hipSuccess)
+      return;
+    ms = h->la_main;
+    ps = h->la_panel;
+    pmaxg = std::min(pc, 256);
+    mmaxg = std::min(h->cus - pc, 256);
+    h->stream = ms;
+    on = true;
+  }
+  // the panel stream starts after everything enqueued on the update stream so far
+  int fork_panel() {
+    if (hipEventRecord(h->la_ev[1], ms) != hipSuccess || hipStreamWaitEvent(ps, h->la_ev[1], 0) != hipSuccess)
+      return ABFT_ERR_HIP;
+    return 0;
+  }
+  // the update stream continues after everything enqueued on the panel stream
+  int join_panel() {
+    if (hipEventRecord(h->la_ev[2], ps) != hipSuccess || hipStreamWaitEvent(ms, h->la_ev[2], 0) != hipSuccess)
+      return ABFT_ERR_HIP;
+    return 0;
+  }
+  int finish() {
+    if (!on) return 0;
+    on = false;
+    h->stream = caller;
+    if (join_panel()) return ABFT_ERR_HIP;
+    if (hipEventRecord(h->la_ev[3], ms) != hipSuccess || hipStreamWaitEvent(caller, h->la_ev[3], 0) != hipSuccess)
+      return ABFT_ERR_HIP;
+    return 0;
+  }
+  ~Look() { (void)finish(); }
 };
 
 // Workspace carve-up shared by the three factorizations.
@@ -611,22 +703,24 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
 template <typename T>
 int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, const Ws& w, const abft_opts* opts,
                int nb, int protect, double ts, int prec, int32_t* dinfo, abft_report* drep) {
-  hipStream_t s = h->stream;
-  TRY(report_init(s, drep, dinfo));
-  if (n == 0) return report_fini(s, drep);
-  TRY(fill_zero(s, w.pflags, (size_t)((n + nb - 1) / nb) * sizeof(int)));
-  TRY(fill_zero(s, w.ctr, CTR_BYTES));
-  TRY(fill_zero(s, w.slots, SLOT_WORDS * sizeof(double)));  // leaf records: sequence numbers restart
+  TRY(report_init(h->stream, drep, dinfo));
+  if (n == 0) return report_fini(h->stream, drep);
+  TRY(fill_zero(h->stream, w.pflags, (size_t)((n + nb - 1) / nb) * sizeof(int)));
+  TRY(fill_zero(h->stream, w.ctr, CTR_BYTES));
+  TRY(fill_zero(h->stream, w.slots, SLOT_WORDS * sizeof(double)));  // leaf records: sequence numbers restart
   const int N = (int)((n + nb - 1) / nb);
   const int ldc = 2 * N;
   const double u = sizeof(T) == 8 ? U64 : U32;
   const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
   const int rnd = op_rnd(prec);
   const bool opf = has_operand_faults(opts);
+  // (the look-ahead moves the work to the update stream when on)
+  Look la(h, opts, !opf, n, nb, (int)((144 * 1024) / ((LEAFW + 1) * sizeof(T))));
+  hipStream_t s = h->stream;
   Prof pf(h, opts);
   Side side(h, !pf.on && !opf);
   int t, prev = ABFT_PROTECT_NONE;
-  LuCtx<T> c{s, dA, lda, n, dipiv, dinfo, &w, 0u, drep, std::min(h->cus, 256)};
+  LuCtx<T> c{s, dA, lda, n, dipiv, dinfo, &w, 0u, drep, la.on ? la.mmaxg : std::min(h->cus, 256)};
   T* porig = (T*)w.porig;
   T* stage = (T*)w.stage;
   for (int k = 0; k < N; ++k) {
@@ -643,11 +737,13 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
     }
     prev = lev;
     t = pf.begin(PH_PANEL);
-    if (lev)
-      if (hipMemcpy2DAsync(porig, n * sizeof(T), dA + c0 + c0 * lda, lda * sizeof(T), (n - c0) * sizeof(T), kw,
-                           hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return ABFT_ERR_HIP;
-    TRY(lu_panel(c, c0, c1));
+    if (!(la.on && k > 0)) {  // (with look-ahead, panel k was factored during iteration k - 1)
+      if (lev)
+        if (hipMemcpy2DAsync(porig, n * sizeof(T), dA + c0 + c0 * lda, lda * sizeof(T), (n - c0) * sizeof(T), kw,
+                             hipMemcpyDeviceToDevice, s) != hipSuccess)
+          return ABFT_ERR_HIP;
+      TRY(lu_panel(c, c0, c1));
+    }
     TRY(perm_build(s, dipiv, c0, kw, n, w.moves));
     // the interchanges of the factored columns to the left and of the row
     // checksums go to the side stream with the carry (nothing before the
@@ -690,7 +786,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       return carry<T>(cs, w, n, nb, k + 1, k + 1, kw, L21, lda, c1, 0, U12, lda, 0, c1, 0, rnd,
                       lev == ABFT_PROTECT_FULL);
     };
-    if (side.on) {  // (w.moves stays unchanged until the join)
+    if (side.on) {  // (w.moves, w.stage and porig stay unchanged until the join)
       TRY(side.fork());
       TRY(laswp(side.s, dA, lda, 0, c0, w.moves, stage, (double*)nullptr, 0, nb));
       if (lev) {
@@ -701,6 +797,43 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       }
     }
     if (opf) TRY(apply_operand_faults<T>(s, opts, k, dA, lda, n, nullptr, 0, c1));
+    if (la.on) {
+      // the next panel's block column first: update, carry (joined), verify
+      const int64_t c2 = std::min<int64_t>(n, c1 + nb);
+      const int kw2 = (int)(c2 - c1);
+      TRY(gemmT(s, prec, 0, 0, 0, (int)m, kw2, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
+      TRY(side.join());
+      if (lev) {
+        TRY(verify_tiles<T>(s, dA, lda, n, c2, nb, k + 1, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                            w.tflags, drep, k, lev));
+        TRY(correct_tiles<T>(s, dA, lda, n, c2, nb, k + 1, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                             w.tflags, drep, k, lev));
+      }
+      // panel k + 1 on the panel stream, beside the rest of the update
+      TRY(la.fork_panel());
+      if (lev)
+        if (hipMemcpy2DAsync(porig, n * sizeof(T), dA + c1 + c1 * lda, lda * sizeof(T), (n - c1) * sizeof(T), kw2,
+                             hipMemcpyDeviceToDevice, la.ps) != hipSuccess)
+          return ABFT_ERR_HIP;
+      c.s = la.ps;
+      c.maxg = la.pmaxg;
+      const int prc = lu_panel(c, c1, c2);
+      c.s = s;
+      c.maxg = la.mmaxg;
+      TRY(prc);
+      if (c2 < n) {
+        TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)(n - c2), kw, -1.0, L21, lda, U12 + (int64_t)kw2 * lda, lda, 1.0,
+                  dA + c1 + c2 * lda, lda, 0, 1));
+        if (lev) {
+          TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 2, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                              w.tflags, drep, k, lev));
+          TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 2, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                               w.tflags, drep, k, lev));
+        }
+      }
+      TRY(la.join_panel());
+      continue;
+    }
     t = pf.begin(PH_TMU);
     TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
     pf.end(t);
@@ -728,7 +861,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
   }
   TRY(report_fini(s, drep));
   pf.finish();
-  return 0;
+  return la.finish();
 }
 
 
@@ -961,6 +1094,14 @@ int abft_destroy(abft_handle h) {
     (void)hipEventDestroy(h->fork_ev);
     (void)hipEventDestroy(h->join_ev);
   }
+  if (h->la_main) {
+    if (hipStreamSynchronize(h->la_main) != hipSuccess) rc = ABFT_ERR_HIP;
+    if (hipStreamSynchronize(h->la_panel) != hipSuccess) rc = ABFT_ERR_HIP;
+    (void)hipStreamDestroy(h->la_main);
+    (void)hipStreamDestroy(h->la_panel);
+  }
+  for (int i = 0; i < 4; ++i)
+    if (h->la_ev[i]) (void)hipEventDestroy(h->la_ev[i]);
   free(h->iter_ms);
   free(h);
   return rc;
@@ -1096,20 +1237,22 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   double ts;
   TRY(check_opts(opts, n, nb, protect, ts));
   if (!dinfo) return -9;
-  hipStream_t s = h->stream;
   use_ws(h, dwork, work_bytes);
   Ws w = carve((char*)dwork, n, nb, ABFT_OP_GEQRF, sizeof(double));
   if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
-  TRY(report_init(s, drep, dinfo));
-  if (n == 0) return report_fini(s, drep);
-  TRY(fill_zero(s, w.pflags, (size_t)((n + nb - 1) / nb) * sizeof(int)));
-  TRY(fill_zero(s, w.ctr, CTR_BYTES));
-  TRY(fill_zero(s, w.slots, SLOT_WORDS * sizeof(double)));  // leaf records: sequence numbers restart
+  TRY(report_init(h->stream, drep, dinfo));
+  if (n == 0) return report_fini(h->stream, drep);
+  TRY(fill_zero(h->stream, w.pflags, (size_t)((n + nb - 1) / nb) * sizeof(int)));
+  TRY(fill_zero(h->stream, w.ctr, CTR_BYTES));
+  TRY(fill_zero(h->stream, w.slots, SLOT_WORDS * sizeof(double)));  // leaf records: sequence numbers restart
   const int N = (int)((n + nb - 1) / nb);
   const int ldc = 2 * N;
   const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);
   const bool opf = has_operand_faults(opts);
-  QrCtx c{s, dA, lda, n, dtau, &w, nb, 0, 0u, drep, std::min(h->cus, 256)};
+  // (the look-ahead moves the work to the update stream when on)
+  Look la(h, opts, !opf, n, nb, (int)((140 * 1024) / ((LEAFW + 1) * sizeof(double))));
+  hipStream_t s = h->stream;
+  QrCtx c{s, dA, lda, n, dtau, &w, nb, 0, 0u, drep, la.on ? la.mmaxg : std::min(h->cus, 256)};
   Prof pf(h, opts);
   Side side(h, any_protected(opts, N, protect) && !pf.on && !opf);
   int t, prev = ABFT_PROTECT_NONE;
@@ -1125,8 +1268,10 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
                                nullptr, nullptr, -1));
     prev = lev;
     t = pf.begin(PH_PANEL);
-    TRY(fill_zero(s, w.Tfac, (size_t)nb * nb * sizeof(double)));
-    TRY(qr_panel(c, c0, c1));
+    if (!(la.on && k > 0)) {  // (with look-ahead, panel k was factored during iteration k - 1)
+      TRY(fill_zero(s, w.Tfac, (size_t)nb * nb * sizeof(double)));
+      TRY(qr_panel(c, c0, c1));
+    }
     // the panel check reads the panel, T and colchk of the panel's columns
     // only: on the side stream it runs beside the trailing update
     auto check_k = [&](hipStream_t cs) -> int {
@@ -1168,6 +1313,47 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
       TRY(carry_k(side.s));
     }
     if (opf) TRY(apply_operand_faults<double>(s, opts, k, dA, lda, n, w.W2, nb, c1));
+    if (la.on) {
+      // the next panel's block column first: update, carry and panel check
+      // (joined: the next panel overwrites T), verify
+      const int64_t c2 = std::min<int64_t>(n, c1 + nb);
+      const int kw2 = (int)(c2 - c1);
+      TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), kw2, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0, 0, 0, 0, nullptr, 0,
+                 1));
+      if (fork) {
+        TRY(side.join());
+      } else if (lev) {
+        TRY(carry_k(s));
+      }
+      if (lev) {
+        TRY(verify_tiles<double>(s, dA, lda, n, c2, nb, k, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                                 w.tflags, drep, k, lev));
+        TRY(correct_tiles<double>(s, dA, lda, n, c2, nb, k, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                                  w.tflags, drep, k, lev));
+      }
+      // panel k + 1 on the panel stream, beside the rest of the update
+      TRY(la.fork_panel());
+      c.s = la.ps;
+      c.maxg = la.pmaxg;
+      c.cb = c1;
+      int prc = fill_zero(la.ps, w.Tfac, (size_t)nb * nb * sizeof(double));
+      if (!prc) prc = qr_panel(c, c1, c2);
+      c.s = s;
+      c.maxg = la.mmaxg;
+      TRY(prc);
+      if (c2 < n) {
+        TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)(n - c2), kw, -1.0, V, lda, w.W2 + (int64_t)kw2 * nb, nb, 1.0,
+                   C + (int64_t)kw2 * lda, lda, 0, 0, 0, 0, nullptr, 0, 1));
+        if (lev) {
+          TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k, k + 2, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                                   w.tflags, drep, k, lev));
+          TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k, k + 2, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                                    w.tflags, drep, k, lev));
+        }
+      }
+      TRY(la.join_panel());
+      continue;
+    }
     t = pf.begin(PH_TMU);
     TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)m, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0, 0, 0, 0, nullptr,
                0, 1));
@@ -1196,7 +1382,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   }
   TRY(report_fini(s, drep));
   pf.finish();
-  return 0;
+  return la.finish();
 }
 
 int abft_gemm(abft_handle h, int32_t transa, int32_t transb, int32_t flags, int64_t m, int64_t n, int64_t k,
