@@ -671,6 +671,50 @@ def campaign_leg(h, torch, dev, args):
             "outcomes": out}
 
 
+def gemm_leg(h, torch, dev, args):
+    """The trailing-update product alone on its first-iteration shapes
+    (m' = n - nb, K = nb): LU's C -= L21 U12 (NN), Cholesky's lower
+    C -= L21 L21^T (NT, lower tiles only) and QR's W = V^T C (TN, K = n) and
+    C -= V W2 (NN), each timed over `reps` launches with HIP events."""
+    n, nb = args.n, args.nb
+    m = n - nb
+    g = torch.Generator(device=dev).manual_seed(5)
+    A = torch.randn((n, nb), dtype=torch.float64, device=dev, generator=g).t().contiguous().t()  # n x nb col-major
+    B = torch.randn((nb, n), dtype=torch.float64, device=dev, generator=g).t().contiguous().t()  # nb x n col-major
+    Cm = torch.randn((n, n), dtype=torch.float64, device=dev, generator=g).t()  # col-major n x n
+    W = torch.zeros((nb, m), dtype=torch.float64, device=dev).t().contiguous().t()
+    out = {}
+    cases = {
+        "lu_nn": (lambda: h.gemm(A[:m], B[:, :m], Cm[:m, :m], alpha=-1.0, beta=1.0), 2.0 * m * m * nb),
+        "chol_nt_lower": (lambda: h.gemm(A[:m], A[:m], Cm[:m, :m], transb=True, alpha=-1.0, beta=1.0, lower=True),
+                          1.0 * m * (m + 1) * nb),
+        "qr_tn": (lambda: h.gemm(A, Cm[:, :m], W, transa=True, alpha=1.0, beta=0.0), 2.0 * nb * m * n),
+        "qr_nn": (lambda: h.gemm(A, W, Cm[:, :m], alpha=-1.0, beta=1.0), 2.0 * n * m * nb),
+    }
+    # a plain device copy of known size (n x n FP64 read and written once):
+    # the reference for scaling the HBM traffic counters of the products
+    Cc = torch.empty_like(Cm)
+    cases["copy_ref"] = (lambda: Cc.copy_(Cm), 0.0)
+    for name, (fn, fl) in cases.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.gemm_reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.gemm_reps
+        if name == "copy_ref":
+            out[name] = {"ms": ms, "bytes": 16.0 * n * n, "gbs": 16.0 * n * n / ms / 1e6}
+            log(f"copy {ms:.3f} ms {16.0 * n * n / ms / 1e6:.0f} GB/s")
+            continue
+        out[name] = {"ms": ms, "tflops": fl / ms / 1e9, "frac_fp64_peak": fl / ms / 1e9 / FP64_PEAK_TFLOPS,
+                     "m": m, "k": nb if name != "qr_tn" else n}
+        log(f"gemm {name}: {ms:.3f} ms {fl / ms / 1e9:.1f} TFLOP/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -695,6 +739,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-overhead", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the backward-error check of each leg")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="time only the trailing-update products on their first-iteration shapes")
+    ap.add_argument("--gemm-reps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the factorization is not sharded "
@@ -707,6 +754,11 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     h = abft.Handle(dev)
+    if args.gemm_only:
+        res = gemm_leg(h, torch, dev, args)
+        h.close()
+        print(json.dumps({"gemm": res, "n": args.n, "nb": args.nb}), flush=True)
+        return
     legs = [x for x in args.legs.split(",") if x]
     t0 = time.perf_counter()
     value, ms_step, per_leg, status, roof = fp64_legs(h, torch, dev, args, legs) if legs else (None, None, {}, {},
