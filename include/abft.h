@@ -148,7 +148,9 @@ typedef struct {
                            overriding `protect` (FP64 blocked factorizations); NULL: `protect` everywhere */
   int32_t lookahead;   /* LU and QR: compute units given to the look-ahead panel stream (<= 0: the
                           one-stream schedule, the default; see below) */
-  int32_t pad_;
+  int32_t tmu_bk;      /* K depth of the trailing-update product's 128 x 128 tiles: 16 (0: default; two
+                          workgroups per CU) or 32 (one workgroup per CU, the block's C read during its last
+                          K step); the results are the same bitwise (same order of the products over K) */
 } abft_opts;
 
 /* Look-ahead (the paper's section "State-of-the-art matrix decompositions":

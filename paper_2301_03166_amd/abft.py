@@ -61,7 +61,7 @@ class Opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("protect", C.c_int32), ("tau_scale", C.c_double),
                 ("faults", C.POINTER(Fault)), ("nfaults", C.c_int32), ("flags", C.c_int32),
                 ("wgs_per_cu", C.c_int32), ("nlevels", C.c_int32), ("levels", C.POINTER(C.c_int8)),
-                ("lookahead", C.c_int32), ("pad_", C.c_int32)]
+                ("lookahead", C.c_int32), ("tmu_bk", C.c_int32)]
 
 
 class AbftError(RuntimeError):
@@ -139,12 +139,14 @@ def protect_level(protect):
 
 
 def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False, graph=False, wgs_per_cu=0, levels=None,
-              lookahead=0):
+              lookahead=0, tmu_bk=0):
     """abft_opts plus the host arrays it points to (keep them alive for the call);
-    lookahead: CUs of the look-ahead panel stream (0 default, < 0 off)"""
+    lookahead: CUs of the look-ahead panel stream (<= 0: off); tmu_bk: K depth
+    of the trailing-update product tiles (0 / 16 / 32)"""
     o = Opts()
     o.wgs_per_cu = int(wgs_per_cu)
     o.lookahead = int(lookahead)
+    o.tmu_bk = int(tmu_bk)
     o.nb, o.protect, o.tau_scale = int(nb), protect_level(protect), float(tau_scale)
     o.flags = (FLAG_PROFILE if profile else 0) | (FLAG_GRAPH if graph else 0)
     keep = []
@@ -239,12 +241,13 @@ class Handle:
 
     # ------------------------------------------------------------ factorizations
     def potrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True,
-              profile=False, levels=None, lookahead=0):
+              profile=False, levels=None, lookahead=0, tmu_bk=0):
         """In-place Cholesky (lower) of column-major A; returns (info, Report) when sync.
         protect: True / False or a PROTECT_* level; levels: one PROTECT_* level per iteration;
-        lookahead: compute units of the look-ahead panel stream (0 default, < 0 one stream)."""
+        lookahead: compute units of the look-ahead panel stream (<= 0: one stream);
+        tmu_bk: K depth of the trailing-update product tiles (0 = 16, or 32)."""
         return self._factor(OP_POTRF, A, nb, protect, tau_scale, faults, report, info, sync, profile=profile,
-                            levels=levels, lookahead=lookahead)
+                            levels=levels, lookahead=lookahead, tmu_bk=tmu_bk)
 
     def potrf_noalloc(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True):
         """abft_potrf_noalloc: the Cholesky of potrf with the library's built-in
@@ -267,21 +270,21 @@ class Handle:
         return int(inf.item()), self.read_report(rep)
 
     def getrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, ipiv=None, report=None, info=None, sync=True,
-              profile=False, levels=None, lookahead=0):
+              profile=False, levels=None, lookahead=0, tmu_bk=0):
         torch = self.torch
         if ipiv is None:
             ipiv = torch.zeros(A.shape[0], dtype=torch.int32, device=self.device)
         out = self._factor(OP_GETRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=ipiv, profile=profile,
-                           levels=levels, lookahead=lookahead)
+                           levels=levels, lookahead=lookahead, tmu_bk=tmu_bk)
         return (ipiv,) + out if sync else ipiv
 
     def geqrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, tau=None, report=None, info=None, sync=True,
-              profile=False, levels=None, lookahead=0):
+              profile=False, levels=None, lookahead=0, tmu_bk=0):
         torch = self.torch
         if tau is None:
             tau = torch.zeros(A.shape[0], dtype=torch.float64, device=self.device)
         out = self._factor(OP_GEQRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=tau, profile=profile,
-                           levels=levels, lookahead=lookahead)
+                           levels=levels, lookahead=lookahead, tmu_bk=tmu_bk)
         return (tau,) + out if sync else tau
 
     def profile(self):
@@ -303,16 +306,20 @@ class Handle:
         return {ph: [buf[q * cap + k] for k in range(cap)] for q, ph in enumerate(self.ITER_PHASES)}
 
     def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None, profile=False, levels=None,
-                lookahead=0):
+                lookahead=0, tmu_bk=0):
         torch = self.torch
         n = A.shape[0]
         if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
             raise AbftError("expected a square float64 device matrix")
         lda = _ld(A)
-        if nb is None or nb == "auto":  # the autotuned block size for this operation and size class
+        if nb is None or nb == "auto":  # the autotuned block size and product tile for this operation and size class
             from . import autotune
-            nb = autotune.lookup_nb({OP_POTRF: "potrf", OP_GETRF: "getrf"}.get(op, "geqrf"), n)
-        opts, keep = make_opts(nb, protect, tau_scale, faults, profile, levels=levels, lookahead=lookahead)
+            name = {OP_POTRF: "potrf", OP_GETRF: "getrf"}.get(op, "geqrf")
+            nb = autotune.lookup_nb(name, n)
+            if tmu_bk == 0:
+                tmu_bk = autotune.lookup_tmu_bk(name, n)
+        opts, keep = make_opts(nb, protect, tau_scale, faults, profile, levels=levels, lookahead=lookahead,
+                               tmu_bk=tmu_bk)
         ws, wbytes = self.workspace(op, n, opts)
         rep = report if report is not None else self.new_report()
         inf = info if info is not None else torch.zeros(1, dtype=torch.int32, device=self.device)

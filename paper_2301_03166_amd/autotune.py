@@ -1,13 +1,15 @@
 """Autotuner of the library's launch shapes, measured on the device.
 
-Two choices are tuned, both by timing the library's own calls on synthetic
+Three choices are tuned, all by timing the library's own calls on synthetic
 inputs of the requested shape (HIP events on the handle's stream, best of a
 few repetitions) and keeping the fastest:
 
 * the block size nb of the large factorizations (it is also the checksum
-  tile: it sets the panel width, the K depth of the trailing-update product
-  and the verify granularity), per operation and size class (the next power
-  of two of n);
+  tile: it sets the panel width, the K extent of the trailing-update product
+  and the verify granularity) jointly with the trailing-update product's
+  tile shape (128 x 128 output tiles with K steps of 16, two workgroups per
+  CU, or of 32, one workgroup per CU), per operation and size class (the
+  next power of two of n);
 * the number of persistent workgroups per compute unit of the batched
   factorizations, per operation and precision (binary32 panels take half the
   LDS, so two workgroups can share a CU).
@@ -16,6 +18,9 @@ Results live in a JSON table beside this file (``tuned.json``); lookups fall
 back to fixed defaults for size classes that were never tuned.
 
     python -m paper_2301_03166_amd.autotune --ops potrf,getrf,geqrf --sizes 8192,16384,32768 --batched
+
+The table committed beside this file was measured on one MI355X with that
+command; its entries record every candidate's time.
 """
 from __future__ import annotations
 
@@ -26,6 +31,7 @@ import time
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 NB_CANDIDATES = (128, 256, 384, 512)
+BK_CANDIDATES = (16, 32)
 WGS_CANDIDATES = (1, 2)
 
 
@@ -63,6 +69,13 @@ def lookup_nb(op: str, n: int, table: dict | None = None) -> int:
     return max(1, min(nb, max(1, int(n))))
 
 
+def lookup_tmu_bk(op: str, n: int, table: dict | None = None) -> int:
+    """K depth of the trailing-update product tiles (16 when untuned)."""
+    t = load() if table is None else table
+    e = t.get("nb", {}).get(f"{op}:{size_class(n)}")
+    return int(e.get("tmu_bk", 16)) if e else 16
+
+
 def lookup_wgs(op: str, prec: str, table: dict | None = None) -> int:
     t = load() if table is None else table
     e = t.get("batched", {}).get(f"{op}:{prec}")
@@ -83,9 +96,10 @@ def _time(fn, reps):
     return best
 
 
-def tune_nb(h, op: str, n: int, candidates=NB_CANDIDATES, reps: int = 2) -> dict:
+def tune_nb(h, op: str, n: int, candidates=NB_CANDIDATES, reps: int = 2, bks=BK_CANDIDATES) -> dict:
     """Time the ABFT factorization `op` of an order-n synthetic matrix for
-    every candidate block size; returns {"best": nb, "ms": {nb: ms}}."""
+    every candidate block size and product tile depth; returns {"best": nb,
+    "tmu_bk": bk, "ms": {"nb/bk": ms}}."""
     import torch
     from . import gen
     dev = h.device
@@ -99,23 +113,23 @@ def tune_nb(h, op: str, n: int, candidates=NB_CANDIDATES, reps: int = 2) -> dict
     for nb in candidates:
         if nb > n:
             continue
-
-        def run():
-            W.copy_(A0)
-            A = W.t()
-            if op == "potrf":
-                h.potrf(A, nb, report=rep, info=info, sync=False)
-            elif op == "getrf":
-                h.getrf(A, nb, ipiv=ipiv, report=rep, info=info, sync=False)
-            else:
-                h.geqrf(A, nb, tau=tau, report=rep, info=info, sync=False)
-        run()
-        torch.cuda.synchronize()
-        res[nb] = _time(run, reps)
+        for bk in bks:
+            def run():
+                W.copy_(A0)
+                A = W.t()
+                if op == "potrf":
+                    h.potrf(A, nb, report=rep, info=info, sync=False, tmu_bk=bk)
+                elif op == "getrf":
+                    h.getrf(A, nb, ipiv=ipiv, report=rep, info=info, sync=False, tmu_bk=bk)
+                else:
+                    h.geqrf(A, nb, tau=tau, report=rep, info=info, sync=False, tmu_bk=bk)
+            run()
+            torch.cuda.synchronize()
+            res[(nb, bk)] = _time(run, reps)
     del A0, W
     torch.cuda.empty_cache()
     best = min(res, key=res.get)
-    return {"best": int(best), "ms": {str(k): v for k, v in res.items()}}
+    return {"best": int(best[0]), "tmu_bk": int(best[1]), "ms": {f"{k[0]}/{k[1]}": v for k, v in res.items()}}
 
 
 def tune_batched(h, op: str, prec: str, count: int = 2048, candidates=WGS_CANDIDATES, reps: int = 3) -> dict:
@@ -171,7 +185,7 @@ def main(argv=None):
         for n in [int(x) for x in args.sizes.split(",") if x]:
             r = tune_nb(h, op, n, cands)
             table.setdefault("nb", {})[f"{op}:{size_class(n)}"] = dict(r, n=n)
-            print(f"[autotune] {op} n={n}: best nb={r['best']}  {r['ms']}", flush=True)
+            print(f"[autotune] {op} n={n}: best nb={r['best']} tmu_bk={r['tmu_bk']}  {r['ms']}", flush=True)
             save(table, args.out)
     if args.batched:
         for op in ("potrf", "getrf"):

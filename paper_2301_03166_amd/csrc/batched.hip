@@ -212,23 +212,38 @@ __device__ void batch_carry(const T* A, int64_t lda, int n, int k, int w, const 
 
 // trailing update A[c1:n, c1:n] -= X Y, X = rows of the LDS panel below the
 // diagonal block, Y = U12 (staged chunk by chunk) or X^T (Cholesky, lower
-// part only).  16 x 16 threads, each with a 4 x 4 register tile of a 64 x 64
-// output block; the C values of the next two blocks of a column of blocks
-// are read ahead while the current one is computed.
+// part only), on the matrix cores: per 64 x 64 output block each of the four
+// waves computes a 32 x 32 quadrant as 2 x 2 tiles of 16 x 16 MFMA products
+// over K = w in steps of 4 (binary64: v_mfma_f64_16x16x4, binary32:
+// v_mfma_f32_16x16x4).  The operand roles are swapped (the MFMA's first
+// operand is the Y side) so that the product is the transposed block and a
+// register holds one column of it: sixteen lanes then read and write sixteen
+// consecutive rows.  The block's C values are read before its products.
+typedef double bf64x4 __attribute__((ext_vector_type(4)));
+typedef float bf32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  typedef bf64x4 V;
+  __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // column (within the 16-wide tile) of register r in lane group kl
+  __device__ static int col(int r, int kl) { return 4 * r + kl; }
+};
+template <>
+struct MfmaAcc<float> {
+  typedef bf32x4 V;
+  __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int col(int r, int kl) { return 4 * kl + r; }
+};
+
 template <typename T, int CHOL>
 __device__ void batch_tmu(T* A, int64_t lda, int n, int c0, int w, const T* P, int ldp, T* Uc) {
+  typedef MfmaAcc<T> M;
   const int c1 = c0 + w, m = n - c1;
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv & 1, wn = wv >> 1;
+  const int il = lane & 15, kl = lane >> 4;
   auto inside = [&](int i, int jj) { return i < m && jj < m && (!CHOL || i >= jj); };
-  auto load_c = [&](int ib, int jb, T(&cv)[4][4]) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int i = ib + tr + 16 * a, jj = jb + tc + 16 * b;
-        cv[a][b] = inside(i, jj) ? A[(c1 + i) + (int64_t)(c1 + jj) * lda] : (T)0;
-      }
-  };
   for (int jb = 0; jb < m; jb += 64) {
     const int jn = min(64, m - jb);
     if (!CHOL) {
@@ -239,50 +254,52 @@ __device__ void batch_tmu(T* A, int64_t lda, int n, int c0, int w, const T* P, i
       }
       __syncthreads();
     }
-    const int ib0 = CHOL ? jb : 0;
-    T c_n1[4][4], c_n2[4][4];
-    load_c(ib0, jb, c_n1);
-    if (ib0 + 64 < m) load_c(ib0 + 64, jb, c_n2);
-    for (int ib = ib0; ib < m; ib += 64) {
-      T cv[4][4];
+    for (int ib = CHOL ? jb : 0; ib < m; ib += 64) {
+      const int r0 = ib + wm * 32, q0 = jb + wn * 32;  // this wave's quadrant (rows, columns of the trailing matrix)
+      if (CHOL && r0 + 31 < q0) continue;            // strictly above the diagonal
+      T cv[2][2][4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          cv[a][b] = c_n1[a][b];
-          c_n1[a][b] = c_n2[a][b];
-        }
-      if (ib + 128 < m) load_c(ib + 128, jb, c_n2);
-      T acc[4][4];
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+          for (int r = 0; r < 4; ++r) {
+            const int i = r0 + 16 * a + il, jj = q0 + 16 * b + M::col(r, kl);
+            cv[b][a][r] = inside(i, jj) ? A[(c1 + i) + (int64_t)(c1 + jj) * lda] : (T)0;
+          }
+      typename M::V acc[2][2];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-      for (int p = 0; p < w; ++p) {
-        T xa[4], yb[4];
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          int i = ib + tr + 16 * a;
-          xa[a] = i < m ? P[(w + i) * ldp + p] : (T)0;
-        }
+        for (int a = 0; a < 2; ++a) acc[b][a] = typename M::V{0, 0, 0, 0};
+      for (int k0 = 0; k0 < w; k0 += 4) {
+        const int k = k0 + kl;
+        T xf[2], yf[2];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          int jj = tc + 16 * b;
-          if (CHOL) yb[b] = (jb + jj < m) ? P[(w + jb + jj) * ldp + p] : (T)0;
-          else yb[b] = Uc[p * 65 + jj];
+        for (int a = 0; a < 2; ++a) {
+          const int i = r0 + 16 * a + il;
+          xf[a] = (k < w && i < m) ? P[(w + i) * ldp + k] : (T)0;
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 2; ++b) {
+          const int jj = q0 + 16 * b + il;
+          if (CHOL) yf[b] = (k < w && jj < m) ? P[(w + jj) * ldp + k] : (T)0;
+          else yf[b] = k < w ? Uc[k * 65 + (jj - jb)] : (T)0;
+        }
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = acc[a][b] + xa[a] * yb[b];
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int a = 0; a < 2; ++a) acc[b][a] = M::mma(yf[b], xf[a], acc[b][a]);
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          int i = ib + tr + 16 * a, jj = jb + tc + 16 * b;
-          if (inside(i, jj)) A[(c1 + i) + (int64_t)(c1 + jj) * lda] = cv[a][b] - acc[a][b];
-        }
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = r0 + 16 * a + il, jj = q0 + 16 * b + M::col(r, kl);
+            if (inside(i, jj)) A[(c1 + i) + (int64_t)(c1 + jj) * lda] = cv[b][a][r] - (T)acc[b][a][r];
+          }
     }
   }
   __syncthreads();

@@ -324,18 +324,28 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, 
   const int64_t nt = tri ? tM * (tM + 1) / 2 : tM * tN;
   if (nt > 0x7fffffff) return 0;
   const dim3 grid((unsigned)nt, (unsigned)S), block(256);
-#define DG_LAUNCH(TA_, TB_, FA_, LO_, TRI_, RO_)                                                                  \
-  hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, TRI_, RO_, 16>), grid, block, 0, s, m, n, k, alpha, A, lda, B, ldb, \
+#define DG_LAUNCH(TA_, TB_, FA_, LO_, TRI_, RO_, BK_)                                                             \
+  hipLaunchKernelGGL((k_dgemm<TA_, TB_, FA_, LO_, TRI_, RO_, BK_>), grid, block, 0, s, m, n, k, alpha, A, lda, B, ldb, \
                      beta, C, ldc, doff, kc, ws)
 #define DG_CASE(TA_, TB_, FA_, LO_)                                                                              \
   if (ta == TA_ && tb == TB_ && modes == FA_ && lower == LO_) {                                                    \
     if (LO_ && tri) {                                                                                              \
-      if (role) DG_LAUNCH(TA_, TB_, FA_, LO_, LO_, 1); else DG_LAUNCH(TA_, TB_, FA_, LO_, LO_, 0);                 \
+      if (role) DG_LAUNCH(TA_, TB_, FA_, LO_, LO_, 1, 16); else DG_LAUNCH(TA_, TB_, FA_, LO_, LO_, 0, 16);         \
     } else {                                                                                                       \
-      if (role) DG_LAUNCH(TA_, TB_, FA_, LO_, 0, 1); else DG_LAUNCH(TA_, TB_, FA_, LO_, 0, 0);                     \
+      if (role) DG_LAUNCH(TA_, TB_, FA_, LO_, 0, 1, 16); else DG_LAUNCH(TA_, TB_, FA_, LO_, 0, 0, 16);             \
     }                                                                                                              \
     return hipGetLastError() == hipSuccess ? 1 : ABFT_ERR_HIP;                                                     \
   }
+  // trailing-update products with 32-deep K tiles (role 2; split-K launches keep 16)
+#define DG_CASE32(TA_, TB_, FA_, LO_)                                                                            \
+  if (role == 2 && S == 1 && ta == TA_ && tb == TB_ && modes == FA_ && lower == LO_) {                           \
+    if (LO_ && tri) DG_LAUNCH(TA_, TB_, FA_, LO_, LO_, 1, 32); else DG_LAUNCH(TA_, TB_, FA_, LO_, 0, 1, 32);       \
+    return hipGetLastError() == hipSuccess ? 1 : ABFT_ERR_HIP;                                                     \
+  }
+  DG_CASE32(0, 0, 0, 0)
+  DG_CASE32(0, 1, 0, 1)
+  DG_CASE32(1, 0, 1, 0)
+  DG_CASE32(0, 0, 1, 0)
   DG_CASE(0, 0, 0, 0)  // C -= L21 U12 (LU), TRSM block updates
   DG_CASE(0, 1, 0, 1)  // C -= L21 L21^T, lower part (Cholesky)
   DG_CASE(0, 1, 0, 0)  // X Y^T
@@ -350,6 +360,7 @@ int dgemm_fast(hipStream_t s, int ta, int tb, int fa, int fb, int lower, int m, 
   DG_CASE(1, 0, 8, 0)  // V1^T V2, V2 unit lower (QR T merge)
   DG_CASE(1, 0, 6, 0)  // |V|^T |R| (QR panel check)
 #undef DG_CASE
+#undef DG_CASE32
 #undef DG_LAUNCH
   return 0;
 }

@@ -355,6 +355,7 @@ int check_opts(const abft_opts* o, int64_t n, int& nb, int& protect, double& ts)
   ts = o->tau_scale > 0 ? o->tau_scale : 4.0;
   if (nb < 1 || nb > MAXNB) return -7;
   if (protect < ABFT_PROTECT_NONE || protect > ABFT_PROTECT_FULL) return -7;
+  if (o->tmu_bk != 0 && o->tmu_bk != 16 && o->tmu_bk != 32) return -7;
   if (o->levels) {
     const int64_t N = (n + nb - 1) / nb;
     if (o->nlevels < N) return -7;
@@ -373,6 +374,9 @@ inline bool any_protected(const abft_opts* o, int N, int protect) {
     if (o->levels[k]) return true;
   return false;
 }
+// role of the trailing-update product launches: 1 = 128 x 128 x 16 tiles
+// (two workgroups per CU), 2 = 128 x 128 x 32 tiles (one per CU)
+inline int tmu_role(const abft_opts* o) { return o->tmu_bk == 32 ? 2 : 1; }
 inline bool has_operand_faults(const abft_opts* o) {
   for (int q = 0; q < (o->faults ? o->nfaults : 0); ++q)
     if (o->faults[q].target == 3 || o->faults[q].target == 4) return true;
@@ -621,6 +625,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
   const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
   const int rnd = op_rnd(prec);
   const bool opf = has_operand_faults(opts);
+  const int trole = tmu_role(opts);  // the trailing-update product's launches (and their tile depth)
   Prof pf(h, opts);
   // (nothing to overlap without checksums; operand faults need the update
   // product and the carry in order)
@@ -669,7 +674,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     }
     if (opf) TRY(apply_operand_faults<T>(s, opts, k, dA, lda, n, nullptr, 0, c1));
     t = pf.begin(PH_TMU);
-    TRY(gemmT(s, prec, 0, 1, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
+    TRY(gemmT(s, prec, 0, 1, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0, trole));
     pf.end(t);
     if (opf) TRY(apply_operand_faults<T>(s, opts, k, dA, lda, n, nullptr, 0, c1));
     pf.tmu_flops += (double)m * (double)(m + 1) * kw;
@@ -714,6 +719,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
   const double tsu = ts * u, tsu_p = 2.0 * ts * u * sqrt((double)nb);
   const int rnd = op_rnd(prec);
   const bool opf = has_operand_faults(opts);
+  const int trole = tmu_role(opts);  // the trailing-update product's launches (and their tile depth)
   // (the look-ahead moves the work to the update stream when on)
   Look la(h, opts, !opf, n, nb, (int)((144 * 1024) / ((LEAFW + 1) * sizeof(T))));
   hipStream_t s = h->stream;
@@ -801,7 +807,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       // the next panel's block column first: update, carry (joined), verify
       const int64_t c2 = std::min<int64_t>(n, c1 + nb);
       const int kw2 = (int)(c2 - c1);
-      TRY(gemmT(s, prec, 0, 0, 0, (int)m, kw2, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
+      TRY(gemmT(s, prec, 0, 0, 0, (int)m, kw2, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, trole));
       TRY(side.join());
       if (lev) {
         TRY(verify_tiles<T>(s, dA, lda, n, c2, nb, k + 1, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
@@ -823,7 +829,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       TRY(prc);
       if (c2 < n) {
         TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)(n - c2), kw, -1.0, L21, lda, U12 + (int64_t)kw2 * lda, lda, 1.0,
-                  dA + c1 + c2 * lda, lda, 0, 1));
+                  dA + c1 + c2 * lda, lda, 0, trole));
         if (lev) {
           TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 2, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                               w.tflags, drep, k, lev));
@@ -835,7 +841,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
       continue;
     }
     t = pf.begin(PH_TMU);
-    TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, 1));
+    TRY(gemmT(s, prec, 0, 0, 0, (int)m, (int)m, kw, -1.0, L21, lda, U12, lda, 1.0, dA + c1 + c1 * lda, lda, 0, trole));
     pf.end(t);
     if (opf) TRY(apply_operand_faults<T>(s, opts, k, dA, lda, n, nullptr, 0, c1));
     pf.tmu_flops += 2.0 * (double)m * (double)m * kw;
@@ -1249,6 +1255,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   const int ldc = 2 * N;
   const double tsu = ts * U64, tsu_p = 2.0 * ts * U64 * sqrt((double)nb);
   const bool opf = has_operand_faults(opts);
+  const int trole = tmu_role(opts);  // the trailing-update product's launches (and their tile depth)
   // (the look-ahead moves the work to the update stream when on)
   Look la(h, opts, !opf, n, nb, (int)((140 * 1024) / ((LEAFW + 1) * sizeof(double))));
   hipStream_t s = h->stream;
@@ -1300,7 +1307,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     int S = 0;
     t = pf.begin(PH_TMU);
     TRY(gemm64(s, 1, 0, 1, 0, 0, kw, (int)m, (int)(n - c0), 1.0, V, lda, C, lda, 0.0, w.W, nb, 0, 0, 0, 0, w.splitk,
-               w.splitk_n, 1, &S));
+               w.splitk_n, trole, &S));
     pf.end(t);
     if (S > 1) TRY(splitk_reduce(s, w.splitk, S, kw, (int)m, 0.0, w.W, nb));
     TRY(gemm64(s, 1, 0, 0, 0, 0, kw, (int)m, kw, 1.0, w.Tfac, nb, w.W, nb, 0.0, w.W2, nb, 0));
@@ -1319,7 +1326,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
       const int64_t c2 = std::min<int64_t>(n, c1 + nb);
       const int kw2 = (int)(c2 - c1);
       TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), kw2, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0, 0, 0, 0, nullptr, 0,
-                 1));
+                 trole));
       if (fork) {
         TRY(side.join());
       } else if (lev) {
@@ -1343,7 +1350,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
       TRY(prc);
       if (c2 < n) {
         TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)(n - c2), kw, -1.0, V, lda, w.W2 + (int64_t)kw2 * nb, nb, 1.0,
-                   C + (int64_t)kw2 * lda, lda, 0, 0, 0, 0, nullptr, 0, 1));
+                   C + (int64_t)kw2 * lda, lda, 0, 0, 0, 0, nullptr, 0, trole));
         if (lev) {
           TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k, k + 2, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                                    w.tflags, drep, k, lev));
@@ -1356,7 +1363,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     }
     t = pf.begin(PH_TMU);
     TRY(gemm64(s, 0, 0, 1, 0, 0, (int)(n - c0), (int)m, kw, -1.0, V, lda, w.W2, nb, 1.0, C, lda, 0, 0, 0, 0, nullptr,
-               0, 1));
+               0, trole));
     pf.end(t);
     if (opf) TRY(apply_operand_faults<double>(s, opts, k, dA, lda, n, w.W2, nb, c1));
     pf.tmu_flops += 4.0 * (double)(n - c0) * (double)m * kw;

@@ -85,3 +85,28 @@ def test_lookahead_mixed_precision_matches_one_stream(h, chol):
     assert ir1.converged and ir2.converged and ir1.iters == ir2.iters
     assert torch.equal(x1, x2)
     assert rep1.status == rep2.status == 0
+
+
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
+def test_product_tile_depth_bitwise(h, kind):
+    """The trailing-update product with 32-deep K tiles against the default
+    16-deep ones: the same MFMA products in the same K order, so the factors
+    and reports are equal bitwise."""
+    n, nb = 1800, 256
+    A = gen.spd(n, 5) if kind == "chol" else gen.general(n, seed=5)
+    outs = []
+    for bk in (0, 32):
+        d = dev(A)
+        if kind == "chol":
+            info, rep = h.potrf(d, nb, tmu_bk=bk)
+            aux = None
+        elif kind == "lu":
+            aux, info, rep = h.getrf(d, nb, tmu_bk=bk)
+        else:
+            aux, info, rep = h.geqrf(d, nb, tmu_bk=bk)
+        assert info == 0 and clean(rep)
+        outs.append((d.cpu().numpy(), None if aux is None else aux.cpu().numpy(), rep.max_ratio))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    if kind != "chol":
+        assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
