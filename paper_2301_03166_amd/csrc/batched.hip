@@ -89,24 +89,56 @@ __device__ __forceinline__ float fms_b<float>(float a, float b, float c) {
   return __fmaf_rn(-b, c, a);
 }
 
+typedef double bf64x4 __attribute__((ext_vector_type(4)));
+typedef float bf32x4 __attribute__((ext_vector_type(4)));
+
+// A small FP64 product on the matrix cores, D (R x C) = sum_k a(r, k) b(k, c)
+// for k < K, with its magnitude twin Dm = sum_k |a|(r, k) |b|(k, c): 16 x 16
+// output tiles dealt to the workgroup's four waves, K in steps of 4
+// (v_mfma_f64_16x16x4).  fa(r, k, v, vm) / fb(k, c, v, vm) return an operand
+// and its magnitude-side value (0 outside the bounds); epi(r, c, d, dm)
+// consumes each output inside R x C.
+template <typename FA, typename FB, typename EPI>
+__device__ void small_mma(int R, int C, int K, FA fa, FB fb, EPI epi) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, il = lane & 15, kl = lane >> 4;
+  const int tr = (R + 15) / 16, tc = (C + 15) / 16;
+  for (int t = wv; t < tr * tc; t += 4) {
+    const int r0 = (t % tr) * 16, q0 = (t / tr) * 16;
+    bf64x4 acc{0, 0, 0, 0}, accm{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      double a, am, b, bm;
+      fa(r0 + il, k0 + kl, a, am);
+      fb(k0 + kl, q0 + il, b, bm);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      accm = __builtin_amdgcn_mfma_f64_16x16x4f64(am, bm, accm, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = r0 + 4 * r + kl, j = q0 + il;  // D[i][j]: lane j + 16 (i % 4), register i / 4
+      if (i < R && j < C) epi(i, j, acc[r], accm[r]);
+    }
+  }
+}
+
 // checksum carry of the batched trailing update  A22 -= X Y  over tile-rows
 // and tile-columns > k: X rows (i >= c1) from the LDS panel P (row i - c0),
 // Y(p, j) from ymat (LU: U12 in A; Cholesky: the transpose of X).  The
 // per-tile-row sums of X (S, Sa), and for LU the per-tile-column sums of
-// U12 (Tm, Ta), are formed in the LDS block sl (2 x 2 BN x BNB doubles);
-// one thread per column then updates that column's checksums of every
-// tile-row (its Y column in registers), and one thread per row the row
-// checksums of every tile-column.  Sums are compensated, in index order.
+// U12 (Tm, Ta), are formed in the LDS block sl (2 x 2 BN x BNB doubles,
+// compensated, in index order); the carries themselves are the products
+// colchk -= S Y, gc = Sa |Y| and rowchk -= X T, gr = |X| Ta (T = S for
+// Cholesky's symmetric update) on the matrix cores, as in the blocked path.
 template <typename T, int CHOL>
 __device__ void batch_carry(const T* A, int64_t lda, int n, int k, int w, const T* P, int ldp, const BatchChk& c,
                             double* sl) {
   const int N = (n + BNB - 1) / BNB;
-  const int c0 = k * BNB, c1 = c0 + w;
+  const int c0 = k * BNB, c1 = c0 + w, m = n - c1;
   const int ldc = 2 * BN;
+  const int M = N - k - 1, R = 2 * M;  // checksum rows (columns) of the trailing tile-rows (tile-columns)
   double* Sl = sl;                 // [2I + e][p]
   double* Sal = sl + 2 * BN * BNB;  // magnitudes
   // S: sums of X over each tile-row I > k (compensated); Sa: |.|-sums
-  for (int e = threadIdx.x; e < (N - k - 1) * BNB; e += blockDim.x) {
+  for (int e = threadIdx.x; e < M * BNB; e += blockDim.x) {
     const int I = k + 1 + e / BNB, p = e % BNB;
     acc2 se{0, 0}, sw{0, 0};
     double sa = 0, swa = 0;
@@ -124,53 +156,44 @@ __device__ void batch_carry(const T* A, int64_t lda, int n, int k, int w, const 
     Sal[(2 * I + 1) * BNB + p] = swa;
   }
   __syncthreads();
+  const int q0 = 2 * (k + 1);  // first checksum row (column) of the trailing tiles
   // column side: colchk(2I+e, j) -= S(2I+e, :) y(:, j);  gc = Sa |y|
-  for (int j = c1 + threadIdx.x; j < n; j += blockDim.x) {
-    double y[BNB];
-#pragma unroll
-    for (int p = 0; p < BNB; ++p)
-      y[p] = p < w ? (CHOL ? (double)P[(j - c0) * ldp + p] : (double)A[(c0 + p) + (int64_t)j * lda]) : 0.0;
-    for (int I = CHOL ? max(k + 1, j / BNB) : k + 1; I < N; ++I) {
-      acc2 ue{0, 0}, uw{0, 0};
-      double ga = 0, gwa = 0;
-#pragma unroll
-      for (int p = 0; p < BNB; ++p) {
-        cfma(ue, -Sl[(2 * I) * BNB + p], y[p]);
-        cfma(uw, -Sl[(2 * I + 1) * BNB + p], y[p]);
-        ga += Sal[(2 * I) * BNB + p] * fabs(y[p]);
-        gwa += Sal[(2 * I + 1) * BNB + p] * fabs(y[p]);
-      }
-      double* ce = &c.colchk[2 * I + (int64_t)j * ldc];
-      acc2 o{ce[0], 0}, ow{ce[1], 0};
-      cmerge(o, ue);
-      cmerge(ow, uw);
-      ce[0] = cval(o);
-      ce[1] = cval(ow);
-      c.gc[2 * I + (int64_t)j * ldc] = ga;
-      c.gc[2 * I + 1 + (int64_t)j * ldc] = gwa;
-    }
-  }
+  small_mma(
+      R, m, w,
+      [&](int r, int p, double& v, double& vm) {
+        const bool in = r < R && p < w;
+        v = in ? Sl[(q0 + r) * BNB + p] : 0.0;
+        vm = in ? Sal[(q0 + r) * BNB + p] : 0.0;
+      },
+      [&](int p, int jj, double& v, double& vm) {
+        double y = 0.0;
+        if (p < w && jj < m)
+          y = CHOL ? (double)P[(c1 + jj - c0) * ldp + p] : (double)A[(c0 + p) + (int64_t)(c1 + jj) * lda];
+        v = y;
+        vm = fabs(y);
+      },
+      [&](int r, int jj, double d, double dm) {
+        const int I = k + 1 + r / 2, j = c1 + jj;
+        if (CHOL && I < j / BNB) return;  // (lower tiles only)
+        double* ce = &c.colchk[(q0 + r) + (int64_t)j * ldc];
+        *ce = *ce - d;
+        c.gc[(q0 + r) + (int64_t)j * ldc] = dm;
+      });
   __syncthreads();
   if (!CHOL) {
     // Tm: row sums of U12 over each tile-column J > k (the S block is free now)
-    for (int e = threadIdx.x; e < (N - k - 1) * BNB; e += blockDim.x) {
+    for (int e = threadIdx.x; e < M * BNB; e += blockDim.x) {
       const int J = k + 1 + e / BNB, p = e % BNB;
       acc2 se{0, 0}, sw{0, 0};
       double sa = 0, swa = 0;
       if (p < w) {
         const int j0 = J * BNB, jn = min(n, j0 + BNB) - j0;
-        double u[BNB];
-#pragma unroll
-        for (int t = 0; t < BNB; ++t) u[t] = t < jn ? (double)A[(c0 + p) + (int64_t)(j0 + t) * lda] : 0.0;
-#pragma unroll
-        for (int t = 0; t < BNB; ++t) {
-          if (t < jn) {
-            const double wj = (double)(t + 1);
-            cadd(se, u[t]);
-            cfma(sw, wj, u[t]);
-            sa += fabs(u[t]);
-            swa += wj * fabs(u[t]);
-          }
+        for (int t = 0; t < jn; ++t) {
+          const double u = (double)A[(c0 + p) + (int64_t)(j0 + t) * lda], wj = (double)(t + 1);
+          cadd(se, u);
+          cfma(sw, wj, u);
+          sa += fabs(u);
+          swa += wj * fabs(u);
         }
       }
       Sl[(2 * J) * BNB + p] = cval(se);
@@ -182,31 +205,25 @@ __device__ void batch_carry(const T* A, int64_t lda, int n, int k, int w, const 
   }
   // row side: rowchk(i, 2J+e) -= x(i, :) t(:, 2J+e);  gr = |x| t_abs
   // (t = S for Cholesky: the symmetric update, t = Tm for LU)
-  for (int i = c1 + threadIdx.x; i < n; i += blockDim.x) {
-    double x[BNB];
-#pragma unroll
-    for (int p = 0; p < BNB; ++p) x[p] = p < w ? (double)P[(i - c0) * ldp + p] : 0.0;
-    const int Jend = CHOL ? i / BNB + 1 : N;
-    for (int J = k + 1; J < Jend; ++J) {
-      acc2 ue{0, 0}, uw{0, 0};
-      double ga = 0, gwa = 0;
-#pragma unroll
-      for (int p = 0; p < BNB; ++p) {
-        cfma(ue, -x[p], Sl[(2 * J) * BNB + p]);
-        cfma(uw, -x[p], Sl[(2 * J + 1) * BNB + p]);
-        ga += fabs(x[p]) * Sal[(2 * J) * BNB + p];
-        gwa += fabs(x[p]) * Sal[(2 * J + 1) * BNB + p];
-      }
-      double* re = &c.rowchk[i + (int64_t)(2 * J) * BMAX];
-      acc2 o{re[0], 0}, ow{re[BMAX], 0};
-      cmerge(o, ue);
-      cmerge(ow, uw);
-      re[0] = cval(o);
-      re[BMAX] = cval(ow);
-      c.gr[i + (int64_t)(2 * J) * BMAX] = ga;
-      c.gr[i + (int64_t)(2 * J + 1) * BMAX] = gwa;
-    }
-  }
+  small_mma(
+      m, R, w,
+      [&](int ii, int p, double& v, double& vm) {
+        const double x = (ii < m && p < w) ? (double)P[(c1 + ii - c0) * ldp + p] : 0.0;
+        v = x;
+        vm = fabs(x);
+      },
+      [&](int p, int q, double& v, double& vm) {
+        const bool in = p < w && q < R;
+        v = in ? Sl[(q0 + q) * BNB + p] : 0.0;
+        vm = in ? Sal[(q0 + q) * BNB + p] : 0.0;
+      },
+      [&](int ii, int q, double d, double dm) {
+        const int i = c1 + ii, J = k + 1 + q / 2;
+        if (CHOL && J > i / BNB) return;
+        double* re = &c.rowchk[i + (int64_t)(q0 + q) * BMAX];
+        *re = *re - d;
+        c.gr[i + (int64_t)(q0 + q) * BMAX] = dm;
+      });
   __syncthreads();
 }
 
@@ -219,8 +236,6 @@ __device__ void batch_carry(const T* A, int64_t lda, int n, int k, int w, const 
 // operand is the Y side) so that the product is the transposed block and a
 // register holds one column of it: sixteen lanes then read and write sixteen
 // consecutive rows.  The block's C values are read before its products.
-typedef double bf64x4 __attribute__((ext_vector_type(4)));
-typedef float bf32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 struct MfmaAcc;
 template <>
