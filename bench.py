@@ -165,7 +165,8 @@ def fp64_legs(h, torch, dev, args, legs):
         A.copy_(pristine[k].t())
         e0, e1 = ev[k]
         e0.record()
-        kw = dict(protect=protect, report=reports[k], info=infos[k], sync=False, profile=prof)
+        kw = dict(protect=protect, report=reports[k], info=infos[k], sync=False, profile=prof,
+                  overlap=bool(args.overlap))
         if k == "chol":
             h.potrf(A, nb, **kw)
         elif k == "lu":
@@ -723,6 +724,8 @@ def main():
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--legs", default="chol,lu,qr")
+    ap.add_argument("--overlap", type=int, default=1,
+                    help="1: verify the trailing tiles beside the next panel (ABFT_FLAG_OVERLAP_VERIFY); 0: serially")
     ap.add_argument("--mp-n", type=int, default=16384)
     ap.add_argument("--mp-nb", type=int, default=512)
     ap.add_argument("--mp-kappas", default="1e2,1e6,1e10")

@@ -158,7 +158,7 @@ typedef struct {
    next panel decomposition runs concurrently with the rest of the update).
    With opts->lookahead > 0, an LU or QR factorization with uniform
    protection and no fault plan runs its work on two streams of the handle
-   restricted to disjoint sets of compute units (created on first use with
+   restricted to disjoint sets of compute units (created for the call with
    hipExtStreamCreateWithCUMask, default priority): the panel stream gets
    opts->lookahead units (raised to what the first panel's cooperative
    leaves need to hold its rows in LDS, at most half the device), the
@@ -172,14 +172,34 @@ typedef struct {
    cooperative leaves get the same shape on both (small panels), and to
    rounding otherwise.  It is off by default: on one MI355X the panel needs
    about a quarter of the device's LDS at n = 32768, and the update loses
-   more on the remaining units than the overlap saves (LU 879 -> 1032 ms,
-   QR 1358 -> 1647 ms with 64 panel units). */
+   more on the remaining units than the overlap saves (LU 883 -> 1063 ms,
+   QR 1342 -> 1631 ms with 64 panel units).  The two restricted streams are
+   created for the call and destroyed at its end. */
 
 /* opts.flags: ABFT_FLAG_PROFILE times the phases of the call with HIP
    events on the handle's stream, all work on that one stream (the call then
    waits for its own completion before returning); ABFT_FLAG_GRAPH lets the batched calls capture and
-   replay HIP graphs (see abft_potrf_batched). */
-enum { ABFT_FLAG_PROFILE = 1, ABFT_FLAG_GRAPH = 2 };
+   replay HIP graphs (see abft_potrf_batched).
+
+   ABFT_FLAG_OVERLAP_VERIFY (FP64 and binary32 blocked factorizations; the
+   paper's section "Design of ABFT-OC" schedules checksum verification
+   beside the panel decomposition): after each trailing update the tiles of
+   the next panel's block column are verified and corrected first, on the
+   handle's stream; the other trailing tiles are verified and corrected on a
+   second stream restricted to half of the compute units (created with
+   hipExtStreamCreateWithCUMask, default priority, for the call and
+   destroyed at its end: while such a stream exists other work on the
+   device runs slower) while the next panel is factored on the handle's
+   stream, and the handle's stream waits for them before the panel's
+   interchanges, checks and the next update.  When the handle's stream is
+   the null stream, the call's work runs on a non-blocking stream of the
+   handle ordered after the null stream on entry and before it on exit (the
+   restricted stream is a blocking stream).  The same tiles are verified
+   with the same sums, so the factors and the report equal those of the
+   serial schedule.  Ignored by profiled calls, calls with operand faults
+   and the look-ahead schedule.  On one MI355X at n = 32768, nb = 512: LU
+   883 -> 838 ms, QR 1342 -> 1303 ms. */
+enum { ABFT_FLAG_PROFILE = 1, ABFT_FLAG_GRAPH = 2, ABFT_FLAG_OVERLAP_VERIFY = 4 };
 
 /* Phase times of the last call made with ABFT_FLAG_PROFILE, with the
    algorithmic work of the timed trailing-update GEMMs and verify passes. */

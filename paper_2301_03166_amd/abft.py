@@ -125,7 +125,7 @@ def _ld(A):
     return max(lda, 1)
 
 
-FLAG_PROFILE, FLAG_GRAPH = 1, 2
+FLAG_PROFILE, FLAG_GRAPH, FLAG_OVERLAP_VERIFY = 1, 2, 4
 GEMM_LOWER, GEMM_UNIT_LOWER_A = 1, 2
 
 
@@ -139,16 +139,17 @@ def protect_level(protect):
 
 
 def make_opts(nb, protect=True, tau_scale=4.0, faults=None, profile=False, graph=False, wgs_per_cu=0, levels=None,
-              lookahead=0, tmu_bk=0):
+              lookahead=0, tmu_bk=0, overlap=False):
     """abft_opts plus the host arrays it points to (keep them alive for the call);
     lookahead: CUs of the look-ahead panel stream (<= 0: off); tmu_bk: K depth
-    of the trailing-update product tiles (0 / 16 / 32)"""
+    of the trailing-update product tiles (0 / 16 / 32); overlap: verify the
+    trailing tiles beside the next panel (ABFT_FLAG_OVERLAP_VERIFY)"""
     o = Opts()
     o.wgs_per_cu = int(wgs_per_cu)
     o.lookahead = int(lookahead)
     o.tmu_bk = int(tmu_bk)
     o.nb, o.protect, o.tau_scale = int(nb), protect_level(protect), float(tau_scale)
-    o.flags = (FLAG_PROFILE if profile else 0) | (FLAG_GRAPH if graph else 0)
+    o.flags = (FLAG_PROFILE if profile else 0) | (FLAG_GRAPH if graph else 0) | (FLAG_OVERLAP_VERIFY if overlap else 0)
     keep = []
     if faults:
         fa = (Fault * len(faults))()
@@ -241,13 +242,15 @@ class Handle:
 
     # ------------------------------------------------------------ factorizations
     def potrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True,
-              profile=False, levels=None, lookahead=0, tmu_bk=0):
+              profile=False, levels=None, lookahead=0, tmu_bk=0, overlap=True):
         """In-place Cholesky (lower) of column-major A; returns (info, Report) when sync.
         protect: True / False or a PROTECT_* level; levels: one PROTECT_* level per iteration;
         lookahead: compute units of the look-ahead panel stream (<= 0: one stream);
-        tmu_bk: K depth of the trailing-update product tiles (0 = 16, or 32)."""
+        tmu_bk: K depth of the trailing-update product tiles (0 = 16, or 32);
+        overlap: verify the trailing tiles beside the next panel (the default;
+        False: everything on the handle's stream)."""
         return self._factor(OP_POTRF, A, nb, protect, tau_scale, faults, report, info, sync, profile=profile,
-                            levels=levels, lookahead=lookahead, tmu_bk=tmu_bk)
+                            levels=levels, lookahead=lookahead, tmu_bk=tmu_bk, overlap=overlap)
 
     def potrf_noalloc(self, A, nb, protect=True, tau_scale=4.0, faults=None, report=None, info=None, sync=True):
         """abft_potrf_noalloc: the Cholesky of potrf with the library's built-in
@@ -270,21 +273,21 @@ class Handle:
         return int(inf.item()), self.read_report(rep)
 
     def getrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, ipiv=None, report=None, info=None, sync=True,
-              profile=False, levels=None, lookahead=0, tmu_bk=0):
+              profile=False, levels=None, lookahead=0, tmu_bk=0, overlap=True):
         torch = self.torch
         if ipiv is None:
             ipiv = torch.zeros(A.shape[0], dtype=torch.int32, device=self.device)
         out = self._factor(OP_GETRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=ipiv, profile=profile,
-                           levels=levels, lookahead=lookahead, tmu_bk=tmu_bk)
+                           levels=levels, lookahead=lookahead, tmu_bk=tmu_bk, overlap=overlap)
         return (ipiv,) + out if sync else ipiv
 
     def geqrf(self, A, nb, protect=True, tau_scale=4.0, faults=None, tau=None, report=None, info=None, sync=True,
-              profile=False, levels=None, lookahead=0, tmu_bk=0):
+              profile=False, levels=None, lookahead=0, tmu_bk=0, overlap=True):
         torch = self.torch
         if tau is None:
             tau = torch.zeros(A.shape[0], dtype=torch.float64, device=self.device)
         out = self._factor(OP_GEQRF, A, nb, protect, tau_scale, faults, report, info, sync, aux=tau, profile=profile,
-                           levels=levels, lookahead=lookahead, tmu_bk=tmu_bk)
+                           levels=levels, lookahead=lookahead, tmu_bk=tmu_bk, overlap=overlap)
         return (tau,) + out if sync else tau
 
     def profile(self):
@@ -306,7 +309,7 @@ class Handle:
         return {ph: [buf[q * cap + k] for k in range(cap)] for q, ph in enumerate(self.ITER_PHASES)}
 
     def _factor(self, op, A, nb, protect, tau_scale, faults, report, info, sync, aux=None, profile=False, levels=None,
-                lookahead=0, tmu_bk=0):
+                lookahead=0, tmu_bk=0, overlap=True):
         torch = self.torch
         n = A.shape[0]
         if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
@@ -319,7 +322,7 @@ class Handle:
             if tmu_bk == 0:
                 tmu_bk = autotune.lookup_tmu_bk(name, n)
         opts, keep = make_opts(nb, protect, tau_scale, faults, profile, levels=levels, lookahead=lookahead,
-                               tmu_bk=tmu_bk)
+                               tmu_bk=tmu_bk, overlap=overlap)
         ws, wbytes = self.workspace(op, n, opts)
         rep = report if report is not None else self.new_report()
         inf = info if info is not None else torch.zeros(1, dtype=torch.int32, device=self.device)

@@ -49,6 +49,13 @@ struct abft_handle_s {
   hipStream_t la_main, la_panel;
   int la_pcus;
   hipEvent_t la_ev[4];
+  // verification beside the next panel: a stream restricted to part of the
+  // compute units (created on first use)
+  hipStream_t vb;
+  hipEvent_t vb_ev[2];
+  // non-blocking stream for overlapped calls made on the null stream
+  hipStream_t own;
+  hipEvent_t own_ev[2];
 };
 
 // a call's workspace: its own, else the one registered with the handle
@@ -277,6 +284,8 @@ struct Look {
       return ABFT_ERR_HIP;
     return 0;
   }
+  // (the restricted streams live for one call, as the verification stream
+  // beside the panel does: their existence slows other work on the device)
   int finish() {
     if (!on) return 0;
     on = false;
@@ -284,9 +293,122 @@ struct Look {
     if (join_panel()) return ABFT_ERR_HIP;
     if (hipEventRecord(h->la_ev[3], ms) != hipSuccess || hipStreamWaitEvent(caller, h->la_ev[3], 0) != hipSuccess)
       return ABFT_ERR_HIP;
+    (void)hipStreamDestroy(h->la_main);
+    (void)hipStreamDestroy(h->la_panel);
+    h->la_main = h->la_panel = nullptr;
+    h->la_pcus = 0;
     return 0;
   }
   ~Look() { (void)finish(); }
+};
+
+// Verification beside the next panel (ABFT_FLAG_OVERLAP_VERIFY).  After the
+// trailing update of iteration k, the tiles of the next panel's block column
+// are verified and corrected on the caller's stream; the other trailing
+// tiles are verified and corrected on a stream restricted to half of the
+// compute units, while the next panel is factored on the caller's stream
+// (the panel reads and writes only its own block column, and its
+// cooperative leaves find the other half free).  join() comes before
+// anything else touches the trailing matrix or its checksums.  The
+// restricted stream is created for each call and destroyed at its end.
+int vb_stream(abft_handle h) {
+  if (h->vb) return 0;
+  const int words = (h->cus + 31) / 32;
+  uint32_t mm[16] = {0};
+  if (words > 16 || h->cus < 2) return ABFT_ERR_UNSUPPORTED;
+  for (int c = 0; c < h->cus / 2; ++c) mm[c / 32] |= 1u << (c % 32);
+  for (int i = 0; i < 2; ++i)
+    if (!h->vb_ev[i] && hipEventCreateWithFlags(&h->vb_ev[i], hipEventDisableTiming) != hipSuccess) {
+      h->vb_ev[i] = nullptr;
+      return ABFT_ERR_HIP;
+    }
+  if (hipExtStreamCreateWithCUMask(&h->vb, words, mm) != hipSuccess) {
+    h->vb = nullptr;
+    return ABFT_ERR_HIP;
+  }
+  return 0;
+}
+
+// A call that overlaps work on the restricted stream runs off the null
+// stream: the restricted stream is a blocking stream, so every launch on
+// the null stream would wait for its work.  When the handle's stream is the
+// null stream, the call's work goes to a non-blocking stream of the handle,
+// ordered after the null stream's earlier work on entry, and the null
+// stream waits for it on exit.
+struct OffNull {
+  abft_handle h;
+  bool on = false;
+  OffNull(abft_handle hh, const abft_opts* o, bool allowed = true) : h(hh) {
+    if (!allowed || h->stream || !(o->flags & ABFT_FLAG_OVERLAP_VERIFY) || (o->flags & ABFT_FLAG_PROFILE) || o->lookahead > 0)
+      return;
+    if (!h->own) {
+      if (hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking) != hipSuccess) {
+        h->own = nullptr;
+        return;
+      }
+      for (int i = 0; i < 2; ++i)
+        if (hipEventCreateWithFlags(&h->own_ev[i], hipEventDisableTiming) != hipSuccess) return;
+    }
+    if (hipEventRecord(h->own_ev[0], nullptr) != hipSuccess || hipStreamWaitEvent(h->own, h->own_ev[0], 0) != hipSuccess)
+      return;
+    h->stream = h->own;
+    on = true;
+  }
+  ~OffNull() {
+    if (!on) return;
+    h->stream = nullptr;
+    if (hipEventRecord(h->own_ev[1], h->own) != hipSuccess || hipStreamWaitEvent(nullptr, h->own_ev[1], 0) != hipSuccess)
+      (void)hipStreamSynchronize(h->own);  // (the caller must still find the work done after its stream)
+  }
+};
+
+struct Beside {
+  abft_handle h;
+  hipStream_t main, s = nullptr;
+  hipEvent_t fe = nullptr, je = nullptr;
+  bool want = false, pending = false;
+  Beside(abft_handle hh, const abft_opts* o, bool allowed) : h(hh), main(hh->stream) {
+    want = allowed && (o->flags & ABFT_FLAG_OVERLAP_VERIFY) && !(o->flags & ABFT_FLAG_PROFILE) && o->lookahead <= 0;
+  }
+  // true when the rest of the trailing matrix can go to the restricted
+  // stream (created on the first such use in the call; without it the
+  // call verifies everything on the caller's stream)
+  bool ready() {
+    if (!want) return false;
+    if (!s) {
+      if (vb_stream(h)) {
+        want = false;
+        return false;
+      }
+      s = h->vb;
+      fe = h->vb_ev[0];
+      je = h->vb_ev[1];
+    }
+    return true;
+  }
+  // the restricted stream starts after everything enqueued on the main stream so far
+  int fork() {
+    pending = true;
+    if (hipEventRecord(fe, main) != hipSuccess || hipStreamWaitEvent(s, fe, 0) != hipSuccess) return ABFT_ERR_HIP;
+    return 0;
+  }
+  // the main stream continues after the restricted stream's work
+  int join() {
+    if (!pending) return 0;
+    pending = false;
+    if (hipEventRecord(je, s) != hipSuccess || hipStreamWaitEvent(main, je, 0) != hipSuccess) return ABFT_ERR_HIP;
+    return 0;
+  }
+  // the restricted stream lives for one call: while a stream restricted to
+  // part of the device exists, other work on the device was measured to run
+  // slower (LU at n = 32768: 880 -> 990 ms)
+  ~Beside() {
+    (void)join();
+    if (s) {
+      (void)hipStreamDestroy(h->vb);
+      h->vb = nullptr;
+    }
+  }
 };
 
 // Workspace carve-up shared by the three factorizations.
@@ -615,6 +737,7 @@ inline int op_rnd(int prec) { return prec == ABFT_BF16 ? 1 : (prec == ABFT_F16 ?
 template <typename T>
 int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const abft_opts* opts, int nb, int protect,
                double ts, int prec, int32_t* dinfo, abft_report* drep, bool one_stream = false) {
+  OffNull off(h, opts, !one_stream);
   hipStream_t s = h->stream;
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
@@ -630,6 +753,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
   // (nothing to overlap without checksums; operand faults need the update
   // product and the carry in order)
   Side side(h, any_protected(opts, N, protect) && !pf.on && !one_stream && !opf);
+  Beside vb(h, opts, !pf.on && !one_stream && !opf);
   int t, prev = ABFT_PROTECT_NONE;
   for (int k = 0; k < N; ++k) {
     const int64_t c0 = (int64_t)k * nb;
@@ -638,6 +762,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     const int lev = level_at(opts, k, protect);
     pf.iters++;
     if (lev > prev) {  // a protected stretch starts from checksums of the data
+      TRY(vb.join());
       t = pf.begin(PH_VERIFY);
       TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k, k, 1, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
                           nullptr, -1));
@@ -646,6 +771,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     prev = lev;
     t = pf.begin(PH_PANEL);
     TRY(chol_panel(s, dA, lda, n, c0, c1, dinfo));
+    TRY(vb.join());  // (the rest of the trailing matrix verified beside the panel)
     // the panel check only reads (the panel, its checksum rows, colchk of the
     // panel's columns): it goes to the side stream with the carry
     const bool fork = side.on && lev && c1 < n;
@@ -690,10 +816,22 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N, drep, frow, fcol));
     if (lev) {
       t = pf.begin(PH_VERIFY);
-      TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+      // with verification beside the next panel: that panel's block column
+      // here, the tiles right of it on the restricted stream
+      const int64_t c2 = std::min<int64_t>(n, c1 + nb);
+      const bool beside = c2 < n && vb.ready();
+      const int64_t ncv = beside ? c2 : n;
+      TRY(verify_tiles<T>(s, dA, lda, n, ncv, nb, k + 1, k + 1, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                           w.tflags, drep, k, lev, frow, fcol));
-      TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+      TRY(correct_tiles<T>(s, dA, lda, n, ncv, nb, k + 1, k + 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                            w.tflags, drep, k, lev));
+      if (beside) {
+        TRY(vb.fork());
+        TRY(verify_tiles<T>(vb.s, dA, lda, n, n, nb, k + 2, k + 2, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                            w.tflags, drep, k, lev, frow, fcol));
+        TRY(correct_tiles<T>(vb.s, dA, lda, n, n, nb, k + 2, k + 2, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                             w.tflags, drep, k, lev));
+      }
       pf.end(t);
       const double mt = (double)m / nb;
       pf.verify_bytes += (double)sizeof(T) * nb * nb * (mt * (mt + 1) / 2);
@@ -708,6 +846,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
 template <typename T>
 int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, const Ws& w, const abft_opts* opts,
                int nb, int protect, double ts, int prec, int32_t* dinfo, abft_report* drep) {
+  OffNull off(h, opts);
   TRY(report_init(h->stream, drep, dinfo));
   if (n == 0) return report_fini(h->stream, drep);
   TRY(fill_zero(h->stream, w.pflags, (size_t)((n + nb - 1) / nb) * sizeof(int)));
@@ -725,6 +864,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
   hipStream_t s = h->stream;
   Prof pf(h, opts);
   Side side(h, !pf.on && !opf);
+  Beside vb(h, opts, !pf.on && !opf && !la.on);
   int t, prev = ABFT_PROTECT_NONE;
   LuCtx<T> c{s, dA, lda, n, dipiv, dinfo, &w, 0u, drep, la.on ? la.mmaxg : std::min(h->cus, 256)};
   T* porig = (T*)w.porig;
@@ -736,6 +876,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
     const int lev = level_at(opts, k, protect);
     pf.iters++;
     if (lev > prev) {  // a protected stretch starts from checksums of the data
+      TRY(vb.join());
       t = pf.begin(PH_VERIFY);
       TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k, k, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu, nullptr,
                           nullptr, -1));
@@ -750,6 +891,7 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
           return ABFT_ERR_HIP;
       TRY(lu_panel(c, c0, c1));
     }
+    TRY(vb.join());  // (the rest of the trailing matrix verified beside the panel; the interchanges move its rows)
     TRY(perm_build(s, dipiv, c0, kw, n, w.moves));
     // the interchanges of the factored columns to the left and of the row
     // checksums go to the side stream with the carry (nothing before the
@@ -857,10 +999,20 @@ int getrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, int32_t* dipiv, con
     if (opts->faults) TRY(apply_faults<T>(s, opts, k, dA, lda, w, n, N, drep, frow, fcol));
     if (lev) {
       t = pf.begin(PH_VERIFY);
-      TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+      const int64_t c2 = std::min<int64_t>(n, c1 + nb);
+      const bool beside = c2 < n && vb.ready();
+      const int64_t ncv = beside ? c2 : n;
+      TRY(verify_tiles<T>(s, dA, lda, n, ncv, nb, k + 1, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                           w.tflags, drep, k, lev, frow, fcol));
-      TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 1, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+      TRY(correct_tiles<T>(s, dA, lda, n, ncv, nb, k + 1, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                            w.tflags, drep, k, lev));
+      if (beside) {
+        TRY(vb.fork());
+        TRY(verify_tiles<T>(vb.s, dA, lda, n, n, nb, k + 1, k + 2, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                            w.tflags, drep, k, lev, frow, fcol));
+        TRY(correct_tiles<T>(vb.s, dA, lda, n, n, nb, k + 1, k + 2, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                             w.tflags, drep, k, lev));
+      }
       pf.end(t);
       pf.verify_bytes += (double)sizeof(T) * (double)m * (double)m;
     }
@@ -1108,6 +1260,18 @@ int abft_destroy(abft_handle h) {
   }
   for (int i = 0; i < 4; ++i)
     if (h->la_ev[i]) (void)hipEventDestroy(h->la_ev[i]);
+  if (h->vb) {
+    if (hipStreamSynchronize(h->vb) != hipSuccess) rc = ABFT_ERR_HIP;
+    (void)hipStreamDestroy(h->vb);
+  }
+  if (h->own) {
+    if (hipStreamSynchronize(h->own) != hipSuccess) rc = ABFT_ERR_HIP;
+    (void)hipStreamDestroy(h->own);
+  }
+  for (int i = 0; i < 2; ++i)
+    if (h->own_ev[i]) (void)hipEventDestroy(h->own_ev[i]);
+  for (int i = 0; i < 2; ++i)
+    if (h->vb_ev[i]) (void)hipEventDestroy(h->vb_ev[i]);
   free(h->iter_ms);
   free(h);
   return rc;
@@ -1246,6 +1410,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   use_ws(h, dwork, work_bytes);
   Ws w = carve((char*)dwork, n, nb, ABFT_OP_GEQRF, sizeof(double));
   if (!dwork || work_bytes < w.bytes) return ABFT_ERR_WORKSPACE;
+  OffNull off(h, opts);
   TRY(report_init(h->stream, drep, dinfo));
   if (n == 0) return report_fini(h->stream, drep);
   TRY(fill_zero(h->stream, w.pflags, (size_t)((n + nb - 1) / nb) * sizeof(int)));
@@ -1262,6 +1427,7 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
   QrCtx c{s, dA, lda, n, dtau, &w, nb, 0, 0u, drep, la.on ? la.mmaxg : std::min(h->cus, 256)};
   Prof pf(h, opts);
   Side side(h, any_protected(opts, N, protect) && !pf.on && !opf);
+  Beside vb(h, opts, !pf.on && !opf && !la.on);
   int t, prev = ABFT_PROTECT_NONE;
   for (int k = 0; k < N; ++k) {
     const int64_t c0 = (int64_t)k * nb;
@@ -1270,15 +1436,18 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     const int lev = level_at(opts, k, protect);
     c.cb = c0;
     pf.iters++;
-    if (lev > prev)  // a protected stretch starts from checksums of the data
+    if (lev > prev) {  // a protected stretch starts from checksums of the data
+      TRY(vb.join());
       TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k, k, 0, 0, w.colchk, ldc, w.rowchk, n, nullptr, nullptr, tsu,
                                nullptr, nullptr, -1));
+    }
     prev = lev;
     t = pf.begin(PH_PANEL);
     if (!(la.on && k > 0)) {  // (with look-ahead, panel k was factored during iteration k - 1)
       TRY(fill_zero(s, w.Tfac, (size_t)nb * nb * sizeof(double)));
       TRY(qr_panel(c, c0, c1));
     }
+    TRY(vb.join());  // (the rest of the trailing matrix verified beside the panel)
     // the panel check reads the panel, T and colchk of the panel's columns
     // only: on the side stream it runs beside the trailing update
     auto check_k = [&](hipStream_t cs) -> int {
@@ -1379,10 +1548,20 @@ int abft_geqrf(abft_handle h, int64_t n, double* dA, int64_t lda, double* dtau, 
     if (opts->faults) TRY(apply_faults<double>(s, opts, k, dA, lda, w, n, N, drep, frow, fcol));
     if (lev) {
       t = pf.begin(PH_VERIFY);
-      TRY(verify_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+      const int64_t c2 = std::min<int64_t>(n, c1 + nb);
+      const bool beside = c2 < n && vb.ready();
+      const int64_t ncv = beside ? c2 : n;
+      TRY(verify_tiles<double>(s, dA, lda, n, ncv, nb, k, k + 1, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                                w.tflags, drep, k, lev, frow, fcol));
-      TRY(correct_tiles<double>(s, dA, lda, n, n, nb, k, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+      TRY(correct_tiles<double>(s, dA, lda, n, ncv, nb, k, k + 1, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
                                 w.tflags, drep, k, lev));
+      if (beside) {
+        TRY(vb.fork());
+        TRY(verify_tiles<double>(vb.s, dA, lda, n, n, nb, k, k + 2, 0, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr,
+                                 tsu, w.tflags, drep, k, lev, frow, fcol));
+        TRY(correct_tiles<double>(vb.s, dA, lda, n, n, nb, k, k + 2, 0, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                                  w.tflags, drep, k, lev));
+      }
       pf.end(t);
       pf.verify_bytes += 8.0 * (double)(n - c0) * (double)m;
     }
