@@ -346,9 +346,11 @@ class Handle:
 
     # ------------------------------------------------------------ mixed precision
     def gesv_mp(self, A, b, prec, nb=256, max_iter=30, chol=False, protect=True, tau_scale=4.0, faults=None,
-                x=None, report=None, ir=None, sync=True, profile=False, lookahead=0):
+                x=None, report=None, ir=None, sync=True, profile=False, lookahead=0, overlap=False):
         """Solve A x = b: binary32 factorization (trailing update in `prec`) + FP64 refinement,
-        or the FP64 factorization and direct solve when prec == F64.  Returns (x, IRReport, Report)."""
+        or the FP64 factorization and direct solve when prec == F64.  Returns (x, IRReport, Report).
+        overlap: the factorization verifies the trailing tiles beside the next panel (off by
+        default: at n = 16384 the restricted stream's creation per call costs what it saves)."""
         torch = self.torch
         n = A.shape[0]
         if A.shape[1] != n or A.dtype != torch.float64 or not A.is_cuda:
@@ -358,7 +360,7 @@ class Handle:
         if x is None:
             x = torch.zeros(n, dtype=torch.float64, device=self.device)
         op = OP_POSV_MP if chol else OP_GESV_MP
-        opts, keep = make_opts(nb, protect, tau_scale, faults, profile, lookahead=lookahead)
+        opts, keep = make_opts(nb, protect, tau_scale, faults, profile, lookahead=lookahead, overlap=overlap)
         ws, wbytes = self.workspace(op, n, opts)
         rep = report if report is not None else self.new_report()
         irb = ir if ir is not None else torch.zeros(C.sizeof(IRReport), dtype=torch.uint8, device=self.device)
