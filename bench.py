@@ -27,6 +27,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -416,7 +417,9 @@ def batched_faults(h, torch, gen, kind, dname, sizes, flat, pristine, views, sta
     tol = 1e-12 if dname == "f64" else 1e-5
     tally = {"flips": len(faults), "corrected": 0, "checksum_repaired": 0, "uncorrectable": 0,
              "undetected_harmless": 0, "undetected_corrupting": 0, "corrected_but_wrong": 0,
-             "other_matrices_changed": 0, "results_within_backward_error": 0}
+             "other_matrices_changed": 0, "results_within_backward_error": 0,
+             "significant_flips": 0, "significant_detected": 0, "subthreshold_flips": 0, "subthreshold_detected": 0,
+             "unverified_flips": 0, "max_undetected_delta_over_tau": 0.0}
     fset = {f["matrix"]: f for f in faults}
     for q, v in enumerate(views):
         rep = Report.from_buffer_copy(raw[q * rsz:(q + 1) * rsz])
@@ -444,6 +447,20 @@ def batched_faults(h, torch, gen, kind, dname, sizes, flat, pristine, views, sta
             tally["checksum_repaired"] += 1
         else:
             tally["undetected_harmless" if same else "undetected_corrupting"] += 1
+        # |delta| / tau of the flip against its column checksum's threshold
+        # (tau < 0: the flip was not verified), as in the fault campaign
+        detected = bool(rep.status & 7)
+        ratio = rep.fault_delta / rep.fault_tau if rep.fault_tau > 0 else (math.inf if rep.fault_tau == 0 else None)
+        if ratio is None:
+            tally["unverified_flips"] += 1
+        else:
+            sig = ratio > 1.0
+            tally["significant_flips" if sig else "subthreshold_flips"] += 1
+            tally["significant_detected" if sig else "subthreshold_detected"] += int(detected)
+            if not detected:
+                tally["max_undetected_delta_over_tau"] = max(tally["max_undetected_delta_over_tau"], ratio)
+    tally["significant_detected_pct"] = (100.0 * tally["significant_detected"] / tally["significant_flips"]
+                                         if tally["significant_flips"] else None)
     del clean
     log(f"batched {kind} {dname} faults: {tally}")
     return tally

@@ -328,11 +328,14 @@ __device__ void batch_tmu(T* A, int64_t lda, int n, int c0, int w, const T* P, i
 // with the carried checksums (thresholds from the magnitudes and the carried
 // magnitude bounds); a clean tile's checksums are refreshed from the sums.
 // Returns the number of flagged sums; *maxr gets the largest |d|/tau of the
-// clean comparisons.
+// clean comparisons.  (frow, fcol): an element planted by a fault plan in
+// this iteration (-1: none); the |d| and tau of the plain column checksum
+// that covers it go to rep.
 template <typename T>
 __device__ int wave_tile32(const T* A, int64_t lda, int I, int J, int h, int w, bool sym, int mode, double* colchk,
                            int ldc, double* rowchk, int ldr, const double* gc, const double* gr, double tsu,
-                           double* lds, double* maxr) {
+                           double* lds, double* maxr, int64_t frow = -1, int64_t fcol = -1,
+                           abft_report* rep = nullptr) {
   const int lane = threadIdx.x & 63;
   const int64_t r0 = (int64_t)I * BNB, c0 = (int64_t)J * BNB;
   double v[16];
@@ -381,6 +384,10 @@ __device__ int wave_tile32(const T* A, int64_t lda, int I, int J, int h, int w, 
     nfl = be + bw;
     if (!be && te > 0) mr = fmax(mr, fabs(de) / te);
     if (!bw && tw > 0) mr = fmax(mr, fabs(dw) / tw);
+    if (rep && col && c0 + x == fcol && frow >= r0 && frow < r0 + h) {
+      rep->fault_d = fabs(de);
+      rep->fault_tau = te;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -412,6 +419,7 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
   __shared__ int s_fail;
   __shared__ int s_nflag;
   __shared__ int s_flagged[BMAXFL];
+  __shared__ int64_t s_frow, s_fcol;  // element planted in this iteration (-1: none)
   if (tid == 0) {
     rep->flagged_tiles = rep->corrected = rep->checksum_repaired = rep->uncorrectable = rep->panel_flags = 0;
     rep->first_flag_iter = 0x7fffffff;
@@ -608,12 +616,15 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
     // ---- trailing update and checksum carry
     batch_tmu<T, CHOL>(A, lda, n, c0, w, P, ldp, Uc);
     if (protect) batch_carry<T, CHOL>(A, lda, n, k, w, P, ldp, c, reinterpret_cast<double*>(Uc));
-    // ---- planned faults of this matrix and iteration
-    if (tid == 0)
+    // ---- planned faults of this matrix and iteration (the last one planted
+    // is recorded: |new - old|, +Inf when either is not finite)
+    if (tid == 0) {
+      s_frow = s_fcol = -1;
       for (int f = 0; f < nfaults; ++f) {
         const abft_fault& F = faults[f];
         if (F.matrix != mi || F.iter != k || F.row < 0 || F.row >= n || F.col < 0 || F.col >= n) continue;
         T* p = A + F.row + (int64_t)F.col * lda;
+        const double before = (double)*p;
         if (sizeof(T) == 8) {
           unsigned long long u = (unsigned long long)__double_as_longlong((double)*p) ^ (1ull << (F.bit & 63));
           *p = (T)__longlong_as_double((long long)u);
@@ -621,7 +632,12 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
           unsigned u = __float_as_uint((float)*p) ^ (1u << (F.bit & 31));
           *p = (T)__uint_as_float(u);
         }
+        const double d = fabs((double)*p - before);
+        rep->fault_delta = (d <= 1.79e308) ? d : __builtin_inf();
+        s_frow = F.row;
+        s_fcol = F.col;
       }
+    }
     __syncthreads();
     // ---- verify (and correct) the trailing tiles
     if (protect) {
@@ -647,7 +663,7 @@ __device__ void factor_one(int mi, int n, T* A, int64_t lda, int32_t* ipiv, Batc
         J += k + 1;
         double mr;
         const int nfl = wave_tile32(A, lda, I, J, min(BNB, n - I * BNB), min(BNB, n - J * BNB), CHOL && I == J, 1,
-                                    c.colchk, ldc, c.rowchk, BMAX, c.gc, c.gr, tsu, wlds, &mr);
+                                    c.colchk, ldc, c.rowchk, BMAX, c.gc, c.gr, tsu, wlds, &mr, s_frow, s_fcol, rep);
         if (nfl) {
           if ((tid & 63) == 0) {
             const int slot = atomicAdd(&s_nflag, 1);
