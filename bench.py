@@ -664,6 +664,8 @@ def campaign_leg(h, torch, dev, args):
                         c["significant"] += 1
                         c["significant_detected"] += int(detected)
             del A0
+            if r % 100 == 99:
+                log(f"campaign {kind}: {r + 1} pairs")
         fr = max(1, tally["faulted_runs"])
         tally["detected_pct"] = 100.0 * (fr - tally["undetected"]) / fr
         tally["significant_detected_pct"] = (100.0 * tally["significant_detected"] / tally["significant_flips"]
@@ -733,7 +735,50 @@ def gemm_leg(h, torch, dev, args):
     return out
 
 
+def trace_summary(path):
+    """Compact summary of a rocprofv3 CSV (the raw traces are too large to
+    keep): for a kernel trace, per kernel (template arguments kept) and
+    stream the launch count, total and average duration, and the durations
+    of each trailing-update product launch (ROLE = 1 instances); for a
+    counter collection, per kernel and counter the dispatch count and the
+    summed value."""
+    import collections
+    import csv
+    import re
+    import statistics
+
+    def short(name):
+        m = re.search(r"(k_\w+)(<[^()]*?>)?", name)
+        return (m.group(1) + (m.group(2) or "")) if m else name[:60]
+
+    with open(path) as f:
+        rd = csv.DictReader(f)
+        if "Counter_Name" in (rd.fieldnames or []):
+            agg = collections.defaultdict(lambda: [0, 0.0])
+            for r in rd:
+                a = agg[(short(r["Kernel_Name"]), r["Counter_Name"])]
+                a[0] += 1
+                a[1] += float(r["Counter_Value"])
+            return {"counters": [{"kernel": k[0], "counter": k[1], "dispatches": v[0], "sum": v[1]}
+                                 for k, v in sorted(agg.items())]}
+        agg = collections.defaultdict(list)
+        first, last = None, 0
+        for r in rd:
+            a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            first = a if first is None else min(first, a)
+            last = max(last, b)
+            agg[(short(r["Kernel_Name"]), r["Stream_Id"])].append((b - a) / 1e6)
+    kern = sorted(({"kernel": k[0], "stream": k[1], "calls": len(v), "total_ms": sum(v), "avg_ms": statistics.mean(v)}
+                   for k, v in agg.items()), key=lambda x: -x["total_ms"])
+    tmu = {f"{k[0]} stream {k[1]}": v for k, v in agg.items()
+           if k[0].startswith("k_dgemm<") and re.search(r", 1, (16|32)>$", k[0])}
+    return {"span_ms": (last - first) / 1e6 if first is not None else 0.0, "kernels": kern, "tmu_launch_ms": tmu}
+
+
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--trace-summary":
+        print(json.dumps(trace_summary(sys.argv[2])), flush=True)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)

@@ -5,7 +5,7 @@
   of them), so the Householder leaf adds its partial Gram rows in several
   exchange groups; at n = 4096, nb = 512 every QR iteration with at least
   1024 rows below the panel splits the long-K product W = V^T C over K.
-* The BASELINE-named small configurations: Cholesky n = 1024, nb = 128, and
+* The small configurations: Cholesky n = 1024, nb = 128, and
   the protected decompositions at n = 8192, nb = 256, once clean and once
   with a single-bit flip, against the oracle given the same fault plan.
 * Full size (n = 32768, nb = 512, the benchmark's launch configuration) and
