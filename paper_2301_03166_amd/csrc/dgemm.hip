@@ -269,8 +269,10 @@ __global__ __launch_bounds__(256, BK == 16 ? 2 : 1) void k_dgemm(int M, int N, i
           acc[ci][ri] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[ci], af[ri], acc[ci][ri], 0, 0, 0);
     }
     // the scheduler's MFMA / LDS-read interleave for one wave's GEMM loop
-    // (measured: +11% on the long-K V^T C product, +1% on the K = nb ones)
-    __builtin_amdgcn_iglp_opt(1);
+    // (measured with 16-deep steps: +11% on the long-K V^T C product, +1% on
+    // the K = nb ones; with 32-deep steps it cost 10-15%, so those keep the
+    // default schedule)
+    if constexpr (BK == 16) __builtin_amdgcn_iglp_opt(1);
   };
   for (int kt = 0; kt + 1 < KT; ++kt) {
     const int cur = kt & 1;
