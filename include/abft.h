@@ -20,11 +20,17 @@
  *     sized with abft_workspace_size().  `opts` and fault plans are host
  *     memory and are read before the call returns.
  *   - Calls are asynchronous on the handle's HIP stream.  Results, `dinfo`
- *     and the report become valid once the stream has been synchronized.
+ *     and the report become valid once the stream has been synchronized;
+ *     until then the caller must not touch dA, the workspace or the report.
  *     The blocked factorizations also use an internal side stream of the
- *     handle (created on first use, default priority) for work that only
- *     reads the panel; it is ordered after the caller's stream by an event
- *     and joined back before the call's last operation on that stream.
+ *     handle (created on first use, default priority) for LU's interchanges
+ *     of the already factored left columns of dA, the panel checks and the
+ *     checksum carries (it writes those columns, the checksum arrays of the
+ *     workspace and the report), and, with ABFT_FLAG_OVERLAP_VERIFY, a
+ *     stream restricted to half of the compute units that verifies and
+ *     corrects trailing tiles of dA (see below).  Both are ordered after
+ *     the caller's stream by events and joined back before the call's last
+ *     operation on that stream.
  *   - Return value: 0 on success; -i when argument i (1-based) is invalid;
  *     ABFT_ERR_HIP when a HIP call failed (launch or cooperative-launch
  *     error); ABFT_ERR_WORKSPACE when `work_bytes` is too small;

@@ -161,12 +161,15 @@ struct Prof {
   }
 };
 
-// The checksum carry of an iteration reads the panel operands (L21, U12 or
-// V, W2) and the checksum rows and writes only the checksum arrays, which
-// the trailing-matrix update never touches: it runs on a side stream,
-// concurrently with the update's product, and the main stream waits for it
-// before the verification.  Profiled calls keep one stream so that each
-// phase's events time that phase alone.
+// The side stream of an iteration runs what the trailing-matrix update's
+// product neither reads nor writes: the checksum carry (it reads the panel
+// operands L21, U12 or V, W2 and the checksum rows, and writes the checksum
+// arrays), the panel checks (they read the panel and write the report and
+// the panel flags) and, for LU, the interchanges of the already factored
+// columns left of the panel and of the row checksums.  It runs concurrently
+// with the update's product, and the main stream waits for it before the
+// verification.  Profiled calls keep one stream so that each phase's
+// events time that phase alone.
 struct Side {
   hipStream_t main, s;
   bool on;
