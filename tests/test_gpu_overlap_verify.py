@@ -126,3 +126,30 @@ def test_overlap_large_vs_oracle(h, kind):
         oaux, _ = oracle.geqrf(O, nb)
         assert np.max(np.abs(aux - oaux)) < 1e-12
         assert np.linalg.norm(np.triu(F) - np.triu(O)) / np.linalg.norm(np.triu(O)) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
+def test_overlap_on_a_caller_stream(h, kind):
+    """A call made on a non-default stream (no detour through the handle's
+    own stream) orders the restricted stream's work after and before that
+    stream: same results as the serial schedule on the default stream."""
+    import torch
+    n, nb = 2600, 256
+    A = matrix(kind, n, 41)
+    ref = run(h, kind, A, nb, overlap=False)
+    st = torch.cuda.Stream()
+    d = dev(A)
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        if kind == "chol":
+            info, rep = h.potrf(d, nb, overlap=True)
+            aux = None
+        elif kind == "lu":
+            aux, info, rep = h.getrf(d, nb, overlap=True)
+        else:
+            aux, info, rep = h.geqrf(d, nb, overlap=True)
+    torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    F = d.cpu().numpy()
+    got = ((np.tril(F) if kind == "chol" else F), None if aux is None else aux.cpu().numpy(), info, rep)
+    same(got, ref)
