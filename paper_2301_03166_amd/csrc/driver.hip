@@ -344,13 +344,19 @@ struct OffNull {
   OffNull(abft_handle hh, const abft_opts* o, bool allowed = true) : h(hh) {
     if (!allowed || h->stream || !(o->flags & ABFT_FLAG_OVERLAP_VERIFY) || (o->flags & ABFT_FLAG_PROFILE) || o->lookahead > 0)
       return;
-    if (!h->own) {
-      if (hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking) != hipSuccess) {
-        h->own = nullptr;
+    if (!h->own) {  // (the stream and both events, or nothing: the call then stays on the null stream)
+      hipStream_t st = nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (hipEventCreateWithFlags(&e0, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess ||
+          hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
         return;
       }
-      for (int i = 0; i < 2; ++i)
-        if (hipEventCreateWithFlags(&h->own_ev[i], hipEventDisableTiming) != hipSuccess) return;
+      h->own = st;
+      h->own_ev[0] = e0;
+      h->own_ev[1] = e1;
     }
     if (hipEventRecord(h->own_ev[0], nullptr) != hipSuccess || hipStreamWaitEvent(h->own, h->own_ev[0], 0) != hipSuccess)
       return;
