@@ -179,10 +179,27 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, double alph
 __global__ void k_splitk_reduce(const double* __restrict__ P, int S, int M, int N, double beta, double* C,
                                 int64_t ldc) {
   const int64_t tot = (int64_t)M * N;
+  const bool narrow = tot <= 0x7fffffff;  // (32-bit index arithmetic)
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % M, j = e / M;
+    int64_t i, j;
+    if (narrow) {
+      const uint32_t jj = (uint32_t)e / (uint32_t)M;
+      j = jj;
+      i = (int64_t)((uint32_t)e - jj * (uint32_t)M);
+    } else {
+      j = e / M;
+      i = e - j * M;
+    }
+    // the partials in order, sixteen requested before the first is added
     double acc = 0.0;
-    for (int q = 0; q < S; ++q) acc += P[(int64_t)q * tot + e];
+    for (int q = 0; q < S; q += 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = q + u < S ? P[(int64_t)(q + u) * tot + e] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (q + u < S) acc += v[u];
+    }
     double* c = C + i + j * ldc;
     *c = (beta == 0.0) ? acc : beta * (*c) + acc;
   }
