@@ -13,6 +13,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+# the in-tree build; ABFT_LIB names another build of the same library
 LIB_PATH = os.environ.get("ABFT_LIB") or os.path.join(HERE, "libabft.so")
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
