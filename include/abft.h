@@ -152,8 +152,8 @@ typedef struct {
   int32_t nlevels;     /* entries of `levels` (0: none) */
   const int8_t* levels; /* host array, levels[k] = ABFT_PROTECT_* of iteration k (k < ceil(n/nb) <= nlevels),
                            overriding `protect` (FP64 blocked factorizations); NULL: `protect` everywhere */
-  int32_t lookahead;   /* LU and QR: compute units given to the look-ahead panel stream (<= 0: the
-                          one-stream schedule, the default; see below) */
+  int32_t lookahead;   /* blocked factorizations: compute units given to the look-ahead panel stream
+                          (<= 0: the one-stream schedule, the default; see below) */
   int32_t tmu_bk;      /* K depth of the trailing-update product's 128 x 128 tiles: 16 (0: default; two
                           workgroups per CU) or 32 (one workgroup per CU, the block's C read during its last
                           K step); the results are the same bitwise (same order of the products over K) */
@@ -162,12 +162,13 @@ typedef struct {
 /* Look-ahead (the paper's section "State-of-the-art matrix decompositions":
    the part of the update that the next panel needs is done first, then the
    next panel decomposition runs concurrently with the rest of the update).
-   With opts->lookahead > 0, an LU or QR factorization with uniform
+   With opts->lookahead > 0, a Cholesky, LU or QR factorization with uniform
    protection and no fault plan runs its work on two streams of the handle
    restricted to disjoint sets of compute units (created for the call with
    hipExtStreamCreateWithCUMask, default priority): the panel stream gets
-   opts->lookahead units (raised to what the first panel's cooperative
-   leaves need to hold its rows in LDS, at most half the device), the
+   opts->lookahead units (for LU and QR raised to what the first panel's
+   cooperative leaves need to hold its rows in LDS, at most half the
+   device), the
    update stream the rest.  Each iteration updates and verifies the next
    panel's block column first, factors that panel on the panel stream while
    the rest of the trailing matrix is updated and verified, and joins before
@@ -175,12 +176,14 @@ typedef struct {
    on entry and the caller's stream after both on exit.  Profiled calls and
    calls with fault plans or per-iteration levels use the one-stream
    schedule.  The factors equal the one-stream schedule's bitwise when the
-   cooperative leaves get the same shape on both (small panels), and to
-   rounding otherwise.  It is off by default: on one MI355X the panel needs
-   about a quarter of the device's LDS at n = 32768, and the update loses
-   more on the remaining units than the overlap saves (LU 883 -> 1063 ms,
-   QR 1342 -> 1631 ms with 64 panel units).  The two restricted streams are
-   created for the call and destroyed at its end. */
+   cooperative leaves get the same shape on both (small panels; always for
+   Cholesky, whose panel has no cooperative leaf), and to rounding
+   otherwise.  It is off by default: on one MI355X the LU and QR panels
+   need about a quarter of the device's LDS at n = 32768, and in all three
+   the update loses more on the remaining units than the overlap saves (LU
+   883 -> 1063 ms, QR 1342 -> 1631 ms with 64 panel units; Cholesky
+   341 -> 380 ms with 32).  The two restricted streams are created for the
+   call and destroyed at its end. */
 
 /* opts.flags: ABFT_FLAG_PROFILE times the phases of the call with HIP
    events on the handle's stream, all work on that one stream (the call then

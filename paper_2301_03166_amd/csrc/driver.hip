@@ -747,6 +747,9 @@ template <typename T>
 int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const abft_opts* opts, int nb, int protect,
                double ts, int prec, int32_t* dinfo, abft_report* drep, bool one_stream = false) {
   OffNull off(h, opts, !one_stream);
+  // (the look-ahead moves the work to the update stream when on; the
+  // Cholesky panel has no cooperative leaf, so any panel share holds it)
+  Look la(h, opts, !one_stream && !has_operand_faults(opts), n, nb, 1 << 30);
   hipStream_t s = h->stream;
   TRY(report_init(s, drep, dinfo));
   if (n == 0) return report_fini(s, drep);
@@ -762,7 +765,7 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
   // (nothing to overlap without checksums; operand faults need the update
   // product and the carry in order)
   Side side(h, any_protected(opts, N, protect) && !pf.on && !one_stream && !opf);
-  Beside vb(h, opts, !pf.on && !one_stream && !opf);
+  Beside vb(h, opts, !pf.on && !one_stream && !opf && !la.on);
   int t, prev = ABFT_PROTECT_NONE;
   for (int k = 0; k < N; ++k) {
     const int64_t c0 = (int64_t)k * nb;
@@ -779,7 +782,8 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
     }
     prev = lev;
     t = pf.begin(PH_PANEL);
-    TRY(chol_panel(s, dA, lda, n, c0, c1, dinfo));
+    // (with look-ahead, panel k was factored during iteration k - 1)
+    if (!(la.on && k > 0)) TRY(chol_panel(s, dA, lda, n, c0, c1, dinfo));
     TRY(vb.join());  // (the rest of the trailing matrix verified beside the panel)
     // the panel check only reads (the panel, its checksum rows, colchk of the
     // panel's columns): it goes to the side stream with the carry
@@ -808,6 +812,40 @@ int potrf_impl(abft_handle h, int64_t n, T* dA, int64_t lda, const Ws& w, const 
       TRY(carry_k(side.s));
     }
     if (opf) TRY(apply_operand_faults<T>(s, opts, k, dA, lda, n, nullptr, 0, c1));
+    if (la.on) {
+      // the next panel's block column first (its lower tiles), the carry
+      // joined, that column verified; then panel k + 1 on the panel stream
+      // beside the rest of the update and its verification
+      const int64_t c2 = std::min<int64_t>(n, c1 + nb);
+      const int kw2 = (int)(c2 - c1);
+      TRY(gemmT(s, prec, 0, 1, 1, (int)m, kw2, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0, trole));
+      if (fork) {
+        TRY(side.join());
+      } else if (lev) {
+        TRY(carry_k(s));
+      }
+      if (lev) {
+        TRY(verify_tiles<T>(s, dA, lda, n, c2, nb, k + 1, k + 1, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                            w.tflags, drep, k, lev));
+        TRY(correct_tiles<T>(s, dA, lda, n, c2, nb, k + 1, k + 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                             w.tflags, drep, k, lev));
+      }
+      TRY(la.fork_panel());
+      TRY(chol_panel(la.ps, dA, lda, n, c1, c2, dinfo));
+      if (c2 < n) {
+        const int64_t m2 = n - c2;
+        TRY(gemmT(s, prec, 0, 1, 1, (int)m2, (int)m2, kw, -1.0, L21 + kw2, lda, L21 + kw2, lda, 1.0,
+                  dA + c2 + c2 * lda, lda, 0, trole));
+        if (lev) {
+          TRY(verify_tiles<T>(s, dA, lda, n, n, nb, k + 2, k + 2, 1, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                              w.tflags, drep, k, lev));
+          TRY(correct_tiles<T>(s, dA, lda, n, n, nb, k + 2, k + 2, 1, w.colchk, ldc, w.rowchk, n, w.gc, w.gr, tsu,
+                               w.tflags, drep, k, lev));
+        }
+      }
+      TRY(la.join_panel());
+      continue;
+    }
     t = pf.begin(PH_TMU);
     TRY(gemmT(s, prec, 0, 1, 1, (int)m, (int)m, kw, -1.0, L21, lda, L21, lda, 1.0, dA + c1 + c1 * lda, lda, 0, trole));
     pf.end(t);

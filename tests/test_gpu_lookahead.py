@@ -35,6 +35,9 @@ def clean(rep):
 
 def run(h, kind, A, nb, **kw):
     d = dev(A)
+    if kind == "chol":
+        info, rep = h.potrf(d, nb, **kw)
+        return np.tril(d.cpu().numpy()), None, info, rep
     if kind == "lu":
         aux, info, rep = h.getrf(d, nb, **kw)
     else:
@@ -42,29 +45,37 @@ def run(h, kind, A, nb, **kw):
     return d.cpu().numpy(), aux.cpu().numpy(), info, rep
 
 
-@pytest.mark.parametrize("kind", ["lu", "qr"])
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
 @pytest.mark.parametrize("n,nb,la", [(3000, 256, 32), (2600, 384, 16), (1000, 128, 8), (700, 512, 32)])
 def test_lookahead_matches_one_stream(h, kind, n, nb, la):
-    A = gen.general(n, seed=n + nb)
+    A = gen.spd(n, n + nb) if kind == "chol" else gen.general(n, seed=n + nb)
     F1, a1, i1, r1 = run(h, kind, A, nb, lookahead=la)
     F2, a2, i2, r2 = run(h, kind, A, nb)
     assert i1 == i2 == 0 and clean(r1) and clean(r2)
     assert r1.max_ratio == r2.max_ratio
-    assert np.array_equal(a1, a2)
+    assert r1.events() == r2.events()
+    if a1 is not None:
+        assert np.array_equal(a1, a2)
     assert np.array_equal(F1, F2)
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("kind", ["lu", "qr"])
+@pytest.mark.parametrize("kind", ["chol", "lu", "qr"])
 def test_lookahead_large_vs_oracle(h, kind):
-    """n = 9472, nb = 512 with a 64-unit panel stream: the first panels
-    need 32-wide leaves spread over the panel stream's workgroups."""
+    """n = 9472, nb = 512 with a 64-unit panel stream: the first LU / QR
+    panels need 32-wide leaves spread over the panel stream's workgroups
+    (the Cholesky panel has no cooperative leaf and keeps its shape)."""
     n, nb = 9472, 512
-    A = gen.general(n, seed=77)
+    A = gen.spd(n, 77) if kind == "chol" else gen.general(n, seed=77)
     F, aux, info, rep = run(h, kind, A, nb, lookahead=64)
     assert info == 0 and clean(rep)
     O = A.copy(order="F")
-    if kind == "lu":
+    if kind == "chol":
+        oracle.potrf(O, nb)
+        O = np.tril(O)
+        assert np.linalg.norm(F - O) / np.linalg.norm(O) < 1e-13
+        assert np.array_equal(F, run(h, kind, A, nb)[0])
+    elif kind == "lu":
         oaux, _, orep = oracle.getrf(O, nb)
         assert np.array_equal(aux, oaux)
         assert np.linalg.norm(F - O) / np.linalg.norm(O) < 1e-12
@@ -74,7 +85,7 @@ def test_lookahead_large_vs_oracle(h, kind):
         assert np.linalg.norm(np.triu(F) - np.triu(O)) / np.linalg.norm(np.triu(O)) < 1e-12
 
 
-@pytest.mark.parametrize("chol", [False])
+@pytest.mark.parametrize("chol", [False, True])
 def test_lookahead_mixed_precision_matches_one_stream(h, chol):
     import torch
     n, nb = 2048, 256
