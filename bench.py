@@ -44,7 +44,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n=7168, nb=512):
+def cpu_baseline(n=8192, nb=512):
     """The plain CPU oracle (as it stands, OpenMP over independent elements
     on every host core) on a bounded sample of the workload: the three ABFT
     decompositions of an n x n matrix, useful TFLOP/s; the time of the
