@@ -814,7 +814,14 @@ __global__ __launch_bounds__(2 * PB_W) void k_perm_build(const int32_t* ipiv, in
     for (; q < lim; ++q) r += mflag[q];
     if (tid >= w) {  // and the moved outer rows with a smaller row index
       const int kx = key[tid];
-      for (q = w; q < 2 * w; ++q) r += (mflag[q] && key[q] < kx);
+      q = w;
+      for (; q < 2 * w && (q & 3); ++q) r += (mflag[q] && key[q] < kx);
+      for (; q + 4 <= 2 * w; q += 4) {
+        const int4 f4 = *reinterpret_cast<const int4*>(&mflag[q]);
+        const int4 k4 = *reinterpret_cast<const int4*>(&key[q]);
+        r += (f4.x && k4.x < kx) + (f4.y && k4.y < kx) + (f4.z && k4.z < kx) + (f4.w && k4.w < kx);
+      }
+      for (; q < 2 * w; ++q) r += (mflag[q] && key[q] < kx);
     }
     moves[1 + 2 * r] = (int)(c0 + key[tid]);
     moves[2 + 2 * r] = (int)(c0 + fin);
